@@ -22,12 +22,16 @@ Forward transform (Sec. 3.4.2, eq. projection and the lines after it):
 u_hat = B^{-1} S(u) with the Shen scalar product S_m(u) = (u, phi_m)^N_w;
 backward transform u(x_j) = sum_l u_hat_l phi_l(x_j) (eq. fast_shen).
 """
+import functools
+
 import numpy as np
 from numpy.polynomial import chebyshev as npcheb
 
-from .linalg import solve_refined
+from .linalg import householder_qr, lstsq_qr, solve_refined
 
 LD = np.longdouble
+# pi to the full x87 extended precision (np.pi is a binary64 constant)
+PI_LD = np.arccos(LD(-1))
 BASES = ("dirichlet", "biharmonic", "chebyshev")
 
 
@@ -44,13 +48,15 @@ def nbasis(basis, N):
     return {"dirichlet": N - 2, "biharmonic": N - 4, "chebyshev": N}[basis]
 
 
+@functools.lru_cache(maxsize=32)
 def tmatrix(N, K=None):
     """T[j, k] = T_k(x_j), k = 0..K-1 (default N), longdouble."""
     K = N if K is None else K
     r = np.mod(np.outer(2 * np.arange(N) + 1, np.arange(K)), 4 * N).astype(LD)
-    return np.cos(np.pi * r / (2 * N))
+    return np.cos(PI_LD * r / (2 * N))
 
 
+@functools.lru_cache(maxsize=32)
 def recombination(basis, N, K=None):
     """P[k, l]: Chebyshev coefficient k of basis function l (K rows, default N)."""
     K = N if K is None else K
@@ -66,11 +72,13 @@ def recombination(basis, N, K=None):
     return P
 
 
+@functools.lru_cache(maxsize=32)
 def synthesis(basis, N):
     """Phi[j, l] = phi_l(x_j) (longdouble)."""
     return tmatrix(N) @ recombination(basis, N)
 
 
+@functools.lru_cache(maxsize=32)
 def derivative_synthesis(basis, N, order):
     """Phi^(order)[j, l] = phi_l^(order)(x_j) (longdouble)."""
     P = recombination(basis, N)
@@ -96,32 +104,62 @@ def scalar_product(basis, u, axis=0):
     """S_m(u) = sum_j u(x_j) phi_m(x_j) pi/N along `axis` (nb outputs)."""
     N = np.shape(u)[axis]
     Phi = synthesis(basis, N)
-    return _apply_left(Phi.T * (LD(np.pi) / N), u, axis)
+    return _apply_left(Phi.T * (PI_LD / N), u, axis)
 
 
+@functools.lru_cache(maxsize=32)
 def mass_matrix(basis, N):
     Phi = synthesis(basis, N)
-    return (Phi.T @ Phi) * (LD(np.pi) / N)
+    return (Phi.T @ Phi) * (PI_LD / N)
 
 
+@functools.lru_cache(maxsize=32)
 def stiffness_matrix(basis, N):
     """A[m, l] = (phi_l'', phi_m)^N_w."""
-    return (synthesis(basis, N).T @ derivative_synthesis(basis, N, 2)) * (LD(np.pi) / N)
+    return (synthesis(basis, N).T @ derivative_synthesis(basis, N, 2)) * (PI_LD / N)
 
 
+@functools.lru_cache(maxsize=32)
 def bilaplace_matrix(basis, N):
     """S[m, l] = (phi_l'''', phi_m)^N_w."""
-    return (synthesis(basis, N).T @ derivative_synthesis(basis, N, 4)) * (LD(np.pi) / N)
+    return (synthesis(basis, N).T @ derivative_synthesis(basis, N, 4)) * (PI_LD / N)
+
+
+@functools.lru_cache(maxsize=16)
+def _projection_qr(basis, N):
+    """Householder QR (extended precision) of the weighted synthesis matrix
+    W^{1/2} Phi, W = diag(pi/N)."""
+    return householder_qr(synthesis(basis, N) * np.sqrt(PI_LD / N))
 
 
 def forward(basis, u, axis=0):
-    """u_hat = B^{-1} S(u) along `axis` (dense LU, refined)."""
+    """u_hat = B^{-1} S(u) along `axis`.
+
+    B u_hat = S(u) are the normal equations of the weighted least-squares
+    problem  min_u_hat sum_j w_j |u(x_j) - sum_l u_hat_l phi_l(x_j)|^2  (the
+    projection of eq. projection); the oracle solves that least-squares
+    problem with a dense Householder QR in extended precision.  B itself is
+    ill-conditioned for the biharmonic basis (cond ~ 1e8 at N = 512), so
+    forming and solving the normal equations directly would lose digits; the
+    small-N test pins both forms against each other."""
     N = np.shape(u)[axis]
-    S = scalar_product(basis, u, axis)
-    S0 = np.moveaxis(S, axis, 0)
-    sh = S0.shape
-    x = solve_refined(mass_matrix(basis, N), S0.reshape(sh[0], -1))
-    return np.moveaxis(x.reshape(sh), 0, axis)
+    V, R = _projection_qr(basis, N)
+    wh = np.sqrt(PI_LD / N)
+    a = np.moveaxis(np.asarray(u), axis, 0)
+    sh = a.shape
+    flat = a.reshape(sh[0], -1)
+    x = lstsq_qr(V, R, flat.real.astype(LD) * wh).astype(np.float64)
+    if np.iscomplexobj(flat):
+        x = x + 1j * lstsq_qr(V, R, flat.imag.astype(LD) * wh).astype(np.float64)
+    return np.moveaxis(x.reshape((x.shape[0],) + sh[1:]), 0, axis)
+
+
+def forward_normal_equations(basis, u):
+    """u_hat = B^{-1} S(u) for a 1D u by dense LU on the assembled mass matrix
+    (refined); the literal form of the projection, used as a cross-check."""
+    N = len(u)
+    S = (synthesis(basis, N).T * (PI_LD / N)) @ np.asarray(u, dtype=LD)
+    return solve_refined(mass_matrix(basis, N), S)
 
 
 def backward(basis, uh, axis=0):

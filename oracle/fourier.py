@@ -12,6 +12,9 @@ with those exact-phase DFT matrices.
 """
 import numpy as np
 
+# 2 pi to the full x87 extended precision
+TWO_PI_LD = 2 * np.arccos(np.longdouble(-1))
+
 
 def wavenumbers(M):
     """Integer wavenumbers in FFT order: 0..ceil(M/2)-1, then -floor(M/2)..-1.
@@ -25,7 +28,7 @@ def dft_matrix(M, sign, rows=None):
     """E[q, j] = exp(sign * 2 pi i ((q*j) mod M) / M) for q in rows (default all)."""
     q = np.arange(M) if rows is None else np.asarray(rows)
     r = np.mod(np.outer(q, np.arange(M)), M).astype(np.longdouble)
-    ang = sign * 2 * np.pi * r / M
+    ang = sign * TWO_PI_LD * r / M
     return (np.cos(ang) + 1j * np.sin(ang)).astype(np.complex128)
 
 
@@ -86,7 +89,7 @@ def padded_backward(uh, Mp, axes=(0, 1)):
         N = out.shape[ax]
         l = wavenumbers(N)
         r = np.mod(np.outer(np.arange(Mp), l), Mp).astype(np.longdouble)
-        ang = 2 * np.pi * r / Mp
+        ang = TWO_PI_LD * r / Mp
         E = (np.cos(ang) + 1j * np.sin(ang)).astype(np.complex128)   # Mp x N
         out = _apply(E, out, ax)
     return out
@@ -100,7 +103,7 @@ def padded_forward_truncate(w, N, axes=(0, 1)):
         Mp = out.shape[ax]
         l = wavenumbers(N)
         r = np.mod(np.outer(l, np.arange(Mp)), Mp).astype(np.longdouble)
-        ang = -2 * np.pi * r / Mp
+        ang = -TWO_PI_LD * r / Mp
         E = (np.cos(ang) + 1j * np.sin(ang)).astype(np.complex128)   # N x Mp
         out = _apply(E, out, ax) / Mp
     return out

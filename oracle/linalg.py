@@ -28,3 +28,44 @@ def solve_refined(A, b, iters=3):
         r = b_ld - A_ld @ x
         x = x + sla.lu_solve(lu, r.astype(np.float64)).astype(LD)
     return x.astype(np.float64)
+
+
+def householder_qr(A):
+    """Dense Householder QR of a real m x n (m >= n) matrix in extended precision.
+
+    Returns (V, R): V holds the n reflector vectors v_i (unit norm, zero
+    above row i), R the n x n upper triangle, with A = Q R and
+    Q^T = H_{n-1} ... H_0, H_i = I - 2 v_i v_i^T."""
+    A = np.array(A, dtype=LD, copy=True)
+    m, n = A.shape
+    V = np.zeros((m, n), dtype=LD)
+    for i in range(n):
+        x = A[i:, i].copy()
+        alpha = -np.sign(x[0]) * np.sqrt((x * x).sum()) if x[0] != 0 else -np.sqrt((x * x).sum())
+        v = x
+        v[0] = v[0] - alpha
+        nv = np.sqrt((v * v).sum())
+        if nv == 0:
+            continue
+        v = v / nv
+        V[i:, i] = v
+        A[i:, i:] -= 2 * np.outer(v, v @ A[i:, i:])
+    return V, np.triu(A[:n, :n])
+
+
+def lstsq_qr(V, R, b):
+    """min ||A x - b||_2 for the factorisation returned by householder_qr;
+    b is real (m or m x k) and is kept in extended precision throughout."""
+    y = np.array(b, dtype=LD, copy=True)
+    vec = y.ndim == 1
+    if vec:
+        y = y[:, None]
+    m, n = V.shape
+    for i in range(n):
+        v = V[i:, i]
+        y[i:] -= 2 * np.outer(v, v @ y[i:])
+    z = y[:n]
+    x = np.zeros_like(z)
+    for i in range(n - 1, -1, -1):
+        x[i] = (z[i] - R[i, i + 1:] @ x[i + 1:]) / R[i, i]
+    return x[:, 0] if vec else x

@@ -148,7 +148,7 @@ def fourier_columns(u, cols, kind_last="r2c"):
         for ax, M in enumerate(phys):
             q = idx[ax][i]
             r = np.mod(q * np.arange(M), M).astype(np.longdouble)
-            e = (np.cos(2 * np.pi * r / M) - 1j * np.sin(2 * np.pi * r / M)).astype(np.complex128) / M
+            e = (np.cos(fourier.TWO_PI_LD * r / M) - 1j * np.sin(fourier.TWO_PI_LD * r / M)).astype(np.complex128) / M
             sh = [1] * len(phys)
             sh[ax] = M
             phase = phase * e.reshape(sh)
@@ -165,3 +165,20 @@ def forward_columns(basis, u, cols, kind_last="r2c"):
 def scalar_product_columns(basis, f, cols, kind_last="r2c"):
     N = f.shape[0]
     return _pad_rows(cheb.scalar_product(basis, fourier_columns(f, cols, kind_last), axis=0), N)
+
+
+def backward_rows(basis, uh, rows, M_last, kind_last="r2c"):
+    """backward() restricted to the physical x-rows `rows` (3D spectral input):
+    for each x_j, c_mn = sum_l u_hat[l, m, n] phi_l(x_j), then the Fourier
+    backward transforms along y and z."""
+    N = uh.shape[0]
+    nb = cheb.nbasis(basis, N)
+    Phi = cheb.synthesis(basis, N)
+    flat = uh[:nb].reshape(nb, -1)
+    re = flat.real.astype(np.longdouble)
+    im = flat.imag.astype(np.longdouble)
+    out = []
+    for j in rows:
+        cj = ((Phi[j] @ re).astype(np.float64) + 1j * (Phi[j] @ im).astype(np.float64)).reshape(uh.shape[1:])
+        out.append(_fourier_backward(cj[None], M_last, kind_last)[0])
+    return np.array(out)

@@ -1,0 +1,44 @@
+"""The C-ABI library loads and exports every entry point its headers declare (CPU-only)."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1708_03188_amd", "libsgm.so")
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names |= set(re.findall(r"\b(sgm_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for n in ("sgm_plan_create", "sgm_forward", "sgm_backward", "sgm_helmholtz_solve", "sgm_biharmonic_solve"):
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsgm.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsgm.so not built")
+def test_status_strings_and_argument_errors_without_gpu():
+    from paper_1708_03188_amd import _lib
+    lib = _lib.load()
+    assert lib.sgm_status_string(0) == b"ok"
+    assert lib.sgm_status_string(-2) == b"unsupported size"
+    assert lib.sgm_version() >= 1
+    # A null descriptor is rejected before any device call.
+    assert lib.sgm_plan_create(None, None) == -1
+    assert b"null" in lib.sgm_last_error()

@@ -181,3 +181,48 @@ def test_spectral_convergence_dirichlet_poisson():
         errs.append(np.abs(C.backward("dirichlet", uh) - u).max())
     assert errs[0] > 1e-3 and errs[-1] < 1e-13
     assert all(errs[i + 1] < errs[i] * 0.2 for i in range(3))
+
+
+@pytest.mark.parametrize("basis", C.BASES)
+def test_least_squares_form_equals_normal_equations(basis):
+    # The projection u_hat = B^{-1} S(u) (Sec. 3.4.2) solved as the dense LU of the
+    # assembled normal equations and as the weighted least-squares problem agree where
+    # B is well conditioned.
+    N = 24
+    x = C.points(N)
+    u = np.exp(x) * np.sin(3 * x + 0.2) + x**2
+    assert np.allclose(C.forward(basis, u), C.forward_normal_equations(basis, u), rtol=0, atol=1e-13)
+
+
+def test_projection_accuracy_against_high_precision():
+    # Biharmonic N = 96 (cond(B) ~ 3e5): the oracle's projection agrees with a
+    # 40-digit mpmath solve of B u_hat = S (exact quadrature, banded Gaussian elimination).
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 40
+    N = 96
+    x = C.points(N)
+    g = np.exp(x) * np.cos(3 * x) + 0.1 * x
+    tab = [mpmath.cos(mpmath.pi * r / (2 * N)) for r in range(4 * N)]
+    gv = [mpmath.mpf(float(v)) for v in g]
+    chat = []
+    for k in range(N):
+        s = mpmath.mpf(0)
+        for j in range(N):
+            s += gv[j] * tab[(k * (2 * j + 1)) % (4 * N)]
+        chat.append(s * 2 / ((2 if k == 0 else 1) * N))
+
+    def comp(k):
+        return [(k, mpmath.mpf(1)), (k + 2, mpmath.mpf(-2 * (k + 2)) / (k + 3)), (k + 4, mpmath.mpf(k + 1) / (k + 3))]
+
+    def D(k):
+        return mpmath.pi if k == 0 else mpmath.pi / 2
+
+    nb = N - 4
+    B = mpmath.matrix(nb, nb)
+    for a in range(nb):
+        for b in range(max(0, a - 4), min(nb, a + 5)):
+            B[a, b] = sum(p1 * p2 * D(m1) for m1, p1 in comp(a) for m2, p2 in comp(b) if m1 == m2)
+    S = mpmath.matrix([sum(p * D(m) * chat[m] for m, p in comp(k)) for k in range(nb)])
+    ref = np.array([float(v) for v in mpmath.lu_solve(B, S)])
+    got = C.forward("biharmonic", g)
+    assert np.abs(got - ref).max() < 1e-15 * np.abs(ref).max() * 10

@@ -77,3 +77,11 @@ def test_column_restricted_forms_match_full():
     ft = T.scalar_product("dirichlet", f)
     hs = T.helmholtz_solve("dirichlet", ft, 1.0, 10).reshape(12, -1)[:, cols]
     assert np.allclose(T.helmholtz_solve("dirichlet", ft, 1.0, 10, cols=cols), hs, atol=1e-15)
+
+
+def test_backward_rows_matches_full():
+    rng = np.random.default_rng(4)
+    vh = synth.random_spectral((12, 8, 5), seed=4, nrows=10)
+    full = T.backward("dirichlet", vh, 8)
+    rows = [0, 5, 11]
+    assert np.allclose(T.backward_rows("dirichlet", vh, rows, 8), full[rows], atol=1e-14)
