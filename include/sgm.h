@@ -1,0 +1,128 @@
+/*
+ * sgm.h -- C ABI of libsgm, a gfx950 (MI355X) implementation of the
+ * data-parallel hot path of the spectral Galerkin method in tensor-product
+ * domains with one non-periodic (Chebyshev/Shen) direction and one or two
+ * periodic (Fourier) directions (Mortensen, "Shenfun - automating the
+ * spectral Galerkin method").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All array arguments are DEVICE pointers owned by the caller.  Real data
+ *   are IEEE binary64; complex data are interleaved (re, im) binary64 pairs.
+ * - Every call is asynchronous on the given stream (a hipStream_t passed as
+ *   void*, NULL = the null stream) and never allocates device memory; plans
+ *   own their workspace and tables, allocated at creation.
+ * - Return value: SGM_OK (0) or a negative SGM_ERR_* code; a human-readable
+ *   detail for the last failing call of the calling thread is available from
+ *   sgm_last_error().  No C++ exception crosses this boundary.
+ * - Physical arrays are C-ordered [x][y] or [x][y][z] with z contiguous; x
+ *   holds the N Gauss-Chebyshev points x_j = cos((2j+1) pi / (2N)) (Sec. 3.4.2),
+ *   y and z the uniform periodic grids 2 pi k / M (Sec. 3.4.1).
+ * - Spectral arrays are C-ordered [l][m] or [l][m][n]: N rows along x (rows
+ *   l >= the number of basis functions are written as zero), the Fourier
+ *   axes in FFT order (0..ceil(M/2)-1, then -floor(M/2)..-1; eq. wavenumber_even);
+ *   an R2C last axis keeps n = 0..M/2 (Sec. 3.4.1, Hermitian symmetry).
+ */
+#ifndef SGM_H
+#define SGM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int sgm_status;
+#define SGM_OK 0
+#define SGM_ERR_INVALID_ARG (-1)
+#define SGM_ERR_UNSUPPORTED_SIZE (-2)
+#define SGM_ERR_HIP (-3)
+#define SGM_ERR_OOM (-4)
+#define SGM_ERR_UNIMPLEMENTED (-5)
+
+/* Basis along the non-periodic axis 0. */
+#define SGM_SHEN_DIRICHLET 1  /* phi_l = T_l - T_{l+2}, l = 0..N-3 (eq. chebdirichlet)              */
+#define SGM_SHEN_BIHARMONIC 2 /* phi_l = T_l - 2(l+2)/(l+3) T_{l+2} + (l+1)/(l+3) T_{l+4},
+                                 l = 0..N-5 (eq. chebbiharmonic)                                    */
+#define SGM_CHEBYSHEV 3       /* phi_l = T_l, l = 0..N-1 (regular Chebyshev basis, Sec. 3.1)        */
+
+/* Transform kind of the last (contiguous) periodic axis. */
+#define SGM_R2C 1 /* real physical data, M/2+1 coefficients (R2CBasis, Sec. 3.1)  */
+#define SGM_C2C 2 /* complex physical data, M coefficients (C2CBasis, Sec. 3.1)   */
+
+typedef struct sgm_plan_s* sgm_plan;
+
+typedef struct {
+    int ndim;      /* 2: [x][y]; 3: [x][y][z]                                          */
+    int basis;     /* SGM_SHEN_DIRICHLET | SGM_SHEN_BIHARMONIC | SGM_CHEBYSHEV         */
+    int N;         /* points along x: >= 3 (Dirichlet), >= 5 (biharmonic), >= 2       */
+    int M1;        /* points along y, >= 1                                             */
+    int M2;        /* points along z (ndim = 3), >= 1; ignored for ndim = 2            */
+    int kind_last; /* SGM_R2C | SGM_C2C for the last axis (y if ndim = 2, z if 3)      */
+    double Ly, Lz; /* periods of y and z; 0 means 2 pi.  Used only by the solves.      */
+    int autotune;  /* 0: default launch shapes; 1: time the candidates once at creation */
+} sgm_plan_desc;
+
+/* Create a plan for the tensor-product space V(x) x V^p(y) [x V^p(z)] (Sec. 4,
+ * TensorProductSpace).  Uploads twiddle, recombination, projection and
+ * solver tables and allocates one spectral-sized workspace on the current
+ * device.  Errors: INVALID_ARG (null pointers, bad enums), UNSUPPORTED_SIZE
+ * (N below the basis minimum, sizes above 65536 points per axis), OOM, HIP. */
+sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out);
+sgm_status sgm_plan_destroy(sgm_plan plan);
+
+/* Physical and spectral shapes in elements (unused trailing dims are 1). */
+sgm_status sgm_plan_shapes(sgm_plan plan, int64_t phys[3], int64_t spec[3]);
+
+/* Forward transform u -> u_hat (Sec. 4 and Sec. 3.4.2): Fourier transforms
+ * with 1/M scaling along the periodic axes (last axis first), then the Shen
+ * forward transform u_hat = B^{-1} S(u) along x (eq. projection), i.e. the
+ * weighted L2 projection onto the basis.  u: physical (real for R2C,
+ * complex for C2C); u_hat: spectral complex.  u and u_hat must not overlap;
+ * u is not modified. */
+sgm_status sgm_forward(sgm_plan plan, const void* u, void* u_hat, void* stream);
+
+/* Backward transform u_hat -> u: u(x_j, y, z) = sum_l u_hat_l phi_l(x_j) e^{i(my+nz)}
+ * (eq. fast_shen, eq. ufourier), unnormalised.  For R2C the imaginary parts of
+ * the n = 0 and n = M/2 coefficients are ignored.  u_hat is not modified. */
+sgm_status sgm_backward(sgm_plan plan, const void* u_hat, void* u, void* stream);
+
+/* Scalar product f_tilde_l = (f, phi_l)^N_w after the Fourier transforms
+ * (Sec. 4, right-hand side formula; the (2 pi)^(d-1) factor is dropped on both
+ * sides of every solve).  Same layouts as sgm_forward. */
+sgm_status sgm_scalar_product(sgm_plan plan, const void* f, void* f_tilde, void* stream);
+
+/* Helmholtz solve alpha u - lap u = f for the Shen-Dirichlet (or regular
+ * Chebyshev is rejected) plan: per Fourier wavenumber column with
+ * kappa^2 = (2pi m/Ly)^2 + (2pi n/Lz)^2, solves (-A + (kappa^2 + alpha) B) u_hat = f_tilde
+ * (eq. cheb_poisson, eq. laplace), A_ml = (phi_l'', phi_m), B_ml = (phi_l, phi_m).
+ * f_tilde and u_hat are spectral arrays (rows >= N-2 of f_tilde ignored); they
+ * may be the same pointer (in-place).  alpha >= 0.  INVALID_ARG otherwise. */
+sgm_status sgm_helmholtz_solve(sgm_plan plan, double alpha, const void* f_tilde, void* u_hat, void* stream);
+
+/* Biharmonic solve lap^2 u = f for the Shen-biharmonic plan (Sec. 4): per column
+ * (S - 2 kappa^2 A + kappa^4 B) u_hat = f_tilde with S_ml = (phi_l'''', phi_m).
+ * Same layout and aliasing rules as sgm_helmholtz_solve. */
+sgm_status sgm_biharmonic_solve(sgm_plan plan, const void* f_tilde, void* u_hat, void* stream);
+
+/* Per-pass timing (diagnostics).  When enabled, every pass kernel this plan
+ * launches is bracketed by two hipEvents recorded on the caller's stream
+ * (the events are created on first use and owned by the plan).  Pass kinds:
+ * 0 last-axis forward FFT, 1 last-axis backward FFT, 2 middle-axis forward FFT,
+ * 3 middle-axis backward FFT, 4 Chebyshev forward (projection), 5 Chebyshev
+ * scalar product, 6 Chebyshev backward, 7 Galerkin solve.
+ * sgm_plan_pass_times waits for the recorded events, adds their durations to
+ * ms[SGM_NPASS] and launch counts to count[SGM_NPASS] (running totals since the
+ * last reset) and, if reset != 0, clears the totals afterwards. */
+#define SGM_NPASS 8
+sgm_status sgm_plan_timing(sgm_plan plan, int enable);
+sgm_status sgm_plan_pass_times(sgm_plan plan, double ms[SGM_NPASS], int64_t count[SGM_NPASS], int reset);
+
+const char* sgm_status_string(sgm_status s);
+const char* sgm_last_error(void);
+int sgm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGM_H */

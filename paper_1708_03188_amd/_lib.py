@@ -1,0 +1,67 @@
+"""ctypes loader for the in-tree libsgm.so.  Fails loudly when it is missing."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsgm.so")
+
+SGM_OK = 0
+SGM_SHEN_DIRICHLET, SGM_SHEN_BIHARMONIC, SGM_CHEBYSHEV = 1, 2, 3
+SGM_R2C, SGM_C2C = 1, 2
+
+
+class SgmError(RuntimeError):
+    pass
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int), ("basis", ctypes.c_int), ("N", ctypes.c_int), ("M1", ctypes.c_int),
+        ("M2", ctypes.c_int), ("kind_last", ctypes.c_int), ("Ly", ctypes.c_double), ("Lz", ctypes.c_double),
+        ("autotune", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+_vp = ctypes.c_void_p
+_SIGS = {
+    "sgm_version": ([], ctypes.c_int),
+    "sgm_last_error": ([], ctypes.c_char_p),
+    "sgm_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "sgm_plan_create": ([ctypes.POINTER(PlanDesc), ctypes.POINTER(_vp)], ctypes.c_int),
+    "sgm_plan_destroy": ([_vp], ctypes.c_int),
+    "sgm_plan_shapes": ([_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "sgm_forward": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "sgm_backward": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "sgm_scalar_product": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "sgm_helmholtz_solve": ([_vp, ctypes.c_double, _vp, _vp, _vp], ctypes.c_int),
+    "sgm_biharmonic_solve": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "sgm_plan_timing": ([_vp, ctypes.c_int], ctypes.c_int),
+    "sgm_plan_pass_times": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), ctypes.c_int],
+                            ctypes.c_int),
+}
+NPASS = 8
+PASS_NAMES = ["last_fwd", "last_bwd", "mid_fwd", "mid_bwd", "cheb_fwd", "cheb_scalar", "cheb_bwd", "solve"]
+
+
+def load():
+    """Load libsgm.so (built by __graft_entry__.build() / paper_1708_03188_amd/build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise SgmError(f"libsgm.so not found at {LIB_PATH}; build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (args, res) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def check(status, what=""):
+    if status != SGM_OK:
+        lib = load()
+        raise SgmError(f"{what}: {lib.sgm_status_string(status).decode()} ({lib.sgm_last_error().decode()})")

@@ -1,0 +1,377 @@
+// Tensor-product space plans and the C ABI for transforms and solves.
+#include <cstdarg>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "tables.h"
+
+namespace sgm {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+void clear_error() { g_last_error.clear(); }
+
+// Upload helper: packs several host vectors into one device allocation.
+struct Blob {
+    std::vector<char> host;
+    size_t add(const void* p, size_t bytes) {
+        size_t off = (host.size() + 255) & ~size_t(255);
+        host.resize(off + bytes);
+        if (bytes) std::memcpy(host.data() + off, p, bytes);
+        return off;
+    }
+    size_t add(const std::vector<double>& v) { return add(v.data(), v.size() * sizeof(double)); }
+};
+
+static int max_lds_bytes() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+        return 65536;
+    return v;
+}
+
+}  // namespace sgm
+
+using namespace sgm;
+
+struct sgm_plan_s {
+    sgm_plan_desc d;
+    int N, M1, M2, ndim, r2c;
+    int spec_last;   // length of the last spectral axis
+    int64_t phys[3], spec[3];
+    int64_t nspec;   // complex elements of the spectral array
+    void* blob = nullptr;
+    void* work = nullptr;
+    RadixPlan rpx, rpy, rpz;  // rpy: middle axis (ndim=3) ; rpz: last axis
+    ChebDev cd;
+    ColGeom geom;
+    int G_last, W_mid, W_cheb, W_solve;
+    // per-pass timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    double pass_ms[SGM_NPASS] = {0};
+    int64_t pass_cnt[SGM_NPASS] = {0};
+};
+
+// Brackets one pass launch with events when the plan's timing is enabled.
+struct PassTimer {
+    sgm_plan_s* p;
+    int kind;
+    hipStream_t s;
+    hipEvent_t e1 = nullptr, e2 = nullptr;
+    PassTimer(sgm_plan_s* p_, int k, hipStream_t s_) : p(p_), kind(k), s(s_) {
+        if (!p->timing) return;
+        e1 = take();
+        e2 = take();
+        if (e1) hipEventRecord(e1, s);
+    }
+    hipEvent_t take() {
+        hipEvent_t e = nullptr;
+        if (!p->ev_pool.empty()) { e = p->ev_pool.back(); p->ev_pool.pop_back(); }
+        else if (hipEventCreate(&e) != hipSuccess) e = nullptr;
+        return e;
+    }
+    ~PassTimer() {
+        if (!p->timing || !e1 || !e2) return;
+        hipEventRecord(e2, s);
+        p->pending.push_back({kind, {e1, e2}});
+    }
+};
+
+static sgm_status make_radix(int L, RadixPlan& rp) {
+    rp.L = L;
+    rp.nst = factor_radices(L, rp.radix);
+    rp.tw = nullptr;
+    if (rp.nst > kMaxStages) {
+        set_error("FFT length %d needs too many stages", L);
+        return SGM_ERR_UNSUPPORTED_SIZE;
+    }
+    return SGM_OK;
+}
+
+static int pick_tile(int L, int want, size_t (*bytes)(int, int), int lds_max) {
+    int w = want;
+    while (w > 1 && bytes(L, w) > (size_t)lds_max) w /= 2;
+    return w;
+}
+
+extern "C" {
+
+int sgm_version(void) { return 1; }
+
+const char* sgm_last_error(void) { return g_last_error.c_str(); }
+
+const char* sgm_status_string(sgm_status s) {
+    switch (s) {
+        case SGM_OK: return "ok";
+        case SGM_ERR_INVALID_ARG: return "invalid argument";
+        case SGM_ERR_UNSUPPORTED_SIZE: return "unsupported size";
+        case SGM_ERR_HIP: return "HIP runtime error";
+        case SGM_ERR_OOM: return "out of device memory";
+        case SGM_ERR_UNIMPLEMENTED: return "not implemented";
+        default: return "unknown status";
+    }
+}
+
+sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
+    clear_error();
+    SGM_CHECK_ARG(desc && out, "null argument");
+    *out = nullptr;
+    const sgm_plan_desc& d = *desc;
+    SGM_CHECK_ARG(d.ndim == 2 || d.ndim == 3, "ndim must be 2 or 3 (got %d)", d.ndim);
+    SGM_CHECK_ARG(d.basis == SGM_SHEN_DIRICHLET || d.basis == SGM_SHEN_BIHARMONIC || d.basis == SGM_CHEBYSHEV,
+                  "unknown basis %d", d.basis);
+    SGM_CHECK_ARG(d.kind_last == SGM_R2C || d.kind_last == SGM_C2C, "unknown kind_last %d", d.kind_last);
+    int minN = d.basis == SGM_SHEN_DIRICHLET ? 3 : d.basis == SGM_SHEN_BIHARMONIC ? 5 : 2;
+    int M2 = d.ndim == 3 ? d.M2 : 1;
+    if (d.N < minN || d.M1 < 1 || M2 < 1 || d.N > 65536 || d.M1 > 65536 || M2 > 65536) {
+        set_error("unsupported sizes N=%d M1=%d M2=%d for basis %d", d.N, d.M1, M2, d.basis);
+        return SGM_ERR_UNSUPPORTED_SIZE;
+    }
+    SGM_CHECK_ARG(d.Ly >= 0 && d.Lz >= 0, "negative period");
+    sgm_plan_s* p = new (std::nothrow) sgm_plan_s();
+    if (!p) return SGM_ERR_OOM;
+    p->d = d;
+    p->N = d.N;
+    p->M1 = d.M1;
+    p->M2 = M2;
+    p->ndim = d.ndim;
+    p->r2c = d.kind_last == SGM_R2C;
+    int Llast = d.ndim == 3 ? M2 : d.M1;
+    p->spec_last = p->r2c ? Llast / 2 + 1 : Llast;
+    p->phys[0] = d.N; p->phys[1] = d.M1; p->phys[2] = d.ndim == 3 ? M2 : 1;
+    p->spec[0] = d.N;
+    if (d.ndim == 3) { p->spec[1] = d.M1; p->spec[2] = p->spec_last; }
+    else { p->spec[1] = p->spec_last; p->spec[2] = 1; }
+    p->nspec = p->spec[0] * p->spec[1] * p->spec[2];
+
+    sgm_status st;
+    if ((st = make_radix(d.N, p->rpx)) != SGM_OK) { delete p; return st; }
+    if (d.ndim == 3 && (st = make_radix(d.M1, p->rpy)) != SGM_OK) { delete p; return st; }
+    if ((st = make_radix(Llast, p->rpz)) != SGM_OK) { delete p; return st; }
+
+    ChebTables ct;
+    std::string err;
+    if (!build_cheb_tables(d.basis, d.N, ct, err)) {
+        set_error("%s", err.c_str());
+        delete p;
+        return SGM_ERR_UNSUPPORTED_SIZE;
+    }
+    Blob b;
+    size_t o_twx = b.add(twiddles(d.N));
+    size_t o_twy = d.ndim == 3 ? b.add(twiddles(d.M1)) : 0;
+    size_t o_twz = b.add(twiddles(Llast));
+    size_t o_theta = b.add(ct.theta), o_beta = b.add(ct.beta), o_gamma = b.add(ct.gamma);
+    size_t o_bs = b.add(ct.bscale), o_fs = b.add(ct.fscale);
+    size_t o_rot[2], o_rt[2], o_sv[2], o_qt[2];
+    for (int q = 0; q < 2; ++q) {
+        o_qt[q] = b.add(ct.qtab[q]);
+        o_rot[q] = b.add(ct.rot[q]);
+        o_rt[q] = b.add(ct.rtab[q]);
+        o_sv[q] = b.add(ct.solve[q]);
+    }
+    hipError_t e = hipMalloc(&p->blob, b.host.size());
+    if (e != hipSuccess) { set_error("hipMalloc tables: %s", hipGetErrorString(e)); delete p; return SGM_ERR_OOM; }
+    e = hipMemcpy(p->blob, b.host.data(), b.host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { set_error("hipMemcpy tables: %s", hipGetErrorString(e)); hipFree(p->blob); delete p; return SGM_ERR_HIP; }
+    e = hipMalloc(&p->work, (size_t)p->nspec * sizeof(double2));
+    if (e != hipSuccess) { set_error("hipMalloc workspace: %s", hipGetErrorString(e)); hipFree(p->blob); delete p; return SGM_ERR_OOM; }
+    char* base = static_cast<char*>(p->blob);
+    auto D = [&](size_t off) { return reinterpret_cast<const double*>(base + off); };
+    p->rpx.tw = reinterpret_cast<const double2*>(base + o_twx);
+    if (d.ndim == 3) p->rpy.tw = reinterpret_cast<const double2*>(base + o_twy);
+    p->rpz.tw = reinterpret_cast<const double2*>(base + o_twz);
+    ChebDev& cd = p->cd;
+    cd.basis = d.basis; cd.N = d.N; cd.nb = ct.nb;
+    for (int q = 0; q < 2; ++q) {
+        cd.npar[q] = ct.npar[q]; cd.mpar[q] = ct.mpar[q];
+        cd.rot[q] = D(o_rot[q]); cd.rtab[q] = D(o_rt[q]); cd.solve[q] = D(o_sv[q]); cd.qtab[q] = D(o_qt[q]);
+    }
+    cd.theta = reinterpret_cast<const double2*>(base + o_theta);
+    cd.beta = D(o_beta); cd.gamma = D(o_gamma); cd.bscale = D(o_bs); cd.fscale = D(o_fs);
+
+    const double twopi = 6.283185307179586476925286766559;
+    double Ly = d.Ly > 0 ? d.Ly : twopi, Lz = d.Lz > 0 ? d.Lz : twopi;
+    ColGeom& g = p->geom;
+    g.ncols = (int)(p->spec[1] * p->spec[2]);
+    g.nlast = p->spec_last;
+    g.Mlast = Llast;
+    g.last_r2c = p->r2c;
+    if (d.ndim == 3) {
+        g.Mmid = d.M1;
+        g.sy = (twopi / Ly) * (twopi / Ly);
+        g.sz = (twopi / Lz) * (twopi / Lz);
+    } else {
+        g.Mmid = 1;
+        g.sy = 0.0;
+        g.sz = (twopi / Ly) * (twopi / Ly);
+    }
+    int lds = max_lds_bytes();
+    p->G_last = pick_tile(Llast, Llast >= 2048 ? 1 : 2048 / Llast, lds_bytes_lines, lds);
+    if (p->G_last > 16) p->G_last = 16;
+    p->W_mid = d.ndim == 3 ? pick_tile(d.M1, 16, lds_bytes_strided, lds) : 1;
+    p->W_cheb = pick_tile(d.N, d.N <= 256 ? 16 : 8, lds_bytes_cheb, lds);
+    int ws = d.N <= 256 ? 16 : 8;
+    while (ws > 1 && lds_bytes_solve(d.N, ws, d.basis) > (size_t)lds) ws /= 2;
+    p->W_solve = ws;
+    if (lds_bytes_lines(Llast, p->G_last) > (size_t)lds || lds_bytes_cheb(d.N, p->W_cheb) > (size_t)lds ||
+        (d.ndim == 3 && lds_bytes_strided(d.M1, p->W_mid) > (size_t)lds)) {
+        set_error("axis length too large for one work-group's LDS (%d bytes)", lds);
+        hipFree(p->work); hipFree(p->blob); delete p;
+        return SGM_ERR_UNSUPPORTED_SIZE;
+    }
+    *out = p;
+    return SGM_OK;
+}
+
+sgm_status sgm_plan_timing(sgm_plan p, int enable) {
+    clear_error();
+    SGM_CHECK_ARG(p, "null plan");
+    p->timing = enable != 0;
+    return SGM_OK;
+}
+
+sgm_status sgm_plan_pass_times(sgm_plan p, double ms[SGM_NPASS], int64_t count[SGM_NPASS], int reset) {
+    clear_error();
+    SGM_CHECK_ARG(p && ms && count, "null argument");
+    for (auto& pe : p->pending) {
+        float t = 0.f;
+        SGM_HIP_TRY(hipEventSynchronize(pe.second.second));
+        SGM_HIP_TRY(hipEventElapsedTime(&t, pe.second.first, pe.second.second));
+        p->pass_ms[pe.first] += t;
+        p->pass_cnt[pe.first] += 1;
+        p->ev_pool.push_back(pe.second.first);
+        p->ev_pool.push_back(pe.second.second);
+    }
+    p->pending.clear();
+    for (int i = 0; i < SGM_NPASS; ++i) { ms[i] = p->pass_ms[i]; count[i] = p->pass_cnt[i]; }
+    if (reset)
+        for (int i = 0; i < SGM_NPASS; ++i) { p->pass_ms[i] = 0; p->pass_cnt[i] = 0; }
+    return SGM_OK;
+}
+
+sgm_status sgm_plan_destroy(sgm_plan p) {
+    clear_error();
+    if (!p) return SGM_OK;
+    for (auto& pe : p->pending) { hipEventDestroy(pe.second.first); hipEventDestroy(pe.second.second); }
+    for (auto e : p->ev_pool) hipEventDestroy(e);
+    hipFree(p->work);
+    hipFree(p->blob);
+    delete p;
+    return SGM_OK;
+}
+
+sgm_status sgm_plan_shapes(sgm_plan p, int64_t phys[3], int64_t spec[3]) {
+    clear_error();
+    SGM_CHECK_ARG(p && phys && spec, "null argument");
+    for (int i = 0; i < 3; ++i) { phys[i] = p->phys[i]; spec[i] = p->spec[i]; }
+    return SGM_OK;
+}
+
+static sgm_status fourier_forward(sgm_plan p, const void* u, double2* uh, hipStream_t s) {
+    int Llast = p->ndim == 3 ? p->M2 : p->M1;
+    int nlines = p->ndim == 3 ? p->N * p->M1 : p->N;
+    {
+        PassTimer t(p, 0, s);
+        if (p->r2c)
+            SGM_HIP_TRY(launch_lines_r2c(static_cast<const double*>(u), uh, Llast, nlines, p->G_last, p->rpz,
+                                         1.0 / Llast, s));
+        else
+            SGM_HIP_TRY(launch_lines_c2c(static_cast<const double2*>(u), uh, Llast, nlines, p->G_last, p->rpz, -1,
+                                         1.0 / Llast, s));
+    }
+    if (p->ndim == 3) {
+        PassTimer t(p, 2, s);
+        SGM_HIP_TRY(launch_strided_c2c(uh, uh, p->M1, p->N, p->spec_last, p->W_mid, p->rpy, -1, 1.0 / p->M1, s));
+    }
+    return SGM_OK;
+}
+
+sgm_status sgm_forward(sgm_plan p, const void* u, void* u_hat, void* stream) {
+    clear_error();
+    SGM_CHECK_ARG(p && u && u_hat, "null argument");
+    SGM_CHECK_ARG(u != u_hat, "u and u_hat must not alias");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double2* uh = static_cast<double2*>(u_hat);
+    sgm_status st = fourier_forward(p, u, uh, s);
+    if (st != SGM_OK) return st;
+    PassTimer t(p, 4, s);
+    SGM_HIP_TRY(launch_cheb_fwd(uh, uh, p->cd, p->geom.ncols, p->W_cheb, p->rpx, kProject, s));
+    return SGM_OK;
+}
+
+sgm_status sgm_scalar_product(sgm_plan p, const void* f, void* f_tilde, void* stream) {
+    clear_error();
+    SGM_CHECK_ARG(p && f && f_tilde, "null argument");
+    SGM_CHECK_ARG(f != f_tilde, "f and f_tilde must not alias");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double2* ft = static_cast<double2*>(f_tilde);
+    sgm_status st = fourier_forward(p, f, ft, s);
+    if (st != SGM_OK) return st;
+    PassTimer t(p, 5, s);
+    SGM_HIP_TRY(launch_cheb_fwd(ft, ft, p->cd, p->geom.ncols, p->W_cheb, p->rpx, kScalarProduct, s));
+    return SGM_OK;
+}
+
+sgm_status sgm_backward(sgm_plan p, const void* u_hat, void* u, void* stream) {
+    clear_error();
+    SGM_CHECK_ARG(p && u && u_hat, "null argument");
+    SGM_CHECK_ARG(u != u_hat, "u and u_hat must not alias");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double2* w = static_cast<double2*>(p->work);
+    {
+        PassTimer t(p, 6, s);
+        SGM_HIP_TRY(launch_cheb_bwd(static_cast<const double2*>(u_hat), w, p->cd, p->geom.ncols, p->W_cheb, p->rpx,
+                                    s));
+    }
+    if (p->ndim == 3) {
+        PassTimer t(p, 3, s);
+        SGM_HIP_TRY(launch_strided_c2c(w, w, p->M1, p->N, p->spec_last, p->W_mid, p->rpy, 1, 1.0, s));
+    }
+    int Llast = p->ndim == 3 ? p->M2 : p->M1;
+    int nlines = p->ndim == 3 ? p->N * p->M1 : p->N;
+    PassTimer t(p, 1, s);
+    if (p->r2c)
+        SGM_HIP_TRY(launch_lines_c2r(w, static_cast<double*>(u), Llast, nlines, p->G_last, p->rpz, s));
+    else
+        SGM_HIP_TRY(launch_lines_c2c(w, static_cast<double2*>(u), Llast, nlines, p->G_last, p->rpz, 1, 1.0, s));
+    return SGM_OK;
+}
+
+sgm_status sgm_helmholtz_solve(sgm_plan p, double alpha, const void* f_tilde, void* u_hat, void* stream) {
+    clear_error();
+    SGM_CHECK_ARG(p && f_tilde && u_hat, "null argument");
+    SGM_CHECK_ARG(p->d.basis == SGM_SHEN_DIRICHLET, "Helmholtz solve needs the Shen-Dirichlet basis");
+    SGM_CHECK_ARG(alpha >= 0.0, "alpha must be >= 0 (got %g)", alpha);
+    PassTimer t(p, 7, static_cast<hipStream_t>(stream));
+    SGM_HIP_TRY(launch_solve(static_cast<const double2*>(f_tilde), static_cast<double2*>(u_hat), p->cd, p->geom,
+                             p->W_solve, SGM_SHEN_DIRICHLET, alpha, static_cast<hipStream_t>(stream)));
+    return SGM_OK;
+}
+
+sgm_status sgm_biharmonic_solve(sgm_plan p, const void* f_tilde, void* u_hat, void* stream) {
+    clear_error();
+    SGM_CHECK_ARG(p && f_tilde && u_hat, "null argument");
+    SGM_CHECK_ARG(p->d.basis == SGM_SHEN_BIHARMONIC, "biharmonic solve needs the Shen-biharmonic basis");
+    PassTimer t(p, 7, static_cast<hipStream_t>(stream));
+    SGM_HIP_TRY(launch_solve(static_cast<const double2*>(f_tilde), static_cast<double2*>(u_hat), p->cd, p->geom,
+                             p->W_solve, SGM_SHEN_BIHARMONIC, 0.0, static_cast<hipStream_t>(stream)));
+    return SGM_OK;
+}
+
+}  // extern "C"

@@ -11,7 +11,7 @@ import numpy as np
 __all__ = [
     "cheb_points", "periodic_points", "smooth_profile", "random_smooth_field",
     "poisson2d_manufactured", "biharmonic3d_manufactured", "gl_noise",
-    "gl_ragged_sizes", "gl_gaussian_ic",
+    "gl_ragged_sizes", "gl_gaussian_ic", "random_spectral",
 ]
 
 
@@ -158,3 +158,23 @@ def gl_gaussian_ic(N, L=100.0, kind=1):
     if kind == 0:
         return (1j * X + Y) * g
     return ((X + Y) * g).astype(np.complex128)
+
+
+def random_spectral(shape, seed, decay=3.0, nrows=None):
+    """Random complex spectral array: N(0,1) (re, im) * (1 + |k|)^-decay with
+    |k| = sqrt(l^2 + m^2 + n^2) from the array indices (FFT-order indices are
+    folded to |wavenumber|).  Rows l >= nrows are zero."""
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    k2 = np.zeros(shape)
+    for ax, M in enumerate(shape):
+        q = np.arange(M)
+        if ax > 0:
+            q = np.minimum(q, M - q)
+        sh = [1] * len(shape)
+        sh[ax] = M
+        k2 = k2 + (q.astype(float) ** 2).reshape(sh)
+    a = a * (1.0 + np.sqrt(k2)) ** (-decay)
+    if nrows is not None:
+        a[nrows:] = 0
+    return a
