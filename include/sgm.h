@@ -60,7 +60,10 @@ typedef struct {
     int M2;        /* points along z (ndim = 3), >= 1; ignored for ndim = 2            */
     int kind_last; /* SGM_R2C | SGM_C2C for the last axis (y if ndim = 2, z if 3)      */
     double Ly, Lz; /* periods of y and z; 0 means 2 pi.  Used only by the solves.      */
-    int autotune;  /* 0: default launch shapes; 1: time the candidates once at creation */
+    int autotune;  /* 0: default kernels (register-resident FFTs for lengths 2^a 3^b with a
+                      compiled instance, generic LDS kernels otherwise); 1: time the
+                      candidates once at creation and keep the fastest; 2: generic
+                      LDS kernels only */
 } sgm_plan_desc;
 
 /* Create a plan for the tensor-product space V(x) x V^p(y) [x V^p(z)] (Sec. 4,

@@ -1,0 +1,30 @@
+// Register-FFT pass kernels for the compile-time lengths (not ABI).
+#pragma once
+#include "kernels.h"
+
+namespace sgm {
+
+enum RegChebMode { kProjCheb = 2, kProjDirichlet = 3, kProjBiharmonic = 4 };
+
+struct RegKernels {
+    int L = 0;
+    int W = 0;       // lines per block
+    int threads = 0; // block size (W * threads per line)
+    size_t lds = 0; // dynamic LDS bytes of every kernel below
+    void (*r2c)(const double*, double2*, int, const double2*, double) = nullptr;
+    void (*c2r)(const double2*, double*, int, const double2*) = nullptr;
+    void (*c2c_f)(const double2*, double2*, int, const double2*, double) = nullptr;
+    void (*c2c_b)(const double2*, double2*, int, const double2*, double) = nullptr;
+    void (*str_f)(const double2*, double2*, int, int, const double2*, double) = nullptr;
+    void (*str_b)(const double2*, double2*, int, int, const double2*, double) = nullptr;
+    void (*cf_sp)(const double2*, double2*, ChebDev, int, const double2*) = nullptr;
+    void (*cf_cheb)(const double2*, double2*, ChebDev, int, const double2*) = nullptr;
+    void (*cf_dir)(const double2*, double2*, ChebDev, int, const double2*) = nullptr;
+    void (*cf_bih)(const double2*, double2*, ChebDev, int, const double2*) = nullptr;
+    void (*cb)(const double2*, double2*, ChebDev, int, const double2*) = nullptr;
+};
+
+// Fill `k` with the kernels for length L; false if L has no compiled instance.
+bool reg_kernels_for(int L, RegKernels& k);
+
+}  // namespace sgm

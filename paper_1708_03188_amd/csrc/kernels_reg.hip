@@ -1,0 +1,434 @@
+// Transform passes built on the register-resident FFT (compile-time lengths).
+//
+// Every block has 256 threads = W lines x NT threads per line.  For
+// strided passes (middle periodic axis, Chebyshev axis) lane -> (column c =
+// lane % W, thread t = lane / W), so one warp-wide access covers W adjacent
+// columns of a row; for contiguous lines lane -> (t = lane % NT, line =
+// lane / NT), so it covers NT adjacent points of a line.
+#include "fft_reg.h"
+#include "kernels.h"
+#include "kernels_reg.h"
+
+namespace sgm {
+
+constexpr int kThreads = 256;
+constexpr int kNTMAX = 32;
+constexpr int kLdsBudget = 131072;
+
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
+template <int L>
+struct Geo {
+    static constexpr Sched sd = make_sched(L, kNTMAX);
+    static constexpr int NT = sd.NT;
+    static constexpr int E = sd.E;
+    // lines per block: fill 256 threads unless the two exchange buffers
+    // (2 * W * L * 16 bytes) would exceed the LDS budget
+    static constexpr int W = cmin(kThreads / NT, kLdsBudget / (32 * L)) > 0 ? cmin(kThreads / NT, kLdsBudget / (32 * L)) : 1;
+    static constexpr int THREADS = W * NT;
+};
+
+// ---------------------------------------------------------------------------
+// contiguous lines
+// ---------------------------------------------------------------------------
+template <int L>
+__global__ void __launch_bounds__(kThreads) kr_lines_r2c(const double* __restrict__ in, double2* __restrict__ out,
+                                                         int nlines, const double2* __restrict__ tw, double scale) {
+    using G = Geo<L>;
+    extern __shared__ double2 lds[];
+    const int t = threadIdx.x % G::NT, g = threadIdx.x / G::NT;
+    double2* b0 = lds + g * L;
+    double2* b1 = lds + (G::W + g) * L;
+    const long l0 = ((long)blockIdx.x * G::W + g) * 2;
+    double2 x[G::E];
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) {
+        const int v = t + G::NT * e;
+        double re = l0 < nlines ? in[l0 * L + v] : 0.0;
+        double im = l0 + 1 < nlines ? in[(l0 + 1) * L + v] : 0.0;
+        x[e] = make_double2(re, im);
+    }
+    reg_fft<L, kNTMAX, -1>(x, b0, b1, 1, t, tw);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) b0[t + G::NT * e] = x[e];
+    __syncthreads();
+    constexpr int Lh = L / 2 + 1;
+    for (int k = t; k < Lh; k += G::NT) {
+        double2 z = b0[k];
+        double2 zr = cconj(b0[k == 0 ? 0 : L - k]);
+        double2 x1 = make_double2(0.5 * scale * (z.x + zr.x), 0.5 * scale * (z.y + zr.y));
+        double2 d = csub(z, zr);
+        double2 x2 = make_double2(0.5 * scale * d.y, -0.5 * scale * d.x);
+        if (l0 < nlines) out[l0 * Lh + k] = x1;
+        if (l0 + 1 < nlines) out[(l0 + 1) * Lh + k] = x2;
+    }
+}
+
+template <int L>
+__global__ void __launch_bounds__(kThreads) kr_lines_c2r(const double2* __restrict__ in, double* __restrict__ out,
+                                                         int nlines, const double2* __restrict__ tw) {
+    using G = Geo<L>;
+    extern __shared__ double2 lds[];
+    const int t = threadIdx.x % G::NT, g = threadIdx.x / G::NT;
+    double2* b0 = lds + g * L;
+    double2* b1 = lds + (G::W + g) * L;
+    const long l0 = ((long)blockIdx.x * G::W + g) * 2;
+    constexpr int Lh = L / 2 + 1;
+    double2 x[G::E];
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) {
+        const int v = t + G::NT * e;
+        const int k = v <= L / 2 ? v : L - v;
+        double2 x1 = l0 < nlines ? in[l0 * Lh + k] : make_double2(0.0, 0.0);
+        double2 x2 = l0 + 1 < nlines ? in[(l0 + 1) * Lh + k] : make_double2(0.0, 0.0);
+        if (v == 0 || 2 * v == L) { x1.y = 0.0; x2.y = 0.0; }
+        if (v > L / 2) { x1.y = -x1.y; x2.y = -x2.y; }
+        x[e] = make_double2(x1.x - x2.y, x1.y + x2.x);
+    }
+    reg_fft<L, kNTMAX, 1>(x, b0, b1, 1, t, tw);
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) {
+        const int v = t + G::NT * e;
+        if (l0 < nlines) out[l0 * L + v] = x[e].x;
+        if (l0 + 1 < nlines) out[(l0 + 1) * L + v] = x[e].y;
+    }
+}
+
+template <int L, int SIGN>
+__global__ void __launch_bounds__(kThreads) kr_lines_c2c(const double2* __restrict__ in, double2* __restrict__ out,
+                                                         int nlines, const double2* __restrict__ tw, double scale) {
+    using G = Geo<L>;
+    extern __shared__ double2 lds[];
+    const int t = threadIdx.x % G::NT, g = threadIdx.x / G::NT;
+    double2* b0 = lds + g * L;
+    double2* b1 = lds + (G::W + g) * L;
+    const long ln = (long)blockIdx.x * G::W + g;
+    double2 x[G::E];
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) x[e] = ln < nlines ? in[ln * L + t + G::NT * e] : make_double2(0.0, 0.0);
+    reg_fft<L, kNTMAX, SIGN>(x, b0, b1, 1, t, tw);
+    if (ln < nlines) {
+#pragma unroll
+        for (int e = 0; e < G::E; ++e) out[ln * L + t + G::NT * e] = cscale(x[e], scale);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// strided lines: data[o][e][c]
+// ---------------------------------------------------------------------------
+template <int L, int SIGN>
+__global__ void __launch_bounds__(kThreads) kr_strided(const double2* in, double2* out, int outer, int inner,
+                                                       const double2* __restrict__ tw, double scale) {
+    using G = Geo<L>;
+    extern __shared__ double2 lds[];
+    const int c = threadIdx.x % G::W, t = threadIdx.x / G::W;
+    const int tiles = (inner + G::W - 1) / G::W;
+    const int o = blockIdx.x / tiles;
+    const int c0 = (blockIdx.x - o * tiles) * G::W;
+    const bool ok = c0 + c < inner;
+    const long base = (long)o * L * inner + c0 + c;
+    double2 x[G::E];
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) x[e] = ok ? in[base + (long)(t + G::NT * e) * inner] : make_double2(0.0, 0.0);
+    reg_fft<L, kNTMAX, SIGN>(x, lds + c, lds + L * G::W + c, G::W, t, tw);
+    if (ok) {
+#pragma unroll
+        for (int e = 0; e < G::E; ++e) out[base + (long)(t + G::NT * e) * inner] = cscale(x[e], scale);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev axis, forward (DCT-II + scalar product / projection)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int makhoul_row(int v, int N) { return v < (N + 1) / 2 ? 2 * v : 2 * (N - 1 - v) + 1; }
+
+// Sequential per-(column, parity) least-squares projection used for the
+// biharmonic basis: boundary-functional projection then Givens + banded R.
+__device__ void project_givens_lane(double2* col, int es, int n, int m, int nrot, const double* rot,
+                                    const double* rt, const double* qt) {
+    double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
+    for (int t = 0; t < m; ++t) {
+        double2 v = col[t * es];
+        double q1 = qt[2 * t], q2 = qt[2 * t + 1];
+        s1.x += q1 * v.x; s1.y += q1 * v.y;
+        s2.x += q2 * v.x; s2.y += q2 * v.y;
+    }
+    auto ld = [&](int t) {
+        if (t >= m) return make_double2(0.0, 0.0);
+        double2 v = col[t * es];
+        double q1 = qt[2 * t], q2 = qt[2 * t + 1];
+        return make_double2(v.x - q1 * s1.x - q2 * s2.x, v.y - q1 * s1.y - q2 * s2.y);
+    };
+    double2 w0 = ld(0), w1 = ld(1);
+    double2 w2 = nrot == 2 ? ld(2) : make_double2(0.0, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double c1 = rot[4 * i], s1r = rot[4 * i + 1];
+        double2 a = w0, b = w1;
+        w0 = make_double2(c1 * a.x + s1r * b.x, c1 * a.y + s1r * b.y);
+        w1 = make_double2(-s1r * a.x + c1 * b.x, -s1r * a.y + c1 * b.y);
+        if (nrot == 2) {
+            double c2 = rot[4 * i + 2], s2r = rot[4 * i + 3];
+            a = w0; b = w2;
+            w0 = make_double2(c2 * a.x + s2r * b.x, c2 * a.y + s2r * b.y);
+            w2 = make_double2(-s2r * a.x + c2 * b.x, -s2r * a.y + c2 * b.y);
+            col[i * es] = w0;
+            w0 = w1; w1 = w2;
+            w2 = ld(i + 3);
+        } else {
+            col[i * es] = w0;
+            w0 = w1;
+            w1 = ld(i + 2);
+        }
+    }
+    double2 x1 = make_double2(0.0, 0.0), x2 = make_double2(0.0, 0.0);
+    for (int i = n - 1; i >= 0; --i) {
+        double r0 = rt[3 * i], r1 = rt[3 * i + 1], r2 = rt[3 * i + 2];
+        double2 z = col[i * es];
+        double2 x = make_double2((z.x - r1 * x1.x - r2 * x2.x) * r0, (z.y - r1 * x1.y - r2 * x2.y) * r0);
+        col[i * es] = x;
+        x2 = x1; x1 = x;
+    }
+}
+
+template <int N, int MODE>
+__global__ void __launch_bounds__(kThreads) kr_cheb_fwd(const double2* in, double2* out, ChebDev cd, int ncols,
+                                                        const double2* __restrict__ tw) {
+    using G = Geo<N>;
+    constexpr int W = G::W, NT = G::NT, E = G::E;
+    extern __shared__ double2 lds[];
+    double2* B0 = lds;
+    double2* B1 = lds + N * W;
+    const int c = threadIdx.x % W, t = threadIdx.x / W;
+    const int c0 = blockIdx.x * W;
+    const bool ok = c0 + c < ncols;
+    double2 x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int v = t + NT * e;
+        x[e] = ok ? in[(long)makhoul_row(v, N) * ncols + c0 + c] : make_double2(0.0, 0.0);
+    }
+    reg_fft<N, kNTMAX, -1>(x, B0 + c, B1 + c, W, t, tw);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) B0[(t + NT * e) * W + c] = x[e];
+    __syncthreads();
+    // DCT-II post-processing: C_k for own k from V_k and V_{N-k}
+    const double2* th = cd.theta;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = t + NT * e;
+        const int kn = k == 0 ? 0 : N - k;
+        double2 V = x[e];
+        double2 cv = cconj(B0[kn * W + c]);
+        double2 a = make_double2(0.5 * (V.x + cv.x), 0.5 * (V.y + cv.y));
+        double2 d = csub(V, cv);
+        double2 b = make_double2(0.5 * d.y, -0.5 * d.x);
+        double2 tk = th[k];
+        x[e] = make_double2(tk.x * a.x - tk.y * a.y, tk.x * b.x - tk.y * b.y);  // C_k
+    }
+    const int nb = cd.nb;
+    if constexpr (MODE == kScalarProduct) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) B1[(t + NT * e) * W + c] = x[e];
+        __syncthreads();
+        const double s = M_PI / N;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int l = t + NT * e;
+            double2 v = make_double2(0.0, 0.0);
+            if (l < nb) {
+                v = x[e];
+                if (l + 2 < N) { double bb = cd.beta[l]; double2 u = B1[(l + 2) * W + c]; v.x += bb * u.x; v.y += bb * u.y; }
+                if (l + 4 < N) { double gg = cd.gamma[l]; double2 u = B1[(l + 4) * W + c]; v.x += gg * u.x; v.y += gg * u.y; }
+                v = cscale(v, s);
+            }
+            if (ok) out[(long)l * ncols + c0 + c] = v;
+        }
+    } else if constexpr (MODE == kProjCheb) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + NT * e;
+            if (ok) out[(long)k * ncols + c0 + c] = cscale(x[e], cd.fscale[k]);
+        }
+    } else if constexpr (MODE == kProjDirichlet) {
+        // c_k = fscale_k C_k; per parity p: lambda_p = (sum_k c_k) / (sum_k 1/c_k-weights);
+        // c*_k = c_k - lambda_p / ck;  u_l = sum_{k <= l, k = l mod 2} c*_k  (prefix sum).
+        // NT is even, so all own positions of thread t have parity t & 1.
+        double2 ps = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + NT * e;
+            x[e] = cscale(x[e], cd.fscale[k]);
+            ps.x += x[e].x; ps.y += x[e].y;
+        }
+        // column/parity partial sums -> B1 scratch [t][c]
+        B1[t * W + c] = ps;
+        __syncthreads();
+        const int p = t & 1;
+        double2 tot = make_double2(0.0, 0.0);
+        for (int tt = p; tt < NT; tt += 2) { double2 v = B1[tt * W + c]; tot.x += v.x; tot.y += v.y; }
+        // sum over parity-p modes of 1/c_k: (#modes) - (1/2 if p == 0)
+        const int mp = (N - p + 1) / 2;
+        const double wsum = (double)mp - (p == 0 ? 0.5 : 0.0);
+        const double2 lam = make_double2(tot.x / wsum, tot.y / wsum);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + NT * e;
+            const double ic = k == 0 ? 0.5 : 1.0;
+            x[e].x -= lam.x * ic;
+            x[e].y -= lam.y * ic;
+        }
+        // prefix sums along each parity chain (chain index i <-> position p + 2i), in
+        // segments: the NT/2 threads of parity p own consecutive segments of length seg.
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) B0[(t + NT * e) * W + c] = x[e];
+        __syncthreads();
+        const int t2 = t >> 1;
+        const int seg = (mp + NT / 2 - 1) / (NT / 2);
+        const int i0 = t2 * seg, i1 = i0 + seg < mp ? i0 + seg : mp;
+        double2 ssum = make_double2(0.0, 0.0);
+#pragma unroll 1
+        for (int i = i0; i < i1; ++i) { double2 v = B0[(p + 2 * i) * W + c]; ssum.x += v.x; ssum.y += v.y; }
+        B1[(NT + t) * W + c] = ssum;   // B1 rows NT.. hold the segment sums
+        __syncthreads();
+        double2 run = make_double2(0.0, 0.0);
+#pragma unroll 1
+        for (int u = 0; u < t2; ++u) { double2 v = B1[(NT + 2 * u + p) * W + c]; run.x += v.x; run.y += v.y; }
+#pragma unroll 1
+        for (int i = i0; i < i1; ++i) {
+            double2 v = B0[(p + 2 * i) * W + c];
+            run.x += v.x; run.y += v.y;
+            B0[(p + 2 * i) * W + c] = run;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int l = t + NT * e;
+            if (ok) out[(long)l * ncols + c0 + c] = l < nb ? B0[l * W + c] : make_double2(0.0, 0.0);
+        }
+    } else {  // kProjBiharmonic: sequential Givens lanes
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + NT * e;
+            B1[k * W + c] = cscale(x[e], cd.bscale[k]);
+        }
+        __syncthreads();
+        const int lane = threadIdx.x;
+        if (lane < 2 * W) {
+            const int p = lane / W, cc = lane - p * W;
+            project_givens_lane(B1 + p * W + cc, 2 * W, cd.npar[p], cd.mpar[p], 2, cd.rot[p], cd.rtab[p], cd.qtab[p]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int l = t + NT * e;
+            if (ok) out[(long)l * ncols + c0 + c] = l < nb ? B1[l * W + c] : make_double2(0.0, 0.0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev axis, backward (recombination + DCT-III)
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(kThreads) kr_cheb_bwd(const double2* in, double2* out, ChebDev cd, int ncols,
+                                                        const double2* __restrict__ tw) {
+    using G = Geo<N>;
+    constexpr int W = G::W, NT = G::NT, E = G::E;
+    extern __shared__ double2 lds[];
+    double2* B0 = lds;
+    double2* B1 = lds + N * W;
+    const int c = threadIdx.x % W, t = threadIdx.x / W;
+    const int c0 = blockIdx.x * W;
+    const bool ok = c0 + c < ncols;
+    const int nb = cd.nb;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int l = t + NT * e;
+        B0[l * W + c] = (ok && l < nb) ? in[(long)l * ncols + c0 + c] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    auto chat = [&](int k) {
+        double2 v = B0[k * W + c];
+        if (k >= 2) { double bb = cd.beta[k - 2]; double2 u = B0[(k - 2) * W + c]; v.x += bb * u.x; v.y += bb * u.y; }
+        if (k >= 4) { double gg = cd.gamma[k - 4]; double2 u = B0[(k - 4) * W + c]; v.x += gg * u.x; v.y += gg * u.y; }
+        return v;
+    };
+#pragma unroll 1
+    for (int e = 0; e < E; ++e) {
+        const int k = t + NT * e;
+        double2 w;
+        if (k == 0) {
+            double2 v = chat(0);
+            w = make_double2(2.0 * v.x, 2.0 * v.y);
+        } else {
+            double2 ck = chat(k), cn = chat(N - k);
+            double2 d = make_double2(ck.x + cn.y, ck.y - cn.x);
+            w = cmul(cconj(cd.theta[k]), d);
+        }
+        B1[k * W + c] = w;
+    }
+    __syncthreads();
+    double2 x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[e] = B1[(t + NT * e) * W + c];
+    __syncthreads();
+    reg_fft<N, kNTMAX, 1>(x, B0 + c, B1 + c, W, t, tw);
+    if (ok) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int v = t + NT * e;
+            out[(long)makhoul_row(v, N) * ncols + c0 + c] = cscale(x[e], 0.5);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+template <int L>
+static size_t lines_lds() { return 2 * sizeof(double2) * (size_t)Geo<L>::W * L; }
+
+template <int L>
+static void fill(RegKernels& k) {
+    k.L = L;
+    k.W = Geo<L>::W;
+    k.threads = Geo<L>::THREADS;
+    k.lds = lines_lds<L>();
+    k.r2c = kr_lines_r2c<L>;
+    k.c2r = kr_lines_c2r<L>;
+    k.c2c_f = kr_lines_c2c<L, -1>;
+    k.c2c_b = kr_lines_c2c<L, 1>;
+    k.str_f = kr_strided<L, -1>;
+    k.str_b = kr_strided<L, 1>;
+    k.cf_sp = kr_cheb_fwd<L, kScalarProduct>;
+    k.cf_cheb = kr_cheb_fwd<L, kProjCheb>;
+    k.cf_dir = kr_cheb_fwd<L, kProjDirichlet>;
+    k.cf_bih = kr_cheb_fwd<L, kProjBiharmonic>;
+    k.cb = kr_cheb_bwd<L>;
+}
+
+bool reg_kernels_for(int L, RegKernels& k) {
+    switch (L) {
+        case 16: fill<16>(k); return true;
+        case 32: fill<32>(k); return true;
+        case 64: fill<64>(k); return true;
+        case 128: fill<128>(k); return true;
+        case 256: fill<256>(k); return true;
+        case 512: fill<512>(k); return true;
+        case 1024: fill<1024>(k); return true;
+        case 48: fill<48>(k); return true;
+        case 96: fill<96>(k); return true;
+        case 192: fill<192>(k); return true;
+        case 384: fill<384>(k); return true;
+        case 768: fill<768>(k); return true;
+        case 144: fill<144>(k); return true;
+        case 288: fill<288>(k); return true;
+        case 576: fill<576>(k); return true;
+        default: return false;
+    }
+}
+
+}  // namespace sgm

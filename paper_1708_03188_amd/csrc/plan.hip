@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "kernels_reg.h"
 #include "tables.h"
 
 namespace sgm {
@@ -60,6 +61,9 @@ struct sgm_plan_s {
     ChebDev cd;
     ColGeom geom;
     int G_last, W_mid, W_cheb, W_solve;
+    // register-FFT kernels for axis lengths with a compiled instance
+    bool hx = false, hy = false, hz = false;
+    RegKernels rkx, rky, rkz;
     // per-pass timing
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -102,6 +106,13 @@ static sgm_status make_radix(int L, RadixPlan& rp) {
         return SGM_ERR_UNSUPPORTED_SIZE;
     }
     return SGM_OK;
+}
+
+template <typename F, typename... A>
+static hipError_t launch_k(F f, long blocks, int threads, size_t lds, hipStream_t s, A... args) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(threads), lds, s, args...);
+    return hipGetLastError();
 }
 
 static int pick_tile(int L, int want, size_t (*bytes)(int, int), int lds_max) {
@@ -235,6 +246,15 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
         hipFree(p->work); hipFree(p->blob); delete p;
         return SGM_ERR_UNSUPPORTED_SIZE;
     }
+    if (d.autotune != 2) {
+        p->hx = reg_kernels_for(d.N, p->rkx);
+        p->hy = d.ndim == 3 && reg_kernels_for(d.M1, p->rky);
+        p->hz = reg_kernels_for(Llast, p->rkz);
+        // the contiguous-line kernels need an even line length for the real pairs
+        if (p->hx && p->rkx.lds > (size_t)lds) p->hx = false;
+        if (p->hy && p->rky.lds > (size_t)lds) p->hy = false;
+        if (p->hz && p->rkz.lds > (size_t)lds) p->hz = false;
+    }
     *out = p;
     return SGM_OK;
 }
@@ -288,18 +308,43 @@ static sgm_status fourier_forward(sgm_plan p, const void* u, double2* uh, hipStr
     int nlines = p->ndim == 3 ? p->N * p->M1 : p->N;
     {
         PassTimer t(p, 0, s);
-        if (p->r2c)
-            SGM_HIP_TRY(launch_lines_r2c(static_cast<const double*>(u), uh, Llast, nlines, p->G_last, p->rpz,
-                                         1.0 / Llast, s));
-        else
-            SGM_HIP_TRY(launch_lines_c2c(static_cast<const double2*>(u), uh, Llast, nlines, p->G_last, p->rpz, -1,
-                                         1.0 / Llast, s));
+        const RegKernels& k = p->rkz;
+        if (p->r2c) {
+            if (p->hz)
+                SGM_HIP_TRY(launch_k(k.r2c, (nlines + 2 * k.W - 1) / (2 * k.W), k.threads, k.lds, s,
+                                     static_cast<const double*>(u), uh, nlines, p->rpz.tw, 1.0 / Llast));
+            else
+                SGM_HIP_TRY(launch_lines_r2c(static_cast<const double*>(u), uh, Llast, nlines, p->G_last, p->rpz,
+                                             1.0 / Llast, s));
+        } else {
+            if (p->hz)
+                SGM_HIP_TRY(launch_k(k.c2c_f, (nlines + k.W - 1) / k.W, k.threads, k.lds, s,
+                                     static_cast<const double2*>(u), uh, nlines, p->rpz.tw, 1.0 / Llast));
+            else
+                SGM_HIP_TRY(launch_lines_c2c(static_cast<const double2*>(u), uh, Llast, nlines, p->G_last, p->rpz,
+                                             -1, 1.0 / Llast, s));
+        }
     }
     if (p->ndim == 3) {
         PassTimer t(p, 2, s);
-        SGM_HIP_TRY(launch_strided_c2c(uh, uh, p->M1, p->N, p->spec_last, p->W_mid, p->rpy, -1, 1.0 / p->M1, s));
+        const RegKernels& k = p->rky;
+        if (p->hy)
+            SGM_HIP_TRY(launch_k(k.str_f, (long)p->N * ((p->spec_last + k.W - 1) / k.W), k.threads, k.lds, s,
+                                 (const double2*)uh, uh, p->N, p->spec_last, p->rpy.tw, 1.0 / p->M1));
+        else
+            SGM_HIP_TRY(launch_strided_c2c(uh, uh, p->M1, p->N, p->spec_last, p->W_mid, p->rpy, -1, 1.0 / p->M1, s));
     }
     return SGM_OK;
+}
+
+static hipError_t cheb_forward_pass(sgm_plan p, double2* data, int mode, hipStream_t s) {
+    if (!p->hx) return launch_cheb_fwd(data, data, p->cd, p->geom.ncols, p->W_cheb, p->rpx, mode, s);
+    const RegKernels& k = p->rkx;
+    auto f = k.cf_sp;
+    if (mode == kProject)
+        f = p->cd.basis == SGM_SHEN_DIRICHLET ? k.cf_dir : p->cd.basis == SGM_SHEN_BIHARMONIC ? k.cf_bih : k.cf_cheb;
+    return launch_k(f, (p->geom.ncols + k.W - 1) / k.W, k.threads, k.lds, s, (const double2*)data, data, p->cd,
+                    p->geom.ncols, p->rpx.tw);
 }
 
 sgm_status sgm_forward(sgm_plan p, const void* u, void* u_hat, void* stream) {
@@ -311,7 +356,7 @@ sgm_status sgm_forward(sgm_plan p, const void* u, void* u_hat, void* stream) {
     sgm_status st = fourier_forward(p, u, uh, s);
     if (st != SGM_OK) return st;
     PassTimer t(p, 4, s);
-    SGM_HIP_TRY(launch_cheb_fwd(uh, uh, p->cd, p->geom.ncols, p->W_cheb, p->rpx, kProject, s));
+    SGM_HIP_TRY(cheb_forward_pass(p, uh, kProject, s));
     return SGM_OK;
 }
 
@@ -324,7 +369,7 @@ sgm_status sgm_scalar_product(sgm_plan p, const void* f, void* f_tilde, void* st
     sgm_status st = fourier_forward(p, f, ft, s);
     if (st != SGM_OK) return st;
     PassTimer t(p, 5, s);
-    SGM_HIP_TRY(launch_cheb_fwd(ft, ft, p->cd, p->geom.ncols, p->W_cheb, p->rpx, kScalarProduct, s));
+    SGM_HIP_TRY(cheb_forward_pass(p, ft, kScalarProduct, s));
     return SGM_OK;
 }
 
@@ -336,20 +381,39 @@ sgm_status sgm_backward(sgm_plan p, const void* u_hat, void* u, void* stream) {
     double2* w = static_cast<double2*>(p->work);
     {
         PassTimer t(p, 6, s);
-        SGM_HIP_TRY(launch_cheb_bwd(static_cast<const double2*>(u_hat), w, p->cd, p->geom.ncols, p->W_cheb, p->rpx,
-                                    s));
+        if (p->hx)
+            SGM_HIP_TRY(launch_k(p->rkx.cb, (p->geom.ncols + p->rkx.W - 1) / p->rkx.W, p->rkx.threads, p->rkx.lds, s,
+                                 static_cast<const double2*>(u_hat), w, p->cd, p->geom.ncols, p->rpx.tw));
+        else
+            SGM_HIP_TRY(launch_cheb_bwd(static_cast<const double2*>(u_hat), w, p->cd, p->geom.ncols, p->W_cheb,
+                                        p->rpx, s));
     }
     if (p->ndim == 3) {
         PassTimer t(p, 3, s);
-        SGM_HIP_TRY(launch_strided_c2c(w, w, p->M1, p->N, p->spec_last, p->W_mid, p->rpy, 1, 1.0, s));
+        const RegKernels& k = p->rky;
+        if (p->hy)
+            SGM_HIP_TRY(launch_k(k.str_b, (long)p->N * ((p->spec_last + k.W - 1) / k.W), k.threads, k.lds, s,
+                                 (const double2*)w, w, p->N, p->spec_last, p->rpy.tw, 1.0));
+        else
+            SGM_HIP_TRY(launch_strided_c2c(w, w, p->M1, p->N, p->spec_last, p->W_mid, p->rpy, 1, 1.0, s));
     }
     int Llast = p->ndim == 3 ? p->M2 : p->M1;
     int nlines = p->ndim == 3 ? p->N * p->M1 : p->N;
     PassTimer t(p, 1, s);
-    if (p->r2c)
-        SGM_HIP_TRY(launch_lines_c2r(w, static_cast<double*>(u), Llast, nlines, p->G_last, p->rpz, s));
-    else
-        SGM_HIP_TRY(launch_lines_c2c(w, static_cast<double2*>(u), Llast, nlines, p->G_last, p->rpz, 1, 1.0, s));
+    const RegKernels& k = p->rkz;
+    if (p->r2c) {
+        if (p->hz)
+            SGM_HIP_TRY(launch_k(k.c2r, (nlines + 2 * k.W - 1) / (2 * k.W), k.threads, k.lds, s, (const double2*)w,
+                                 static_cast<double*>(u), nlines, p->rpz.tw));
+        else
+            SGM_HIP_TRY(launch_lines_c2r(w, static_cast<double*>(u), Llast, nlines, p->G_last, p->rpz, s));
+    } else {
+        if (p->hz)
+            SGM_HIP_TRY(launch_k(k.c2c_b, (nlines + k.W - 1) / k.W, k.threads, k.lds, s, (const double2*)w,
+                                 static_cast<double2*>(u), nlines, p->rpz.tw, 1.0));
+        else
+            SGM_HIP_TRY(launch_lines_c2c(w, static_cast<double2*>(u), Llast, nlines, p->G_last, p->rpz, 1, 1.0, s));
+    }
     return SGM_OK;
 }
 
