@@ -121,6 +121,52 @@ sgm_status sgm_biharmonic_solve(sgm_plan plan, const void* f_tilde, void* u_hat,
 sgm_status sgm_plan_timing(sgm_plan plan, int enable);
 sgm_status sgm_plan_pass_times(sgm_plan plan, double ms[SGM_NPASS], int64_t count[SGM_NPASS], int reset);
 
+/* ---- Complex Ginzburg-Landau, ragged batch (Sec. 6) ------------------------------
+ * u_t = u + (1 + i b) lap u - (1 + i c)|u|^2 u on the periodic square [-L/2, L/2)^2
+ * with Fourier x Fourier bases (eq. Ginz_var; the paper's case is b = 0, c = 1.5,
+ * L = 100).  A batch holds `count` independent problems of possibly different
+ * sizes N_i; every packed array stores problem i as an N_i x N_i C-ordered
+ * complex array ([x][y], FFT order for spectra) at complex offset offsets[i].
+ * The nonlinear term uses the 3/2 rule: retained modes evaluated on the
+ * floor(3N/2)^2 grid (other padded modes zero), product formed there, forward
+ * transformed with 1/M per axis and truncated (Sec. 6, padded transforms). */
+#define SGM_RK4 1   /* the explicit four-stage Runge-Kutta scheme of Sec. 6            */
+#define SGM_IFRK4 2 /* the same RK4 after the integrating factor exp(-Lhat t), Lhat =
+                       1 - (1 + i b)|k|^2 (Lawson); exact for the linear part          */
+
+typedef struct sgm_gl_s* sgm_gl;
+
+typedef struct {
+    int count;      /* number of problems, >= 1                                          */
+    const int* N;   /* host array[count]: points per side, 2 <= N_i <= 4096              */
+    double L;       /* side of the square (> 0)                                          */
+    double b, c;    /* equation coefficients                                             */
+    double dt;      /* time step of sgm_gl_step                                          */
+    int scheme;     /* SGM_RK4 | SGM_IFRK4                                               */
+    int graph;      /* 1: sgm_gl_step captures one step as a hipGraph (per state pointer
+                       and stream) and replays it; 0: launches the kernels directly      */
+} sgm_gl_desc;
+
+/* Create a batch: uploads the per-problem descriptors, work lists and twiddle
+ * tables and allocates two state-sized stage buffers and one padded workspace
+ * (sum_i N_i floor(3 N_i / 2) complex elements).  Errors: INVALID_ARG,
+ * UNSUPPORTED_SIZE, OOM, HIP. */
+sgm_status sgm_gl_create(const sgm_gl_desc* desc, sgm_gl* out);
+sgm_status sgm_gl_destroy(sgm_gl gl);
+/* offsets[0..count]: packed layout (complex elements); offsets[count] = total. */
+sgm_status sgm_gl_offsets(sgm_gl gl, int64_t* offsets);
+/* u_hat = (1/N^2) sum_x u(x) e^{-i k.x} per problem (Sec. 3.4.1 forward, both axes). */
+sgm_status sgm_gl_forward(sgm_gl gl, const void* u, void* u_hat, void* stream);
+/* u(x) = sum_k u_hat_k e^{i k.x} per problem (unnormalised). */
+sgm_status sgm_gl_backward(sgm_gl gl, const void* u_hat, void* u, void* stream);
+/* rhs = (1 - (1 + i b)|k|^2) u_hat - F_trunc[(1 + i c)|u_p|^2 u_p] with k = (2 pi/L) *
+ * integer wavenumbers (the right-hand side of eq. Ginz_var after dividing by the
+ * diagonal mass (2 pi)^2).  u_hat and rhs must not overlap. */
+sgm_status sgm_gl_rhs(sgm_gl gl, const void* u_hat, void* rhs, void* stream);
+/* Advance every problem by nsteps steps of dt in place (nsteps >= 0).  Calls that
+ * overlap on one batch object race (they share its stage buffers). */
+sgm_status sgm_gl_step(sgm_gl gl, void* u_hat, int nsteps, void* stream);
+
 const char* sgm_status_string(sgm_status s);
 const char* sgm_last_error(void);
 int sgm_version(void);

@@ -22,6 +22,14 @@ class PlanDesc(ctypes.Structure):
     ]
 
 
+class GLDesc(ctypes.Structure):
+    _fields_ = [
+        ("count", ctypes.c_int), ("N", ctypes.POINTER(ctypes.c_int)), ("L", ctypes.c_double), ("b", ctypes.c_double),
+        ("c", ctypes.c_double), ("dt", ctypes.c_double), ("scheme", ctypes.c_int), ("graph", ctypes.c_int),
+    ]
+
+
+SGM_RK4, SGM_IFRK4 = 1, 2
 _lib = None
 
 _vp = ctypes.c_void_p
@@ -38,6 +46,13 @@ _SIGS = {
     "sgm_helmholtz_solve": ([_vp, ctypes.c_double, _vp, _vp, _vp], ctypes.c_int),
     "sgm_biharmonic_solve": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "sgm_plan_timing": ([_vp, ctypes.c_int], ctypes.c_int),
+    "sgm_gl_create": ([ctypes.POINTER(GLDesc), ctypes.POINTER(_vp)], ctypes.c_int),
+    "sgm_gl_destroy": ([_vp], ctypes.c_int),
+    "sgm_gl_offsets": ([_vp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "sgm_gl_forward": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "sgm_gl_backward": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "sgm_gl_rhs": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "sgm_gl_step": ([_vp, _vp, ctypes.c_int, _vp], ctypes.c_int),
     "sgm_plan_pass_times": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), ctypes.c_int],
                             ctypes.c_int),
 }

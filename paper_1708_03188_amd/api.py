@@ -110,3 +110,75 @@ class Plan:
         _need(out, torch.complex128, self.spec_shape, "u_hat")
         check(self._lib.sgm_biharmonic_solve(self._h, _ptr(f_tilde), _ptr(out), _stream()), "sgm_biharmonic_solve")
         return out
+
+
+class GLBatch:
+    """Ragged batch of complex Ginzburg-Landau problems on [-L/2, L/2)^2.
+
+    All arrays are packed complex128 device vectors of length `total`; problem i
+    occupies [offsets[i], offsets[i+1]) as an N_i x N_i C-ordered array."""
+
+    def __init__(self, sizes, L=100.0, b=0.0, c=1.5, dt=0.025, scheme="rk4", graph=True):
+        lib = load()
+        self._lib = lib
+        self.sizes = [int(n) for n in sizes]
+        arr = (ctypes.c_int * len(self.sizes))(*self.sizes)
+        d = _lib.GLDesc(len(self.sizes), arr, float(L), float(b), float(c), float(dt),
+                        _lib.SGM_IFRK4 if scheme == "ifrk4" else _lib.SGM_RK4, int(bool(graph)))
+        h = ctypes.c_void_p()
+        check(lib.sgm_gl_create(ctypes.byref(d), ctypes.byref(h)), "sgm_gl_create")
+        self._h = h
+        offs = (ctypes.c_int64 * (len(self.sizes) + 1))()
+        check(lib.sgm_gl_offsets(h, offs), "sgm_gl_offsets")
+        self.offsets = list(offs)
+        self.total = self.offsets[-1]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sgm_gl_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pack(self, arrays, device="cuda"):
+        """Concatenate N_i x N_i arrays (numpy or torch) into one packed device vector."""
+        parts = [torch.as_tensor(a, dtype=torch.complex128).reshape(-1) for a in arrays]
+        return torch.cat(parts).to(device).contiguous()
+
+    def unpack(self, packed):
+        """Split a packed vector into a list of N_i x N_i tensors (views)."""
+        return [packed[self.offsets[i]:self.offsets[i + 1]].view(n, n) for i, n in enumerate(self.sizes)]
+
+    def _vec(self, t, name):
+        _need(t, torch.complex128, (self.total,), name)
+
+    def forward(self, u, out=None):
+        self._vec(u, "u")
+        out = torch.empty_like(u) if out is None else out
+        self._vec(out, "u_hat")
+        check(self._lib.sgm_gl_forward(self._h, _ptr(u), _ptr(out), _stream()), "sgm_gl_forward")
+        return out
+
+    def backward(self, uh, out=None):
+        self._vec(uh, "u_hat")
+        out = torch.empty_like(uh) if out is None else out
+        self._vec(out, "u")
+        check(self._lib.sgm_gl_backward(self._h, _ptr(uh), _ptr(out), _stream()), "sgm_gl_backward")
+        return out
+
+    def rhs(self, uh, out=None):
+        self._vec(uh, "u_hat")
+        out = torch.empty_like(uh) if out is None else out
+        self._vec(out, "rhs")
+        check(self._lib.sgm_gl_rhs(self._h, _ptr(uh), _ptr(out), _stream()), "sgm_gl_rhs")
+        return out
+
+    def step(self, uh, nsteps=1):
+        """Advance the packed state in place by nsteps time steps."""
+        self._vec(uh, "u_hat")
+        check(self._lib.sgm_gl_step(self._h, _ptr(uh), int(nsteps), _stream()), "sgm_gl_step")
+        return uh

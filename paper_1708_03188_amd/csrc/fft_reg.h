@@ -57,7 +57,7 @@ constexpr int sched_m(const Sched& s, int S) {
 // Stages alternate between two buffers so one barrier per exchange suffices.
 template <int L, int NTMAX, int SIGN, int S>
 __device__ __forceinline__ void reg_stages(double2* x, double2* b0, double2* b1, int ps, int t,
-                                           const double2* __restrict__ tw) {
+                                           const double2* __restrict__ tw, bool act) {
     constexpr Sched sd = make_sched(L, NTMAX);
     if constexpr (S < sd.nst) {
         constexpr int p = sd.rad[S];
@@ -85,15 +85,19 @@ __device__ __forceinline__ void reg_stages(double2* x, double2* b0, double2* b1,
                 for (int r = 0; r < p; ++r) x[q + r * Q] = y[r];
             } else {
                 const int j = (i - k) * p + k;
+                if (act) {
 #pragma unroll
-                for (int r = 0; r < p; ++r) buf[(j + r * m) * ps] = y[r];
+                    for (int r = 0; r < p; ++r) buf[(j + r * m) * ps] = y[r];
+                }
             }
         }
         if constexpr (!last) {
             __syncthreads();
+            if (act) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) x[e] = buf[(t + NT * e) * ps];
-            reg_stages<L, NTMAX, SIGN, S + 1>(x, b0, b1, ps, t, tw);
+                for (int e = 0; e < E; ++e) x[e] = buf[(t + NT * e) * ps];
+            }
+            reg_stages<L, NTMAX, SIGN, S + 1>(x, b0, b1, ps, t, tw, act);
         }
     }
 }
@@ -101,10 +105,12 @@ __device__ __forceinline__ void reg_stages(double2* x, double2* b0, double2* b1,
 // Transform the line held in x (own positions t + NT*e) in place.
 // b0/b1: this line's two exchange buffers (position stride ps).  Contains
 // barriers: every thread of the block must call it the same number of times.
+// Threads with act == false take part in the barriers only (no LDS traffic);
+// their x is left undefined.
 template <int L, int NTMAX, int SIGN>
 __device__ __forceinline__ void reg_fft(double2* x, double2* b0, double2* b1, int ps, int t,
-                                        const double2* __restrict__ tw) {
-    reg_stages<L, NTMAX, SIGN, 0>(x, b0, b1, ps, t, tw);
+                                        const double2* __restrict__ tw, bool act = true) {
+    reg_stages<L, NTMAX, SIGN, 0>(x, b0, b1, ps, t, tw, act);
 }
 
 }  // namespace sgm

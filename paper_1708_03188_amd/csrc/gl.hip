@@ -1,0 +1,718 @@
+// Complex Ginzburg-Landau: ragged batches of doubly periodic problems.
+//
+// One right-hand-side evaluation is three persistent launches over a work
+// list that covers every problem of the batch:
+//   A  rows    : zero-pad each spectral row (ky) to M = floor(3N/2), inverse FFT
+//   B  columns : zero-pad each column (kx) to M, inverse FFT, form
+//                (1 + i c)|u|^2 u on the fine grid, forward FFT (1/M), truncate
+//   C  rows    : forward FFT (1/M), truncate to the N retained ky, and apply the
+//                Runge-Kutta stage update (or write the right-hand side).
+// Each block takes work items (problem, first line) in a grid-stride loop and
+// dispatches on the problem's padded length: a register-FFT specialisation
+// for the compiled lengths, the generic LDS FFT otherwise.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fft_reg.h"
+#include "kernels.h"
+#include "kernels_reg.h"
+#include "tables.h"
+
+namespace sgm {
+
+constexpr int kGlThreads = 256;
+constexpr int kGlNTMAX = 32;
+constexpr int kGlLds = 131072;
+
+constexpr int gmin(int a, int b) { return a < b ? a : b; }
+
+template <int M>
+struct GGeo {
+    static constexpr Sched sd = make_sched(M, kGlNTMAX);
+    static constexpr int NT = sd.NT;
+    static constexpr int E = sd.E;
+    static constexpr int W = gmin(kGlThreads / NT, kGlLds / (32 * M)) > 0 ? gmin(kGlThreads / NT, kGlLds / (32 * M)) : 1;
+    static constexpr int THREADS = W * NT;
+};
+
+struct GLProb {
+    int N, M;
+    int kind;       // index into the compiled padded lengths, -1 = generic
+    int wrows;      // lines per block, rows passes
+    int wcols;      // lines per block, column pass
+    long off_s;     // complex offset of the N x N arrays
+    long off_w;     // complex offset of the N x M workspace
+    long off_e;     // complex offset of the 1D integrating-factor table
+    RadixPlan rp;   // FFT of length M (tw valid for both paths)
+};
+
+struct GLItem {
+    int prob;
+    int line0;
+};
+
+enum GLMode { kGlRhs = 0, kGlRk4 = 1, kGlIfRk4 = 2 };
+
+struct GLStage {
+    const double2* vin;  // stage input (state for stage 0)
+    double2* state;
+    double2* v;
+    double2* acc;
+    double2* rhs;        // kGlRhs output
+    const double2* etab; // exp(-(1 + i b) k^2 dt / 2) per problem and 1D wavenumber
+    double ks;           // 2 pi / L
+    double b, c, dt;
+    double edt;          // exp(dt / 2)
+    int mode, stage;
+};
+
+__device__ __forceinline__ int gwn(int q, int M) { return q < (M + 1) / 2 ? q : q - M; }
+__device__ __forceinline__ bool kept(int l, int N) { return l >= -(N / 2) && l <= (N - 1) / 2; }
+__device__ __forceinline__ int nidx(int l, int N) { return l >= 0 ? l : l + N; }
+
+// Stage update of one retained mode.  k = N(v) = -F_trunc[(1 + i c)|u_p|^2 u_p].
+__device__ __forceinline__ void stage_update(const GLStage& s, const GLProb& pr, long idx, int kxi, int kyi,
+                                             double2 k) {
+    if (s.mode == kGlRhs || s.mode == kGlRk4) {
+        const double kx = gwn(kxi, pr.N) * s.ks, ky = gwn(kyi, pr.N) * s.ks;
+        const double k2 = kx * kx + ky * ky;
+        const double2 vv = s.vin[idx];
+        // dU = (1 - (1 + i b) k^2) v + k
+        const double2 du = make_double2((1.0 - k2) * vv.x + s.b * k2 * vv.y + k.x,
+                                        (1.0 - k2) * vv.y - s.b * k2 * vv.x + k.y);
+        if (s.mode == kGlRhs) { s.rhs[idx] = du; return; }
+        const double2 u0 = s.state[idx];
+        const double dt = s.dt;
+        if (s.stage == 0) {
+            s.acc[idx] = make_double2(u0.x + dt / 6 * du.x, u0.y + dt / 6 * du.y);
+            s.v[idx] = make_double2(u0.x + dt / 2 * du.x, u0.y + dt / 2 * du.y);
+        } else if (s.stage < 3) {
+            double2 a = s.acc[idx];
+            s.acc[idx] = make_double2(a.x + dt / 3 * du.x, a.y + dt / 3 * du.y);
+            const double bb = s.stage == 1 ? dt / 2 : dt;
+            s.v[idx] = make_double2(u0.x + bb * du.x, u0.y + bb * du.y);
+        } else {
+            double2 a = s.acc[idx];
+            s.state[idx] = make_double2(a.x + dt / 6 * du.x, a.y + dt / 6 * du.y);
+        }
+        return;
+    }
+    // integrating-factor RK4; E = exp(Lhat dt/2) = e^{dt/2} ex(kx) ex(ky)
+    const double2 ex = s.etab[pr.off_e + kxi], ey = s.etab[pr.off_e + kyi];
+    const double2 E = cscale(cmul(ex, ey), s.edt);
+    const double2 u0 = s.state[idx];
+    const double dt = s.dt;
+    if (s.stage == 0) {
+        const double2 E2 = cmul(E, E);
+        const double2 a = make_double2(u0.x + dt / 6 * k.x, u0.y + dt / 6 * k.y);
+        s.acc[idx] = cmul(E2, a);
+        s.v[idx] = cmul(E, make_double2(u0.x + dt / 2 * k.x, u0.y + dt / 2 * k.y));
+    } else if (s.stage == 1) {
+        const double2 Ek = cmul(E, k);
+        double2 a = s.acc[idx];
+        s.acc[idx] = make_double2(a.x + dt / 3 * Ek.x, a.y + dt / 3 * Ek.y);
+        const double2 Eu = cmul(E, u0);
+        s.v[idx] = make_double2(Eu.x + dt / 2 * k.x, Eu.y + dt / 2 * k.y);
+    } else if (s.stage == 2) {
+        const double2 Ek = cmul(E, k);
+        double2 a = s.acc[idx];
+        s.acc[idx] = make_double2(a.x + dt / 3 * Ek.x, a.y + dt / 3 * Ek.y);
+        const double2 E2u = cmul(E, cmul(E, u0));
+        s.v[idx] = make_double2(E2u.x + dt * Ek.x, E2u.y + dt * Ek.y);
+    } else {
+        double2 a = s.acc[idx];
+        s.state[idx] = make_double2(a.x + dt / 6 * k.x, a.y + dt / 6 * k.y);
+    }
+}
+
+// ---------------- register-FFT specialisations -----------------------------
+template <int M>
+__device__ __attribute__((noinline)) void rows_inv_reg(const GLProb& pr, int line0, const double2* src, double2* work, double2* lds) {
+    using G = GGeo<M>;
+    const int t = threadIdx.x % G::NT, g = threadIdx.x / G::NT;
+    const int row = line0 + g;
+    const bool act = threadIdx.x < G::THREADS && row < pr.N;
+    const int N = pr.N;
+    double2 x[G::E];
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) {
+        const int q = t + G::NT * e;
+        const int l = gwn(q, M);
+        x[e] = (act && kept(l, N)) ? src[pr.off_s + (long)row * N + nidx(l, N)] : make_double2(0.0, 0.0);
+    }
+    reg_fft<M, kGlNTMAX, 1>(x, lds + g * M, lds + (G::W + g) * M, 1, t, pr.rp.tw, act);
+    if (act) {
+#pragma unroll
+        for (int e = 0; e < G::E; ++e) work[pr.off_w + (long)row * M + t + G::NT * e] = x[e];
+    }
+}
+
+template <int M>
+__device__ __attribute__((noinline)) void cols_reg(const GLProb& pr, int line0, double2* work, double2* lds, double cnl) {
+    using G = GGeo<M>;
+    const int c = threadIdx.x % G::W, t = threadIdx.x / G::W;
+    const int y = line0 + c;
+    const bool act = threadIdx.x < G::THREADS && y < M;
+    const int N = pr.N;
+    double2 x[G::E];
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) {
+        const int q = t + G::NT * e;
+        const int l = gwn(q, M);
+        x[e] = (act && kept(l, N)) ? work[pr.off_w + (long)nidx(l, N) * M + y] : make_double2(0.0, 0.0);
+    }
+    reg_fft<M, kGlNTMAX, 1>(x, lds + c, lds + M * G::W + c, G::W, t, pr.rp.tw, act);
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) {
+        const double2 u = x[e];
+        const double r2 = u.x * u.x + u.y * u.y;
+        // (1 + i c) r2 u
+        x[e] = make_double2(r2 * (u.x - cnl * u.y), r2 * (u.y + cnl * u.x));
+    }
+    __syncthreads();
+    reg_fft<M, kGlNTMAX, -1>(x, lds + c, lds + M * G::W + c, G::W, t, pr.rp.tw, act);
+    if (act) {
+        const double s = 1.0 / M;
+#pragma unroll
+        for (int e = 0; e < G::E; ++e) {
+            const int q = t + G::NT * e;
+            const int l = gwn(q, M);
+            if (kept(l, N)) work[pr.off_w + (long)nidx(l, N) * M + y] = cscale(x[e], s);
+        }
+    }
+}
+
+template <int M>
+__device__ __attribute__((noinline)) void rows_fwd_reg(const GLProb& pr, int line0, const double2* work, double2* lds, const GLStage& st) {
+    using G = GGeo<M>;
+    const int t = threadIdx.x % G::NT, g = threadIdx.x / G::NT;
+    const int row = line0 + g;
+    const bool act = threadIdx.x < G::THREADS && row < pr.N;
+    const int N = pr.N;
+    double2 x[G::E];
+#pragma unroll
+    for (int e = 0; e < G::E; ++e)
+        x[e] = act ? work[pr.off_w + (long)row * M + t + G::NT * e] : make_double2(0.0, 0.0);
+    reg_fft<M, kGlNTMAX, -1>(x, lds + g * M, lds + (G::W + g) * M, 1, t, pr.rp.tw, act);
+    if (act) {
+        const double s = -1.0 / M;
+#pragma unroll
+        for (int e = 0; e < G::E; ++e) {
+            const int q = t + G::NT * e;
+            const int l = gwn(q, M);
+            if (kept(l, N)) {
+                const int ky = nidx(l, N);
+                stage_update(st, pr, pr.off_s + (long)row * N + ky, row, ky, cscale(x[e], s));
+            }
+        }
+    }
+}
+
+// ---------------- generic (any M) paths ------------------------------------
+__device__ void rows_inv_gen(const GLProb& pr, int line0, const double2* src, double2* work, double2* lds) {
+    const int M = pr.M, N = pr.N, W = pr.wrows;
+    double2* A = lds;
+    double2* B = lds + (long)W * M;
+    for (int f = threadIdx.x; f < W * M; f += blockDim.x) {
+        const int g = f / M, q = f - g * M;
+        const int row = line0 + g, l = gwn(q, M);
+        A[f] = (row < N && kept(l, N)) ? src[pr.off_s + (long)row * N + nidx(l, N)] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    double2* R = lds_fft<1>(A, B, pr.rp, W, 1, M, false);
+    for (int f = threadIdx.x; f < W * M; f += blockDim.x) {
+        const int g = f / M, q = f - g * M;
+        const int row = line0 + g;
+        if (row < N) work[pr.off_w + (long)row * M + q] = R[f];
+    }
+}
+
+__device__ void cols_gen(const GLProb& pr, int line0, double2* work, double2* lds, double cnl) {
+    const int M = pr.M, N = pr.N, W = pr.wcols;
+    double2* A = lds;
+    double2* B = lds + (long)W * M;
+    for (int f = threadIdx.x; f < W * M; f += blockDim.x) {
+        const int q = f / W, c = f - q * W;
+        const int y = line0 + c, l = gwn(q, M);
+        A[f] = (y < M && kept(l, N)) ? work[pr.off_w + (long)nidx(l, N) * M + y] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    double2* R = lds_fft<1>(A, B, pr.rp, W, W, 1, true);
+    for (int f = threadIdx.x; f < W * M; f += blockDim.x) {
+        const double2 u = R[f];
+        const double r2 = u.x * u.x + u.y * u.y;
+        R[f] = make_double2(r2 * (u.x - cnl * u.y), r2 * (u.y + cnl * u.x));
+    }
+    __syncthreads();
+    double2* O = (R == A) ? B : A;
+    double2* R2 = lds_fft<-1>(R, O, pr.rp, W, W, 1, true);
+    const double s = 1.0 / M;
+    for (int f = threadIdx.x; f < W * M; f += blockDim.x) {
+        const int q = f / W, c = f - q * W;
+        const int y = line0 + c, l = gwn(q, M);
+        if (y < M && kept(l, N)) work[pr.off_w + (long)nidx(l, N) * M + y] = cscale(R2[f], s);
+    }
+}
+
+__device__ void rows_fwd_gen(const GLProb& pr, int line0, const double2* work, double2* lds, const GLStage& st) {
+    const int M = pr.M, N = pr.N, W = pr.wrows;
+    double2* A = lds;
+    double2* B = lds + (long)W * M;
+    for (int f = threadIdx.x; f < W * M; f += blockDim.x) {
+        const int g = f / M;
+        const int row = line0 + g;
+        A[f] = row < N ? work[pr.off_w + (long)row * M + (f - g * M)] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    double2* R = lds_fft<-1>(A, B, pr.rp, W, 1, M, false);
+    const double s = -1.0 / M;
+    for (int f = threadIdx.x; f < W * M; f += blockDim.x) {
+        const int g = f / M, q = f - g * M;
+        const int row = line0 + g, l = gwn(q, M);
+        if (row < N && kept(l, N)) {
+            const int ky = nidx(l, N);
+            stage_update(st, pr, pr.off_s + (long)row * N + ky, row, ky, cscale(R[f], s));
+        }
+    }
+}
+
+// ---------------- persistent pass kernels ----------------------------------
+#define SGM_GL_SWITCH(KIND, CALL_REG, CALL_GEN)  \
+    switch (KIND) {                               \
+        case 0: CALL_REG(48); break;              \
+        case 1: CALL_REG(96); break;              \
+        case 2: CALL_REG(192); break;             \
+        case 3: CALL_REG(288); break;             \
+        case 4: CALL_REG(384); break;             \
+        case 5: CALL_REG(576); break;             \
+        case 6: CALL_REG(768); break;             \
+        default: CALL_GEN; break;                 \
+    }
+static const int kGlRegM[7] = {48, 96, 192, 288, 384, 576, 768};
+
+template <int M>
+constexpr int ggeo_w() { return GGeo<M>::W; }
+static int reg_w(int kind) {
+    switch (kind) {
+        case 0: return ggeo_w<48>();
+        case 1: return ggeo_w<96>();
+        case 2: return ggeo_w<192>();
+        case 3: return ggeo_w<288>();
+        case 4: return ggeo_w<384>();
+        case 5: return ggeo_w<576>();
+        case 6: return ggeo_w<768>();
+        default: return 0;
+    }
+}
+
+// GEN = false: problems whose padded length has a register specialisation;
+// GEN = true: every other problem (generic LDS FFT), in its own launch so the
+// register specialisations keep their allocation.
+template <bool GEN>
+__global__ void __launch_bounds__(kGlThreads) k_gl_rows_inv(const GLProb* probs, const GLItem* items, int nitems,
+                                                            const double2* src, double2* work) {
+    extern __shared__ double2 lds[];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const GLItem item = items[it];
+        const GLProb pr = probs[item.prob];
+        if constexpr (GEN) {
+            rows_inv_gen(pr, item.line0, src, work, lds);
+        } else {
+#define R_(MM) rows_inv_reg<MM>(pr, item.line0, src, work, lds)
+            SGM_GL_SWITCH(pr.kind, R_, (void)0)
+#undef R_
+        }
+        __syncthreads();
+    }
+}
+
+template <bool GEN>
+__global__ void __launch_bounds__(kGlThreads) k_gl_cols(const GLProb* probs, const GLItem* items, int nitems,
+                                                        double2* work, double cnl) {
+    extern __shared__ double2 lds[];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const GLItem item = items[it];
+        const GLProb pr = probs[item.prob];
+        if constexpr (GEN) {
+            cols_gen(pr, item.line0, work, lds, cnl);
+        } else {
+#define C_(MM) cols_reg<MM>(pr, item.line0, work, lds, cnl)
+            SGM_GL_SWITCH(pr.kind, C_, (void)0)
+#undef C_
+        }
+        __syncthreads();
+    }
+}
+
+template <bool GEN>
+__global__ void __launch_bounds__(kGlThreads) k_gl_rows_fwd(const GLProb* probs, const GLItem* items, int nitems,
+                                                            const double2* work, GLStage st) {
+    extern __shared__ double2 lds[];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const GLItem item = items[it];
+        const GLProb pr = probs[item.prob];
+        if constexpr (GEN) {
+            rows_fwd_gen(pr, item.line0, work, lds, st);
+        } else {
+#define F_(MM) rows_fwd_reg<MM>(pr, item.line0, work, lds, st)
+            SGM_GL_SWITCH(pr.kind, F_, (void)0)
+#undef F_
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace sgm
+
+using namespace sgm;
+
+struct sgm_gl_s {
+    sgm_gl_desc d;
+    std::vector<int> N, M;
+    std::vector<int64_t> off_s, off_w, off_e;
+    std::vector<GLProb> hprobs;
+    std::vector<RadixPlan> rpN;   // FFT of length N (forward/backward helpers)
+    std::vector<int> hasN;
+    std::vector<RegKernels> rkN;
+    // work lists [0] register-specialised problems, [1] generic ones;
+    // A: rows (passes A and C share it), B: columns
+    int nA[2] = {0, 0}, nB[2] = {0, 0};
+    size_t lds[2] = {0, 0};
+    int gridA[2] = {0, 0}, gridB[2] = {0, 0};
+    void* dev = nullptr;         // probs + items + twiddles + etab
+    GLProb* dprobs = nullptr;
+    GLItem* ditemsA[2] = {nullptr, nullptr};
+    GLItem* ditemsB[2] = {nullptr, nullptr};
+    double2* etab = nullptr;
+    double2* v = nullptr;
+    double2* acc = nullptr;
+    double2* work = nullptr;
+    hipStream_t cap = nullptr;   // private stream for graph capture
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void* graph_state = nullptr;
+};
+
+static int glkind(int M) {
+    for (int i = 0; i < 7; ++i)
+        if (kGlRegM[i] == M) return i;
+    return -1;
+}
+
+extern "C" sgm_status sgm_gl_destroy(sgm_gl g) {
+    clear_error();
+    if (!g) return SGM_OK;
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    if (g->cap) hipStreamDestroy(g->cap);
+    hipFree(g->v);
+    hipFree(g->acc);
+    hipFree(g->work);
+    hipFree(g->dev);
+    delete g;
+    return SGM_OK;
+}
+
+extern "C" sgm_status sgm_gl_create(const sgm_gl_desc* desc, sgm_gl* out) {
+    clear_error();
+    SGM_CHECK_ARG(desc && out && desc->N, "null argument");
+    *out = nullptr;
+    const sgm_gl_desc& d = *desc;
+    SGM_CHECK_ARG(d.count >= 1, "count must be >= 1");
+    SGM_CHECK_ARG(d.L > 0 && std::isfinite(d.L) && std::isfinite(d.dt) && std::isfinite(d.b) && std::isfinite(d.c),
+                  "L must be > 0 and all coefficients finite");
+    SGM_CHECK_ARG(d.scheme == SGM_RK4 || d.scheme == SGM_IFRK4, "unknown scheme %d", d.scheme);
+    for (int i = 0; i < d.count; ++i)
+        if (d.N[i] < 2 || d.N[i] > 4096) {
+            set_error("problem %d: N = %d outside 2..4096", i, d.N[i]);
+            return SGM_ERR_UNSUPPORTED_SIZE;
+        }
+    sgm_gl_s* g = new (std::nothrow) sgm_gl_s();
+    if (!g) return SGM_ERR_OOM;
+    g->d = d;
+    g->d.N = nullptr;
+    const int n = d.count;
+    g->N.assign(d.N, d.N + n);
+    int64_t os = 0, ow = 0, oe = 0;
+    // twiddle tables: one per distinct length (M_i and N_i)
+    std::vector<int> lens;
+    for (int i = 0; i < n; ++i) {
+        int Mi = (3 * g->N[i]) / 2;
+        g->M.push_back(Mi);
+        g->off_s.push_back(os);
+        g->off_w.push_back(ow);
+        g->off_e.push_back(oe);
+        os += (int64_t)g->N[i] * g->N[i];
+        ow += (int64_t)g->N[i] * Mi;
+        oe += g->N[i];
+        lens.push_back(Mi);
+        lens.push_back(g->N[i]);
+    }
+    g->off_s.push_back(os);
+    std::sort(lens.begin(), lens.end());
+    lens.erase(std::unique(lens.begin(), lens.end()), lens.end());
+    // host blob: probs | itemsA | itemsB | etab | twiddles
+    std::vector<GLItem> itA[2], itB[2];
+    std::vector<std::pair<long, int>> costA, costB;  // larger problems first
+    g->hprobs.resize(n);
+    int maxlA = 0, maxlB = 0;
+    for (int i = 0; i < n; ++i) {
+        GLProb& pr = g->hprobs[i];
+        pr.N = g->N[i];
+        pr.M = g->M[i];
+        pr.kind = glkind(pr.M);
+        int W = pr.kind >= 0 ? reg_w(pr.kind) : std::max(1, std::min(16, 4096 / pr.M));
+        pr.wrows = W;
+        pr.wcols = W;
+        pr.off_s = g->off_s[i];
+        pr.off_w = g->off_w[i];
+        pr.off_e = g->off_e[i];
+        pr.rp.L = pr.M;
+        pr.rp.nst = factor_radices(pr.M, pr.rp.radix);
+        size_t lds = 2 * sizeof(double2) * (size_t)W * pr.M;
+        const int gk = pr.kind < 0 ? 1 : 0;
+        g->lds[gk] = std::max(g->lds[gk], lds);
+        (void)maxlA; (void)maxlB;
+    }
+    // work lists, problems in decreasing size so the grid-stride loop balances
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return g->N[a] > g->N[b]; });
+    for (int i : order) {
+        const GLProb& pr = g->hprobs[i];
+        const int gk = pr.kind < 0 ? 1 : 0;
+        for (int r = 0; r < pr.N; r += pr.wrows) itA[gk].push_back({i, r});
+        for (int y = 0; y < pr.M; y += pr.wcols) itB[gk].push_back({i, y});
+    }
+    for (int k = 0; k < 2; ++k) {
+        g->nA[k] = (int)itA[k].size();
+        g->nB[k] = (int)itB[k].size();
+    }
+    // integrating factor table ex(q) = exp(-(1 + i b) k_q^2 dt/2), k_q = 2 pi/L * wavenumber
+    std::vector<double> etab(2 * (size_t)oe);
+    const long double twopi = 6.283185307179586476925286766559L;
+    for (int i = 0; i < n; ++i)
+        for (int q = 0; q < g->N[i]; ++q) {
+            int l = q < (g->N[i] + 1) / 2 ? q : q - g->N[i];
+            long double k = twopi / (long double)d.L * l;
+            long double a = -k * k * (long double)d.dt / 2;
+            long double mag = expl(a);
+            etab[2 * (g->off_e[i] + q)] = (double)(mag * cosl(d.b * a));
+            etab[2 * (g->off_e[i] + q) + 1] = (double)(mag * sinl(d.b * a));
+        }
+    std::vector<char> blob;
+    auto add = [&](const void* p, size_t bytes) {
+        size_t off = (blob.size() + 255) & ~size_t(255);
+        blob.resize(off + bytes);
+        if (bytes) std::memcpy(blob.data() + off, p, bytes);
+        return off;
+    };
+    size_t o_probs = add(g->hprobs.data(), n * sizeof(GLProb));
+    size_t o_A[2], o_B[2];
+    for (int k = 0; k < 2; ++k) {
+        o_A[k] = add(itA[k].data(), itA[k].size() * sizeof(GLItem));
+        o_B[k] = add(itB[k].data(), itB[k].size() * sizeof(GLItem));
+    }
+    size_t o_e = add(etab.data(), etab.size() * sizeof(double));
+    std::vector<size_t> o_tw(lens.size());
+    for (size_t j = 0; j < lens.size(); ++j) {
+        std::vector<double> tw = twiddles(lens[j]);
+        o_tw[j] = add(tw.data(), tw.size() * sizeof(double));
+    }
+    auto twptr = [&](char* base, int L) {
+        size_t j = std::lower_bound(lens.begin(), lens.end(), L) - lens.begin();
+        return reinterpret_cast<const double2*>(base + o_tw[j]);
+    };
+    hipError_t e = hipMalloc(&g->dev, blob.size());
+    if (e != hipSuccess) { set_error("hipMalloc: %s", hipGetErrorString(e)); sgm_gl_destroy(g); return SGM_ERR_OOM; }
+    char* base = static_cast<char*>(g->dev);
+    // patch device twiddle pointers into the descriptors before upload
+    for (int i = 0; i < n; ++i) g->hprobs[i].rp.tw = twptr(base, g->M[i]);
+    std::memcpy(blob.data() + o_probs, g->hprobs.data(), n * sizeof(GLProb));
+    e = hipMemcpy(g->dev, blob.data(), blob.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { set_error("hipMemcpy: %s", hipGetErrorString(e)); sgm_gl_destroy(g); return SGM_ERR_HIP; }
+    g->dprobs = reinterpret_cast<GLProb*>(base + o_probs);
+    for (int k = 0; k < 2; ++k) {
+        g->ditemsA[k] = reinterpret_cast<GLItem*>(base + o_A[k]);
+        g->ditemsB[k] = reinterpret_cast<GLItem*>(base + o_B[k]);
+    }
+    g->etab = reinterpret_cast<double2*>(base + o_e);
+    g->rpN.resize(n);
+    g->hasN.resize(n);
+    g->rkN.resize(n);
+    for (int i = 0; i < n; ++i) {
+        g->rpN[i].L = g->N[i];
+        g->rpN[i].nst = factor_radices(g->N[i], g->rpN[i].radix);
+        g->rpN[i].tw = twptr(base, g->N[i]);
+        g->hasN[i] = reg_kernels_for(g->N[i], g->rkN[i]);
+    }
+    if (hipMalloc(&g->v, os * sizeof(double2)) != hipSuccess || hipMalloc(&g->acc, os * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&g->work, ow * sizeof(double2)) != hipSuccess) {
+        set_error("hipMalloc of the stage buffers failed");
+        sgm_gl_destroy(g);
+        return SGM_ERR_OOM;
+    }
+    int dev = 0, ncu = 256, lmax = 65536;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    hipDeviceGetAttribute(&lmax, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    for (int k = 0; k < 2; ++k) {
+        if (g->lds[k] > (size_t)lmax) {
+            set_error("padded length too large for one work-group's LDS");
+            sgm_gl_destroy(g);
+            return SGM_ERR_UNSUPPORTED_SIZE;
+        }
+        int per_cu = std::max(1, (int)(lmax / std::max<size_t>(g->lds[k], 1)));
+        if (per_cu > 4) per_cu = 4;
+        g->gridA[k] = std::min(g->nA[k], ncu * per_cu);
+        g->gridB[k] = std::min(g->nB[k], ncu * per_cu);
+    }
+    *out = g;
+    return SGM_OK;
+}
+
+extern "C" sgm_status sgm_gl_offsets(sgm_gl g, int64_t* offsets) {
+    clear_error();
+    SGM_CHECK_ARG(g && offsets, "null argument");
+    for (size_t i = 0; i < g->off_s.size(); ++i) offsets[i] = g->off_s[i];
+    return SGM_OK;
+}
+
+// One right-hand-side evaluation: passes A, B, C.
+static sgm_status gl_eval(sgm_gl g, const double2* src, const GLStage& st, hipStream_t s) {
+    for (int k = 0; k < 2; ++k) {
+        if (!g->nA[k]) continue;
+        auto ka = k ? k_gl_rows_inv<true> : k_gl_rows_inv<false>;
+        hipLaunchKernelGGL(ka, dim3(g->gridA[k]), dim3(kGlThreads), g->lds[k], s, (const GLProb*)g->dprobs,
+                           (const GLItem*)g->ditemsA[k], g->nA[k], src, g->work);
+        SGM_HIP_TRY(hipGetLastError());
+    }
+    for (int k = 0; k < 2; ++k) {
+        if (!g->nB[k]) continue;
+        auto kb = k ? k_gl_cols<true> : k_gl_cols<false>;
+        hipLaunchKernelGGL(kb, dim3(g->gridB[k]), dim3(kGlThreads), g->lds[k], s, (const GLProb*)g->dprobs,
+                           (const GLItem*)g->ditemsB[k], g->nB[k], g->work, g->d.c);
+        SGM_HIP_TRY(hipGetLastError());
+    }
+    for (int k = 0; k < 2; ++k) {
+        if (!g->nA[k]) continue;
+        auto kc = k ? k_gl_rows_fwd<true> : k_gl_rows_fwd<false>;
+        hipLaunchKernelGGL(kc, dim3(g->gridA[k]), dim3(kGlThreads), g->lds[k], s, (const GLProb*)g->dprobs,
+                           (const GLItem*)g->ditemsA[k], g->nA[k], (const double2*)g->work, st);
+        SGM_HIP_TRY(hipGetLastError());
+    }
+    return SGM_OK;
+}
+
+static GLStage base_stage(sgm_gl g) {
+    GLStage st{};
+    st.v = g->v;
+    st.acc = g->acc;
+    st.etab = g->etab;
+    st.ks = 6.283185307179586476925286766559 / g->d.L;
+    st.b = g->d.b;
+    st.c = g->d.c;
+    st.dt = g->d.dt;
+    st.edt = std::exp(g->d.dt / 2);
+    return st;
+}
+
+extern "C" sgm_status sgm_gl_rhs(sgm_gl g, const void* u_hat, void* rhs, void* stream) {
+    clear_error();
+    SGM_CHECK_ARG(g && u_hat && rhs, "null argument");
+    SGM_CHECK_ARG(u_hat != rhs, "u_hat and rhs must not alias");
+    GLStage st = base_stage(g);
+    st.mode = kGlRhs;
+    st.vin = static_cast<const double2*>(u_hat);
+    st.rhs = static_cast<double2*>(rhs);
+    return gl_eval(g, st.vin, st, static_cast<hipStream_t>(stream));
+}
+
+static sgm_status gl_enqueue_step(sgm_gl g, double2* state, hipStream_t s) {
+    GLStage st = base_stage(g);
+    st.mode = g->d.scheme == SGM_IFRK4 ? kGlIfRk4 : kGlRk4;
+    st.state = state;
+    for (int k = 0; k < 4; ++k) {
+        st.stage = k;
+        st.vin = k == 0 ? state : g->v;
+        sgm_status r = gl_eval(g, st.vin, st, s);
+        if (r != SGM_OK) return r;
+    }
+    return SGM_OK;
+}
+
+extern "C" sgm_status sgm_gl_step(sgm_gl g, void* u_hat, int nsteps, void* stream) {
+    clear_error();
+    SGM_CHECK_ARG(g && u_hat, "null argument");
+    SGM_CHECK_ARG(nsteps >= 0, "nsteps must be >= 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double2* state = static_cast<double2*>(u_hat);
+    if (!g->d.graph) {
+        for (int i = 0; i < nsteps; ++i) {
+            sgm_status r = gl_enqueue_step(g, state, s);
+            if (r != SGM_OK) return r;
+        }
+        return SGM_OK;
+    }
+    if (!g->exec || g->graph_state != u_hat) {
+        if (g->exec) { hipGraphExecDestroy(g->exec); g->exec = nullptr; }
+        if (g->graph) { hipGraphDestroy(g->graph); g->graph = nullptr; }
+        if (!g->cap) SGM_HIP_TRY(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
+        SGM_HIP_TRY(hipStreamBeginCapture(g->cap, hipStreamCaptureModeRelaxed));
+        sgm_status r = gl_enqueue_step(g, state, g->cap);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(g->cap, &graph);
+        if (r != SGM_OK) { if (graph) hipGraphDestroy(graph); return r; }
+        SGM_HIP_TRY(e);
+        g->graph = graph;
+        SGM_HIP_TRY(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+        g->graph_state = u_hat;
+    }
+    for (int i = 0; i < nsteps; ++i) SGM_HIP_TRY(hipGraphLaunch(g->exec, s));
+    return SGM_OK;
+}
+
+// Physical <-> spectral helpers (not on the time-stepping path): per problem,
+// the contiguous y transform then the strided x transform.
+static sgm_status gl_transform(sgm_gl g, const double2* in, double2* out, int sign, hipStream_t s) {
+    for (size_t i = 0; i < g->N.size(); ++i) {
+        const int N = g->N[i];
+        const double2* src = in + g->off_s[i];
+        double2* dst = out + g->off_s[i];
+        const double sc = sign < 0 ? 1.0 / N : 1.0;
+        if (g->hasN[i]) {
+            const RegKernels& k = g->rkN[i];
+            hipLaunchKernelGGL(sign < 0 ? k.c2c_f : k.c2c_b, dim3((N + k.W - 1) / k.W), dim3(k.threads), k.lds, s, src,
+                               dst, N, g->rpN[i].tw, sc);
+            SGM_HIP_TRY(hipGetLastError());
+            hipLaunchKernelGGL(sign < 0 ? k.str_f : k.str_b, dim3((N + k.W - 1) / k.W), dim3(k.threads), k.lds, s,
+                               (const double2*)dst, dst, 1, N, g->rpN[i].tw, sc);
+            SGM_HIP_TRY(hipGetLastError());
+        } else {
+            int G = std::max(1, std::min(16, 2048 / N));
+            SGM_HIP_TRY(launch_lines_c2c(src, dst, N, N, G, g->rpN[i], sign, sc, s));
+            int W = std::max(1, std::min(16, 2048 / N));
+            SGM_HIP_TRY(launch_strided_c2c(dst, dst, N, 1, N, W, g->rpN[i], sign, sc, s));
+        }
+    }
+    return SGM_OK;
+}
+
+extern "C" sgm_status sgm_gl_forward(sgm_gl g, const void* u, void* u_hat, void* stream) {
+    clear_error();
+    SGM_CHECK_ARG(g && u && u_hat, "null argument");
+    SGM_CHECK_ARG(u != u_hat, "u and u_hat must not alias");
+    return gl_transform(g, static_cast<const double2*>(u), static_cast<double2*>(u_hat), -1,
+                        static_cast<hipStream_t>(stream));
+}
+
+extern "C" sgm_status sgm_gl_backward(sgm_gl g, const void* u_hat, void* u, void* stream) {
+    clear_error();
+    SGM_CHECK_ARG(g && u && u_hat, "null argument");
+    SGM_CHECK_ARG(u != u_hat, "u and u_hat must not alias");
+    return gl_transform(g, static_cast<const double2*>(u_hat), static_cast<double2*>(u), 1,
+                        static_cast<hipStream_t>(stream));
+}

@@ -9,6 +9,7 @@
 
 #include "kernels.h"
 #include "kernels_reg.h"
+#include "solve_chain.h"
 #include "tables.h"
 
 namespace sgm {
@@ -423,8 +424,13 @@ sgm_status sgm_helmholtz_solve(sgm_plan p, double alpha, const void* f_tilde, vo
     SGM_CHECK_ARG(p->d.basis == SGM_SHEN_DIRICHLET, "Helmholtz solve needs the Shen-Dirichlet basis");
     SGM_CHECK_ARG(alpha >= 0.0, "alpha must be >= 0 (got %g)", alpha);
     PassTimer t(p, 7, static_cast<hipStream_t>(stream));
-    SGM_HIP_TRY(launch_solve(static_cast<const double2*>(f_tilde), static_cast<double2*>(u_hat), p->cd, p->geom,
-                             p->W_solve, SGM_SHEN_DIRICHLET, alpha, static_cast<hipStream_t>(stream)));
+    if (p->d.autotune == 2)
+        SGM_HIP_TRY(launch_solve(static_cast<const double2*>(f_tilde), static_cast<double2*>(u_hat), p->cd, p->geom,
+                                 p->W_solve, SGM_SHEN_DIRICHLET, alpha, static_cast<hipStream_t>(stream)));
+    else
+        SGM_HIP_TRY(launch_solve_chain(static_cast<const double2*>(f_tilde), static_cast<double2*>(u_hat),
+                                       static_cast<double*>(p->work), p->cd, p->geom, SGM_SHEN_DIRICHLET, alpha,
+                                       static_cast<hipStream_t>(stream)));
     return SGM_OK;
 }
 
@@ -433,8 +439,13 @@ sgm_status sgm_biharmonic_solve(sgm_plan p, const void* f_tilde, void* u_hat, vo
     SGM_CHECK_ARG(p && f_tilde && u_hat, "null argument");
     SGM_CHECK_ARG(p->d.basis == SGM_SHEN_BIHARMONIC, "biharmonic solve needs the Shen-biharmonic basis");
     PassTimer t(p, 7, static_cast<hipStream_t>(stream));
-    SGM_HIP_TRY(launch_solve(static_cast<const double2*>(f_tilde), static_cast<double2*>(u_hat), p->cd, p->geom,
-                             p->W_solve, SGM_SHEN_BIHARMONIC, 0.0, static_cast<hipStream_t>(stream)));
+    if (p->d.autotune == 2)
+        SGM_HIP_TRY(launch_solve(static_cast<const double2*>(f_tilde), static_cast<double2*>(u_hat), p->cd, p->geom,
+                                 p->W_solve, SGM_SHEN_BIHARMONIC, 0.0, static_cast<hipStream_t>(stream)));
+    else
+        SGM_HIP_TRY(launch_solve_chain(static_cast<const double2*>(f_tilde), static_cast<double2*>(u_hat),
+                                       static_cast<double*>(p->work), p->cd, p->geom, SGM_SHEN_BIHARMONIC, 0.0,
+                                       static_cast<hipStream_t>(stream)));
     return SGM_OK;
 }
 
