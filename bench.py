@@ -101,7 +101,7 @@ def main():
 
     torch.cuda.set_device(0)
     N = M1 = M2 = 256
-    p = Plan("dirichlet", N, M1, M2)
+    p = Plan("dirichlet", N, M1, M2, autotune=True)
     u = torch.from_numpy(synth.random_smooth_field((N, M1, M2), seed=2)).cuda()
     uh = torch.empty(p.spec_shape, dtype=torch.complex128, device="cuda")
     v = torch.empty_like(u)

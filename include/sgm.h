@@ -63,7 +63,8 @@ typedef struct {
     int autotune;  /* 0: default kernels (register-resident FFTs for lengths 2^a 3^b with a
                       compiled instance, generic LDS kernels otherwise); 1: time the
                       candidates once at creation and keep the fastest; 2: generic
-                      LDS kernels only */
+                      LDS kernels only; 16 + v: pin register-kernel variant v
+                      (0..3) wherever it is compiled (diagnostics) */
 } sgm_plan_desc;
 
 /* Create a plan for the tensor-product space V(x) x V^p(y) [x V^p(z)] (Sec. 4,

@@ -33,12 +33,13 @@ def _need(t, dtype, shape, name):
 class Plan:
     """TensorProductSpace V(x) x V^p(y) [x V^p(z)] with x the Chebyshev/Shen axis."""
 
-    def __init__(self, basis, N, M1, M2=None, kind_last="r2c", Ly=0.0, Lz=0.0, autotune=False, generic=False):
+    def __init__(self, basis, N, M1, M2=None, kind_last="r2c", Ly=0.0, Lz=0.0, autotune=False, generic=False,
+                 variant=None):
         lib = load()
         self._lib = lib
         ndim = 2 if M2 is None else 3
         d = PlanDesc(ndim, BASES[basis], int(N), int(M1), int(M2 or 1), KINDS[kind_last], float(Ly), float(Lz),
-                     2 if generic else int(bool(autotune)))
+                     2 if generic else (16 + int(variant)) if variant is not None else int(bool(autotune)))
         h = ctypes.c_void_p()
         check(lib.sgm_plan_create(ctypes.byref(d), ctypes.byref(h)), "sgm_plan_create")
         self._h = h

@@ -55,7 +55,7 @@ constexpr int sched_m(const Sched& s, int S) {
 
 // Exchange buffer addressing for one line: position v lives at base[v * ps].
 // Stages alternate between two buffers so one barrier per exchange suffices.
-template <int L, int NTMAX, int SIGN, int S>
+template <int L, int NTMAX, int SIGN, int S, int NBUF>
 __device__ __forceinline__ void reg_stages(double2* x, double2* b0, double2* b1, int ps, int t,
                                            const double2* __restrict__ tw, bool act) {
     constexpr Sched sd = make_sched(L, NTMAX);
@@ -66,7 +66,7 @@ __device__ __forceinline__ void reg_stages(double2* x, double2* b0, double2* b1,
         constexpr int NT = sd.NT;
         constexpr int Q = E / p;
         constexpr bool last = (S == sd.nst - 1);
-        double2* buf = (S & 1) ? b1 : b0;
+        double2* buf = (NBUF == 2 && (S & 1)) ? b1 : b0;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int i = t + NT * q;
@@ -97,7 +97,9 @@ __device__ __forceinline__ void reg_stages(double2* x, double2* b0, double2* b1,
 #pragma unroll
                 for (int e = 0; e < E; ++e) x[e] = buf[(t + NT * e) * ps];
             }
-            reg_stages<L, NTMAX, SIGN, S + 1>(x, b0, b1, ps, t, tw, act);
+            // one buffer: every thread must have read it before the next stage writes
+            if constexpr (NBUF == 1 && S + 1 < sd.nst - 1) __syncthreads();
+            reg_stages<L, NTMAX, SIGN, S + 1, NBUF>(x, b0, b1, ps, t, tw, act);
         }
     }
 }
@@ -106,11 +108,12 @@ __device__ __forceinline__ void reg_stages(double2* x, double2* b0, double2* b1,
 // b0/b1: this line's two exchange buffers (position stride ps).  Contains
 // barriers: every thread of the block must call it the same number of times.
 // Threads with act == false take part in the barriers only (no LDS traffic);
-// their x is left undefined.
-template <int L, int NTMAX, int SIGN>
+// their x is left undefined.  NBUF = 2 alternates two exchange buffers (one
+// barrier per exchange); NBUF = 1 reuses b0 (two barriers, half the LDS).
+template <int L, int NTMAX, int SIGN, int NBUF = 2>
 __device__ __forceinline__ void reg_fft(double2* x, double2* b0, double2* b1, int ps, int t,
                                         const double2* __restrict__ tw, bool act = true) {
-    reg_stages<L, NTMAX, SIGN, 0>(x, b0, b1, ps, t, tw, act);
+    reg_stages<L, NTMAX, SIGN, 0, NBUF>(x, b0, b1, ps, t, tw, act);
 }
 
 }  // namespace sgm

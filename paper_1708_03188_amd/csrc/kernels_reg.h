@@ -10,7 +10,9 @@ struct RegKernels {
     int L = 0;
     int W = 0;       // lines per block
     int threads = 0; // block size (W * threads per line)
-    size_t lds = 0; // dynamic LDS bytes of every kernel below
+    size_t lds = 0;      // dynamic LDS bytes of the Fourier-line kernels
+    size_t lds_cheb = 0; // dynamic LDS bytes of the Chebyshev-axis kernels (two tiles)
+    int variant = 0;
     void (*r2c)(const double*, double2*, int, const double2*, double) = nullptr;
     void (*c2r)(const double2*, double*, int, const double2*) = nullptr;
     void (*c2c_f)(const double2*, double2*, int, const double2*, double) = nullptr;
@@ -24,7 +26,9 @@ struct RegKernels {
     void (*cb)(const double2*, double2*, ChebDev, int, const double2*) = nullptr;
 };
 
-// Fill `k` with the kernels for length L; false if L has no compiled instance.
-bool reg_kernels_for(int L, RegKernels& k);
+constexpr int kRegVariants = 4;
+// Fill `k` with variant `variant` of the kernels for length L; false if L (or
+// that variant) has no compiled instance.
+bool reg_kernels_for(int L, RegKernels& k, int variant = 0);
 
 }  // namespace sgm

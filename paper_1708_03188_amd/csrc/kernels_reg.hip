@@ -17,28 +17,33 @@ constexpr int kLdsBudget = 131072;
 
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 
-template <int L>
+// Launch geometry of one variant: NTMAX bounds the threads per line (so
+// E = L / NT points per thread), NB is the number of exchange buffers.
+template <int L, int NTMAX_, int NB_>
 struct Geo {
-    static constexpr Sched sd = make_sched(L, kNTMAX);
+    static constexpr int NTMAX = NTMAX_;
+    static constexpr int NB = NB_;
+    static constexpr Sched sd = make_sched(L, NTMAX);
     static constexpr int NT = sd.NT;
     static constexpr int E = sd.E;
-    // lines per block: fill 256 threads unless the two exchange buffers
-    // (2 * W * L * 16 bytes) would exceed the LDS budget
-    static constexpr int W = cmin(kThreads / NT, kLdsBudget / (32 * L)) > 0 ? cmin(kThreads / NT, kLdsBudget / (32 * L)) : 1;
+    // lines per block: fill 256 threads unless the exchange buffers
+    // (NB * W * L * 16 bytes) would exceed the LDS budget
+    static constexpr int W = cmin(kThreads / NT, kLdsBudget / (16 * NB * L)) > 0 ? cmin(kThreads / NT, kLdsBudget / (16 * NB * L)) : 1;
     static constexpr int THREADS = W * NT;
+    // offset of the second exchange buffer (elements)
+    static constexpr int B1OFF = NB == 2 ? W * L : 0;
 };
 
 // ---------------------------------------------------------------------------
 // contiguous lines
 // ---------------------------------------------------------------------------
-template <int L>
+template <int L, class G>
 __global__ void __launch_bounds__(kThreads) kr_lines_r2c(const double* __restrict__ in, double2* __restrict__ out,
                                                          int nlines, const double2* __restrict__ tw, double scale) {
-    using G = Geo<L>;
     extern __shared__ double2 lds[];
     const int t = threadIdx.x % G::NT, g = threadIdx.x / G::NT;
     double2* b0 = lds + g * L;
-    double2* b1 = lds + (G::W + g) * L;
+    double2* b1 = lds + G::B1OFF + g * L;
     const long l0 = ((long)blockIdx.x * G::W + g) * 2;
     double2 x[G::E];
 #pragma unroll
@@ -48,7 +53,7 @@ __global__ void __launch_bounds__(kThreads) kr_lines_r2c(const double* __restric
         double im = l0 + 1 < nlines ? in[(l0 + 1) * L + v] : 0.0;
         x[e] = make_double2(re, im);
     }
-    reg_fft<L, kNTMAX, -1>(x, b0, b1, 1, t, tw);
+    reg_fft<L, G::NTMAX, -1, G::NB>(x, b0, b1, 1, t, tw);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < G::E; ++e) b0[t + G::NT * e] = x[e];
@@ -65,14 +70,13 @@ __global__ void __launch_bounds__(kThreads) kr_lines_r2c(const double* __restric
     }
 }
 
-template <int L>
+template <int L, class G>
 __global__ void __launch_bounds__(kThreads) kr_lines_c2r(const double2* __restrict__ in, double* __restrict__ out,
                                                          int nlines, const double2* __restrict__ tw) {
-    using G = Geo<L>;
     extern __shared__ double2 lds[];
     const int t = threadIdx.x % G::NT, g = threadIdx.x / G::NT;
     double2* b0 = lds + g * L;
-    double2* b1 = lds + (G::W + g) * L;
+    double2* b1 = lds + G::B1OFF + g * L;
     const long l0 = ((long)blockIdx.x * G::W + g) * 2;
     constexpr int Lh = L / 2 + 1;
     double2 x[G::E];
@@ -86,7 +90,7 @@ __global__ void __launch_bounds__(kThreads) kr_lines_c2r(const double2* __restri
         if (v > L / 2) { x1.y = -x1.y; x2.y = -x2.y; }
         x[e] = make_double2(x1.x - x2.y, x1.y + x2.x);
     }
-    reg_fft<L, kNTMAX, 1>(x, b0, b1, 1, t, tw);
+    reg_fft<L, G::NTMAX, 1, G::NB>(x, b0, b1, 1, t, tw);
 #pragma unroll
     for (int e = 0; e < G::E; ++e) {
         const int v = t + G::NT * e;
@@ -95,19 +99,18 @@ __global__ void __launch_bounds__(kThreads) kr_lines_c2r(const double2* __restri
     }
 }
 
-template <int L, int SIGN>
+template <int L, class G, int SIGN>
 __global__ void __launch_bounds__(kThreads) kr_lines_c2c(const double2* __restrict__ in, double2* __restrict__ out,
                                                          int nlines, const double2* __restrict__ tw, double scale) {
-    using G = Geo<L>;
     extern __shared__ double2 lds[];
     const int t = threadIdx.x % G::NT, g = threadIdx.x / G::NT;
     double2* b0 = lds + g * L;
-    double2* b1 = lds + (G::W + g) * L;
+    double2* b1 = lds + G::B1OFF + g * L;
     const long ln = (long)blockIdx.x * G::W + g;
     double2 x[G::E];
 #pragma unroll
     for (int e = 0; e < G::E; ++e) x[e] = ln < nlines ? in[ln * L + t + G::NT * e] : make_double2(0.0, 0.0);
-    reg_fft<L, kNTMAX, SIGN>(x, b0, b1, 1, t, tw);
+    reg_fft<L, G::NTMAX, SIGN, G::NB>(x, b0, b1, 1, t, tw);
     if (ln < nlines) {
 #pragma unroll
         for (int e = 0; e < G::E; ++e) out[ln * L + t + G::NT * e] = cscale(x[e], scale);
@@ -117,10 +120,9 @@ __global__ void __launch_bounds__(kThreads) kr_lines_c2c(const double2* __restri
 // ---------------------------------------------------------------------------
 // strided lines: data[o][e][c]
 // ---------------------------------------------------------------------------
-template <int L, int SIGN>
+template <int L, class G, int SIGN>
 __global__ void __launch_bounds__(kThreads) kr_strided(const double2* in, double2* out, int outer, int inner,
                                                        const double2* __restrict__ tw, double scale) {
-    using G = Geo<L>;
     extern __shared__ double2 lds[];
     const int c = threadIdx.x % G::W, t = threadIdx.x / G::W;
     const int tiles = (inner + G::W - 1) / G::W;
@@ -131,7 +133,7 @@ __global__ void __launch_bounds__(kThreads) kr_strided(const double2* in, double
     double2 x[G::E];
 #pragma unroll
     for (int e = 0; e < G::E; ++e) x[e] = ok ? in[base + (long)(t + G::NT * e) * inner] : make_double2(0.0, 0.0);
-    reg_fft<L, kNTMAX, SIGN>(x, lds + c, lds + L * G::W + c, G::W, t, tw);
+    reg_fft<L, G::NTMAX, SIGN, G::NB>(x, lds + c, lds + G::B1OFF + c, G::W, t, tw);
     if (ok) {
 #pragma unroll
         for (int e = 0; e < G::E; ++e) out[base + (long)(t + G::NT * e) * inner] = cscale(x[e], scale);
@@ -191,14 +193,13 @@ __device__ void project_givens_lane(double2* col, int es, int n, int m, int nrot
     }
 }
 
-template <int N, int MODE>
+template <int N, class G, int MODE>
 __global__ void __launch_bounds__(kThreads) kr_cheb_fwd(const double2* in, double2* out, ChebDev cd, int ncols,
                                                         const double2* __restrict__ tw) {
-    using G = Geo<N>;
     constexpr int W = G::W, NT = G::NT, E = G::E;
     extern __shared__ double2 lds[];
     double2* B0 = lds;
-    double2* B1 = lds + N * W;
+    double2* B1 = lds + N * W;  // second tile buffer (the LDS always holds two N x W tiles here)
     const int c = threadIdx.x % W, t = threadIdx.x / W;
     const int c0 = blockIdx.x * W;
     const bool ok = c0 + c < ncols;
@@ -208,7 +209,7 @@ __global__ void __launch_bounds__(kThreads) kr_cheb_fwd(const double2* in, doubl
         const int v = t + NT * e;
         x[e] = ok ? in[(long)makhoul_row(v, N) * ncols + c0 + c] : make_double2(0.0, 0.0);
     }
-    reg_fft<N, kNTMAX, -1>(x, B0 + c, B1 + c, W, t, tw);
+    reg_fft<N, G::NTMAX, -1, G::NB>(x, B0 + c, (G::NB == 2 ? B1 : B0) + c, W, t, tw);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) B0[(t + NT * e) * W + c] = x[e];
@@ -332,14 +333,13 @@ __global__ void __launch_bounds__(kThreads) kr_cheb_fwd(const double2* in, doubl
 // ---------------------------------------------------------------------------
 // Chebyshev axis, backward (recombination + DCT-III)
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, class G>
 __global__ void __launch_bounds__(kThreads) kr_cheb_bwd(const double2* in, double2* out, ChebDev cd, int ncols,
                                                         const double2* __restrict__ tw) {
-    using G = Geo<N>;
     constexpr int W = G::W, NT = G::NT, E = G::E;
     extern __shared__ double2 lds[];
     double2* B0 = lds;
-    double2* B1 = lds + N * W;
+    double2* B1 = lds + N * W;  // second tile buffer (the LDS always holds two N x W tiles here)
     const int c = threadIdx.x % W, t = threadIdx.x / W;
     const int c0 = blockIdx.x * W;
     const bool ok = c0 + c < ncols;
@@ -350,32 +350,34 @@ __global__ void __launch_bounds__(kThreads) kr_cheb_bwd(const double2* in, doubl
         B0[l * W + c] = (ok && l < nb) ? in[(long)l * ncols + c0 + c] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    auto chat = [&](int k) {
-        double2 v = B0[k * W + c];
-        if (k >= 2) { double bb = cd.beta[k - 2]; double2 u = B0[(k - 2) * W + c]; v.x += bb * u.x; v.y += bb * u.y; }
-        if (k >= 4) { double gg = cd.gamma[k - 4]; double2 u = B0[(k - 4) * W + c]; v.x += gg * u.x; v.y += gg * u.y; }
-        return v;
-    };
-#pragma unroll 1
+    // Chebyshev coefficients c_k = u_k + beta_{k-2} u_{k-2} + gamma_{k-4} u_{k-4} into B1
+    const bool has_gamma = cd.basis == SGM_SHEN_BIHARMONIC;
+    const bool has_beta = cd.basis != SGM_CHEBYSHEV;
+#pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = t + NT * e;
-        double2 w;
-        if (k == 0) {
-            double2 v = chat(0);
-            w = make_double2(2.0 * v.x, 2.0 * v.y);
-        } else {
-            double2 ck = chat(k), cn = chat(N - k);
-            double2 d = make_double2(ck.x + cn.y, ck.y - cn.x);
-            w = cmul(cconj(cd.theta[k]), d);
-        }
-        B1[k * W + c] = w;
+        double2 v = B0[k * W + c];
+        if (has_beta && k >= 2) { double bb = cd.beta[k - 2]; double2 u = B0[(k - 2) * W + c]; v.x += bb * u.x; v.y += bb * u.y; }
+        if (has_gamma && k >= 4) { double gg = cd.gamma[k - 4]; double2 u = B0[(k - 4) * W + c]; v.x += gg * u.x; v.y += gg * u.y; }
+        B1[k * W + c] = v;
     }
     __syncthreads();
+    // DCT-III input W_0 = 2 c_0, W_k = e^{i pi k/(2N)} (c_k - i c_{N-k})
     double2 x[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) x[e] = B1[(t + NT * e) * W + c];
+    for (int e = 0; e < E; ++e) {
+        const int k = t + NT * e;
+        const double2 ck = B1[k * W + c];
+        if (k == 0) {
+            x[e] = make_double2(2.0 * ck.x, 2.0 * ck.y);
+        } else {
+            const double2 cn = B1[(N - k) * W + c];
+            const double2 d = make_double2(ck.x + cn.y, ck.y - cn.x);
+            x[e] = cmul(cconj(cd.theta[k]), d);
+        }
+    }
     __syncthreads();
-    reg_fft<N, kNTMAX, 1>(x, B0 + c, B1 + c, W, t, tw);
+    reg_fft<N, G::NTMAX, 1, G::NB>(x, B0 + c, (G::NB == 2 ? B1 : B0) + c, W, t, tw);
     if (ok) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -388,45 +390,64 @@ __global__ void __launch_bounds__(kThreads) kr_cheb_bwd(const double2* in, doubl
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
-template <int L>
-static size_t lines_lds() { return 2 * sizeof(double2) * (size_t)Geo<L>::W * L; }
-
-template <int L>
-static void fill(RegKernels& k) {
+template <int L, class G>
+static void fill_g(RegKernels& k) {
     k.L = L;
-    k.W = Geo<L>::W;
-    k.threads = Geo<L>::THREADS;
-    k.lds = lines_lds<L>();
-    k.r2c = kr_lines_r2c<L>;
-    k.c2r = kr_lines_c2r<L>;
-    k.c2c_f = kr_lines_c2c<L, -1>;
-    k.c2c_b = kr_lines_c2c<L, 1>;
-    k.str_f = kr_strided<L, -1>;
-    k.str_b = kr_strided<L, 1>;
-    k.cf_sp = kr_cheb_fwd<L, kScalarProduct>;
-    k.cf_cheb = kr_cheb_fwd<L, kProjCheb>;
-    k.cf_dir = kr_cheb_fwd<L, kProjDirichlet>;
-    k.cf_bih = kr_cheb_fwd<L, kProjBiharmonic>;
-    k.cb = kr_cheb_bwd<L>;
+    k.W = G::W;
+    k.threads = G::THREADS;
+    k.lds = sizeof(double2) * (size_t)G::NB * G::W * L;
+    k.lds_cheb = 2 * sizeof(double2) * (size_t)G::W * L;
+    k.r2c = kr_lines_r2c<L, G>;
+    k.c2r = kr_lines_c2r<L, G>;
+    k.c2c_f = kr_lines_c2c<L, G, -1>;
+    k.c2c_b = kr_lines_c2c<L, G, 1>;
+    k.str_f = kr_strided<L, G, -1>;
+    k.str_b = kr_strided<L, G, 1>;
+    k.cf_sp = kr_cheb_fwd<L, G, kScalarProduct>;
+    k.cf_cheb = kr_cheb_fwd<L, G, kProjCheb>;
+    k.cf_dir = kr_cheb_fwd<L, G, kProjDirichlet>;
+    k.cf_bih = kr_cheb_fwd<L, G, kProjBiharmonic>;
+    k.cb = kr_cheb_bwd<L, G>;
 }
 
-bool reg_kernels_for(int L, RegKernels& k) {
+// Variant v: 0 = (32 threads per line max, two buffers), 1 = (32, one buffer),
+// 2 = (16, two buffers), 3 = (16, one buffer).  Only the hot lengths carry all
+// four; the others have variant 0 only.
+template <int L>
+static bool fill_v(int v, RegKernels& k) {
+    switch (v) {
+        case 0: fill_g<L, Geo<L, 32, 2>>(k); return true;
+        case 1: fill_g<L, Geo<L, 32, 1>>(k); return true;
+        case 2: fill_g<L, Geo<L, 16, 2>>(k); return true;
+        case 3: fill_g<L, Geo<L, 16, 1>>(k); return true;
+        default: return false;
+    }
+}
+template <int L>
+static bool fill0(int v, RegKernels& k) {
+    if (v != 0) return false;
+    fill_g<L, Geo<L, 32, 2>>(k);
+    return true;
+}
+
+bool reg_kernels_for(int L, RegKernels& k, int variant) {
+    k.variant = variant;
     switch (L) {
-        case 16: fill<16>(k); return true;
-        case 32: fill<32>(k); return true;
-        case 64: fill<64>(k); return true;
-        case 128: fill<128>(k); return true;
-        case 256: fill<256>(k); return true;
-        case 512: fill<512>(k); return true;
-        case 1024: fill<1024>(k); return true;
-        case 48: fill<48>(k); return true;
-        case 96: fill<96>(k); return true;
-        case 192: fill<192>(k); return true;
-        case 384: fill<384>(k); return true;
-        case 768: fill<768>(k); return true;
-        case 144: fill<144>(k); return true;
-        case 288: fill<288>(k); return true;
-        case 576: fill<576>(k); return true;
+        case 16: return fill0<16>(variant, k);
+        case 32: return fill0<32>(variant, k);
+        case 64: return fill0<64>(variant, k);
+        case 128: return fill_v<128>(variant, k);
+        case 256: return fill_v<256>(variant, k);
+        case 512: return fill_v<512>(variant, k);
+        case 1024: return fill0<1024>(variant, k);
+        case 48: return fill0<48>(variant, k);
+        case 96: return fill0<96>(variant, k);
+        case 192: return fill0<192>(variant, k);
+        case 384: return fill0<384>(variant, k);
+        case 768: return fill0<768>(variant, k);
+        case 144: return fill0<144>(variant, k);
+        case 288: return fill0<288>(variant, k);
+        case 576: return fill0<576>(variant, k);
         default: return false;
     }
 }

@@ -1,6 +1,9 @@
 // Tensor-product space plans and the C ABI for transforms and solves.
+#include <array>
 #include <cstdarg>
 #include <cstring>
+#include <functional>
+#include <tuple>
 #include <map>
 #include <mutex>
 #include <new>
@@ -120,6 +123,89 @@ static int pick_tile(int L, int want, size_t (*bytes)(int, int), int lds_max) {
     int w = want;
     while (w > 1 && bytes(L, w) > (size_t)lds_max) w /= 2;
     return w;
+}
+
+static sgm_status fourier_forward(sgm_plan p, const void* u, double2* uh, hipStream_t s);
+static hipError_t cheb_forward_pass(sgm_plan p, double2* data, int mode, hipStream_t s);
+extern "C" sgm_status sgm_backward(sgm_plan p, const void* u_hat, void* u, void* stream);
+
+// Autotuner: for every axis with register kernels, time each compiled variant
+// (tile width and exchange-buffer count) on the plan's own passes and keep the
+// fastest.  Choices are remembered per process, keyed by the plan geometry.
+struct TuneKey {
+    int ndim, basis, N, M1, M2, kind;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(ndim, basis, N, M1, M2, kind) < std::tie(o.ndim, o.basis, o.N, o.M1, o.M2, o.kind);
+    }
+};
+static std::map<TuneKey, std::array<int, 3>> g_tuned;
+static std::mutex g_tune_mu;
+
+static float time_ms(const std::function<void()>& f, int reps) {
+    hipEvent_t a, b;
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    f();  // warm-up
+    hipEventRecord(a, nullptr);
+    for (int i = 0; i < reps; ++i) f();
+    hipEventRecord(b, nullptr);
+    hipEventSynchronize(b);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, a, b);
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    return ms / reps;
+}
+
+static sgm_status autotune_plan(sgm_plan p, int lds_max) {
+    TuneKey key{p->ndim, p->d.basis, p->N, p->M1, p->M2, p->d.kind_last};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            int Llast = p->ndim == 3 ? p->M2 : p->M1;
+            if (p->hx) reg_kernels_for(p->N, p->rkx, it->second[0]);
+            if (p->hy) reg_kernels_for(p->M1, p->rky, it->second[1]);
+            if (p->hz) reg_kernels_for(Llast, p->rkz, it->second[2]);
+            return SGM_OK;
+        }
+    }
+    const size_t phys_bytes = (size_t)p->phys[0] * p->phys[1] * p->phys[2] * (p->r2c ? sizeof(double) : sizeof(double2));
+    void* u = nullptr;
+    void* uh = nullptr;
+    if (hipMalloc(&u, phys_bytes) != hipSuccess) return SGM_ERR_OOM;
+    if (hipMalloc(&uh, (size_t)p->nspec * sizeof(double2)) != hipSuccess) { hipFree(u); return SGM_ERR_OOM; }
+    hipMemset(u, 0, phys_bytes);
+    hipMemset(uh, 0, (size_t)p->nspec * sizeof(double2));
+    hipDeviceSynchronize();
+    const int Llast = p->ndim == 3 ? p->M2 : p->M1;
+    std::array<int, 3> best{0, 0, 0};
+    struct Ax { bool has; RegKernels* rk; int L; int idx; };
+    Ax axes[3] = {{p->hx, &p->rkx, p->N, 0}, {p->hy, &p->rky, p->M1, 1}, {p->hz, &p->rkz, Llast, 2}};
+    for (auto& ax : axes) {
+        if (!ax.has) continue;
+        float tbest = 1e30f;
+        for (int v = 0; v < kRegVariants; ++v) {
+            RegKernels cand;
+            if (!reg_kernels_for(ax.L, cand, v)) continue;
+            if ((ax.idx == 0 ? cand.lds_cheb : cand.lds) > (size_t)lds_max) continue;
+            RegKernels saved = *ax.rk;
+            *ax.rk = cand;
+            float t = time_ms([&]() {
+                fourier_forward(p, u, static_cast<double2*>(uh), nullptr);
+                cheb_forward_pass(p, static_cast<double2*>(uh), kProject, nullptr);
+                sgm_backward(p, uh, u, nullptr);
+            }, 3);
+            *ax.rk = saved;
+            if (t < tbest) { tbest = t; best[ax.idx] = v; }
+        }
+        reg_kernels_for(ax.L, *ax.rk, best[ax.idx]);
+    }
+    hipFree(u);
+    hipFree(uh);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[key] = best;
+    return SGM_OK;
 }
 
 extern "C" {
@@ -248,13 +334,19 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
         return SGM_ERR_UNSUPPORTED_SIZE;
     }
     if (d.autotune != 2) {
-        p->hx = reg_kernels_for(d.N, p->rkx);
-        p->hy = d.ndim == 3 && reg_kernels_for(d.M1, p->rky);
-        p->hz = reg_kernels_for(Llast, p->rkz);
-        // the contiguous-line kernels need an even line length for the real pairs
-        if (p->hx && p->rkx.lds > (size_t)lds) p->hx = false;
+        // autotune >= 16 pins variant (autotune - 16) where it exists (diagnostics)
+        const int v0 = d.autotune >= 16 ? d.autotune - 16 : 0;
+        auto pick = [&](int L, RegKernels& k) { return reg_kernels_for(L, k, v0) || reg_kernels_for(L, k, 0); };
+        p->hx = pick(d.N, p->rkx);
+        p->hy = d.ndim == 3 && pick(d.M1, p->rky);
+        p->hz = pick(Llast, p->rkz);
+        if (p->hx && p->rkx.lds_cheb > (size_t)lds) p->hx = false;
         if (p->hy && p->rky.lds > (size_t)lds) p->hy = false;
         if (p->hz && p->rkz.lds > (size_t)lds) p->hz = false;
+        if (d.autotune == 1) {
+            sgm_status st2 = autotune_plan(p, lds);
+            if (st2 != SGM_OK) { hipFree(p->work); hipFree(p->blob); delete p; return st2; }
+        }
     }
     *out = p;
     return SGM_OK;
@@ -344,7 +436,7 @@ static hipError_t cheb_forward_pass(sgm_plan p, double2* data, int mode, hipStre
     auto f = k.cf_sp;
     if (mode == kProject)
         f = p->cd.basis == SGM_SHEN_DIRICHLET ? k.cf_dir : p->cd.basis == SGM_SHEN_BIHARMONIC ? k.cf_bih : k.cf_cheb;
-    return launch_k(f, (p->geom.ncols + k.W - 1) / k.W, k.threads, k.lds, s, (const double2*)data, data, p->cd,
+    return launch_k(f, (p->geom.ncols + k.W - 1) / k.W, k.threads, k.lds_cheb, s, (const double2*)data, data, p->cd,
                     p->geom.ncols, p->rpx.tw);
 }
 
@@ -383,7 +475,7 @@ sgm_status sgm_backward(sgm_plan p, const void* u_hat, void* u, void* stream) {
     {
         PassTimer t(p, 6, s);
         if (p->hx)
-            SGM_HIP_TRY(launch_k(p->rkx.cb, (p->geom.ncols + p->rkx.W - 1) / p->rkx.W, p->rkx.threads, p->rkx.lds, s,
+            SGM_HIP_TRY(launch_k(p->rkx.cb, (p->geom.ncols + p->rkx.W - 1) / p->rkx.W, p->rkx.threads, p->rkx.lds_cheb, s,
                                  static_cast<const double2*>(u_hat), w, p->cd, p->geom.ncols, p->rpx.tw));
         else
             SGM_HIP_TRY(launch_cheb_bwd(static_cast<const double2*>(u_hat), w, p->cd, p->geom.ncols, p->W_cheb,

@@ -173,3 +173,32 @@ def test_full_size_sampled(Plan, basis, N):
     mask[:, :, 0] = False
     mask[:, :, -1] = False
     assert rel_err(back[mask], vh[mask]) < TOL_T
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("basis", ["dirichlet", "biharmonic"])
+@pytest.mark.parametrize("shape", [(128, 256, 128), (256, 128, 512), (512, 128, 256), (256, 64)])
+def test_kernel_variants(Plan, variant, basis, shape):
+    # every compiled tile/buffer variant of the register kernels agrees with the oracle
+    print(f"[case] variant={variant} basis={basis} shape={shape}", flush=True)
+    N = shape[0]
+    p = Plan(basis, *shape, variant=variant)
+    u = _phys(shape, "r2c", seed=N + variant)
+    rng = np.random.default_rng(variant)
+    uh = host(p.forward(dev(u)))
+    if len(shape) == 3:
+        cols = _sample_cols(p.spec_shape, rng, n=12)
+        assert rel_err(uh.reshape(N, -1)[:, cols], T.forward_columns(basis, u, cols)) < TOL_T
+        vh = synth.random_spectral(p.spec_shape, seed=5, nrows=C.nbasis(basis, N))
+        rows = np.array([0, N // 3, N - 1])
+        assert rel_err(host(p.backward(dev(vh)))[rows], T.backward_rows(basis, vh, rows, shape[-1])) < TOL_T
+    else:
+        assert rel_err(uh, T.forward(basis, u)) < TOL_T
+
+
+def test_autotuned_plan(Plan):
+    p = Plan("dirichlet", 256, 128, 128, autotune=True)
+    u = _phys((256, 128, 128), "r2c", seed=3)
+    uh = host(p.forward(dev(u)))
+    cols = _sample_cols(p.spec_shape, np.random.default_rng(1), n=8)
+    assert rel_err(uh.reshape(256, -1)[:, cols], T.forward_columns("dirichlet", u, cols)) < TOL_T
