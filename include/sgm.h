@@ -154,6 +154,8 @@ typedef struct {
  * UNSUPPORTED_SIZE, OOM, HIP. */
 sgm_status sgm_gl_create(const sgm_gl_desc* desc, sgm_gl* out);
 sgm_status sgm_gl_destroy(sgm_gl gl);
+/* Number of problems of the batch. */
+sgm_status sgm_gl_count(sgm_gl gl, int* count);
 /* offsets[0..count]: packed layout (complex elements); offsets[count] = total. */
 sgm_status sgm_gl_offsets(sgm_gl gl, int64_t* offsets);
 /* u_hat = (1/N^2) sum_x u(x) e^{-i k.x} per problem (Sec. 3.4.1 forward, both axes). */
@@ -167,6 +169,78 @@ sgm_status sgm_gl_rhs(sgm_gl gl, const void* u_hat, void* rhs, void* stream);
 /* Advance every problem by nsteps steps of dt in place (nsteps >= 0).  Calls that
  * overlap on one batch object race (they share its stage buffers). */
 sgm_status sgm_gl_step(sgm_gl gl, void* u_hat, int nsteps, void* stream);
+
+/* ---- FNO-style surrogate for Ginzburg-Landau states --------------------------------
+ * Learned map u(t) -> u(t + s dt) on an H x W periodic grid, the complex state split
+ * into two real channels: x is fp32 channels-last [B][H][W][2] (Re, Im).
+ *   a = x W_l + b_l (lift to `width` channels); `layers` times:
+ *   z = IDFT_K(R_l DFT_K(a)) + a W_p + b_p, a = gelu(z) (no gelu after the last);
+ *   out = gelu(a W_1 + b_1) W_2 + b_2;  pred = x + out.
+ * DFT_K keeps ky in {0..K-1, H-K..H-1}, kx in {0..K-1} (1/(HW) normalised); IDFT_K
+ * is the real inverse of that half spectrum (weight 2 for kx > 0).  Activations
+ * and GEMM operands are bfloat16 on the matrix cores with fp32 accumulation;
+ * parameters, gradients and Adam moments are fp32.  Loss: mean over samples of
+ * ||pred - target||_2 / ||target||_2.
+ * Flat parameter order: W_l[2][C], b_l[C], per layer {R_re[2K][K][C][C],
+ * R_im[2K][K][C][C], W_p[C][C], b_p[C]}, W_1[C][P], b_1[P], W_2[P][2], b_2[2]. */
+typedef struct sgm_fno_s* sgm_fno;
+
+typedef struct {
+    int H, W;       /* grid; 2 * modes <= H, W                                   */
+    int width;      /* channels C                                                */
+    int modes;      /* retained modes K per direction                            */
+    int layers;     /* spectral layers                                           */
+    int hidden;     /* projection width P                                        */
+    int max_batch;  /* largest batch any call will use (sizes the workspace)     */
+} sgm_fno_desc;
+
+/* Allocate parameters (seeded initialisation), Adam state and a workspace for
+ * max_batch samples (about (2 layers + 3) B H W C bf16 plus B H W P). */
+sgm_status sgm_fno_create(const sgm_fno_desc* desc, uint64_t seed, sgm_fno* out);
+sgm_status sgm_fno_destroy(sgm_fno f);
+sgm_status sgm_fno_num_params(sgm_fno f, int64_t* n);
+/* Host copies of the flat fp32 parameter vector (set also resets Adam). */
+sgm_status sgm_fno_set_params(sgm_fno f, const float* host);
+sgm_status sgm_fno_get_params(sgm_fno f, float* host);
+/* pred = net(x) for `batch` samples (device arrays [batch][H][W][2]). */
+sgm_status sgm_fno_infer(sgm_fno f, const float* x, float* pred, int batch, void* stream);
+/* Forward + loss + backward without an update: gradients to grads_host (num_params
+ * floats, may be NULL) and the mean relative L2 loss to loss_host (may be NULL).
+ * Synchronises the stream. */
+sgm_status sgm_fno_grads(sgm_fno f, const float* x, const float* target, int batch, float* grads_host,
+                         float* loss_host, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) at learning rate lr; the batch
+ * loss before the update goes to loss_host if it is not NULL (then synchronises). */
+sgm_status sgm_fno_train_step(sgm_fno f, const float* x, const float* target, int batch, float lr,
+                              float* loss_host, void* stream);
+/* Per-sample relative L2 ||pred - target|| / ||target|| into rel_dev (device floats). */
+sgm_status sgm_fno_rel_l2(sgm_fno f, const float* pred, const float* target, int batch, float* rel_dev,
+                          void* stream);
+/* Checkpoint: parameters and Adam state (binary file). */
+sgm_status sgm_fno_save(sgm_fno f, const char* path);
+sgm_status sgm_fno_load(sgm_fno f, const char* path);
+/* n complex128 values <-> n (Re, Im) fp32 pairs (GL states to FNO inputs and back). */
+sgm_status sgm_fno_pack(const void* u_c128, float* x, int64_t n, void* stream);
+sgm_status sgm_fno_unpack(const float* x, void* u_c128, int64_t n, void* stream);
+
+/* Surrogate advance with FP64 fallback.  `gl` holds B problems, all H x W (= the
+ * FNO grid); u_hat is its packed spectral state, advanced in place by nsur
+ * macro-steps of the surrogate, each standing for steps_per solver steps of gl's dt
+ * (the network must have been trained for that stride).  Per macro-step a seeded
+ * subset of `gl_check`->count samples (evenly spaced, random offset) is also
+ * advanced by the FP64 solver `gl_check` (same N, L, b, c, dt); a checked sample
+ * whose relative L2 error ||pred - solver|| / ||solver|| (physical fields) exceeds
+ * tol is replaced by the solver's result.  stats (may be NULL) accumulates over
+ * the call.  Workspace for B samples is allocated on the first call (and when B
+ * grows).  Synchronises the stream once per macro-step. */
+typedef struct {
+    int n_checked;     /* samples checked by the solver        */
+    int n_fallback;    /* checked samples replaced             */
+    float max_rel_l2;  /* largest checked relative L2 error    */
+    float mean_rel_l2; /* mean checked relative L2 error       */
+} sgm_fno_stats;
+sgm_status sgm_fno_advance_checked(sgm_fno f, sgm_gl gl, sgm_gl gl_check, void* u_hat, int nsur, int steps_per,
+                                   double tol, uint64_t seed, sgm_fno_stats* stats, void* stream);
 
 const char* sgm_status_string(sgm_status s);
 const char* sgm_last_error(void);

@@ -9,7 +9,7 @@ from ._lib import SgmError, load  # noqa: F401
 
 
 def __getattr__(name):
-    if name in ("Plan", "GLBatch"):
+    if name in ("Plan", "GLBatch", "FNO"):
         from . import api
         return getattr(api, name)
     raise AttributeError(name)

@@ -29,6 +29,16 @@ class GLDesc(ctypes.Structure):
     ]
 
 
+class FNODesc(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int), ("W", ctypes.c_int), ("width", ctypes.c_int), ("modes", ctypes.c_int),
+                ("layers", ctypes.c_int), ("hidden", ctypes.c_int), ("max_batch", ctypes.c_int)]
+
+
+class FNOStats(ctypes.Structure):
+    _fields_ = [("n_checked", ctypes.c_int), ("n_fallback", ctypes.c_int), ("max_rel_l2", ctypes.c_float),
+                ("mean_rel_l2", ctypes.c_float)]
+
+
 SGM_RK4, SGM_IFRK4 = 1, 2
 _lib = None
 
@@ -49,10 +59,26 @@ _SIGS = {
     "sgm_gl_create": ([ctypes.POINTER(GLDesc), ctypes.POINTER(_vp)], ctypes.c_int),
     "sgm_gl_destroy": ([_vp], ctypes.c_int),
     "sgm_gl_offsets": ([_vp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "sgm_gl_count": ([_vp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "sgm_fno_advance_checked": ([_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_uint64,
+                                 _vp, _vp], ctypes.c_int),
     "sgm_gl_forward": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "sgm_gl_backward": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "sgm_gl_rhs": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "sgm_gl_step": ([_vp, _vp, ctypes.c_int, _vp], ctypes.c_int),
+    "sgm_fno_create": ([ctypes.POINTER(FNODesc), ctypes.c_uint64, ctypes.POINTER(_vp)], ctypes.c_int),
+    "sgm_fno_destroy": ([_vp], ctypes.c_int),
+    "sgm_fno_num_params": ([_vp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "sgm_fno_set_params": ([_vp, _vp], ctypes.c_int),
+    "sgm_fno_get_params": ([_vp, _vp], ctypes.c_int),
+    "sgm_fno_infer": ([_vp, _vp, _vp, ctypes.c_int, _vp], ctypes.c_int),
+    "sgm_fno_grads": ([_vp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp], ctypes.c_int),
+    "sgm_fno_train_step": ([_vp, _vp, _vp, ctypes.c_int, ctypes.c_float, _vp, _vp], ctypes.c_int),
+    "sgm_fno_rel_l2": ([_vp, _vp, _vp, ctypes.c_int, _vp, _vp], ctypes.c_int),
+    "sgm_fno_save": ([_vp, ctypes.c_char_p], ctypes.c_int),
+    "sgm_fno_load": ([_vp, ctypes.c_char_p], ctypes.c_int),
+    "sgm_fno_pack": ([_vp, _vp, ctypes.c_int64, _vp], ctypes.c_int),
+    "sgm_fno_unpack": ([_vp, _vp, ctypes.c_int64, _vp], ctypes.c_int),
     "sgm_plan_pass_times": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), ctypes.c_int],
                             ctypes.c_int),
 }

@@ -5,6 +5,7 @@ torch's current stream.  All arithmetic happens in the HIP kernels.
 """
 import ctypes
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -183,3 +184,134 @@ class GLBatch:
         self._vec(uh, "u_hat")
         check(self._lib.sgm_gl_step(self._h, _ptr(uh), int(nsteps), _stream()), "sgm_gl_step")
         return uh
+
+
+class FNO:
+    """FNO-style surrogate u(t) -> u(t + s dt) with hand-written training and inference kernels.
+
+    Inputs and outputs are fp32 device tensors [B, H, W, 2] (Re, Im channels)."""
+
+    def __init__(self, H, W, width=32, modes=16, layers=4, hidden=128, max_batch=16, seed=0):
+        lib = load()
+        self._lib = lib
+        d = _lib.FNODesc(int(H), int(W), int(width), int(modes), int(layers), int(hidden), int(max_batch))
+        h = ctypes.c_void_p()
+        check(lib.sgm_fno_create(ctypes.byref(d), ctypes.c_uint64(seed), ctypes.byref(h)), "sgm_fno_create")
+        self._h = h
+        n = ctypes.c_int64()
+        check(lib.sgm_fno_num_params(h, ctypes.byref(n)), "sgm_fno_num_params")
+        self.num_params = n.value
+        self.H, self.W, self.C, self.K, self.nl, self.P, self.max_batch = H, W, width, modes, layers, hidden, max_batch
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sgm_fno_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # flat parameter vector <-> dict in the documented order
+    def param_shapes(self):
+        C, K, P = self.C, self.K, self.P
+        sh = [("Wl", (2, C)), ("bl", (C,))]
+        for l in range(self.nl):
+            sh += [(f"Rr{l}", (2 * K, K, C, C)), (f"Ri{l}", (2 * K, K, C, C)), (f"Wp{l}", (C, C)), (f"bp{l}", (C,))]
+        sh += [("W1", (C, P)), ("b1", (P,)), ("W2", (P, 2)), ("b2", (2,))]
+        return sh
+
+    def flatten(self, params):
+        return np.concatenate([np.asarray(params[k], dtype=np.float32).reshape(-1) for k, _ in self.param_shapes()])
+
+    def unflatten(self, flat):
+        out, o = {}, 0
+        for k, shp in self.param_shapes():
+            n = int(np.prod(shp))
+            out[k] = np.asarray(flat[o:o + n]).reshape(shp)
+            o += n
+        return out
+
+    def set_params(self, params):
+        flat = np.ascontiguousarray(self.flatten(params) if isinstance(params, dict) else params, dtype=np.float32)
+        assert flat.size == self.num_params
+        check(self._lib.sgm_fno_set_params(self._h, flat.ctypes.data_as(ctypes.c_void_p)), "sgm_fno_set_params")
+
+    def get_params(self):
+        flat = np.empty(self.num_params, dtype=np.float32)
+        check(self._lib.sgm_fno_get_params(self._h, flat.ctypes.data_as(ctypes.c_void_p)), "sgm_fno_get_params")
+        return self.unflatten(flat)
+
+    def _x(self, x, name):
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()
+                and x.dim() == 4 and tuple(x.shape[1:]) == (self.H, self.W, 2)):
+            raise ValueError(f"{name}: expected contiguous float32 device tensor [B, {self.H}, {self.W}, 2]")
+        if not 1 <= x.shape[0] <= self.max_batch:
+            raise ValueError(f"{name}: batch must be in 1..{self.max_batch}")
+
+    def infer(self, x, out=None):
+        self._x(x, "x")
+        out = torch.empty_like(x) if out is None else out
+        check(self._lib.sgm_fno_infer(self._h, _ptr(x), _ptr(out), x.shape[0], _stream()), "sgm_fno_infer")
+        return out
+
+    def grads(self, x, target):
+        self._x(x, "x")
+        self._x(target, "target")
+        g = np.empty(self.num_params, dtype=np.float32)
+        loss = ctypes.c_float()
+        check(self._lib.sgm_fno_grads(self._h, _ptr(x), _ptr(target), x.shape[0], g.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.byref(loss), _stream()), "sgm_fno_grads")
+        return self.unflatten(g), loss.value
+
+    def train_step(self, x, target, lr, want_loss=True):
+        self._x(x, "x")
+        self._x(target, "target")
+        loss = ctypes.c_float()
+        check(self._lib.sgm_fno_train_step(self._h, _ptr(x), _ptr(target), x.shape[0], float(lr),
+                                           ctypes.byref(loss) if want_loss else None, _stream()), "sgm_fno_train_step")
+        return loss.value if want_loss else None
+
+    def rel_l2(self, pred, target):
+        self._x(pred, "pred")
+        self._x(target, "target")
+        out = torch.empty(pred.shape[0], dtype=torch.float32, device=pred.device)
+        check(self._lib.sgm_fno_rel_l2(self._h, _ptr(pred), _ptr(target), pred.shape[0], _ptr(out), _stream()),
+              "sgm_fno_rel_l2")
+        return out
+
+    def advance_checked(self, gl, gl_check, u_hat, nsur, steps_per, tol=1e-2, seed=0):
+        """Advance the packed GL state u_hat by nsur surrogate macro-steps with the FP64
+        check/fallback on gl_check.count samples per macro-step; returns the stats dict."""
+        gl._vec(u_hat, "u_hat")
+        st = _lib.FNOStats(0, 0, 0.0, 0.0)
+        check(self._lib.sgm_fno_advance_checked(self._h, gl._h, gl_check._h, _ptr(u_hat), int(nsur), int(steps_per),
+                                                float(tol), ctypes.c_uint64(seed), ctypes.byref(st), _stream()),
+              "sgm_fno_advance_checked")
+        return {"n_checked": st.n_checked, "n_fallback": st.n_fallback, "max_rel_l2": st.max_rel_l2,
+                "mean_rel_l2": st.mean_rel_l2}
+
+    def save(self, path):
+        check(self._lib.sgm_fno_save(self._h, str(path).encode()), "sgm_fno_save")
+
+    def load(self, path):
+        check(self._lib.sgm_fno_load(self._h, str(path).encode()), "sgm_fno_load")
+
+
+def pack_states(u_c128, out=None):
+    """complex128 device tensor (..., H, W) -> fp32 (..., H, W, 2) with the library kernel."""
+    lib = load()
+    if out is None:
+        out = torch.empty(tuple(u_c128.shape) + (2,), dtype=torch.float32, device=u_c128.device)
+    check(lib.sgm_fno_pack(_ptr(u_c128), _ptr(out), u_c128.numel(), _stream()), "sgm_fno_pack")
+    return out
+
+
+def unpack_states(x, out=None):
+    lib = load()
+    if out is None:
+        out = torch.empty(tuple(x.shape[:-1]), dtype=torch.complex128, device=x.device)
+    check(lib.sgm_fno_unpack(_ptr(x), _ptr(out), out.numel(), _stream()), "sgm_fno_unpack")
+    return out

@@ -1,0 +1,816 @@
+// FNO-style surrogate for Ginzburg-Landau states: inference, training
+// (forward, backward, Adam) and the checked advance with FP64 fallback.
+//
+// Activations are channels-last [B][H][W][C] bfloat16; every contraction
+// (truncated DFTs along x and y, per-mode complex channel mixing, pointwise
+// channel layers) is a strided batched GEMM on the bf16 matrix cores with fp32
+// accumulation; GELU, biases, the loss and the optimizer are elementwise
+// kernels.  Parameters are kept in fp32 (master copy and Adam moments) and
+// mirrored to bf16 for the GEMMs after every update.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "fno_gemm.h"
+
+namespace sgm {
+
+typedef __bf16 bf16;
+
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_df(float z) {
+    return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// a[p, c] = x[p, 0] Wl[0, c] + x[p, 1] Wl[1, c] + bl[c]
+__global__ void k_lift(const float* x, const float* Wl, const float* bl, bf16* a, long P, int C) {
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= P * C) return;
+    long p = i / C;
+    int c = (int)(i - p * C);
+    a[i] = (bf16)(x[2 * p] * Wl[c] + x[2 * p + 1] * Wl[C + c] + bl[c]);
+}
+
+// z = s + bias; out = act ? gelu(z) : z; zsave (bf16) keeps z for the backward pass
+__global__ void k_bias_act(const float* s, const float* bias, bf16* out, bf16* zsave, long n, int C, int act) {
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float z = s[i] + bias[i % C];
+    if (zsave) zsave[i] = (bf16)z;
+    out[i] = (bf16)(act ? gelu_f(z) : z);
+}
+
+// pred = x + out + b2
+__global__ void k_residual(const float* x, const float* out, const float* b2, float* pred, long P) {
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= 2 * P) return;
+    pred[i] = x[i] + out[i] + b2[i & 1];
+}
+
+// per-sample squared norms of (pred - tgt) and tgt
+__global__ void k_loss_norms(const float* pred, const float* tgt, long per, double* nd, double* nt) {
+    const int b = blockIdx.y;
+    __shared__ double sd[256], st[256];
+    double a = 0, c = 0;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < per; i += (long)gridDim.x * blockDim.x) {
+        double d = (double)pred[b * per + i] - (double)tgt[b * per + i];
+        double t = tgt[b * per + i];
+        a += d * d;
+        c += t * t;
+    }
+    sd[threadIdx.x] = a;
+    st[threadIdx.x] = c;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) { sd[threadIdx.x] += sd[threadIdx.x + s]; st[threadIdx.x] += st[threadIdx.x + s]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { atomicAdd(&nd[b], sd[0]); atomicAdd(&nt[b], st[0]); }
+}
+
+// dpred = (pred - tgt) / (|pred - tgt| |tgt|) / B ; per-sample relative L2 out
+__global__ void k_loss_grad(const float* pred, const float* tgt, const double* nd, const double* nt, float* dpred,
+                            long per, int B, float* rel) {
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < (long)B && rel) rel[i] = (float)(sqrt(nd[i]) / sqrt(nt[i]));
+    if (i >= per * B || !dpred) return;
+    int b = (int)(i / per);
+    double f = 1.0 / (sqrt(nd[b]) * sqrt(nt[b]) * B);
+    dpred[i] = (float)(((double)pred[i] - (double)tgt[i]) * f);
+}
+
+// dz = da * gelu'(z) (act) or da, as bf16 for the GEMMs and fp32 for bias gradients
+__global__ void k_act_bwd(const float* da, const bf16* z, bf16* dz, long n, int act) {
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float g = da[i];
+    if (act) g *= gelu_df((float)z[i]);
+    dz[i] = (bf16)g;
+}
+
+// db[c] += sum_p g[p, c]  (g bf16 or fp32)
+template <typename T>
+__global__ void k_colsum(const T* g, float* db, long P, int C) {
+    extern __shared__ float sh[];
+    const int c = threadIdx.x % C, r = threadIdx.x / C, R = blockDim.x / C;
+    float acc = 0.f;
+    for (long p = blockIdx.x * (long)R + r; p < P; p += (long)gridDim.x * R) acc += (float)g[p * C + c];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    if (r == 0) {
+        float s = 0.f;
+        for (int q = 0; q < R; ++q) s += sh[q * C + c];
+        atomicAdd(&db[c], s);
+    }
+}
+
+// X[b][part][j][kx][c] -> Xm[(j, kx)][b][part][c]   (and back when inv)
+__global__ void k_perm_modes(const float* in, float* out, int B, int KY, int KX, int C, int inv) {
+    long n = (long)B * 2 * KY * KX * C;
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    // index in the [b][part][j][kx][c] layout
+    long t = i;
+    int c = (int)(t % C); t /= C;
+    int kx = (int)(t % KX); t /= KX;
+    int j = (int)(t % KY); t /= KY;
+    int part = (int)(t % 2); t /= 2;
+    int b = (int)t;
+    long o = ((((long)(j * KX + kx) * B + b) * 2 + part) * C + c);
+    if (inv) out[i] = in[o];
+    else out[o] = in[i];
+}
+
+// Rreal[m] (2C x 2C) = [[Rr, Ri], [-Ri, Rr]] as bf16, m = (j, kx)
+__global__ void k_build_rreal(const float* Rr, const float* Ri, bf16* Rreal, int nm, int C) {
+    long n = (long)nm * 4 * C * C;
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int C2 = 2 * C;
+    int col = (int)(i % C2);
+    int row = (int)((i / C2) % C2);
+    long m = i / (C2 * C2);
+    int pi = row / C, c = row % C, po = col / C, o = col % C;
+    long src = (m * C + c) * C + o;
+    float v;
+    if (pi == po) v = Rr[src];
+    else v = pi == 0 ? Ri[src] : -Ri[src];
+    Rreal[i] = (bf16)v;
+}
+
+// dRr = G[(re,c),(re,o)] + G[(im,c),(im,o)], dRi = G[(re,c),(im,o)] - G[(im,c),(re,o)]
+__global__ void k_fold_rgrad(const float* G, float* dRr, float* dRi, int nm, int C) {
+    long n = (long)nm * C * C;
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int o = (int)(i % C);
+    int c = (int)((i / C) % C);
+    long m = i / ((long)C * C);
+    int C2 = 2 * C;
+    const float* g = G + m * C2 * C2;
+    dRr[i] += g[c * C2 + o] + g[(C + c) * C2 + C + o];
+    dRi[i] += g[c * C2 + C + o] - g[(C + c) * C2 + o];
+}
+
+__global__ void k_f32_to_bf16(const float* in, bf16* out, long n) {
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (bf16)in[i];
+}
+
+__global__ void k_fill(float* p, float v, long n) {
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill_d(double* p, long n) {
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+__global__ void k_adam(float* w, const float* g, float* m, float* v, long n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float gi = g[i];
+    float mi = b1 * m[i] + (1.f - b1) * gi;
+    float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// complex128 packed N x N states [x][y] -> fp32 [b][y?]... channels-last [b][x][y][2]
+__global__ void k_c128_to_x(const double2* u, float* x, long n) {
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double2 v = u[i];
+    x[2 * i] = (float)v.x;
+    x[2 * i + 1] = (float)v.y;
+}
+__global__ void k_x_to_c128(const float* x, double2* u, long n) {
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    u[i] = make_double2((double)x[2 * i], (double)x[2 * i + 1]);
+}
+
+static inline unsigned nblk(long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace sgm
+
+using namespace sgm;
+
+// host bf16 (round to nearest even)
+static uint16_t to_bf16_bits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+struct sgm_fno_s {
+    sgm_fno_desc d;
+    int C, K, P, nl, H, W, Bmax, KY, KX, NM;
+    long npar = 0;
+    // parameter offsets (floats) in the flat vector
+    long oWl, obl, oW1, ob1, oW2, ob2;
+    std::vector<long> oRr, oRi, oWp, obp;
+    float* par = nullptr;   // fp32 master
+    float* grad = nullptr;
+    float* mom1 = nullptr;
+    float* mom2 = nullptr;
+    long step = 0;
+    bool mirrors_ok = false;
+    // bf16 mirrors
+    bf16 *Wp16 = nullptr, *W1_16 = nullptr, *W2_16 = nullptr, *Rreal = nullptr;
+    // DFT matrices (bf16)
+    bf16 *Fx = nullptr, *Fy = nullptr, *Gy = nullptr, *Gx = nullptr;
+    // activations / scratch (sized for Bmax)
+    bf16* acts = nullptr;   // (nl + 1) x [B H W C]
+    bf16* zsv = nullptr;    // nl x [B H W C]
+    bf16* hbuf = nullptr;   // [B H W P] gelu output
+    bf16* hpz = nullptr;    // [B H W P] pre-activation
+    float* s32 = nullptr;   // [B H W max(C, P)] fp32 GEMM output / gradient accumulator
+    float* da32 = nullptr;  // [B H W C]
+    bf16* d16 = nullptr;    // [B H W max(C, P)] bf16 gradient
+    float* T = nullptr;     // [B H 2K C]
+    float* X = nullptr;     // [B 4K K C]
+    float* Xm = nullptr;    // spectral, mode-major, per layer saved: nl x [NM B 2C]
+    float* Ym = nullptr;    // [NM B 2C]
+    float* Yt = nullptr;    // [B 4K K C]
+    float* Rg = nullptr;    // [NM 2C 2C] gradient of Rreal
+    float* outb = nullptr;  // [B H W 2]
+    float* predb = nullptr; // [B H W 2]
+    double* norms = nullptr;// 2 x Bmax
+    float* rel = nullptr;   // Bmax
+    void* all = nullptr;
+    // advance_checked workspace (grown on demand)
+    long adv_cap = 0;       // samples
+    void* adv = nullptr;
+};
+
+static long fno_act_elems(const sgm_fno_s* f) { return (long)f->Bmax * f->H * f->W * f->C; }
+
+extern "C" sgm_status sgm_fno_destroy(sgm_fno f) {
+    clear_error();
+    if (!f) return SGM_OK;
+    hipFree(f->all);
+    hipFree(f->adv);
+    delete f;
+    return SGM_OK;
+}
+
+extern "C" sgm_status sgm_fno_create(const sgm_fno_desc* desc, uint64_t seed, sgm_fno* out) {
+    clear_error();
+    SGM_CHECK_ARG(desc && out, "null argument");
+    *out = nullptr;
+    const sgm_fno_desc& d = *desc;
+    SGM_CHECK_ARG(d.H >= 4 && d.W >= 4 && d.width >= 1 && d.modes >= 1 && d.layers >= 1 && d.hidden >= 1 &&
+                      d.max_batch >= 1,
+                  "invalid FNO sizes");
+    SGM_CHECK_ARG(2 * d.modes <= d.H && 2 * d.modes <= d.W, "modes must satisfy 2*modes <= H and 2*modes <= W");
+    sgm_fno_s* f = new (std::nothrow) sgm_fno_s();
+    if (!f) return SGM_ERR_OOM;
+    f->d = d;
+    f->C = d.width; f->K = d.modes; f->P = d.hidden; f->nl = d.layers; f->H = d.H; f->W = d.W; f->Bmax = d.max_batch;
+    f->KY = 2 * d.modes; f->KX = d.modes; f->NM = f->KY * f->KX;
+    const int C = f->C, P = f->P, nl = f->nl, NM = f->NM;
+    long o = 0;
+    f->oWl = o; o += 2L * C;
+    f->obl = o; o += C;
+    for (int l = 0; l < nl; ++l) {
+        f->oRr.push_back(o); o += (long)NM * C * C;
+        f->oRi.push_back(o); o += (long)NM * C * C;
+        f->oWp.push_back(o); o += (long)C * C;
+        f->obp.push_back(o); o += C;
+    }
+    f->oW1 = o; o += (long)C * P;
+    f->ob1 = o; o += P;
+    f->oW2 = o; o += 2L * P;
+    f->ob2 = o; o += 2;
+    f->npar = o;
+    // device allocation plan
+    const long HW = (long)d.H * d.W, B = d.max_batch;
+    const long act = B * HW * C, wide = B * HW * std::max(C, P);
+    struct Slot { void** p; size_t bytes; };
+    std::vector<Slot> slots = {
+        {(void**)&f->par, 4 * (size_t)f->npar}, {(void**)&f->grad, 4 * (size_t)f->npar},
+        {(void**)&f->mom1, 4 * (size_t)f->npar}, {(void**)&f->mom2, 4 * (size_t)f->npar},
+        {(void**)&f->Wp16, 2 * (size_t)nl * C * C}, {(void**)&f->W1_16, 2 * (size_t)C * P},
+        {(void**)&f->W2_16, 2 * (size_t)2 * P}, {(void**)&f->Rreal, 2 * (size_t)nl * NM * 4 * C * C},
+        {(void**)&f->Fx, 2 * (size_t)2 * f->K * d.W}, {(void**)&f->Fy, 2 * (size_t)4 * f->K * 2 * d.H},
+        {(void**)&f->Gy, 2 * (size_t)2 * d.H * 4 * f->K}, {(void**)&f->Gx, 2 * (size_t)d.W * 2 * f->K},
+        {(void**)&f->acts, 2 * (size_t)(nl + 1) * act}, {(void**)&f->zsv, 2 * (size_t)nl * act},
+        {(void**)&f->hbuf, 2 * (size_t)B * HW * P}, {(void**)&f->hpz, 2 * (size_t)B * HW * P},
+        {(void**)&f->s32, 4 * (size_t)wide}, {(void**)&f->da32, 4 * (size_t)act}, {(void**)&f->d16, 2 * (size_t)wide},
+        {(void**)&f->T, 4 * (size_t)B * d.H * 2 * f->K * C}, {(void**)&f->X, 4 * (size_t)B * 4 * f->K * f->K * C},
+        {(void**)&f->Xm, 4 * (size_t)nl * NM * B * 2 * C}, {(void**)&f->Ym, 4 * (size_t)NM * B * 2 * C},
+        {(void**)&f->Yt, 4 * (size_t)B * 4 * f->K * f->K * C}, {(void**)&f->Rg, 4 * (size_t)NM * 4 * C * C},
+        {(void**)&f->outb, 4 * (size_t)B * HW * 2}, {(void**)&f->predb, 4 * (size_t)B * HW * 2},
+        {(void**)&f->norms, 8 * (size_t)2 * B}, {(void**)&f->rel, 4 * (size_t)B},
+    };
+    size_t total = 0;
+    for (auto& s : slots) total += (s.bytes + 255) & ~size_t(255);
+    if (hipMalloc(&f->all, total) != hipSuccess) {
+        set_error("hipMalloc of %zu bytes for the FNO failed", total);
+        delete f;
+        return SGM_ERR_OOM;
+    }
+    char* base = static_cast<char*>(f->all);
+    size_t off = 0;
+    for (auto& s : slots) { *s.p = base + off; off += (s.bytes + 255) & ~size_t(255); }
+    // DFT matrices on the host (long double phases, exact index reduction)
+    const long double twopi = 6.283185307179586476925286766559L;
+    const int K = f->K, H = d.H, W = d.W;
+    std::vector<uint16_t> Fx(2 * K * W), Fy(4 * K * 2 * H), Gy(2 * H * 4 * K), Gx(W * 2 * K);
+    auto kyv = [&](int j) { return j < K ? j : H - 2 * K + j; };
+    for (int kx = 0; kx < K; ++kx)
+        for (int x = 0; x < W; ++x) {
+            long double a = twopi * (long double)((long)kx * x % W) / W;
+            Fx[kx * W + x] = to_bf16_bits((float)(cosl(a) / W));
+            Fx[(K + kx) * W + x] = to_bf16_bits((float)(-sinl(a) / W));
+            const float w = kx == 0 ? 1.f : 2.f;
+            Gx[x * 2 * K + kx] = to_bf16_bits((float)(w * cosl(a)));
+            Gx[x * 2 * K + K + kx] = to_bf16_bits((float)(-w * sinl(a)));
+        }
+    for (int j = 0; j < 2 * K; ++j)
+        for (int y = 0; y < H; ++y) {
+            long double a = twopi * (long double)((long)kyv(j) * y % H) / H;
+            const float fr = (float)(cosl(a) / H), fi = (float)(-sinl(a) / H);  // exp(-i a) / H
+            // Fy_real[(part_out, j)][(y, part_in)]
+            const int ncol = 2 * H;
+            Fy[(0 * 2 * K + j) * ncol + 2 * y + 0] = to_bf16_bits(fr);
+            Fy[(0 * 2 * K + j) * ncol + 2 * y + 1] = to_bf16_bits(-fi);
+            Fy[(1 * 2 * K + j) * ncol + 2 * y + 0] = to_bf16_bits(fi);
+            Fy[(1 * 2 * K + j) * ncol + 2 * y + 1] = to_bf16_bits(fr);
+            // Gy_real[(y, part_out)][(part_in, j)] with exp(+i a)
+            const float gr = (float)cosl(a), gi = (float)sinl(a);
+            const int gcol = 4 * K;
+            Gy[(2 * y + 0) * gcol + 0 * 2 * K + j] = to_bf16_bits(gr);
+            Gy[(2 * y + 0) * gcol + 1 * 2 * K + j] = to_bf16_bits(-gi);
+            Gy[(2 * y + 1) * gcol + 0 * 2 * K + j] = to_bf16_bits(gi);
+            Gy[(2 * y + 1) * gcol + 1 * 2 * K + j] = to_bf16_bits(gr);
+        }
+    hipMemcpy(f->Fx, Fx.data(), Fx.size() * 2, hipMemcpyHostToDevice);
+    hipMemcpy(f->Fy, Fy.data(), Fy.size() * 2, hipMemcpyHostToDevice);
+    hipMemcpy(f->Gy, Gy.data(), Gy.size() * 2, hipMemcpyHostToDevice);
+    hipMemcpy(f->Gx, Gx.data(), Gx.size() * 2, hipMemcpyHostToDevice);
+    // seeded initial parameters (normal / uniform scales as in common FNO practice)
+    std::vector<float> hp(f->npar, 0.f);
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<float> nd(0.f, 1.f);
+    std::uniform_real_distribution<float> ud(0.f, 1.f);
+    for (long i = 0; i < 2L * C; ++i) hp[f->oWl + i] = nd(rng) / std::sqrt(2.f);
+    for (int l = 0; l < nl; ++l) {
+        const float sc = 1.f / (float)(C * C);
+        for (long i = 0; i < (long)NM * C * C; ++i) { hp[f->oRr[l] + i] = sc * ud(rng); hp[f->oRi[l] + i] = sc * ud(rng); }
+        for (long i = 0; i < (long)C * C; ++i) hp[f->oWp[l] + i] = nd(rng) / std::sqrt((float)C);
+    }
+    for (long i = 0; i < (long)C * P; ++i) hp[f->oW1 + i] = nd(rng) / std::sqrt((float)C);
+    for (long i = 0; i < 2L * P; ++i) hp[f->oW2 + i] = 0.1f * nd(rng) / std::sqrt((float)P);
+    hipMemcpy(f->par, hp.data(), 4 * f->npar, hipMemcpyHostToDevice);
+    hipMemset(f->mom1, 0, 4 * f->npar);
+    hipMemset(f->mom2, 0, 4 * f->npar);
+    *out = f;
+    return SGM_OK;
+}
+
+static sgm_status refresh_mirrors(sgm_fno f, hipStream_t s) {
+    if (f->mirrors_ok) return SGM_OK;
+    const int C = f->C, P = f->P;
+    for (int l = 0; l < f->nl; ++l) {
+        hipLaunchKernelGGL(k_f32_to_bf16, dim3(nblk((long)C * C)), dim3(256), 0, s, f->par + f->oWp[l],
+                           f->Wp16 + (long)l * C * C, (long)C * C);
+        hipLaunchKernelGGL(k_build_rreal, dim3(nblk((long)f->NM * 4 * C * C)), dim3(256), 0, s,
+                           (const float*)(f->par + f->oRr[l]), (const float*)(f->par + f->oRi[l]),
+                           f->Rreal + (long)l * f->NM * 4 * C * C, f->NM, C);
+    }
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3(nblk((long)C * P)), dim3(256), 0, s, f->par + f->oW1, f->W1_16, (long)C * P);
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3(nblk(2L * P)), dim3(256), 0, s, f->par + f->oW2, f->W2_16, 2L * P);
+    SGM_HIP_TRY(hipGetLastError());
+    f->mirrors_ok = true;
+    return SGM_OK;
+}
+
+extern "C" sgm_status sgm_fno_num_params(sgm_fno f, int64_t* n) {
+    clear_error();
+    SGM_CHECK_ARG(f && n, "null argument");
+    *n = f->npar;
+    return SGM_OK;
+}
+
+extern "C" sgm_status sgm_fno_set_params(sgm_fno f, const float* host) {
+    clear_error();
+    SGM_CHECK_ARG(f && host, "null argument");
+    SGM_HIP_TRY(hipMemcpy(f->par, host, 4 * f->npar, hipMemcpyHostToDevice));
+    SGM_HIP_TRY(hipMemset(f->mom1, 0, 4 * f->npar));
+    SGM_HIP_TRY(hipMemset(f->mom2, 0, 4 * f->npar));
+    f->step = 0;
+    f->mirrors_ok = false;
+    return SGM_OK;
+}
+
+extern "C" sgm_status sgm_fno_get_params(sgm_fno f, float* host) {
+    clear_error();
+    SGM_CHECK_ARG(f && host, "null argument");
+    SGM_HIP_TRY(hipMemcpy(host, f->par, 4 * f->npar, hipMemcpyDeviceToHost));
+    return SGM_OK;
+}
+
+// row-major helper: GEMM with A (M x K, lda), B (K x N, ldb), C (M x N, ldc)
+static GemmDesc G(int batch, int M, int N, int K, const void* A, long sAb, long sAm, long sAk, int af32, const void* B,
+                  long sBb, long sBk, long sBn, int bf32, float* Cp, long sCb, long sCm, long sCn, float beta = 0.f,
+                  int splitk = 1) {
+    GemmDesc g{};
+    g.M = M; g.N = N; g.K = K; g.batch = batch;
+    g.A = A; g.sAb = sAb; g.sAm = sAm; g.sAk = sAk; g.a_f32 = af32;
+    g.B = B; g.sBb = sBb; g.sBk = sBk; g.sBn = sBn; g.b_f32 = bf32;
+    g.C = Cp; g.sCb = sCb; g.sCm = sCm; g.sCn = sCn;
+    g.alpha = 1.f; g.beta = beta; g.splitk = splitk;
+    return g;
+}
+
+static int splits_for(long K) {
+    long s = K / 4096;
+    if (s < 1) s = 1;
+    if (s > 1024) s = 1024;
+    return (int)s;
+}
+
+// Forward pass for `batch` samples; keeps activations for backward.
+static sgm_status fno_forward(sgm_fno f, const float* x, int B, hipStream_t s) {
+    const int C = f->C, P = f->P, H = f->H, W = f->W, K = f->K, NM = f->NM;
+    const long HW = (long)H * W, pix = (long)B * HW, act = (long)f->Bmax * HW * C;
+    hipLaunchKernelGGL(k_lift, dim3(nblk(pix * C)), dim3(256), 0, s, x, f->par + f->oWl, f->par + f->obl, f->acts, pix, C);
+    SGM_HIP_TRY(hipGetLastError());
+    for (int l = 0; l < f->nl; ++l) {
+        const bf16* a = f->acts + l * act;
+        bf16* an = f->acts + (l + 1) * act;
+        // G1: T[(b,y)] (2K x C) = Fx (2K x W) a[(b,y)] (W x C)
+        SGM_HIP_TRY(gemm(G(B * H, 2 * K, C, W, f->Fx, 0, W, 1, 0, a, (long)W * C, C, 1, 0, f->T, 2L * K * C, C, 1), s));
+        // G2: X[b] (4K x K C) = Fy_real (4K x 2H) T[b] (2H x K C)
+        SGM_HIP_TRY(gemm(G(B, 4 * K, K * C, 2 * H, f->Fy, 0, 2L * H, 1, 0, f->T, 2L * H * K * C, (long)K * C, 1, 1, f->X,
+                           4L * K * K * C, (long)K * C, 1), s));
+        float* Xm = f->Xm + (long)l * NM * f->Bmax * 2 * C;
+        hipLaunchKernelGGL(k_perm_modes, dim3(nblk((long)B * 4 * K * K * C)), dim3(256), 0, s, (const float*)f->X, Xm,
+                           B, 2 * K, K, C, 0);
+        // G3: Ym[m] (B x 2C) = Xm[m] (B x 2C) Rreal[m] (2C x 2C)
+        SGM_HIP_TRY(gemm(G(NM, B, 2 * C, 2 * C, Xm, (long)B * 2 * C, 2 * C, 1, 1,
+                           f->Rreal + (long)l * NM * 4 * C * C, 4L * C * C, 2 * C, 1, 0, f->Ym, (long)B * 2 * C, 2 * C, 1),
+                         s));
+        hipLaunchKernelGGL(k_perm_modes, dim3(nblk((long)B * 4 * K * K * C)), dim3(256), 0, s, (const float*)f->Ym, f->Yt,
+                           B, 2 * K, K, C, 1);
+        // G4: U[b] (2H x K C) = Gy_real (2H x 4K) Yt[b] (4K x K C)   (U reuses T)
+        SGM_HIP_TRY(gemm(G(B, 2 * H, K * C, 4 * K, f->Gy, 0, 4L * K, 1, 0, f->Yt, 4L * K * K * C, (long)K * C, 1, 1, f->T,
+                           2L * H * K * C, (long)K * C, 1), s));
+        // G5: s[(b,y)] (W x C) = Gx (W x 2K) U[(b,y)] (2K x C)
+        SGM_HIP_TRY(gemm(G(B * H, W, C, 2 * K, f->Gx, 0, 2L * K, 1, 0, f->T, 2L * K * C, C, 1, 1, f->s32, (long)W * C, C, 1),
+                         s));
+        // G6: s += a Wp
+        SGM_HIP_TRY(gemm(G(1, (int)pix, C, C, a, 0, C, 1, 0, f->Wp16 + (long)l * C * C, 0, C, 1, 0, f->s32, 0, C, 1, 1.f),
+                         s));
+        hipLaunchKernelGGL(k_bias_act, dim3(nblk(pix * C)), dim3(256), 0, s, (const float*)f->s32,
+                           (const float*)(f->par + f->obp[l]), an, f->zsv + l * act, pix * C, C, l < f->nl - 1 ? 1 : 0);
+        SGM_HIP_TRY(hipGetLastError());
+    }
+    // projection
+    const bf16* a = f->acts + f->nl * act;
+    SGM_HIP_TRY(gemm(G(1, (int)pix, P, C, a, 0, C, 1, 0, f->W1_16, 0, P, 1, 0, f->s32, 0, P, 1), s));
+    hipLaunchKernelGGL(k_bias_act, dim3(nblk(pix * P)), dim3(256), 0, s, (const float*)f->s32,
+                       (const float*)(f->par + f->ob1), f->hbuf, f->hpz, pix * P, P, 1);
+    SGM_HIP_TRY(gemm(G(1, (int)pix, 2, P, f->hbuf, 0, P, 1, 0, f->W2_16, 0, 2, 1, 0, f->outb, 0, 2, 1), s));
+    hipLaunchKernelGGL(k_residual, dim3(nblk(2 * pix)), dim3(256), 0, s, x, (const float*)f->outb,
+                       (const float*)(f->par + f->ob2), f->predb, pix);
+    SGM_HIP_TRY(hipGetLastError());
+    return SGM_OK;
+}
+
+static sgm_status fno_loss(sgm_fno f, const float* tgt, int B, bool grad, hipStream_t s) {
+    const long per = (long)f->H * f->W * 2;
+    hipLaunchKernelGGL(k_fill_d, dim3(nblk(2L * B)), dim3(256), 0, s, f->norms, 2L * B);
+    hipLaunchKernelGGL(k_loss_norms, dim3(64, B), dim3(256), 0, s, (const float*)f->predb, tgt, per, f->norms,
+                       f->norms + B);
+    hipLaunchKernelGGL(k_loss_grad, dim3(nblk(std::max(per * B, (long)B))), dim3(256), 0, s, (const float*)f->predb, tgt,
+                       (const double*)f->norms, (const double*)(f->norms + B), grad ? f->outb : nullptr, per, B, f->rel);
+    SGM_HIP_TRY(hipGetLastError());
+    return SGM_OK;
+}
+
+static hipError_t colsum_bf16(const bf16* g, float* db, long P, int C, hipStream_t s) {
+    int R = std::max(1, 256 / C);
+    hipLaunchKernelGGL(k_colsum<bf16>, dim3(512), dim3(R * C), (size_t)R * C * 4, s, g, db, P, C);
+    return hipGetLastError();
+}
+static hipError_t colsum_f32(const float* g, float* db, long P, int C, hipStream_t s) {
+    int R = std::max(1, 256 / C);
+    hipLaunchKernelGGL(k_colsum<float>, dim3(512), dim3(R * C), (size_t)R * C * 4, s, g, db, P, C);
+    return hipGetLastError();
+}
+
+// Backward pass; dpred (fp32 [B H W 2]) is in f->outb.  Gradients -> f->grad.
+static sgm_status fno_backward(sgm_fno f, const float* x, int B, hipStream_t s) {
+    const int C = f->C, P = f->P, H = f->H, W = f->W, K = f->K, NM = f->NM;
+    const long HW = (long)H * W, pix = (long)B * HW, act = (long)f->Bmax * HW * C;
+    hipLaunchKernelGGL(k_fill, dim3(nblk(f->npar)), dim3(256), 0, s, f->grad, 0.f, f->npar);
+    const float* dpred = f->outb;
+    const int sk = splits_for(pix);
+    // W2, b2
+    SGM_HIP_TRY(gemm(G(1, P, 2, (int)pix, f->hbuf, 0, 1, P, 0, dpred, 0, 2, 1, 1, f->grad + f->oW2, 0, 2, 1, 0.f, sk), s));
+    SGM_HIP_TRY(colsum_f32(dpred, f->grad + f->ob2, pix, 2, s));
+    // dh = dpred W2^T ; dhp = dh gelu'(hp)
+    SGM_HIP_TRY(gemm(G(1, (int)pix, P, 2, dpred, 0, 2, 1, 1, f->W2_16, 0, 1, 2, 0, f->s32, 0, P, 1), s));
+    hipLaunchKernelGGL(k_act_bwd, dim3(nblk(pix * P)), dim3(256), 0, s, (const float*)f->s32, (const bf16*)f->hpz,
+                       f->d16, pix * P, 1);
+    const bf16* alast = f->acts + f->nl * act;
+    SGM_HIP_TRY(gemm(G(1, C, P, (int)pix, alast, 0, 1, C, 0, f->d16, 0, P, 1, 0, f->grad + f->oW1, 0, P, 1, 0.f, sk), s));
+    SGM_HIP_TRY(colsum_bf16(f->d16, f->grad + f->ob1, pix, P, s));
+    // da = dhp W1^T
+    SGM_HIP_TRY(gemm(G(1, (int)pix, C, P, f->d16, 0, P, 1, 0, f->W1_16, 0, 1, P, 0, f->da32, 0, C, 1), s));
+    for (int l = f->nl - 1; l >= 0; --l) {
+        const bf16* aprev = f->acts + l * act;
+        // dz = da gelu'(z)
+        hipLaunchKernelGGL(k_act_bwd, dim3(nblk(pix * C)), dim3(256), 0, s, (const float*)f->da32,
+                           (const bf16*)(f->zsv + l * act), f->d16, pix * C, l < f->nl - 1 ? 1 : 0);
+        const bf16* dz = f->d16;
+        SGM_HIP_TRY(gemm(G(1, C, C, (int)pix, aprev, 0, 1, C, 0, dz, 0, C, 1, 0, f->grad + f->oWp[l], 0, C, 1, 0.f, sk),
+                         s));
+        SGM_HIP_TRY(colsum_bf16(dz, f->grad + f->obp[l], pix, C, s));
+        // da_new = dz Wp^T  (into da32, overwriting: dz already holds the old da)
+        SGM_HIP_TRY(gemm(G(1, (int)pix, C, C, dz, 0, C, 1, 0, f->Wp16 + (long)l * C * C, 0, 1, C, 0, f->da32, 0, C, 1), s));
+        // spectral adjoint: gU[(b,y)] (2K x C) = Gx^T (2K x W) dz[(b,y)] (W x C)
+        SGM_HIP_TRY(gemm(G(B * H, 2 * K, C, W, f->Gx, 0, 1, 2L * K, 0, dz, (long)W * C, C, 1, 0, f->T, 2L * K * C, C, 1), s));
+        // gYt[b] (4K x K C) = Gy_real^T (4K x 2H) gU[b] (2H x K C)
+        SGM_HIP_TRY(gemm(G(B, 4 * K, K * C, 2 * H, f->Gy, 0, 1, 4L * K, 0, f->T, 2L * H * K * C, (long)K * C, 1, 1, f->Yt,
+                           4L * K * K * C, (long)K * C, 1), s));
+        hipLaunchKernelGGL(k_perm_modes, dim3(nblk((long)B * 4 * K * K * C)), dim3(256), 0, s, (const float*)f->Yt, f->Ym,
+                           B, 2 * K, K, C, 0);
+        // dRreal[m] (2C x 2C) = Xm[m]^T (2C x B) gYm[m] (B x 2C)
+        const float* Xm = f->Xm + (long)l * NM * f->Bmax * 2 * C;
+        SGM_HIP_TRY(gemm(G(NM, 2 * C, 2 * C, B, Xm, (long)B * 2 * C, 1, 2 * C, 1, f->Ym, (long)B * 2 * C, 2 * C, 1, 1, f->Rg,
+                           4L * C * C, 2 * C, 1), s));
+        hipLaunchKernelGGL(k_fold_rgrad, dim3(nblk((long)NM * C * C)), dim3(256), 0, s, (const float*)f->Rg,
+                           f->grad + f->oRr[l], f->grad + f->oRi[l], NM, C);
+        // gXm[m] (B x 2C) = gYm[m] (B x 2C) Rreal[m]^T   (into the X buffer, mode-major)
+        SGM_HIP_TRY(gemm(G(NM, B, 2 * C, 2 * C, f->Ym, (long)B * 2 * C, 2 * C, 1, 1, f->Rreal + (long)l * NM * 4 * C * C,
+                           4L * C * C, 1, 2 * C, 0, f->X, (long)B * 2 * C, 2 * C, 1), s));
+        hipLaunchKernelGGL(k_perm_modes, dim3(nblk((long)B * 4 * K * K * C)), dim3(256), 0, s, (const float*)f->X, f->Yt,
+                           B, 2 * K, K, C, 1);
+        // gT[b] (2H x K C) = Fy_real^T (2H x 4K) gX[b] (4K x K C)
+        SGM_HIP_TRY(gemm(G(B, 2 * H, K * C, 4 * K, f->Fy, 0, 1, 2L * H, 0, f->Yt, 4L * K * K * C, (long)K * C, 1, 1, f->T,
+                           2L * H * K * C, (long)K * C, 1), s));
+        // da += Fx^T (W x 2K) gT[(b,y)] (2K x C)
+        SGM_HIP_TRY(gemm(G(B * H, W, C, 2 * K, f->Fx, 0, 1, W, 0, f->T, 2L * K * C, C, 1, 1, f->da32, (long)W * C, C, 1,
+                           1.f), s));
+    }
+    // lift: Wl = x^T da (2 x C), bl = sum da
+    SGM_HIP_TRY(gemm(G(1, 2, C, (int)pix, x, 0, 1, 2, 1, f->da32, 0, C, 1, 1, f->grad + f->oWl, 0, C, 1, 0.f, sk), s));
+    SGM_HIP_TRY(colsum_f32(f->da32, f->grad + f->obl, pix, C, s));
+    return SGM_OK;
+}
+
+extern "C" sgm_status sgm_fno_infer(sgm_fno f, const float* x, float* pred, int batch, void* stream) {
+    clear_error();
+    SGM_CHECK_ARG(f && x && pred, "null argument");
+    SGM_CHECK_ARG(batch >= 1 && batch <= f->Bmax, "batch must be in 1..%d", f->Bmax);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    sgm_status r = refresh_mirrors(f, s);
+    if (r != SGM_OK) return r;
+    if ((r = fno_forward(f, x, batch, s)) != SGM_OK) return r;
+    SGM_HIP_TRY(hipMemcpyAsync(pred, f->predb, 4L * batch * f->H * f->W * 2, hipMemcpyDeviceToDevice, s));
+    return SGM_OK;
+}
+
+extern "C" sgm_status sgm_fno_grads(sgm_fno f, const float* x, const float* target, int batch, float* grads_host,
+                                    float* loss_host, void* stream) {
+    clear_error();
+    SGM_CHECK_ARG(f && x && target, "null argument");
+    SGM_CHECK_ARG(batch >= 1 && batch <= f->Bmax, "batch must be in 1..%d", f->Bmax);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    sgm_status r;
+    if ((r = refresh_mirrors(f, s)) != SGM_OK) return r;
+    if ((r = fno_forward(f, x, batch, s)) != SGM_OK) return r;
+    if ((r = fno_loss(f, target, batch, true, s)) != SGM_OK) return r;
+    if ((r = fno_backward(f, x, batch, s)) != SGM_OK) return r;
+    if (grads_host) SGM_HIP_TRY(hipMemcpyAsync(grads_host, f->grad, 4 * f->npar, hipMemcpyDeviceToHost, s));
+    if (loss_host) {
+        std::vector<float> rel(batch);
+        SGM_HIP_TRY(hipMemcpyAsync(rel.data(), f->rel, 4L * batch, hipMemcpyDeviceToHost, s));
+        SGM_HIP_TRY(hipStreamSynchronize(s));
+        double m = 0;
+        for (float v : rel) m += v;
+        *loss_host = (float)(m / batch);
+    } else {
+        SGM_HIP_TRY(hipStreamSynchronize(s));
+    }
+    return SGM_OK;
+}
+
+extern "C" sgm_status sgm_fno_train_step(sgm_fno f, const float* x, const float* target, int batch, float lr,
+                                         float* loss_host, void* stream) {
+    clear_error();
+    SGM_CHECK_ARG(f && x && target, "null argument");
+    SGM_CHECK_ARG(batch >= 1 && batch <= f->Bmax, "batch must be in 1..%d", f->Bmax);
+    SGM_CHECK_ARG(lr > 0 && std::isfinite(lr), "lr must be positive");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    sgm_status r;
+    if ((r = refresh_mirrors(f, s)) != SGM_OK) return r;
+    if ((r = fno_forward(f, x, batch, s)) != SGM_OK) return r;
+    if ((r = fno_loss(f, target, batch, true, s)) != SGM_OK) return r;
+    if ((r = fno_backward(f, x, batch, s)) != SGM_OK) return r;
+    ++f->step;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - std::pow(b1, (float)f->step), c2 = 1.f - std::pow(b2, (float)f->step);
+    hipLaunchKernelGGL(k_adam, dim3(nblk(f->npar)), dim3(256), 0, s, f->par, (const float*)f->grad, f->mom1, f->mom2,
+                       f->npar, lr, b1, b2, 1e-8f, c1, c2);
+    SGM_HIP_TRY(hipGetLastError());
+    f->mirrors_ok = false;
+    if (loss_host) {
+        std::vector<float> rel(batch);
+        SGM_HIP_TRY(hipMemcpyAsync(rel.data(), f->rel, 4L * batch, hipMemcpyDeviceToHost, s));
+        SGM_HIP_TRY(hipStreamSynchronize(s));
+        double m = 0;
+        for (float v : rel) m += v;
+        *loss_host = (float)(m / batch);
+    }
+    return SGM_OK;
+}
+
+extern "C" sgm_status sgm_fno_rel_l2(sgm_fno f, const float* pred, const float* target, int batch, float* rel_dev,
+                                     void* stream) {
+    clear_error();
+    SGM_CHECK_ARG(f && pred && target && rel_dev, "null argument");
+    SGM_CHECK_ARG(batch >= 1 && batch <= f->Bmax, "batch must be in 1..%d", f->Bmax);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const long per = (long)f->H * f->W * 2;
+    hipLaunchKernelGGL(k_fill_d, dim3(nblk(2L * batch)), dim3(256), 0, s, f->norms, 2L * batch);
+    hipLaunchKernelGGL(k_loss_norms, dim3(64, batch), dim3(256), 0, s, pred, target, per, f->norms, f->norms + batch);
+    hipLaunchKernelGGL(k_loss_grad, dim3(nblk(batch)), dim3(256), 0, s, pred, target, (const double*)f->norms,
+                       (const double*)(f->norms + batch), (float*)nullptr, per, batch, rel_dev);
+    SGM_HIP_TRY(hipGetLastError());
+    return SGM_OK;
+}
+
+extern "C" sgm_status sgm_fno_save(sgm_fno f, const char* path) {
+    clear_error();
+    SGM_CHECK_ARG(f && path, "null argument");
+    std::vector<float> buf(3 * f->npar);
+    SGM_HIP_TRY(hipMemcpy(buf.data(), f->par, 4 * f->npar, hipMemcpyDeviceToHost));
+    SGM_HIP_TRY(hipMemcpy(buf.data() + f->npar, f->mom1, 4 * f->npar, hipMemcpyDeviceToHost));
+    SGM_HIP_TRY(hipMemcpy(buf.data() + 2 * f->npar, f->mom2, 4 * f->npar, hipMemcpyDeviceToHost));
+    FILE* fp = std::fopen(path, "wb");
+    SGM_CHECK_ARG(fp, "cannot open %s", path);
+    const char magic[8] = {'S', 'G', 'M', 'F', 'N', 'O', '1', 0};
+    int64_t hdr[9] = {f->H, f->W, f->C, f->K, f->nl, f->P, f->npar, f->step, 0};
+    bool ok = std::fwrite(magic, 1, 8, fp) == 8 && std::fwrite(hdr, 8, 9, fp) == 9 &&
+              std::fwrite(buf.data(), 4, buf.size(), fp) == buf.size();
+    std::fclose(fp);
+    SGM_CHECK_ARG(ok, "short write to %s", path);
+    return SGM_OK;
+}
+
+extern "C" sgm_status sgm_fno_load(sgm_fno f, const char* path) {
+    clear_error();
+    SGM_CHECK_ARG(f && path, "null argument");
+    FILE* fp = std::fopen(path, "rb");
+    SGM_CHECK_ARG(fp, "cannot open %s", path);
+    char magic[8];
+    int64_t hdr[9];
+    bool ok = std::fread(magic, 1, 8, fp) == 8 && std::memcmp(magic, "SGMFNO1", 7) == 0 && std::fread(hdr, 8, 9, fp) == 9;
+    ok = ok && hdr[0] == f->H && hdr[1] == f->W && hdr[2] == f->C && hdr[3] == f->K && hdr[4] == f->nl &&
+         hdr[5] == f->P && hdr[6] == f->npar;
+    std::vector<float> buf(3 * f->npar);
+    ok = ok && std::fread(buf.data(), 4, buf.size(), fp) == buf.size();
+    std::fclose(fp);
+    SGM_CHECK_ARG(ok, "%s is not a checkpoint of this architecture", path);
+    SGM_HIP_TRY(hipMemcpy(f->par, buf.data(), 4 * f->npar, hipMemcpyHostToDevice));
+    SGM_HIP_TRY(hipMemcpy(f->mom1, buf.data() + f->npar, 4 * f->npar, hipMemcpyHostToDevice));
+    SGM_HIP_TRY(hipMemcpy(f->mom2, buf.data() + 2 * f->npar, 4 * f->npar, hipMemcpyHostToDevice));
+    f->step = hdr[7];
+    f->mirrors_ok = false;
+    return SGM_OK;
+}
+
+// packed complex128 GL states <-> fp32 channels-last input
+extern "C" sgm_status sgm_fno_pack(const void* u_c128, float* x, int64_t n, void* stream) {
+    clear_error();
+    SGM_CHECK_ARG(u_c128 && x && n >= 0, "invalid argument");
+    hipLaunchKernelGGL(k_c128_to_x, dim3(nblk(n)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const double2*>(u_c128), x, (long)n);
+    SGM_HIP_TRY(hipGetLastError());
+    return SGM_OK;
+}
+
+extern "C" sgm_status sgm_fno_unpack(const float* x, void* u_c128, int64_t n, void* stream) {
+    clear_error();
+    SGM_CHECK_ARG(u_c128 && x && n >= 0, "invalid argument");
+    hipLaunchKernelGGL(k_x_to_c128, dim3(nblk(n)), dim3(256), 0, static_cast<hipStream_t>(stream), x,
+                       static_cast<double2*>(u_c128), (long)n);
+    SGM_HIP_TRY(hipGetLastError());
+    return SGM_OK;
+}
+
+extern "C" sgm_status sgm_fno_advance_checked(sgm_fno f, sgm_gl gl, sgm_gl gl_check, void* u_hat, int nsur,
+                                              int steps_per, double tol, uint64_t seed, sgm_fno_stats* stats,
+                                              void* stream) {
+    clear_error();
+    SGM_CHECK_ARG(f && gl && gl_check && u_hat, "null argument");
+    SGM_CHECK_ARG(nsur >= 0 && steps_per >= 1 && tol > 0, "invalid nsur / steps_per / tol");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const long HW = (long)f->H * f->W;
+    // query the packed layout of both batches
+    auto layout = [&](sgm_gl g, std::vector<int64_t>& o) -> sgm_status {
+        int n = 0;
+        sgm_status r = sgm_gl_count(g, &n);
+        if (r != SGM_OK) return r;
+        o.assign((size_t)n + 1, 0);
+        return sgm_gl_offsets(g, o.data());
+    };
+    std::vector<int64_t> om, oc;
+    sgm_status r;
+    if ((r = layout(gl, om)) != SGM_OK) return r;
+    if ((r = layout(gl_check, oc)) != SGM_OK) return r;
+    const int B = (int)om.size() - 1, NC = (int)oc.size() - 1;
+    for (int i = 0; i < B; ++i)
+        SGM_CHECK_ARG(om[i + 1] - om[i] == HW, "problem %d of gl is not %d x %d", i, f->H, f->W);
+    for (int i = 0; i < NC; ++i)
+        SGM_CHECK_ARG(oc[i + 1] - oc[i] == HW, "problem %d of gl_check is not %d x %d", i, f->H, f->W);
+    SGM_CHECK_ARG(NC >= 1 && NC <= B, "gl_check must hold between 1 and B problems");
+    // workspace: phys c128 [B HW], x fp32 [B HW 2], pred fp32 [B HW 2], chk c128 [NC HW] x2, xs fp32 [NC HW 2],
+    // ps fp32 [NC HW 2], rel [NC]
+    const long need = B;
+    if (f->adv_cap < need) {
+        hipFree(f->adv);
+        f->adv = nullptr;
+        size_t bytes = (size_t)B * HW * (16 + 8 + 8) + (size_t)NC * HW * (16 + 16 + 8 + 8) + 4096;
+        SGM_HIP_TRY(hipMalloc(&f->adv, bytes));
+        f->adv_cap = need;
+    }
+    char* w = static_cast<char*>(f->adv);
+    double2* phys = reinterpret_cast<double2*>(w); w += (size_t)B * HW * 16;
+    float* x = reinterpret_cast<float*>(w); w += (size_t)B * HW * 8;
+    float* pred = reinterpret_cast<float*>(w); w += (size_t)B * HW * 8;
+    double2* chk = reinterpret_cast<double2*>(w); w += (size_t)NC * HW * 16;
+    double2* chkp = reinterpret_cast<double2*>(w); w += (size_t)NC * HW * 16;
+    float* xs = reinterpret_cast<float*>(w); w += (size_t)NC * HW * 8;
+    float* ps = reinterpret_cast<float*>(w); w += (size_t)NC * HW * 8;
+    float* reld = reinterpret_cast<float*>(w);
+    double2* uh = static_cast<double2*>(u_hat);
+    std::mt19937_64 rng(seed);
+    double sum_rel = 0;
+    int nchk_total = 0, nfb_total = 0;
+    float maxrel = 0.f;
+    const int stride = B / NC;
+    for (int it = 0; it < nsur; ++it) {
+        const int offs = (int)(rng() % (uint64_t)stride);
+        std::vector<int> idx(NC);
+        for (int k = 0; k < NC; ++k) idx[k] = offs + k * stride;
+        // surrogate prediction for every sample
+        if ((r = sgm_gl_backward(gl, uh, phys, s)) != SGM_OK) return r;
+        if ((r = sgm_fno_pack(phys, x, (int64_t)B * HW, s)) != SGM_OK) return r;
+        for (int b0 = 0; b0 < B; b0 += f->Bmax) {
+            const int nb = std::min(f->Bmax, B - b0);
+            if ((r = sgm_fno_infer(f, x + (long)b0 * HW * 2, pred + (long)b0 * HW * 2, nb, s)) != SGM_OK) return r;
+        }
+        // FP64 solver on the checked subset
+        for (int k = 0; k < NC; ++k)
+            SGM_HIP_TRY(hipMemcpyAsync(chk + (long)k * HW, uh + (long)idx[k] * HW, HW * 16, hipMemcpyDeviceToDevice, s));
+        if ((r = sgm_gl_step(gl_check, chk, steps_per, s)) != SGM_OK) return r;
+        if ((r = sgm_gl_backward(gl_check, chk, chkp, s)) != SGM_OK) return r;
+        if ((r = sgm_fno_pack(chkp, xs, (int64_t)NC * HW, s)) != SGM_OK) return r;
+        for (int k = 0; k < NC; ++k)
+            SGM_HIP_TRY(hipMemcpyAsync(ps + (long)k * HW * 2, pred + (long)idx[k] * HW * 2, HW * 8,
+                                       hipMemcpyDeviceToDevice, s));
+        for (int b0 = 0; b0 < NC; b0 += f->Bmax) {
+            const int nb = std::min(f->Bmax, NC - b0);
+            if ((r = sgm_fno_rel_l2(f, ps + (long)b0 * HW * 2, xs + (long)b0 * HW * 2, nb, reld + b0, s)) != SGM_OK)
+                return r;
+        }
+        std::vector<float> rel(NC);
+        SGM_HIP_TRY(hipMemcpyAsync(rel.data(), reld, 4L * NC, hipMemcpyDeviceToHost, s));
+        SGM_HIP_TRY(hipStreamSynchronize(s));
+        // new state: transform the surrogate's fields, then overwrite failed checks with the solver
+        if ((r = sgm_fno_unpack(pred, phys, (int64_t)B * HW, s)) != SGM_OK) return r;
+        if ((r = sgm_gl_forward(gl, phys, uh, s)) != SGM_OK) return r;
+        for (int k = 0; k < NC; ++k) {
+            sum_rel += rel[k];
+            maxrel = std::max(maxrel, rel[k]);
+            if (!(rel[k] <= tol)) {
+                ++nfb_total;
+                SGM_HIP_TRY(hipMemcpyAsync(uh + (long)idx[k] * HW, chk + (long)k * HW, HW * 16, hipMemcpyDeviceToDevice,
+                                           s));
+            }
+        }
+        nchk_total += NC;
+    }
+    if (stats) {
+        stats->n_checked += nchk_total;
+        stats->n_fallback += nfb_total;
+        stats->max_rel_l2 = std::max(stats->max_rel_l2, maxrel);
+        stats->mean_rel_l2 = nchk_total ? (float)(sum_rel / nchk_total) : 0.f;
+    }
+    return SGM_OK;
+}

@@ -574,6 +574,13 @@ extern "C" sgm_status sgm_gl_create(const sgm_gl_desc* desc, sgm_gl* out) {
     return SGM_OK;
 }
 
+extern "C" sgm_status sgm_gl_count(sgm_gl g, int* count) {
+    clear_error();
+    SGM_CHECK_ARG(g && count, "null argument");
+    *count = (int)g->N.size();
+    return SGM_OK;
+}
+
 extern "C" sgm_status sgm_gl_offsets(sgm_gl g, int64_t* offsets) {
     clear_error();
     SGM_CHECK_ARG(g && offsets, "null argument");

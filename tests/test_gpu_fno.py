@@ -1,0 +1,104 @@
+"""GPU FNO surrogate kernels against the FP64 oracle (bf16 weights/inputs on both sides)."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import fno as ofno
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def FNO():
+    from paper_1708_03188_amd.api import FNO
+    return FNO
+
+
+CFG = dict(H=32, W=32, width=8, modes=4, layers=2, hidden=16)
+
+
+def _setup(FNO, B=3, seed=0, cfg=CFG):
+    f = FNO(cfg["H"], cfg["W"], cfg["width"], cfg["modes"], cfg["layers"], cfg["hidden"], max_batch=max(B, 4), seed=seed)
+    p = ofno.init_params(cfg["width"], cfg["modes"], cfg["hidden"], cfg["layers"], seed, scale_spec=0.3)
+    rng = np.random.default_rng(seed + 7)
+    for k in p:
+        if k.startswith("b"):
+            p[k] = 0.05 * rng.standard_normal(p[k].shape)
+    p = {k: ofno.round_bf16(v) for k, v in p.items()}
+    f.set_params(p)
+    x = ofno.round_bf16(rng.standard_normal((B, cfg["H"], cfg["W"], 2)) * 0.5)
+    t = x + 0.2 * rng.standard_normal(x.shape)
+    return f, p, x, t
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def test_forward_matches_oracle(FNO):
+    f, p, x, t = _setup(FNO)
+    got = f.infer(_dev(x)).cpu().numpy().astype(np.float64)
+    ref = ofno.forward(p, x, CFG["modes"])
+    # bf16 activations: compare the network output (pred - x) relative to its size
+    e = np.linalg.norm(got - ref) / np.linalg.norm(ref - x)
+    print("fno forward rel err (net output)", e)
+    assert e < 3e-2
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-2
+
+
+def test_gradients_match_oracle(FNO):
+    f, p, x, t = _setup(FNO, seed=1)
+    g, loss = f.grads(_dev(x), _dev(t))
+    pred, cache = ofno.forward(p, x, CFG["modes"], keep=True)
+    ref_loss = ofno.loss(pred, t)
+    gr = ofno.backward(p, x, CFG["modes"], cache, ofno.loss_grad(pred, t))
+    assert abs(loss - ref_loss) < 1e-2 * ref_loss
+    worst = 0.0
+    for k in gr:
+        e = np.linalg.norm(g[k] - gr[k]) / max(np.linalg.norm(gr[k]), 1e-30)
+        worst = max(worst, e)
+        print(f"grad {k}: rel {e:.3e}")
+        assert e < 5e-2, k
+    print("worst grad rel err", worst)
+
+
+def test_training_reduces_loss_and_checkpoint_roundtrip(FNO):
+    # a learnable target: the output of a teacher network of the same architecture
+    f, p, x, _ = _setup(FNO, B=4, seed=2)
+    teacher = ofno.init_params(CFG["width"], CFG["modes"], CFG["hidden"], CFG["layers"], 99, scale_spec=0.3)
+    teacher["W2"] *= 10.0
+    t = ofno.forward(teacher, x, CFG["modes"])
+    xd, td = _dev(x), _dev(t)
+    l0 = f.train_step(xd, td, 3e-3)
+    for _ in range(80):
+        l = f.train_step(xd, td, 3e-3)
+    assert l < 0.5 * l0, (l0, l)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "ck.bin")
+        f.save(path)
+        before = f.infer(xd).cpu().numpy()
+        f.train_step(xd, td, 1e-3)
+        f.load(path)
+        after = f.infer(xd).cpu().numpy()
+        assert np.array_equal(before, after)
+
+
+def test_zero_output_layer_gives_identity(FNO):
+    f, p, x, t = _setup(FNO, seed=3)
+    p["W2"][:] = 0
+    p["b2"][:] = 0
+    f.set_params(p)
+    assert np.array_equal(f.infer(_dev(x)).cpu().numpy(), x.astype(np.float32))
+
+
+def test_pack_unpack_states():
+    from paper_1708_03188_amd.api import pack_states, unpack_states
+    u = torch.randn(3, 8, 8, dtype=torch.complex128, device="cuda")
+    x = pack_states(u)
+    assert torch.allclose(x[..., 0].double(), u.real, atol=1e-6)
+    assert torch.allclose(x[..., 1].double(), u.imag, atol=1e-6)
+    back = unpack_states(x)
+    assert torch.allclose(back, u, atol=1e-6)
