@@ -32,6 +32,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true", help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--legs", default="transforms,biharmonic,gl,surrogate",
+                    help="comma list of measured legs (the transform leg always runs)")
     return ap.parse_args()
 
 
@@ -51,6 +53,50 @@ def pass_bytes(N, M1, M2, nb):
         "cheb_bwd": specnb + spec,         # rows >= nb are not read
         "solve": specnb + spec,
     }
+
+
+VARIANT_GEO = {0: (32, 2), 1: (32, 1), 2: (16, 2), 3: (16, 1)}
+PASS_KERNEL = {"last_fwd": ("kr_lines_r2c", 2), "last_bwd": ("kr_lines_c2r", 2), "mid_fwd": ("kr_strided", 1),
+               "mid_bwd": ("kr_strided", 1), "cheb_fwd": ("kr_cheb_fwd", 0), "cheb_bwd": ("kr_cheb_bwd", 0)}
+
+
+def kernel_source_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    # the transform-pass kernels only (device code the counters measured)
+    files = ["kernels_reg.hip", "fft_reg.h", "fft_lds.h", "kernels.h", "kernels_reg.h", "common.h"]
+    for f in [os.path.join(ROOT, "paper_1708_03188_amd", "csrc", n) for n in files]:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(pass_name, variants, L):
+    """HBM bytes per launch of the pass's kernel from the committed counter summary,
+    or None if the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_256cube_dirichlet.md")
+    if pass_name not in PASS_KERNEL or not os.path.exists(path):
+        return None
+    name, axis = PASS_KERNEL[pass_name]
+    v = variants[axis]
+    if v < 0:
+        return None
+    nt, nb = VARIANT_GEO[v]
+    with open(path) as fh:
+        txt = fh.read()
+    if f"kernel-source hash: {kernel_source_hash()}" not in txt:
+        return None
+    sign = ""
+    if name == "kr_strided":
+        sign = ", -1>" if pass_name == "mid_fwd" else ", 1>"
+    key = f"sgm::{name}<{L}, sgm::Geo<{L}, {nt}, {nb}>"
+    for line in txt.splitlines():
+        if key in line and (not sign or line.split("|")[1].strip().endswith(sign)) and \
+                (name != "kr_cheb_fwd" or line.split("|")[1].strip().endswith(", 3>")):
+            cells = [c.strip() for c in line.split("|")]
+            return float(cells[4]) * 1e6
+    return None
 
 
 def cpu_baseline(N, M1, M2):
@@ -86,6 +132,102 @@ def cpu_baseline(N, M1, M2):
                   f"{kr} of {N} x-rows ({t_rows:.1f} s) of the same 256^3 field, extrapolated linearly "
                   f"to the full transform pair ({t_full:.0f} s)",
     }
+
+
+def _timed(fn, reps):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def leg_biharmonic(steps):
+    """512 x 256 x 256 Shen-biharmonic space: transform pair and biharmonic solves."""
+    import torch
+    import synth
+    from paper_1708_03188_amd.api import Plan
+    N, M1, M2 = 512, 256, 256
+    p = Plan("biharmonic", N, M1, M2, autotune=True)
+    _, _, _, u0, f0 = synth.biharmonic3d_manufactured(N, M1, M2)
+    u = torch.from_numpy(u0 + synth.random_smooth_field((N, M1, M2), seed=3, rank=2) * 1e-3).cuda()
+    f = torch.from_numpy(f0).cuda()
+    uh = torch.empty(p.spec_shape, dtype=torch.complex128, device="cuda")
+    v = torch.empty_like(u)
+    ms = _timed(lambda: (p.forward(u, out=uh), p.backward(uh, out=v)), max(5, steps // 5))
+    ft = p.scalar_product(f)
+    sol = torch.empty_like(ft)
+    ms_s = _timed(lambda: p.biharmonic_solve(ft, out=sol), max(5, steps // 5))
+    dof = N * M1 * M2
+    M2r = M2 // 2 + 1
+    pair_bytes = 2 * dof * 8 + 2 * N * M1 * M2r * 16
+    solve_bytes = 2 * (N - 4) * M1 * M2r * 16
+    return {"workload": "Shen-biharmonic N=512 x Fourier 256x256 R2C, float64",
+            "fwd_bwd_Gdofs": round(dof / (ms * 1e-3) / 1e9, 3), "ms_fwd_bwd": round(ms, 4),
+            "fwd_bwd_hbm_frac": round(pair_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "biharmonic_solves_per_s": round(1e3 / ms_s, 1),
+            "solve_hbm_frac": round(solve_bytes / (ms_s * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def leg_gl(steps):
+    """64 ragged Ginzburg-Landau problems N_i = 128..512, IF-RK4, dt 0.05, hipGraph steps."""
+    import torch
+    import synth
+    from paper_1708_03188_amd.api import GLBatch
+    sizes = synth.gl_ragged_sizes(64)
+    g = GLBatch(sizes, L=100.0, b=1.5, c=-2.0, dt=0.05, scheme="ifrk4", graph=True)
+    u = g.forward(g.pack([synth.gl_noise(n, 4000 + i) for i, n in enumerate(sizes)]))
+    reps = max(10, steps // 2)
+    ms = _timed(lambda: g.step(u, 1), reps)
+    modes = sum(n * n for n in sizes)
+    comp = 160 * modes  # compulsory bytes per IF-RK4 step: stage inputs/outputs and state
+    return {"workload": "64 ragged complex GL problems (N_i = 128,192,256,384,512), IF-RK4 dt=0.05, 3/2 rule",
+            "batch_steps_per_s": round(1e3 / ms, 1), "ms_per_step": round(ms, 4),
+            "problem_steps_per_s": round(64 * 1e3 / ms, 1),
+            "compulsory_hbm_frac": round(comp / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def leg_surrogate():
+    """FNO surrogate at 256^2 vs the plain FP64 solver (reduced-size C5 training set)."""
+    import time
+    import torch
+    import synth
+    from paper_1708_03188_amd.api import FNO, GLBatch
+    from paper_1708_03188_amd import surrogate as S
+    N, L, b, c, dt, stride = 256, 100.0, 1.5, -2.0, 0.05, 10
+    t0 = time.perf_counter()
+    train_data = S.generate_trajectories(64, 20, N, L=L, b=b, c=c, dt=dt, stride=stride, seed=5000)
+    test_data = S.generate_trajectories(8, 8, N, L=L, b=b, c=c, dt=dt, stride=stride, seed=5600)
+    t_gen = time.perf_counter() - t0
+    f = FNO(N, N, width=32, modes=16, layers=4, hidden=128, max_batch=16, seed=5)
+    t0 = time.perf_counter()
+    S.train(f, train_data, steps=600, batch=8, lr=2e-3)
+    t_train = time.perf_counter() - t0
+    mean, mx = S.evaluate(f, test_data)
+    ident, _ = S.identity_error(test_data)
+    B = 64
+    gl = GLBatch([N] * B, L=L, b=b, c=c, dt=dt, scheme="ifrk4")
+    glc = GLBatch([N] * 4, L=L, b=b, c=c, dt=dt, scheme="ifrk4")
+    u = gl.forward(gl.pack([synth.gl_noise(N, 9000 + i) for i in range(B)]))
+    gl.step(u, 200)
+    ms_plain = _timed(lambda: gl.step(u, stride), 5) / stride
+    stats = {}
+    ms_sur = _timed(lambda: stats.update(f.advance_checked(gl, glc, u, 1, stride, tol=1e-2, seed=1)), 5) / stride
+    return {"workload": "GL 256^2 (L=100, b=1.5, c=-2, dt=0.05), FNO width 32, 16x16 modes, 4 layers, bf16 MFMA; "
+                        "trained on 64 trajectories x 20 snapshots (10-step stride) from the FP64 solver",
+            "plain_problem_steps_per_s": round(B * 1e3 / ms_plain, 1),
+            "surrogate_problem_steps_per_s": round(B * 1e3 / ms_sur, 1),
+            "speedup": round(ms_plain / ms_sur, 3),
+            "heldout_rel_l2_mean": round(mean, 4), "heldout_rel_l2_max": round(mx, 4),
+            "persistence_rel_l2_mean": round(ident, 4),
+            "check_fraction": 4 / B, "last_call_checks": stats,
+            "data_gen_s": round(t_gen, 2), "train_s": round(t_train, 2), "train_steps": 600}
 
 
 def main():
@@ -181,12 +323,21 @@ def main():
                                "float64; step = forward + backward transform",
                    "N": N, "M1": M1, "M2": M2, "basis": "shen_dirichlet", "kind_last": "r2c"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dom, p.variants(), N), "algorithmic_bytes": nbytes[dom]},
+        "plan_variants_xyz": p.variants(),
         "passes": {k: {kk: round(vv, 2) for kk, vv in d.items()} for k, d in per_pass.items()},
         "helmholtz_solves_per_s": round(1e3 / ms_solve, 1),
         "poisson_pipeline_solves_per_s": round(1e3 / ms_poisson, 1),
         "transform_pair_algorithmic_GBps": round((2 * dof * 8 + 2 * N * M1 * (M2 // 2 + 1) * 16) / (ms * 1e-3) / 1e9, 1),
     }
+    legs = set(args.legs.split(","))
+    if "biharmonic" in legs:
+        out["biharmonic_512x256x256"] = leg_biharmonic(args.steps)
+    if "gl" in legs:
+        out["gl_ragged_batch"] = leg_gl(args.steps)
+    if "surrogate" in legs:
+        out["surrogate_256"] = leg_surrogate()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, M1, M2)
     print(json.dumps(out))

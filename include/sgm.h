@@ -120,6 +120,9 @@ sgm_status sgm_biharmonic_solve(sgm_plan plan, const void* f_tilde, void* u_hat,
  * last reset) and, if reset != 0, clears the totals afterwards. */
 #define SGM_NPASS 8
 sgm_status sgm_plan_timing(sgm_plan plan, int enable);
+/* Register-kernel variant in use per axis (x, y, z): 0..3, or -1 where the axis runs
+ * the generic LDS kernels (diagnostics; chosen at creation, see autotune). */
+sgm_status sgm_plan_variants(sgm_plan plan, int variant[3]);
 sgm_status sgm_plan_pass_times(sgm_plan plan, double ms[SGM_NPASS], int64_t count[SGM_NPASS], int reset);
 
 /* ---- Complex Ginzburg-Landau, ragged batch (Sec. 6) ------------------------------

@@ -56,6 +56,7 @@ _SIGS = {
     "sgm_helmholtz_solve": ([_vp, ctypes.c_double, _vp, _vp, _vp], ctypes.c_int),
     "sgm_biharmonic_solve": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "sgm_plan_timing": ([_vp, ctypes.c_int], ctypes.c_int),
+    "sgm_plan_variants": ([_vp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "sgm_gl_create": ([ctypes.POINTER(GLDesc), ctypes.POINTER(_vp)], ctypes.c_int),
     "sgm_gl_destroy": ([_vp], ctypes.c_int),
     "sgm_gl_offsets": ([_vp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),

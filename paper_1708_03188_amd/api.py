@@ -67,6 +67,12 @@ class Plan:
         """Bracket every pass kernel of this plan with hipEvents (diagnostics)."""
         check(self._lib.sgm_plan_timing(self._h, int(bool(enable))), "sgm_plan_timing")
 
+    def variants(self):
+        """Register-kernel variant per axis (x, y, z); -1 = generic kernels."""
+        v = (ctypes.c_int * 3)()
+        check(self._lib.sgm_plan_variants(self._h, v), "sgm_plan_variants")
+        return list(v)
+
     def pass_times(self, reset=False):
         """{pass name: (total ms, launches)} accumulated since the last reset."""
         ms = (ctypes.c_double * _lib.NPASS)()

@@ -359,6 +359,15 @@ sgm_status sgm_plan_timing(sgm_plan p, int enable) {
     return SGM_OK;
 }
 
+sgm_status sgm_plan_variants(sgm_plan p, int variant[3]) {
+    clear_error();
+    SGM_CHECK_ARG(p && variant, "null argument");
+    variant[0] = p->hx ? p->rkx.variant : -1;
+    variant[1] = p->hy ? p->rky.variant : -1;
+    variant[2] = p->hz ? p->rkz.variant : -1;
+    return SGM_OK;
+}
+
 sgm_status sgm_plan_pass_times(sgm_plan p, double ms[SGM_NPASS], int64_t count[SGM_NPASS], int reset) {
     clear_error();
     SGM_CHECK_ARG(p && ms && count, "null argument");
