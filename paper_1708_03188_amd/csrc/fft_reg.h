@@ -22,9 +22,10 @@ struct Sched {
 constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
 constexpr int clcm(int a, int b) { return a / cgcd(a, b) * b; }
 
-// Radix schedule: 3s first, then 8s, with one 4 or 2 for the remaining power of two.
-// E = lcm(radices) * 2^j, the smallest such that NT = L/E <= NTMAX.
-constexpr Sched make_sched(int L, int NTMAX) {
+// Radix schedule: 3s first, then 8s (or 4s when MAXR = 4), with one 4 or 2 for the
+// remaining power of two.  E = lcm(radices) * 2^j, the smallest such that
+// NT = L/E <= NTMAX.
+constexpr Sched make_sched(int L, int NTMAX, int MAXR = 8) {
     Sched s{};
     s.L = L;
     int a = 0, b = 0, r = L;
@@ -33,11 +34,16 @@ constexpr Sched make_sched(int L, int NTMAX) {
     if (r != 1) { s.nst = -1; return s; }
     int n = 0;
     for (int i = 0; i < b; ++i) s.rad[n++] = 3;
-    int r8 = a / 3, rem = a % 3;
-    if (rem == 1 && r8 > 0) { --r8; s.rad[n++] = 4; s.rad[n++] = 4; }
-    else if (rem == 1) s.rad[n++] = 2;
-    else if (rem == 2) s.rad[n++] = 4;
-    for (int i = 0; i < r8; ++i) s.rad[n++] = 8;
+    if (MAXR >= 8) {
+        int r8 = a / 3, rem = a % 3;
+        if (rem == 1 && r8 > 0) { --r8; s.rad[n++] = 4; s.rad[n++] = 4; }
+        else if (rem == 1) s.rad[n++] = 2;
+        else if (rem == 2) s.rad[n++] = 4;
+        for (int i = 0; i < r8; ++i) s.rad[n++] = 8;
+    } else {
+        for (int i = 0; i < a / 2; ++i) s.rad[n++] = 4;
+        if (a % 2) s.rad[n++] = 2;
+    }
     s.nst = n;
     int E = 1;
     for (int i = 0; i < n; ++i) E = clcm(E, s.rad[i]);
@@ -55,10 +61,10 @@ constexpr int sched_m(const Sched& s, int S) {
 
 // Exchange buffer addressing for one line: position v lives at base[v * ps].
 // Stages alternate between two buffers so one barrier per exchange suffices.
-template <int L, int NTMAX, int SIGN, int S, int NBUF>
+template <int L, int NTMAX, int SIGN, int S, int NBUF, int MAXR>
 __device__ __forceinline__ void reg_stages(double2* x, double2* b0, double2* b1, int ps, int t,
                                            const double2* __restrict__ tw, bool act) {
-    constexpr Sched sd = make_sched(L, NTMAX);
+    constexpr Sched sd = make_sched(L, NTMAX, MAXR);
     if constexpr (S < sd.nst) {
         constexpr int p = sd.rad[S];
         constexpr int m = sched_m(sd, S);
@@ -99,7 +105,7 @@ __device__ __forceinline__ void reg_stages(double2* x, double2* b0, double2* b1,
             }
             // one buffer: every thread must have read it before the next stage writes
             if constexpr (NBUF == 1 && S + 1 < sd.nst - 1) __syncthreads();
-            reg_stages<L, NTMAX, SIGN, S + 1, NBUF>(x, b0, b1, ps, t, tw, act);
+            reg_stages<L, NTMAX, SIGN, S + 1, NBUF, MAXR>(x, b0, b1, ps, t, tw, act);
         }
     }
 }
@@ -110,10 +116,10 @@ __device__ __forceinline__ void reg_stages(double2* x, double2* b0, double2* b1,
 // Threads with act == false take part in the barriers only (no LDS traffic);
 // their x is left undefined.  NBUF = 2 alternates two exchange buffers (one
 // barrier per exchange); NBUF = 1 reuses b0 (two barriers, half the LDS).
-template <int L, int NTMAX, int SIGN, int NBUF = 2>
+template <int L, int NTMAX, int SIGN, int NBUF = 2, int MAXR = 8>
 __device__ __forceinline__ void reg_fft(double2* x, double2* b0, double2* b1, int ps, int t,
                                         const double2* __restrict__ tw, bool act = true) {
-    reg_stages<L, NTMAX, SIGN, 0, NBUF>(x, b0, b1, ps, t, tw, act);
+    reg_stages<L, NTMAX, SIGN, 0, NBUF, MAXR>(x, b0, b1, ps, t, tw, act);
 }
 
 }  // namespace sgm

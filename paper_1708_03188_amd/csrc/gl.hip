@@ -24,18 +24,25 @@
 namespace sgm {
 
 constexpr int kGlThreads = 256;
-constexpr int kGlNTMAX = 32;
-constexpr int kGlLds = 131072;
 
 constexpr int gmin(int a, int b) { return a < b ? a : b; }
 
+// GL launch geometry, chosen by measurement on the ragged batch: radices <= 4
+// (12 points per thread for the 3-smooth padded lengths), up to 64 threads per
+// line, one exchange buffer, at most 64 KB of LDS per block.
+constexpr int kGlNTMAX = 64;
+constexpr int kGlMaxR = 4;
+constexpr int kGlNB = 1;
+constexpr int kGlLds = 65536;
+
 template <int M>
 struct GGeo {
-    static constexpr Sched sd = make_sched(M, kGlNTMAX);
+    static constexpr Sched sd = make_sched(M, kGlNTMAX, kGlMaxR);
     static constexpr int NT = sd.NT;
     static constexpr int E = sd.E;
-    static constexpr int W = gmin(kGlThreads / NT, kGlLds / (32 * M)) > 0 ? gmin(kGlThreads / NT, kGlLds / (32 * M)) : 1;
+    static constexpr int W = gmin(kGlThreads / NT, kGlLds / (16 * kGlNB * M)) > 0 ? gmin(kGlThreads / NT, kGlLds / (16 * kGlNB * M)) : 1;
     static constexpr int THREADS = W * NT;
+    static constexpr int B1OFF = kGlNB == 2 ? W * M : 0;
 };
 
 struct GLProb {
@@ -143,7 +150,7 @@ __device__ __attribute__((noinline)) void rows_inv_reg(const GLProb& pr, int lin
         const int l = gwn(q, M);
         x[e] = (act && kept(l, N)) ? src[pr.off_s + (long)row * N + nidx(l, N)] : make_double2(0.0, 0.0);
     }
-    reg_fft<M, kGlNTMAX, 1>(x, lds + g * M, lds + (G::W + g) * M, 1, t, pr.rp.tw, act);
+    reg_fft<M, kGlNTMAX, 1, kGlNB, kGlMaxR>(x, lds + g * M, lds + G::B1OFF + g * M, 1, t, pr.rp.tw, act);
     if (act) {
 #pragma unroll
         for (int e = 0; e < G::E; ++e) work[pr.off_w + (long)row * M + t + G::NT * e] = x[e];
@@ -164,7 +171,7 @@ __device__ __attribute__((noinline)) void cols_reg(const GLProb& pr, int line0, 
         const int l = gwn(q, M);
         x[e] = (act && kept(l, N)) ? work[pr.off_w + (long)nidx(l, N) * M + y] : make_double2(0.0, 0.0);
     }
-    reg_fft<M, kGlNTMAX, 1>(x, lds + c, lds + M * G::W + c, G::W, t, pr.rp.tw, act);
+    reg_fft<M, kGlNTMAX, 1, kGlNB, kGlMaxR>(x, lds + c, lds + G::B1OFF + c, G::W, t, pr.rp.tw, act);
 #pragma unroll
     for (int e = 0; e < G::E; ++e) {
         const double2 u = x[e];
@@ -173,7 +180,7 @@ __device__ __attribute__((noinline)) void cols_reg(const GLProb& pr, int line0, 
         x[e] = make_double2(r2 * (u.x - cnl * u.y), r2 * (u.y + cnl * u.x));
     }
     __syncthreads();
-    reg_fft<M, kGlNTMAX, -1>(x, lds + c, lds + M * G::W + c, G::W, t, pr.rp.tw, act);
+    reg_fft<M, kGlNTMAX, -1, kGlNB, kGlMaxR>(x, lds + c, lds + G::B1OFF + c, G::W, t, pr.rp.tw, act);
     if (act) {
         const double s = 1.0 / M;
 #pragma unroll
@@ -196,7 +203,7 @@ __device__ __attribute__((noinline)) void rows_fwd_reg(const GLProb& pr, int lin
 #pragma unroll
     for (int e = 0; e < G::E; ++e)
         x[e] = act ? work[pr.off_w + (long)row * M + t + G::NT * e] : make_double2(0.0, 0.0);
-    reg_fft<M, kGlNTMAX, -1>(x, lds + g * M, lds + (G::W + g) * M, 1, t, pr.rp.tw, act);
+    reg_fft<M, kGlNTMAX, -1, kGlNB, kGlMaxR>(x, lds + g * M, lds + G::B1OFF + g * M, 1, t, pr.rp.tw, act);
     if (act) {
         const double s = -1.0 / M;
 #pragma unroll
@@ -467,12 +474,13 @@ extern "C" sgm_status sgm_gl_create(const sgm_gl_desc* desc, sgm_gl* out) {
         int W = pr.kind >= 0 ? reg_w(pr.kind) : std::max(1, std::min(16, 4096 / pr.M));
         pr.wrows = W;
         pr.wcols = W;
+        const size_t lds_reg = sizeof(double2) * (size_t)kGlNB * W * pr.M;
         pr.off_s = g->off_s[i];
         pr.off_w = g->off_w[i];
         pr.off_e = g->off_e[i];
         pr.rp.L = pr.M;
         pr.rp.nst = factor_radices(pr.M, pr.rp.radix);
-        size_t lds = 2 * sizeof(double2) * (size_t)W * pr.M;
+        size_t lds = pr.kind >= 0 ? lds_reg : 2 * sizeof(double2) * (size_t)W * pr.M;
         const int gk = pr.kind < 0 ? 1 : 0;
         g->lds[gk] = std::max(g->lds[gk], lds);
         (void)maxlA; (void)maxlB;

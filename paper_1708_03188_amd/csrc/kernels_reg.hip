@@ -198,8 +198,11 @@ __global__ void __launch_bounds__(kThreads) kr_cheb_fwd(const double2* in, doubl
                                                         const double2* __restrict__ tw) {
     constexpr int W = G::W, NT = G::NT, E = G::E;
     extern __shared__ double2 lds[];
+    // one N x W tile (B0), a second one only as the FFT's other exchange buffer,
+    // then 2 NT x W scratch entries for the reductions
     double2* B0 = lds;
-    double2* B1 = lds + N * W;  // second tile buffer (the LDS always holds two N x W tiles here)
+    double2* B1 = lds + G::B1OFF;
+    double2* SC = lds + G::NB * N * W;
     const int c = threadIdx.x % W, t = threadIdx.x / W;
     const int c0 = blockIdx.x * W;
     const bool ok = c0 + c < ncols;
@@ -209,7 +212,7 @@ __global__ void __launch_bounds__(kThreads) kr_cheb_fwd(const double2* in, doubl
         const int v = t + NT * e;
         x[e] = ok ? in[(long)makhoul_row(v, N) * ncols + c0 + c] : make_double2(0.0, 0.0);
     }
-    reg_fft<N, G::NTMAX, -1, G::NB>(x, B0 + c, (G::NB == 2 ? B1 : B0) + c, W, t, tw);
+    reg_fft<N, G::NTMAX, -1, G::NB>(x, B0 + c, B1 + c, W, t, tw);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) B0[(t + NT * e) * W + c] = x[e];
@@ -228,10 +231,11 @@ __global__ void __launch_bounds__(kThreads) kr_cheb_fwd(const double2* in, doubl
         double2 tk = th[k];
         x[e] = make_double2(tk.x * a.x - tk.y * a.y, tk.x * b.x - tk.y * b.y);  // C_k
     }
+    __syncthreads();  // every V read before B0 is reused
     const int nb = cd.nb;
     if constexpr (MODE == kScalarProduct) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) B1[(t + NT * e) * W + c] = x[e];
+        for (int e = 0; e < E; ++e) B0[(t + NT * e) * W + c] = x[e];
         __syncthreads();
         const double s = M_PI / N;
 #pragma unroll
@@ -240,8 +244,8 @@ __global__ void __launch_bounds__(kThreads) kr_cheb_fwd(const double2* in, doubl
             double2 v = make_double2(0.0, 0.0);
             if (l < nb) {
                 v = x[e];
-                if (l + 2 < N) { double bb = cd.beta[l]; double2 u = B1[(l + 2) * W + c]; v.x += bb * u.x; v.y += bb * u.y; }
-                if (l + 4 < N) { double gg = cd.gamma[l]; double2 u = B1[(l + 4) * W + c]; v.x += gg * u.x; v.y += gg * u.y; }
+                if (l + 2 < N) { double bb = cd.beta[l]; double2 u = B0[(l + 2) * W + c]; v.x += bb * u.x; v.y += bb * u.y; }
+                if (l + 4 < N) { double gg = cd.gamma[l]; double2 u = B0[(l + 4) * W + c]; v.x += gg * u.x; v.y += gg * u.y; }
                 v = cscale(v, s);
             }
             if (ok) out[(long)l * ncols + c0 + c] = v;
@@ -253,8 +257,8 @@ __global__ void __launch_bounds__(kThreads) kr_cheb_fwd(const double2* in, doubl
             if (ok) out[(long)k * ncols + c0 + c] = cscale(x[e], cd.fscale[k]);
         }
     } else if constexpr (MODE == kProjDirichlet) {
-        // c_k = fscale_k C_k; per parity p: lambda_p = (sum_k c_k) / (sum_k 1/c_k-weights);
-        // c*_k = c_k - lambda_p / ck;  u_l = sum_{k <= l, k = l mod 2} c*_k  (prefix sum).
+        // c_k = fscale_k C_k; per parity p: lambda_p = (sum_k c_k) / (sum_k 1/c_k);
+        // c*_k = c_k - lambda_p / c_k;  u_l = sum_{k <= l, k = l mod 2} c*_k  (prefix sum).
         // NT is even, so all own positions of thread t have parity t & 1.
         double2 ps = make_double2(0.0, 0.0);
 #pragma unroll
@@ -263,13 +267,11 @@ __global__ void __launch_bounds__(kThreads) kr_cheb_fwd(const double2* in, doubl
             x[e] = cscale(x[e], cd.fscale[k]);
             ps.x += x[e].x; ps.y += x[e].y;
         }
-        // column/parity partial sums -> B1 scratch [t][c]
-        B1[t * W + c] = ps;
+        SC[t * W + c] = ps;
         __syncthreads();
         const int p = t & 1;
         double2 tot = make_double2(0.0, 0.0);
-        for (int tt = p; tt < NT; tt += 2) { double2 v = B1[tt * W + c]; tot.x += v.x; tot.y += v.y; }
-        // sum over parity-p modes of 1/c_k: (#modes) - (1/2 if p == 0)
+        for (int tt = p; tt < NT; tt += 2) { double2 v = SC[tt * W + c]; tot.x += v.x; tot.y += v.y; }
         const int mp = (N - p + 1) / 2;
         const double wsum = (double)mp - (p == 0 ? 0.5 : 0.0);
         const double2 lam = make_double2(tot.x / wsum, tot.y / wsum);
@@ -279,24 +281,22 @@ __global__ void __launch_bounds__(kThreads) kr_cheb_fwd(const double2* in, doubl
             const double ic = k == 0 ? 0.5 : 1.0;
             x[e].x -= lam.x * ic;
             x[e].y -= lam.y * ic;
+            B0[k * W + c] = x[e];
         }
+        __syncthreads();
         // prefix sums along each parity chain (chain index i <-> position p + 2i), in
-        // segments: the NT/2 threads of parity p own consecutive segments of length seg.
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < E; ++e) B0[(t + NT * e) * W + c] = x[e];
-        __syncthreads();
+        // segments: the NT/2 threads of parity p own consecutive segments of length seg
         const int t2 = t >> 1;
         const int seg = (mp + NT / 2 - 1) / (NT / 2);
         const int i0 = t2 * seg, i1 = i0 + seg < mp ? i0 + seg : mp;
         double2 ssum = make_double2(0.0, 0.0);
 #pragma unroll 1
         for (int i = i0; i < i1; ++i) { double2 v = B0[(p + 2 * i) * W + c]; ssum.x += v.x; ssum.y += v.y; }
-        B1[(NT + t) * W + c] = ssum;   // B1 rows NT.. hold the segment sums
+        SC[(NT + t) * W + c] = ssum;
         __syncthreads();
         double2 run = make_double2(0.0, 0.0);
 #pragma unroll 1
-        for (int u = 0; u < t2; ++u) { double2 v = B1[(NT + 2 * u + p) * W + c]; run.x += v.x; run.y += v.y; }
+        for (int u = 0; u < t2; ++u) { double2 v = SC[(NT + 2 * u + p) * W + c]; run.x += v.x; run.y += v.y; }
 #pragma unroll 1
         for (int i = i0; i < i1; ++i) {
             double2 v = B0[(p + 2 * i) * W + c];
@@ -313,19 +313,19 @@ __global__ void __launch_bounds__(kThreads) kr_cheb_fwd(const double2* in, doubl
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = t + NT * e;
-            B1[k * W + c] = cscale(x[e], cd.bscale[k]);
+            B0[k * W + c] = cscale(x[e], cd.bscale[k]);
         }
         __syncthreads();
         const int lane = threadIdx.x;
         if (lane < 2 * W) {
             const int p = lane / W, cc = lane - p * W;
-            project_givens_lane(B1 + p * W + cc, 2 * W, cd.npar[p], cd.mpar[p], 2, cd.rot[p], cd.rtab[p], cd.qtab[p]);
+            project_givens_lane(B0 + p * W + cc, 2 * W, cd.npar[p], cd.mpar[p], 2, cd.rot[p], cd.rtab[p], cd.qtab[p]);
         }
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int l = t + NT * e;
-            if (ok) out[(long)l * ncols + c0 + c] = l < nb ? B1[l * W + c] : make_double2(0.0, 0.0);
+            if (ok) out[(long)l * ncols + c0 + c] = l < nb ? B0[l * W + c] : make_double2(0.0, 0.0);
         }
     }
 }
@@ -339,7 +339,7 @@ __global__ void __launch_bounds__(kThreads) kr_cheb_bwd(const double2* in, doubl
     constexpr int W = G::W, NT = G::NT, E = G::E;
     extern __shared__ double2 lds[];
     double2* B0 = lds;
-    double2* B1 = lds + N * W;  // second tile buffer (the LDS always holds two N x W tiles here)
+    double2* B1 = lds + G::B1OFF;
     const int c = threadIdx.x % W, t = threadIdx.x / W;
     const int c0 = blockIdx.x * W;
     const bool ok = c0 + c < ncols;
@@ -350,34 +350,37 @@ __global__ void __launch_bounds__(kThreads) kr_cheb_bwd(const double2* in, doubl
         B0[l * W + c] = (ok && l < nb) ? in[(long)l * ncols + c0 + c] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    // Chebyshev coefficients c_k = u_k + beta_{k-2} u_{k-2} + gamma_{k-4} u_{k-4} into B1
+    // Chebyshev coefficients c_k = u_k + beta_{k-2} u_{k-2} + gamma_{k-4} u_{k-4} (own k)
     const bool has_gamma = cd.basis == SGM_SHEN_BIHARMONIC;
     const bool has_beta = cd.basis != SGM_CHEBYSHEV;
+    double2 x[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = t + NT * e;
         double2 v = B0[k * W + c];
         if (has_beta && k >= 2) { double bb = cd.beta[k - 2]; double2 u = B0[(k - 2) * W + c]; v.x += bb * u.x; v.y += bb * u.y; }
         if (has_gamma && k >= 4) { double gg = cd.gamma[k - 4]; double2 u = B0[(k - 4) * W + c]; v.x += gg * u.x; v.y += gg * u.y; }
-        B1[k * W + c] = v;
+        x[e] = v;
     }
     __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) B0[(t + NT * e) * W + c] = x[e];
+    __syncthreads();
     // DCT-III input W_0 = 2 c_0, W_k = e^{i pi k/(2N)} (c_k - i c_{N-k})
-    double2 x[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = t + NT * e;
-        const double2 ck = B1[k * W + c];
+        const double2 ck = x[e];
         if (k == 0) {
             x[e] = make_double2(2.0 * ck.x, 2.0 * ck.y);
         } else {
-            const double2 cn = B1[(N - k) * W + c];
+            const double2 cn = B0[(N - k) * W + c];
             const double2 d = make_double2(ck.x + cn.y, ck.y - cn.x);
             x[e] = cmul(cconj(cd.theta[k]), d);
         }
     }
     __syncthreads();
-    reg_fft<N, G::NTMAX, 1, G::NB>(x, B0 + c, (G::NB == 2 ? B1 : B0) + c, W, t, tw);
+    reg_fft<N, G::NTMAX, 1, G::NB>(x, B0 + c, B1 + c, W, t, tw);
     if (ok) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -396,7 +399,7 @@ static void fill_g(RegKernels& k) {
     k.W = G::W;
     k.threads = G::THREADS;
     k.lds = sizeof(double2) * (size_t)G::NB * G::W * L;
-    k.lds_cheb = 2 * sizeof(double2) * (size_t)G::W * L;
+    k.lds_cheb = sizeof(double2) * ((size_t)G::NB * G::W * L + 2 * (size_t)G::NT * G::W);
     k.r2c = kr_lines_r2c<L, G>;
     k.c2r = kr_lines_c2r<L, G>;
     k.c2c_f = kr_lines_c2c<L, G, -1>;
