@@ -149,7 +149,13 @@ typedef struct {
     int scheme;     /* SGM_RK4 | SGM_IFRK4                                               */
     int graph;      /* 1: sgm_gl_step captures one step as a hipGraph (per state pointer
                        and stream) and replays it; 0: launches the kernels directly      */
+    int tune;       /* launch configuration of the time-stepping kernels: 0 default;
+                       1 time every candidate on one step at creation (on the current
+                       device, default stream) and keep the fastest; 16 + k pin
+                       candidate k, 0 <= k < SGM_GL_NVARIANT                             */
 } sgm_gl_desc;
+#define SGM_GL_NVARIANT 6 /* candidate = 2 * geometry (3 FFT tilings) + grid mode
+                             (0 persistent grid, 1 one work-group per work item)         */
 
 /* Create a batch: uploads the per-problem descriptors, work lists and twiddle
  * tables and allocates two state-sized stage buffers and one padded workspace
@@ -159,6 +165,8 @@ sgm_status sgm_gl_create(const sgm_gl_desc* desc, sgm_gl* out);
 sgm_status sgm_gl_destroy(sgm_gl gl);
 /* Number of problems of the batch. */
 sgm_status sgm_gl_count(sgm_gl gl, int* count);
+/* Launch configuration in use (0 <= *variant < SGM_GL_NVARIANT). */
+sgm_status sgm_gl_variant(sgm_gl gl, int* variant);
 /* offsets[0..count]: packed layout (complex elements); offsets[count] = total. */
 sgm_status sgm_gl_offsets(sgm_gl gl, int64_t* offsets);
 /* u_hat = (1/N^2) sum_x u(x) e^{-i k.x} per problem (Sec. 3.4.1 forward, both axes). */

@@ -26,6 +26,7 @@ class GLDesc(ctypes.Structure):
     _fields_ = [
         ("count", ctypes.c_int), ("N", ctypes.POINTER(ctypes.c_int)), ("L", ctypes.c_double), ("b", ctypes.c_double),
         ("c", ctypes.c_double), ("dt", ctypes.c_double), ("scheme", ctypes.c_int), ("graph", ctypes.c_int),
+        ("tune", ctypes.c_int),
     ]
 
 
@@ -61,6 +62,7 @@ _SIGS = {
     "sgm_gl_destroy": ([_vp], ctypes.c_int),
     "sgm_gl_offsets": ([_vp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "sgm_gl_count": ([_vp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "sgm_gl_variant": ([_vp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "sgm_fno_advance_checked": ([_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_uint64,
                                  _vp, _vp], ctypes.c_int),
     "sgm_gl_forward": ([_vp, _vp, _vp, _vp], ctypes.c_int),

@@ -124,15 +124,19 @@ class GLBatch:
     """Ragged batch of complex Ginzburg-Landau problems on [-L/2, L/2)^2.
 
     All arrays are packed complex128 device vectors of length `total`; problem i
-    occupies [offsets[i], offsets[i+1]) as an N_i x N_i C-ordered array."""
+    occupies [offsets[i], offsets[i+1]) as an N_i x N_i C-ordered array.
 
-    def __init__(self, sizes, L=100.0, b=0.0, c=1.5, dt=0.025, scheme="rk4", graph=True):
+    tune: False (default launch configuration), True (time every candidate at
+    creation, keep the fastest) or an int 0 <= k < 6 pinning candidate k."""
+
+    def __init__(self, sizes, L=100.0, b=0.0, c=1.5, dt=0.025, scheme="rk4", graph=True, tune=False):
         lib = load()
         self._lib = lib
         self.sizes = [int(n) for n in sizes]
         arr = (ctypes.c_int * len(self.sizes))(*self.sizes)
         d = _lib.GLDesc(len(self.sizes), arr, float(L), float(b), float(c), float(dt),
-                        _lib.SGM_IFRK4 if scheme == "ifrk4" else _lib.SGM_RK4, int(bool(graph)))
+                        _lib.SGM_IFRK4 if scheme == "ifrk4" else _lib.SGM_RK4, int(bool(graph)),
+                        1 if tune is True else 0 if tune is False else 16 + int(tune))
         h = ctypes.c_void_p()
         check(lib.sgm_gl_create(ctypes.byref(d), ctypes.byref(h)), "sgm_gl_create")
         self._h = h
@@ -140,6 +144,13 @@ class GLBatch:
         check(lib.sgm_gl_offsets(h, offs), "sgm_gl_offsets")
         self.offsets = list(offs)
         self.total = self.offsets[-1]
+
+    @property
+    def variant(self):
+        """Launch configuration in use: 2 * FFT tiling + grid mode."""
+        v = ctypes.c_int()
+        check(self._lib.sgm_gl_variant(self._h, ctypes.byref(v)), "sgm_gl_variant")
+        return v.value
 
     def close(self):
         if getattr(self, "_h", None):

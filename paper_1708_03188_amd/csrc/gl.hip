@@ -1,16 +1,22 @@
 // Complex Ginzburg-Landau: ragged batches of doubly periodic problems.
 //
-// One right-hand-side evaluation is three persistent launches over a work
-// list that covers every problem of the batch:
-//   A  rows    : zero-pad each spectral row (ky) to M = floor(3N/2), inverse FFT
+// A right-hand-side evaluation is a pass over rows and a pass over columns of
+// the zero-padded M = floor(3N/2) grid of every problem of the batch:
+//   A  rows    : zero-pad each spectral row (ky) to M, inverse FFT
 //   B  columns : zero-pad each column (kx) to M, inverse FFT, form
 //                (1 + i c)|u|^2 u on the fine grid, forward FFT (1/M), truncate
 //   C  rows    : forward FFT (1/M), truncate to the N retained ky, and apply the
 //                Runge-Kutta stage update (or write the right-hand side).
-// Each block takes work items (problem, first line) in a grid-stride loop and
-// dispatches on the problem's padded length: a register-FFT specialisation
-// for the compiled lengths, the generic LDS FFT otherwise.
+// Within a time step pass C of stage s also performs pass A of stage s+1: the
+// new stage input of a row is already in the thread's registers at exactly the
+// padded positions the inverse transform needs.  Each launch covers every
+// problem through a work list of (problem, first line) items and dispatches on
+// the problem's padded length: a register-FFT specialisation for the compiled
+// lengths, the generic LDS FFT otherwise.  Launch geometry (radix schedule,
+// lines per block, exchange buffers) and grid mode (persistent grid-stride or
+// one block per item) are chosen by measurement at batch creation.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -27,22 +33,26 @@ constexpr int kGlThreads = 256;
 
 constexpr int gmin(int a, int b) { return a < b ? a : b; }
 
-// GL launch geometry, chosen by measurement on the ragged batch: radices <= 4
-// (12 points per thread for the 3-smooth padded lengths), up to 64 threads per
-// line, one exchange buffer, at most 64 KB of LDS per block.
-constexpr int kGlNTMAX = 64;
-constexpr int kGlMaxR = 4;
-constexpr int kGlNB = 1;
-constexpr int kGlLds = 65536;
+// Launch configurations: threads-per-line bound, largest radix, exchange
+// buffers, LDS budget per block.
+template <int NTMAX_, int MAXR_, int NB_, int LDSB_>
+struct GLCfg {
+    static constexpr int NTMAX = NTMAX_, MAXR = MAXR_, NB = NB_, LDSB = LDSB_;
+};
+using GLCfgA = GLCfg<64, 4, 1, 65536>;   // 12 points per thread, small tiles
+using GLCfgB = GLCfg<32, 8, 1, 98304>;   // 24 points per thread, wider column tiles
+using GLCfgC = GLCfg<64, 4, 2, 131072>;  // two exchange buffers
+constexpr int kGlCfgs = 3;
 
-template <int M>
+template <int M, class CF>
 struct GGeo {
-    static constexpr Sched sd = make_sched(M, kGlNTMAX, kGlMaxR);
+    static constexpr Sched sd = make_sched(M, CF::NTMAX, CF::MAXR);
     static constexpr int NT = sd.NT;
     static constexpr int E = sd.E;
-    static constexpr int W = gmin(kGlThreads / NT, kGlLds / (16 * kGlNB * M)) > 0 ? gmin(kGlThreads / NT, kGlLds / (16 * kGlNB * M)) : 1;
+    static constexpr int W0 = gmin(kGlThreads / NT, CF::LDSB / (16 * CF::NB * M));
+    static constexpr int W = W0 > 0 ? W0 : 1;
     static constexpr int THREADS = W * NT;
-    static constexpr int B1OFF = kGlNB == 2 ? W * M : 0;
+    static constexpr int B1OFF = CF::NB == 2 ? W * M : 0;
 };
 
 struct GLProb {
@@ -81,8 +91,11 @@ __device__ __forceinline__ bool kept(int l, int N) { return l >= -(N / 2) && l <
 __device__ __forceinline__ int nidx(int l, int N) { return l >= 0 ? l : l + N; }
 
 // Stage update of one retained mode.  k = N(v) = -F_trunc[(1 + i c)|u_p|^2 u_p].
-__device__ __forceinline__ void stage_update(const GLStage& s, const GLProb& pr, long idx, int kxi, int kyi,
-                                             double2 k) {
+// Returns the input of the next stage (stages 0..2); stores it in s.v when
+// store_v (the explicit scheme needs it again for L v).
+__device__ __forceinline__ double2 stage_update(const GLStage& s, const GLProb& pr, long idx, int kxi, int kyi,
+                                                double2 k, bool store_v) {
+    double2 vn = make_double2(0.0, 0.0);
     if (s.mode == kGlRhs || s.mode == kGlRk4) {
         const double kx = gwn(kxi, pr.N) * s.ks, ky = gwn(kyi, pr.N) * s.ks;
         const double k2 = kx * kx + ky * ky;
@@ -90,22 +103,24 @@ __device__ __forceinline__ void stage_update(const GLStage& s, const GLProb& pr,
         // dU = (1 - (1 + i b) k^2) v + k
         const double2 du = make_double2((1.0 - k2) * vv.x + s.b * k2 * vv.y + k.x,
                                         (1.0 - k2) * vv.y - s.b * k2 * vv.x + k.y);
-        if (s.mode == kGlRhs) { s.rhs[idx] = du; return; }
+        if (s.mode == kGlRhs) { s.rhs[idx] = du; return vn; }
         const double2 u0 = s.state[idx];
         const double dt = s.dt;
         if (s.stage == 0) {
             s.acc[idx] = make_double2(u0.x + dt / 6 * du.x, u0.y + dt / 6 * du.y);
-            s.v[idx] = make_double2(u0.x + dt / 2 * du.x, u0.y + dt / 2 * du.y);
+            vn = make_double2(u0.x + dt / 2 * du.x, u0.y + dt / 2 * du.y);
         } else if (s.stage < 3) {
             double2 a = s.acc[idx];
             s.acc[idx] = make_double2(a.x + dt / 3 * du.x, a.y + dt / 3 * du.y);
             const double bb = s.stage == 1 ? dt / 2 : dt;
-            s.v[idx] = make_double2(u0.x + bb * du.x, u0.y + bb * du.y);
+            vn = make_double2(u0.x + bb * du.x, u0.y + bb * du.y);
         } else {
             double2 a = s.acc[idx];
             s.state[idx] = make_double2(a.x + dt / 6 * du.x, a.y + dt / 6 * du.y);
+            return vn;
         }
-        return;
+        if (store_v) s.v[idx] = vn;
+        return vn;
     }
     // integrating-factor RK4; E = exp(Lhat dt/2) = e^{dt/2} ex(kx) ex(ky)
     const double2 ex = s.etab[pr.off_e + kxi], ey = s.etab[pr.off_e + kyi];
@@ -116,29 +131,32 @@ __device__ __forceinline__ void stage_update(const GLStage& s, const GLProb& pr,
         const double2 E2 = cmul(E, E);
         const double2 a = make_double2(u0.x + dt / 6 * k.x, u0.y + dt / 6 * k.y);
         s.acc[idx] = cmul(E2, a);
-        s.v[idx] = cmul(E, make_double2(u0.x + dt / 2 * k.x, u0.y + dt / 2 * k.y));
+        vn = cmul(E, make_double2(u0.x + dt / 2 * k.x, u0.y + dt / 2 * k.y));
     } else if (s.stage == 1) {
         const double2 Ek = cmul(E, k);
         double2 a = s.acc[idx];
         s.acc[idx] = make_double2(a.x + dt / 3 * Ek.x, a.y + dt / 3 * Ek.y);
         const double2 Eu = cmul(E, u0);
-        s.v[idx] = make_double2(Eu.x + dt / 2 * k.x, Eu.y + dt / 2 * k.y);
+        vn = make_double2(Eu.x + dt / 2 * k.x, Eu.y + dt / 2 * k.y);
     } else if (s.stage == 2) {
         const double2 Ek = cmul(E, k);
         double2 a = s.acc[idx];
         s.acc[idx] = make_double2(a.x + dt / 3 * Ek.x, a.y + dt / 3 * Ek.y);
         const double2 E2u = cmul(E, cmul(E, u0));
-        s.v[idx] = make_double2(E2u.x + dt * Ek.x, E2u.y + dt * Ek.y);
+        vn = make_double2(E2u.x + dt * Ek.x, E2u.y + dt * Ek.y);
     } else {
         double2 a = s.acc[idx];
         s.state[idx] = make_double2(a.x + dt / 6 * k.x, a.y + dt / 6 * k.y);
+        return vn;
     }
+    if (store_v) s.v[idx] = vn;
+    return vn;
 }
 
 // ---------------- register-FFT specialisations -----------------------------
-template <int M>
+template <int M, class CF>
 __device__ __attribute__((noinline)) void rows_inv_reg(const GLProb& pr, int line0, const double2* src, double2* work, double2* lds) {
-    using G = GGeo<M>;
+    using G = GGeo<M, CF>;
     const int t = threadIdx.x % G::NT, g = threadIdx.x / G::NT;
     const int row = line0 + g;
     const bool act = threadIdx.x < G::THREADS && row < pr.N;
@@ -150,16 +168,16 @@ __device__ __attribute__((noinline)) void rows_inv_reg(const GLProb& pr, int lin
         const int l = gwn(q, M);
         x[e] = (act && kept(l, N)) ? src[pr.off_s + (long)row * N + nidx(l, N)] : make_double2(0.0, 0.0);
     }
-    reg_fft<M, kGlNTMAX, 1, kGlNB, kGlMaxR>(x, lds + g * M, lds + G::B1OFF + g * M, 1, t, pr.rp.tw, act);
+    reg_fft<M, CF::NTMAX, 1, CF::NB, CF::MAXR>(x, lds + g * M, lds + G::B1OFF + g * M, 1, t, pr.rp.tw, act);
     if (act) {
 #pragma unroll
         for (int e = 0; e < G::E; ++e) work[pr.off_w + (long)row * M + t + G::NT * e] = x[e];
     }
 }
 
-template <int M>
+template <int M, class CF>
 __device__ __attribute__((noinline)) void cols_reg(const GLProb& pr, int line0, double2* work, double2* lds, double cnl) {
-    using G = GGeo<M>;
+    using G = GGeo<M, CF>;
     const int c = threadIdx.x % G::W, t = threadIdx.x / G::W;
     const int y = line0 + c;
     const bool act = threadIdx.x < G::THREADS && y < M;
@@ -171,7 +189,7 @@ __device__ __attribute__((noinline)) void cols_reg(const GLProb& pr, int line0, 
         const int l = gwn(q, M);
         x[e] = (act && kept(l, N)) ? work[pr.off_w + (long)nidx(l, N) * M + y] : make_double2(0.0, 0.0);
     }
-    reg_fft<M, kGlNTMAX, 1, kGlNB, kGlMaxR>(x, lds + c, lds + G::B1OFF + c, G::W, t, pr.rp.tw, act);
+    reg_fft<M, CF::NTMAX, 1, CF::NB, CF::MAXR>(x, lds + c, lds + G::B1OFF + c, G::W, t, pr.rp.tw, act);
 #pragma unroll
     for (int e = 0; e < G::E; ++e) {
         const double2 u = x[e];
@@ -180,7 +198,7 @@ __device__ __attribute__((noinline)) void cols_reg(const GLProb& pr, int line0, 
         x[e] = make_double2(r2 * (u.x - cnl * u.y), r2 * (u.y + cnl * u.x));
     }
     __syncthreads();
-    reg_fft<M, kGlNTMAX, -1, kGlNB, kGlMaxR>(x, lds + c, lds + G::B1OFF + c, G::W, t, pr.rp.tw, act);
+    reg_fft<M, CF::NTMAX, -1, CF::NB, CF::MAXR>(x, lds + c, lds + G::B1OFF + c, G::W, t, pr.rp.tw, act);
     if (act) {
         const double s = 1.0 / M;
 #pragma unroll
@@ -192,9 +210,12 @@ __device__ __attribute__((noinline)) void cols_reg(const GLProb& pr, int line0, 
     }
 }
 
-template <int M>
-__device__ __attribute__((noinline)) void rows_fwd_reg(const GLProb& pr, int line0, const double2* work, double2* lds, const GLStage& st) {
-    using G = GGeo<M>;
+// FUSE: after the stage update, zero-pad the new stage input of the row and
+// inverse-transform it along y (pass A of the next stage) into the workspace.
+template <int M, class CF, bool FUSE>
+__device__ __attribute__((noinline)) void rows_fwd_reg(const GLProb& pr, int line0, double2* work, double2* lds,
+                                                       const GLStage& st) {
+    using G = GGeo<M, CF>;
     const int t = threadIdx.x % G::NT, g = threadIdx.x / G::NT;
     const int row = line0 + g;
     const bool act = threadIdx.x < G::THREADS && row < pr.N;
@@ -203,17 +224,26 @@ __device__ __attribute__((noinline)) void rows_fwd_reg(const GLProb& pr, int lin
 #pragma unroll
     for (int e = 0; e < G::E; ++e)
         x[e] = act ? work[pr.off_w + (long)row * M + t + G::NT * e] : make_double2(0.0, 0.0);
-    reg_fft<M, kGlNTMAX, -1, kGlNB, kGlMaxR>(x, lds + g * M, lds + G::B1OFF + g * M, 1, t, pr.rp.tw, act);
-    if (act) {
-        const double s = -1.0 / M;
+    reg_fft<M, CF::NTMAX, -1, CF::NB, CF::MAXR>(x, lds + g * M, lds + G::B1OFF + g * M, 1, t, pr.rp.tw, act);
+    const double s = -1.0 / M;
+    const bool store_v = !FUSE || st.mode == kGlRk4;
 #pragma unroll
-        for (int e = 0; e < G::E; ++e) {
-            const int q = t + G::NT * e;
-            const int l = gwn(q, M);
-            if (kept(l, N)) {
-                const int ky = nidx(l, N);
-                stage_update(st, pr, pr.off_s + (long)row * N + ky, row, ky, cscale(x[e], s));
-            }
+    for (int e = 0; e < G::E; ++e) {
+        const int q = t + G::NT * e;
+        const int l = gwn(q, M);
+        double2 vn = make_double2(0.0, 0.0);
+        if (act && kept(l, N)) {
+            const int ky = nidx(l, N);
+            vn = stage_update(st, pr, pr.off_s + (long)row * N + ky, row, ky, cscale(x[e], s), store_v);
+        }
+        x[e] = vn;
+    }
+    if constexpr (FUSE) {
+        __syncthreads();
+        reg_fft<M, CF::NTMAX, 1, CF::NB, CF::MAXR>(x, lds + g * M, lds + G::B1OFF + g * M, 1, t, pr.rp.tw, act);
+        if (act) {
+#pragma unroll
+            for (int e = 0; e < G::E; ++e) work[pr.off_w + (long)row * M + t + G::NT * e] = x[e];
         }
     }
 }
@@ -264,7 +294,8 @@ __device__ void cols_gen(const GLProb& pr, int line0, double2* work, double2* ld
     }
 }
 
-__device__ void rows_fwd_gen(const GLProb& pr, int line0, const double2* work, double2* lds, const GLStage& st) {
+__device__ void rows_fwd_gen(const GLProb& pr, int line0, double2* work, double2* lds, const GLStage& st,
+                             bool fuse) {
     const int M = pr.M, N = pr.N, W = pr.wrows;
     double2* A = lds;
     double2* B = lds + (long)W * M;
@@ -276,49 +307,59 @@ __device__ void rows_fwd_gen(const GLProb& pr, int line0, const double2* work, d
     __syncthreads();
     double2* R = lds_fft<-1>(A, B, pr.rp, W, 1, M, false);
     const double s = -1.0 / M;
+    const bool store_v = !fuse || st.mode == kGlRk4;
     for (int f = threadIdx.x; f < W * M; f += blockDim.x) {
         const int g = f / M, q = f - g * M;
         const int row = line0 + g, l = gwn(q, M);
+        double2 vn = make_double2(0.0, 0.0);
         if (row < N && kept(l, N)) {
             const int ky = nidx(l, N);
-            stage_update(st, pr, pr.off_s + (long)row * N + ky, row, ky, cscale(R[f], s));
+            vn = stage_update(st, pr, pr.off_s + (long)row * N + ky, row, ky, cscale(R[f], s), store_v);
         }
+        R[f] = vn;
+    }
+    if (!fuse) return;
+    __syncthreads();
+    double2* O = (R == A) ? B : A;
+    double2* R2 = lds_fft<1>(R, O, pr.rp, W, 1, M, false);
+    for (int f = threadIdx.x; f < W * M; f += blockDim.x) {
+        const int g = f / M;
+        const int row = line0 + g;
+        if (row < N) work[pr.off_w + (long)row * M + (f - g * M)] = R2[f];
     }
 }
 
-// ---------------- persistent pass kernels ----------------------------------
-#define SGM_GL_SWITCH(KIND, CALL_REG, CALL_GEN)  \
-    switch (KIND) {                               \
-        case 0: CALL_REG(48); break;              \
-        case 1: CALL_REG(96); break;              \
-        case 2: CALL_REG(192); break;             \
-        case 3: CALL_REG(288); break;             \
-        case 4: CALL_REG(384); break;             \
-        case 5: CALL_REG(576); break;             \
-        case 6: CALL_REG(768); break;             \
-        default: CALL_GEN; break;                 \
+// ---------------- pass kernels ---------------------------------------------
+#define SGM_GL_SWITCH(KIND, CALL_REG)  \
+    switch (KIND) {                     \
+        case 0: CALL_REG(48); break;    \
+        case 1: CALL_REG(96); break;    \
+        case 2: CALL_REG(192); break;   \
+        case 3: CALL_REG(288); break;   \
+        case 4: CALL_REG(384); break;   \
+        case 5: CALL_REG(576); break;   \
+        case 6: CALL_REG(768); break;   \
+        default: break;                 \
     }
 static const int kGlRegM[7] = {48, 96, 192, 288, 384, 576, 768};
 
-template <int M>
-constexpr int ggeo_w() { return GGeo<M>::W; }
+template <class CF>
 static int reg_w(int kind) {
     switch (kind) {
-        case 0: return ggeo_w<48>();
-        case 1: return ggeo_w<96>();
-        case 2: return ggeo_w<192>();
-        case 3: return ggeo_w<288>();
-        case 4: return ggeo_w<384>();
-        case 5: return ggeo_w<576>();
-        case 6: return ggeo_w<768>();
+        case 0: return GGeo<48, CF>::W;
+        case 1: return GGeo<96, CF>::W;
+        case 2: return GGeo<192, CF>::W;
+        case 3: return GGeo<288, CF>::W;
+        case 4: return GGeo<384, CF>::W;
+        case 5: return GGeo<576, CF>::W;
+        case 6: return GGeo<768, CF>::W;
         default: return 0;
     }
 }
 
-// GEN = false: problems whose padded length has a register specialisation;
-// GEN = true: every other problem (generic LDS FFT), in its own launch so the
-// register specialisations keep their allocation.
-template <bool GEN>
+// Items are taken in a grid-stride loop (a persistent grid when gridDim.x is
+// smaller than the item count, one block per item otherwise).
+template <class CF, bool GEN>
 __global__ void __launch_bounds__(kGlThreads) k_gl_rows_inv(const GLProb* probs, const GLItem* items, int nitems,
                                                             const double2* src, double2* work) {
     extern __shared__ double2 lds[];
@@ -328,15 +369,15 @@ __global__ void __launch_bounds__(kGlThreads) k_gl_rows_inv(const GLProb* probs,
         if constexpr (GEN) {
             rows_inv_gen(pr, item.line0, src, work, lds);
         } else {
-#define R_(MM) rows_inv_reg<MM>(pr, item.line0, src, work, lds)
-            SGM_GL_SWITCH(pr.kind, R_, (void)0)
+#define R_(MM) rows_inv_reg<MM, CF>(pr, item.line0, src, work, lds)
+            SGM_GL_SWITCH(pr.kind, R_)
 #undef R_
         }
         __syncthreads();
     }
 }
 
-template <bool GEN>
+template <class CF, bool GEN>
 __global__ void __launch_bounds__(kGlThreads) k_gl_cols(const GLProb* probs, const GLItem* items, int nitems,
                                                         double2* work, double cnl) {
     extern __shared__ double2 lds[];
@@ -346,29 +387,52 @@ __global__ void __launch_bounds__(kGlThreads) k_gl_cols(const GLProb* probs, con
         if constexpr (GEN) {
             cols_gen(pr, item.line0, work, lds, cnl);
         } else {
-#define C_(MM) cols_reg<MM>(pr, item.line0, work, lds, cnl)
-            SGM_GL_SWITCH(pr.kind, C_, (void)0)
+#define C_(MM) cols_reg<MM, CF>(pr, item.line0, work, lds, cnl)
+            SGM_GL_SWITCH(pr.kind, C_)
 #undef C_
         }
         __syncthreads();
     }
 }
 
-template <bool GEN>
+template <class CF, bool GEN, bool FUSE>
 __global__ void __launch_bounds__(kGlThreads) k_gl_rows_fwd(const GLProb* probs, const GLItem* items, int nitems,
-                                                            const double2* work, GLStage st) {
+                                                            double2* work, GLStage st) {
     extern __shared__ double2 lds[];
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const GLItem item = items[it];
         const GLProb pr = probs[item.prob];
         if constexpr (GEN) {
-            rows_fwd_gen(pr, item.line0, work, lds, st);
+            rows_fwd_gen(pr, item.line0, work, lds, st, FUSE);
         } else {
-#define F_(MM) rows_fwd_reg<MM>(pr, item.line0, work, lds, st)
-            SGM_GL_SWITCH(pr.kind, F_, (void)0)
+#define F_(MM) rows_fwd_reg<MM, CF, FUSE>(pr, item.line0, work, lds, st)
+            SGM_GL_SWITCH(pr.kind, F_)
 #undef F_
         }
         __syncthreads();
+    }
+}
+
+// Launch table of one configuration.
+struct GLKern {
+    void (*rows_inv)(const GLProb*, const GLItem*, int, const double2*, double2*);
+    void (*cols)(const GLProb*, const GLItem*, int, double2*, double);
+    void (*rows_fwd)(const GLProb*, const GLItem*, int, double2*, GLStage);
+    void (*rows_fwd_fused)(const GLProb*, const GLItem*, int, double2*, GLStage);
+    int (*w)(int);
+    int nb, ldsb;
+};
+template <class CF, bool GEN>
+static GLKern glkern() {
+    return {k_gl_rows_inv<CF, GEN>, k_gl_cols<CF, GEN>, k_gl_rows_fwd<CF, GEN, false>, k_gl_rows_fwd<CF, GEN, true>,
+            reg_w<CF>, CF::NB, CF::LDSB};
+}
+static GLKern glkern_cfg(int cfg, bool gen) {
+    if (gen) return glkern<GLCfgA, true>();
+    switch (cfg) {
+        case 1: return glkern<GLCfgB, false>();
+        case 2: return glkern<GLCfgC, false>();
+        default: return glkern<GLCfgA, false>();
     }
 }
 
@@ -376,23 +440,27 @@ __global__ void __launch_bounds__(kGlThreads) k_gl_rows_fwd(const GLProb* probs,
 
 using namespace sgm;
 
+// Work lists 0..kGlCfgs-1: register-specialised problems tiled for that
+// configuration; list kGlCfgs: problems on the generic path.
+constexpr int kGlLists = kGlCfgs + 1;
+
 struct sgm_gl_s {
     sgm_gl_desc d;
     std::vector<int> N, M;
     std::vector<int64_t> off_s, off_w, off_e;
-    std::vector<GLProb> hprobs;
     std::vector<RadixPlan> rpN;   // FFT of length N (forward/backward helpers)
     std::vector<int> hasN;
     std::vector<RegKernels> rkN;
-    // work lists [0] register-specialised problems, [1] generic ones;
-    // A: rows (passes A and C share it), B: columns
-    int nA[2] = {0, 0}, nB[2] = {0, 0};
-    size_t lds[2] = {0, 0};
-    int gridA[2] = {0, 0}, gridB[2] = {0, 0};
+    // rows lists (passes A and C) and column lists (pass B)
+    int nA[kGlLists] = {}, nB[kGlLists] = {};
+    size_t lds[kGlLists] = {};
+    bool cfg_ok[kGlCfgs] = {};
+    int cfg = 0, gridmode = 0;
+    int ncu = 256, lmax = 65536;
     void* dev = nullptr;         // probs + items + twiddles + etab
-    GLProb* dprobs = nullptr;
-    GLItem* ditemsA[2] = {nullptr, nullptr};
-    GLItem* ditemsB[2] = {nullptr, nullptr};
+    GLProb* dprobs[kGlLists] = {};
+    GLItem* ditemsA[kGlLists] = {};
+    GLItem* ditemsB[kGlLists] = {};
     double2* etab = nullptr;
     double2* v = nullptr;
     double2* acc = nullptr;
@@ -423,6 +491,115 @@ extern "C" sgm_status sgm_gl_destroy(sgm_gl g) {
     return SGM_OK;
 }
 
+static int gl_grid(sgm_gl g, int k, int n) {
+    if (g->gridmode == 1) return n;
+    const int per_cu = std::min(8, std::max(1, (int)(g->lmax / std::max<size_t>(g->lds[k], 1))));
+    return std::min(n, g->ncu * per_cu);
+}
+
+// pass 0: rows inverse (A), 1: columns (B), 2: rows forward + stage update (C),
+// 3: C fused with A of the next stage.
+static sgm_status gl_pass(sgm_gl g, int pass, const double2* src, const GLStage& st, hipStream_t s) {
+    const int lists[2] = {g->cfg, kGlCfgs};
+    for (int k : lists) {
+        const int n = pass == 1 ? g->nB[k] : g->nA[k];
+        if (!n) continue;
+        const GLKern kn = glkern_cfg(k == kGlCfgs ? 0 : k, k == kGlCfgs);
+        const GLItem* items = pass == 1 ? g->ditemsB[k] : g->ditemsA[k];
+        const dim3 grid(gl_grid(g, k, n)), block(kGlThreads);
+        const GLProb* probs = g->dprobs[k];
+        if (pass == 0)
+            hipLaunchKernelGGL(kn.rows_inv, grid, block, g->lds[k], s, probs, items, n, src, g->work);
+        else if (pass == 1)
+            hipLaunchKernelGGL(kn.cols, grid, block, g->lds[k], s, probs, items, n, g->work, g->d.c);
+        else
+            hipLaunchKernelGGL(pass == 3 ? kn.rows_fwd_fused : kn.rows_fwd, grid, block, g->lds[k], s, probs, items, n,
+                               g->work, st);
+        SGM_HIP_TRY(hipGetLastError());
+    }
+    return SGM_OK;
+}
+
+static GLStage base_stage(sgm_gl g) {
+    GLStage st{};
+    st.v = g->v;
+    st.acc = g->acc;
+    st.etab = g->etab;
+    st.ks = 6.283185307179586476925286766559 / g->d.L;
+    st.b = g->d.b;
+    st.c = g->d.c;
+    st.dt = g->d.dt;
+    st.edt = std::exp(g->d.dt / 2);
+    return st;
+}
+
+// One time step: A(state), then per stage B and C, C of stages 0..2 fused
+// with A of the following stage.
+static sgm_status gl_enqueue_step(sgm_gl g, double2* state, hipStream_t s) {
+    GLStage st = base_stage(g);
+    st.mode = g->d.scheme == SGM_IFRK4 ? kGlIfRk4 : kGlRk4;
+    st.state = state;
+    sgm_status r = gl_pass(g, 0, state, st, s);
+    for (int k = 0; k < 4 && r == SGM_OK; ++k) {
+        st.stage = k;
+        st.vin = k == 0 ? state : g->v;
+        r = gl_pass(g, 1, nullptr, st, s);
+        if (r == SGM_OK) r = gl_pass(g, k < 3 ? 3 : 2, nullptr, st, s);
+    }
+    return r;
+}
+
+// Times one step of each candidate configuration on a scratch state and keeps
+// the fastest.  Runs on the default stream before the batch is handed out.
+static sgm_status gl_autotune(sgm_gl g, int64_t os) {
+    double2* state = nullptr;
+    if (hipMalloc(&state, (size_t)os * sizeof(double2)) != hipSuccess) {
+        set_error("hipMalloc of the tuning state failed");
+        return SGM_ERR_OOM;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    sgm_status r = SGM_OK;
+    float best = 1e30f;
+    int bcfg = 0, bgrid = 0;
+    if (hipMemset(state, 0, (size_t)os * sizeof(double2)) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess) {
+        set_error("tuning set-up failed");
+        r = SGM_ERR_HIP;
+    }
+    for (int v = 0; v < 2 * kGlCfgs && r == SGM_OK; ++v) {
+        if (!g->cfg_ok[v / 2]) continue;
+        g->cfg = v / 2;
+        g->gridmode = v % 2;
+        r = gl_enqueue_step(g, state, nullptr);
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 3 && r == SGM_OK; ++rep) {
+            hipEventRecord(e0, nullptr);
+            r = gl_enqueue_step(g, state, nullptr);
+            if (r == SGM_OK) r = gl_enqueue_step(g, state, nullptr);
+            hipEventRecord(e1, nullptr);
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                set_error("tuning run failed");
+                r = SGM_ERR_HIP;
+                break;
+            }
+            float ms = 0;
+            hipEventElapsedTime(&ms, e0, e1);
+            tmin = std::min(tmin, ms);
+        }
+        if (r == SGM_OK && tmin < best) {
+            best = tmin;
+            bcfg = g->cfg;
+            bgrid = g->gridmode;
+        }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipFree(state);
+    g->cfg = bcfg;
+    g->gridmode = bgrid;
+    return r;
+}
+
 extern "C" sgm_status sgm_gl_create(const sgm_gl_desc* desc, sgm_gl* out) {
     clear_error();
     SGM_CHECK_ARG(desc && out && desc->N, "null argument");
@@ -432,6 +609,8 @@ extern "C" sgm_status sgm_gl_create(const sgm_gl_desc* desc, sgm_gl* out) {
     SGM_CHECK_ARG(d.L > 0 && std::isfinite(d.L) && std::isfinite(d.dt) && std::isfinite(d.b) && std::isfinite(d.c),
                   "L must be > 0 and all coefficients finite");
     SGM_CHECK_ARG(d.scheme == SGM_RK4 || d.scheme == SGM_IFRK4, "unknown scheme %d", d.scheme);
+    SGM_CHECK_ARG(d.tune == 0 || d.tune == 1 || (d.tune >= 16 && d.tune < 16 + 2 * kGlCfgs), "invalid tune %d",
+                  d.tune);
     for (int i = 0; i < d.count; ++i)
         if (d.N[i] < 2 || d.N[i] > 4096) {
             set_error("problem %d: N = %d outside 2..4096", i, d.N[i]);
@@ -461,44 +640,56 @@ extern "C" sgm_status sgm_gl_create(const sgm_gl_desc* desc, sgm_gl* out) {
     g->off_s.push_back(os);
     std::sort(lens.begin(), lens.end());
     lens.erase(std::unique(lens.begin(), lens.end()), lens.end());
-    // host blob: probs | itemsA | itemsB | etab | twiddles
-    std::vector<GLItem> itA[2], itB[2];
-    std::vector<std::pair<long, int>> costA, costB;  // larger problems first
-    g->hprobs.resize(n);
-    int maxlA = 0, maxlB = 0;
-    for (int i = 0; i < n; ++i) {
-        GLProb& pr = g->hprobs[i];
-        pr.N = g->N[i];
-        pr.M = g->M[i];
-        pr.kind = glkind(pr.M);
-        int W = pr.kind >= 0 ? reg_w(pr.kind) : std::max(1, std::min(16, 4096 / pr.M));
-        pr.wrows = W;
-        pr.wcols = W;
-        const size_t lds_reg = sizeof(double2) * (size_t)kGlNB * W * pr.M;
-        pr.off_s = g->off_s[i];
-        pr.off_w = g->off_w[i];
-        pr.off_e = g->off_e[i];
-        pr.rp.L = pr.M;
-        pr.rp.nst = factor_radices(pr.M, pr.rp.radix);
-        size_t lds = pr.kind >= 0 ? lds_reg : 2 * sizeof(double2) * (size_t)W * pr.M;
-        const int gk = pr.kind < 0 ? 1 : 0;
-        g->lds[gk] = std::max(g->lds[gk], lds);
-        (void)maxlA; (void)maxlB;
-    }
-    // work lists, problems in decreasing size so the grid-stride loop balances
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&g->ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    hipDeviceGetAttribute(&g->lmax, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    // per list: problem descriptors (line tiling depends on the configuration)
+    // and items, problems in decreasing size so the grid-stride loop balances
+    std::vector<GLProb> hp[kGlLists];
+    std::vector<GLItem> itA[kGlLists], itB[kGlLists];
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return g->N[a] > g->N[b]; });
-    for (int i : order) {
-        const GLProb& pr = g->hprobs[i];
-        const int gk = pr.kind < 0 ? 1 : 0;
-        for (int r = 0; r < pr.N; r += pr.wrows) itA[gk].push_back({i, r});
-        for (int y = 0; y < pr.M; y += pr.wcols) itB[gk].push_back({i, y});
-    }
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < kGlLists; ++k) {
+        hp[k].resize(n);
+        for (int i = 0; i < n; ++i) {
+            GLProb& pr = hp[k][i];
+            pr.N = g->N[i];
+            pr.M = g->M[i];
+            pr.kind = glkind(pr.M);
+            pr.off_s = g->off_s[i];
+            pr.off_w = g->off_w[i];
+            pr.off_e = g->off_e[i];
+            pr.rp.L = pr.M;
+            pr.rp.nst = factor_radices(pr.M, pr.rp.radix);
+            size_t lds;
+            if (k == kGlCfgs) {
+                pr.wrows = pr.wcols = std::max(1, std::min(16, 4096 / pr.M));
+                lds = 2 * sizeof(double2) * (size_t)pr.wrows * pr.M;
+            } else {
+                const GLKern kn = glkern_cfg(k, false);
+                pr.wrows = pr.wcols = pr.kind >= 0 ? kn.w(pr.kind) : 1;
+                lds = sizeof(double2) * (size_t)kn.nb * pr.wrows * pr.M;
+            }
+            const bool mine = (k == kGlCfgs) == (pr.kind < 0);
+            if (mine) g->lds[k] = std::max(g->lds[k], lds);
+        }
+        for (int i : order) {
+            const GLProb& pr = hp[k][i];
+            if ((k == kGlCfgs) != (pr.kind < 0)) continue;
+            for (int r = 0; r < pr.N; r += pr.wrows) itA[k].push_back({i, r});
+            for (int y = 0; y < pr.M; y += pr.wcols) itB[k].push_back({i, y});
+        }
         g->nA[k] = (int)itA[k].size();
         g->nB[k] = (int)itB[k].size();
     }
+    if (g->lds[kGlCfgs] > (size_t)g->lmax) {
+        set_error("padded length too large for one work-group's LDS");
+        sgm_gl_destroy(g);
+        return SGM_ERR_UNSUPPORTED_SIZE;
+    }
+    for (int k = 0; k < kGlCfgs; ++k) g->cfg_ok[k] = g->lds[k] <= (size_t)g->lmax;
     // integrating factor table ex(q) = exp(-(1 + i b) k_q^2 dt/2), k_q = 2 pi/L * wavenumber
     std::vector<double> etab(2 * (size_t)oe);
     const long double twopi = 6.283185307179586476925286766559L;
@@ -511,16 +702,17 @@ extern "C" sgm_status sgm_gl_create(const sgm_gl_desc* desc, sgm_gl* out) {
             etab[2 * (g->off_e[i] + q)] = (double)(mag * cosl(d.b * a));
             etab[2 * (g->off_e[i] + q) + 1] = (double)(mag * sinl(d.b * a));
         }
+    // device blob: probs[k] | itemsA[k] | itemsB[k] | etab | twiddles
     std::vector<char> blob;
     auto add = [&](const void* p, size_t bytes) {
         size_t off = (blob.size() + 255) & ~size_t(255);
         blob.resize(off + bytes);
-        if (bytes) std::memcpy(blob.data() + off, p, bytes);
+        if (bytes && p) std::memcpy(blob.data() + off, p, bytes);
         return off;
     };
-    size_t o_probs = add(g->hprobs.data(), n * sizeof(GLProb));
-    size_t o_A[2], o_B[2];
-    for (int k = 0; k < 2; ++k) {
+    size_t o_p[kGlLists], o_A[kGlLists], o_B[kGlLists];
+    for (int k = 0; k < kGlLists; ++k) {
+        o_p[k] = add(nullptr, n * sizeof(GLProb));
         o_A[k] = add(itA[k].data(), itA[k].size() * sizeof(GLItem));
         o_B[k] = add(itB[k].data(), itB[k].size() * sizeof(GLItem));
     }
@@ -538,12 +730,14 @@ extern "C" sgm_status sgm_gl_create(const sgm_gl_desc* desc, sgm_gl* out) {
     if (e != hipSuccess) { set_error("hipMalloc: %s", hipGetErrorString(e)); sgm_gl_destroy(g); return SGM_ERR_OOM; }
     char* base = static_cast<char*>(g->dev);
     // patch device twiddle pointers into the descriptors before upload
-    for (int i = 0; i < n; ++i) g->hprobs[i].rp.tw = twptr(base, g->M[i]);
-    std::memcpy(blob.data() + o_probs, g->hprobs.data(), n * sizeof(GLProb));
+    for (int k = 0; k < kGlLists; ++k) {
+        for (int i = 0; i < n; ++i) hp[k][i].rp.tw = twptr(base, g->M[i]);
+        std::memcpy(blob.data() + o_p[k], hp[k].data(), n * sizeof(GLProb));
+    }
     e = hipMemcpy(g->dev, blob.data(), blob.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) { set_error("hipMemcpy: %s", hipGetErrorString(e)); sgm_gl_destroy(g); return SGM_ERR_HIP; }
-    g->dprobs = reinterpret_cast<GLProb*>(base + o_probs);
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < kGlLists; ++k) {
+        g->dprobs[k] = reinterpret_cast<GLProb*>(base + o_p[k]);
         g->ditemsA[k] = reinterpret_cast<GLItem*>(base + o_A[k]);
         g->ditemsB[k] = reinterpret_cast<GLItem*>(base + o_B[k]);
     }
@@ -563,20 +757,18 @@ extern "C" sgm_status sgm_gl_create(const sgm_gl_desc* desc, sgm_gl* out) {
         sgm_gl_destroy(g);
         return SGM_ERR_OOM;
     }
-    int dev = 0, ncu = 256, lmax = 65536;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    hipDeviceGetAttribute(&lmax, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    for (int k = 0; k < 2; ++k) {
-        if (g->lds[k] > (size_t)lmax) {
-            set_error("padded length too large for one work-group's LDS");
+    if (d.tune >= 16) {
+        const int v = d.tune - 16;
+        if (!g->cfg_ok[v / 2]) {
+            set_error("configuration %d needs more LDS than a work-group has", v);
             sgm_gl_destroy(g);
             return SGM_ERR_UNSUPPORTED_SIZE;
         }
-        int per_cu = std::max(1, (int)(lmax / std::max<size_t>(g->lds[k], 1)));
-        if (per_cu > 4) per_cu = 4;
-        g->gridA[k] = std::min(g->nA[k], ncu * per_cu);
-        g->gridB[k] = std::min(g->nB[k], ncu * per_cu);
+        g->cfg = v / 2;
+        g->gridmode = v % 2;
+    } else if (d.tune == 1) {
+        sgm_status r = gl_autotune(g, os);
+        if (r != SGM_OK) { sgm_gl_destroy(g); return r; }
     }
     *out = g;
     return SGM_OK;
@@ -589,50 +781,18 @@ extern "C" sgm_status sgm_gl_count(sgm_gl g, int* count) {
     return SGM_OK;
 }
 
+extern "C" sgm_status sgm_gl_variant(sgm_gl g, int* variant) {
+    clear_error();
+    SGM_CHECK_ARG(g && variant, "null argument");
+    *variant = 2 * g->cfg + g->gridmode;
+    return SGM_OK;
+}
+
 extern "C" sgm_status sgm_gl_offsets(sgm_gl g, int64_t* offsets) {
     clear_error();
     SGM_CHECK_ARG(g && offsets, "null argument");
     for (size_t i = 0; i < g->off_s.size(); ++i) offsets[i] = g->off_s[i];
     return SGM_OK;
-}
-
-// One right-hand-side evaluation: passes A, B, C.
-static sgm_status gl_eval(sgm_gl g, const double2* src, const GLStage& st, hipStream_t s) {
-    for (int k = 0; k < 2; ++k) {
-        if (!g->nA[k]) continue;
-        auto ka = k ? k_gl_rows_inv<true> : k_gl_rows_inv<false>;
-        hipLaunchKernelGGL(ka, dim3(g->gridA[k]), dim3(kGlThreads), g->lds[k], s, (const GLProb*)g->dprobs,
-                           (const GLItem*)g->ditemsA[k], g->nA[k], src, g->work);
-        SGM_HIP_TRY(hipGetLastError());
-    }
-    for (int k = 0; k < 2; ++k) {
-        if (!g->nB[k]) continue;
-        auto kb = k ? k_gl_cols<true> : k_gl_cols<false>;
-        hipLaunchKernelGGL(kb, dim3(g->gridB[k]), dim3(kGlThreads), g->lds[k], s, (const GLProb*)g->dprobs,
-                           (const GLItem*)g->ditemsB[k], g->nB[k], g->work, g->d.c);
-        SGM_HIP_TRY(hipGetLastError());
-    }
-    for (int k = 0; k < 2; ++k) {
-        if (!g->nA[k]) continue;
-        auto kc = k ? k_gl_rows_fwd<true> : k_gl_rows_fwd<false>;
-        hipLaunchKernelGGL(kc, dim3(g->gridA[k]), dim3(kGlThreads), g->lds[k], s, (const GLProb*)g->dprobs,
-                           (const GLItem*)g->ditemsA[k], g->nA[k], (const double2*)g->work, st);
-        SGM_HIP_TRY(hipGetLastError());
-    }
-    return SGM_OK;
-}
-
-static GLStage base_stage(sgm_gl g) {
-    GLStage st{};
-    st.v = g->v;
-    st.acc = g->acc;
-    st.etab = g->etab;
-    st.ks = 6.283185307179586476925286766559 / g->d.L;
-    st.b = g->d.b;
-    st.c = g->d.c;
-    st.dt = g->d.dt;
-    st.edt = std::exp(g->d.dt / 2);
-    return st;
 }
 
 extern "C" sgm_status sgm_gl_rhs(sgm_gl g, const void* u_hat, void* rhs, void* stream) {
@@ -643,20 +803,11 @@ extern "C" sgm_status sgm_gl_rhs(sgm_gl g, const void* u_hat, void* rhs, void* s
     st.mode = kGlRhs;
     st.vin = static_cast<const double2*>(u_hat);
     st.rhs = static_cast<double2*>(rhs);
-    return gl_eval(g, st.vin, st, static_cast<hipStream_t>(stream));
-}
-
-static sgm_status gl_enqueue_step(sgm_gl g, double2* state, hipStream_t s) {
-    GLStage st = base_stage(g);
-    st.mode = g->d.scheme == SGM_IFRK4 ? kGlIfRk4 : kGlRk4;
-    st.state = state;
-    for (int k = 0; k < 4; ++k) {
-        st.stage = k;
-        st.vin = k == 0 ? state : g->v;
-        sgm_status r = gl_eval(g, st.vin, st, s);
-        if (r != SGM_OK) return r;
-    }
-    return SGM_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    sgm_status r = gl_pass(g, 0, st.vin, st, s);
+    if (r == SGM_OK) r = gl_pass(g, 1, nullptr, st, s);
+    if (r == SGM_OK) r = gl_pass(g, 2, nullptr, st, s);
+    return r;
 }
 
 extern "C" sgm_status sgm_gl_step(sgm_gl g, void* u_hat, int nsteps, void* stream) {

@@ -132,3 +132,34 @@ def test_c4_batch_sampled_problems(GLBatch):
     for i in range(5):
         ref = ogl.ifrk4_step(ogl.forward(us[i]), dt, L, b, c)
         assert rel_err(host(out[i]), ref) < TOL_STEP, sizes[i]
+
+
+ALL_M = [32, 64, 128, 192, 256, 384, 512, 33, 10]   # every compiled padded length + generic
+_REF = {}
+
+
+def _ref_step(scheme):
+    if scheme not in _REF:
+        L, b, c, dt = 100.0, 1.5, -2.0, 0.05
+        uhs = _spectral_inputs(ALL_M, 50, amp=0.05)
+        step = ogl.rk4_step if scheme == "rk4" else ogl.ifrk4_step
+        _REF[scheme] = (uhs, [step(u, dt, L, b, c) for u in uhs])
+    return _REF[scheme]
+
+
+@pytest.mark.parametrize("scheme", ["rk4", "ifrk4"])
+@pytest.mark.parametrize("tune", [0, 1, 2, 3, 4, 5, True])
+def test_launch_configurations(GLBatch, scheme, tune):
+    # every FFT tiling and grid mode, and the tuned choice, on one step of a batch
+    # holding each compiled padded length and two generic ones
+    print(f"[case] gl config tune={tune} scheme={scheme}", flush=True)
+    uhs, ref = _ref_step(scheme)
+    g = GLBatch(ALL_M, L=100.0, b=1.5, c=-2.0, dt=0.05, scheme=scheme, graph=True, tune=tune)
+    if tune is not True:
+        assert g.variant == tune
+    assert 0 <= g.variant < 6
+    st = g.pack(uhs)
+    g.step(st, 1)
+    out = g.unpack(st)
+    for i, n in enumerate(ALL_M):
+        assert rel_err(host(out[i]), ref[i]) < TOL_STEP, (n, g.variant)
