@@ -13,6 +13,7 @@
 #include "kernels.h"
 #include "kernels_reg.h"
 #include "solve_chain.h"
+#include "solve_seg.h"
 #include "tables.h"
 
 namespace sgm {
@@ -65,6 +66,12 @@ struct sgm_plan_s {
     ChebDev cd;
     ColGeom geom;
     int G_last, W_mid, W_cheb, W_solve;
+    // segmented solves: lanes per chain (0 = chains too long), boundary table
+    // valid for seg_alpha once seg_ok
+    int seg_K = 0;
+    double* seg_tab = nullptr;
+    bool seg_ok = false;
+    double seg_alpha = 0.0;
     // register-FFT kernels for axis lengths with a compiled instance
     bool hx = false, hy = false, hz = false;
     RegKernels rkx, rky, rkz;
@@ -348,6 +355,15 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
             if (st2 != SGM_OK) { hipFree(p->work); hipFree(p->blob); delete p; return st2; }
         }
     }
+    if (d.basis != SGM_CHEBYSHEV && d.autotune != 2) {
+        p->seg_K = seg_lanes(std::max(cd.npar[0], cd.npar[1]));
+        const size_t nt = seg_table_doubles(d.basis, p->seg_K, g.ncols);
+        if (p->seg_K > 0 && nt > 0 && hipMalloc(&p->seg_tab, nt * sizeof(double)) != hipSuccess) {
+            set_error("hipMalloc solve table failed");
+            hipFree(p->work); hipFree(p->blob); delete p;
+            return SGM_ERR_OOM;
+        }
+    }
     *out = p;
     return SGM_OK;
 }
@@ -392,6 +408,7 @@ sgm_status sgm_plan_destroy(sgm_plan p) {
     if (!p) return SGM_OK;
     for (auto& pe : p->pending) { hipEventDestroy(pe.second.first); hipEventDestroy(pe.second.second); }
     for (auto e : p->ev_pool) hipEventDestroy(e);
+    hipFree(p->seg_tab);
     hipFree(p->work);
     hipFree(p->blob);
     delete p;
@@ -519,6 +536,24 @@ sgm_status sgm_backward(sgm_plan p, const void* u_hat, void* u, void* stream) {
     return SGM_OK;
 }
 
+// Segmented solve where the chains fit, else one lane per chain.  The
+// boundary table is refilled (one extra launch) when alpha changes.
+static sgm_status solve_dispatch(sgm_plan p, int kind, double alpha, const void* f, void* u, hipStream_t s) {
+    if (p->seg_K > 0) {
+        if (!p->seg_ok || p->seg_alpha != alpha) {
+            SGM_HIP_TRY(launch_seg_table(p->seg_tab, p->cd, p->geom, kind, p->seg_K, alpha, s));
+            p->seg_ok = true;
+            p->seg_alpha = alpha;
+        }
+        SGM_HIP_TRY(launch_solve_seg(static_cast<const double2*>(f), static_cast<double2*>(u), p->seg_tab, p->cd,
+                                     p->geom, kind, p->seg_K, alpha, s));
+        return SGM_OK;
+    }
+    SGM_HIP_TRY(launch_solve_chain(static_cast<const double2*>(f), static_cast<double2*>(u),
+                                   static_cast<double*>(p->work), p->cd, p->geom, kind, alpha, s));
+    return SGM_OK;
+}
+
 sgm_status sgm_helmholtz_solve(sgm_plan p, double alpha, const void* f_tilde, void* u_hat, void* stream) {
     clear_error();
     SGM_CHECK_ARG(p && f_tilde && u_hat, "null argument");
@@ -529,9 +564,7 @@ sgm_status sgm_helmholtz_solve(sgm_plan p, double alpha, const void* f_tilde, vo
         SGM_HIP_TRY(launch_solve(static_cast<const double2*>(f_tilde), static_cast<double2*>(u_hat), p->cd, p->geom,
                                  p->W_solve, SGM_SHEN_DIRICHLET, alpha, static_cast<hipStream_t>(stream)));
     else
-        SGM_HIP_TRY(launch_solve_chain(static_cast<const double2*>(f_tilde), static_cast<double2*>(u_hat),
-                                       static_cast<double*>(p->work), p->cd, p->geom, SGM_SHEN_DIRICHLET, alpha,
-                                       static_cast<hipStream_t>(stream)));
+        return solve_dispatch(p, SGM_SHEN_DIRICHLET, alpha, f_tilde, u_hat, static_cast<hipStream_t>(stream));
     return SGM_OK;
 }
 
@@ -544,9 +577,7 @@ sgm_status sgm_biharmonic_solve(sgm_plan p, const void* f_tilde, void* u_hat, vo
         SGM_HIP_TRY(launch_solve(static_cast<const double2*>(f_tilde), static_cast<double2*>(u_hat), p->cd, p->geom,
                                  p->W_solve, SGM_SHEN_BIHARMONIC, 0.0, static_cast<hipStream_t>(stream)));
     else
-        SGM_HIP_TRY(launch_solve_chain(static_cast<const double2*>(f_tilde), static_cast<double2*>(u_hat),
-                                       static_cast<double*>(p->work), p->cd, p->geom, SGM_SHEN_BIHARMONIC, 0.0,
-                                       static_cast<hipStream_t>(stream)));
+        return solve_dispatch(p, SGM_SHEN_BIHARMONIC, 0.0, f_tilde, u_hat, static_cast<hipStream_t>(stream));
     return SGM_OK;
 }
 

@@ -1,0 +1,469 @@
+// Per-wavenumber Galerkin solves with each chain split over K lanes.
+//
+// The system of one (column, parity) chain is the one solved by the
+// one-lane-per-chain kernel:
+//   M x = f,  M = band (offsets -P..Q) + sum_r U_r(i) V_r(j) [j >= i + S],
+// eliminated bottom-up with the state
+//   rx[d] = x_{i+1+d},  rs[r] = sum_{j >= i+S} V_r(j) x_j   (d < Q, r < NR)
+// kept as affine functions c + w . (x_i, .., x_{i-P+1}) of the window.  The
+// w parts depend on the matrix only; the c parts are linear in f.
+//
+// Here the n rows of a chain are cut into K segments of at most R rows, one
+// lane each, with the segment's rows held in registers:
+//  1. w at the bottom of every segment comes from a table filled by a plain
+//     sequential sweep of the w recurrence (it depends on kappa^2 and alpha
+//     only and is cached per plan);
+//  2. each lane eliminates its segment with the incoming c state left
+//     symbolic, c = h + Mat c_in, which also yields the segment's map
+//     c_out = H + Mat c_in;
+//  3. a K-step scan over the lanes of the chain (wave shuffles) fixes c_in;
+//  4. the top-down recovery x_i = a_i + b_i . (x_{i-1}, ..) runs the same
+//     way: symbolic in the window entering the segment, a scan, then the
+//     final sweep that writes x.
+// f is read once and x written once: no workspace traffic.
+#include "kernels.h"
+#include "solve_seg.h"
+
+namespace sgm {
+
+namespace {
+
+constexpr double kHalfPi = 1.5707963267948966192;
+
+__device__ __forceinline__ int wnum(int q, int M) { return q < (M + 1) / 2 ? q : q - M; }
+
+template <int KIND>
+struct SegTraits {
+    static constexpr int P = KIND == SGM_SHEN_DIRICHLET ? 1 : 2;
+    static constexpr int Q = P, S = P, NR = P;
+    static constexpr int NC = Q + NR;      // c-state components
+    static constexpr int WS = NC * P;      // w-state doubles
+};
+
+// Band, tail factors of row i of the chain of parity p.
+template <int KIND>
+__device__ __forceinline__ void row_coeffs(const ChebDev& cd, int p, int i, int n, double mu1, double mu2,
+                                           double* band, double* U, double* V) {
+    constexpr int P = SegTraits<KIND>::P, Q = SegTraits<KIND>::Q, NR = SegTraits<KIND>::NR;
+    if constexpr (KIND == SGM_SHEN_DIRICHLET) {
+        const double k = (double)(p + 2 * i);
+        const double ck = (p + 2 * i) == 0 ? 2.0 : 1.0;
+        band[0] = i >= 1 ? -mu1 * kHalfPi : 0.0;
+        band[1] = 4.0 * kHalfPi * (k + 1.0) * (k + 2.0) + mu1 * kHalfPi * (ck + 1.0);
+        band[2] = i + 1 < n ? -mu1 * kHalfPi : 0.0;
+        U[0] = 8.0 * kHalfPi * (k + 1.0);
+        V[0] = 1.0;
+    } else {
+        const double* row = cd.solve[p] + 20 * i;
+#pragma unroll
+        for (int d = -P; d <= Q; ++d) band[d + P] = row[d + 2] + mu1 * row[7 + d] + mu2 * row[12 + d];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) { U[r] = row[15 + r]; V[r] = row[17 + r]; }
+    }
+}
+
+__device__ __forceinline__ void chain_mu(const ColGeom& g, int kind, int col, double alpha, double& mu1, double& mu2) {
+    const int iy = col / g.nlast, iz = col - iy * g.nlast;
+    const double m = g.Mmid > 1 ? (double)wnum(iy, g.Mmid) : 0.0;
+    const double nn = g.last_r2c ? (double)iz : (double)wnum(iz, g.Mlast);
+    const double k2 = g.sy * m * m + g.sz * nn * nn;
+    mu1 = kind == SGM_SHEN_DIRICHLET ? k2 + alpha : -2.0 * k2;
+    mu2 = kind == SGM_SHEN_DIRICHLET ? 0.0 : k2 * k2;
+}
+
+// One step of the w recurrence (row i); returns 1/coef0 and b.
+template <int KIND>
+__device__ __forceinline__ double w_step(const double* band, const double* U, const double* V, const double* Vnext,
+                                         bool inside, double (&wx)[SegTraits<KIND>::Q][SegTraits<KIND>::P],
+                                         double (&ws)[SegTraits<KIND>::NR][SegTraits<KIND>::P],
+                                         double (&b)[SegTraits<KIND>::P]) {
+    constexpr int P = SegTraits<KIND>::P, Q = SegTraits<KIND>::Q, NR = SegTraits<KIND>::NR, S = SegTraits<KIND>::S;
+    double coef[P + 1];
+    coef[0] = band[P];
+#pragma unroll
+    for (int e = 1; e <= P; ++e) coef[e] = band[P - e];
+#pragma unroll
+    for (int d = 1; d <= Q; ++d)
+#pragma unroll
+        for (int e = 0; e < P; ++e) coef[e] += band[P + d] * wx[d - 1][e];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int e = 0; e < P; ++e) coef[e] += U[r] * ws[r][e];
+    const double inv = 1.0 / coef[0];
+#pragma unroll
+    for (int e = 0; e < P; ++e) b[e] = -coef[e + 1] * inv;
+    // new w of x_i, x_{i+1}, ..; rep substitution x_i -> b . window
+    double nwx[Q][P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) nwx[0][e] = b[e];
+#pragma unroll
+    for (int d = 1; d < Q; ++d)
+#pragma unroll
+        for (int e = 0; e < P; ++e) nwx[d][e] = wx[d - 1][0] * b[e] + (e + 1 < P ? wx[d - 1][e + 1] : 0.0);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const double Vt = S == 1 ? V[r] : Vnext[r];
+        double o[P];
+#pragma unroll
+        for (int e = 0; e < P; ++e) o[e] = ws[r][0] * b[e] + (e + 1 < P ? ws[r][e + 1] : 0.0);
+        if (inside)
+#pragma unroll
+            for (int e = 0; e < P; ++e) o[e] += Vt * nwx[S - 1][e];
+#pragma unroll
+        for (int e = 0; e < P; ++e) ws[r][e] = o[e];
+    }
+#pragma unroll
+    for (int d = 0; d < Q; ++d)
+#pragma unroll
+        for (int e = 0; e < P; ++e) wx[d][e] = nwx[d][e];
+    return inv;
+}
+
+// w state at the bottom of every segment but the last: one lane per chain.
+template <int KIND>
+__global__ void __launch_bounds__(256) k_seg_table(ChebDev cd, ColGeom g, double alpha, int R, int K, double* tab) {
+    using T = SegTraits<KIND>;
+    constexpr int P = T::P, Q = T::Q, NR = T::NR, WS = T::WS;
+    const int chain = blockIdx.x * blockDim.x + threadIdx.x;
+    if (chain >= 2 * g.ncols) return;
+    const int p = chain / g.ncols, col = chain - p * g.ncols;
+    const int n = cd.npar[p];
+    double mu1, mu2;
+    chain_mu(g, KIND, col, alpha, mu1, mu2);
+    double wx[Q][P], ws[NR][P], Vnext[NR];
+#pragma unroll
+    for (int d = 0; d < Q; ++d)
+#pragma unroll
+        for (int e = 0; e < P; ++e) wx[d][e] = 0.0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        Vnext[r] = 0.0;
+#pragma unroll
+        for (int e = 0; e < P; ++e) ws[r][e] = 0.0;
+    }
+    auto store = [&](int s) {
+        double* o = tab + ((long)s * 2 * g.ncols + chain) * WS;
+#pragma unroll
+        for (int d = 0; d < Q; ++d)
+#pragma unroll
+            for (int e = 0; e < P; ++e) o[d * P + e] = wx[d][e];
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int e = 0; e < P; ++e) o[(Q + r) * P + e] = ws[r][e];
+    };
+    // boundaries at or beyond n see the zero state
+    for (int s = K - 2; s >= 0 && (s + 1) * R >= n; --s) store(s);
+    for (int i = n - 1; i >= R; --i) {
+        double band[2 * P + 1], U[NR], V[NR], b[P];
+        row_coeffs<KIND>(cd, p, i, n, mu1, mu2, band, U, V);
+        w_step<KIND>(band, U, V, Vnext, (i - 1 + T::S) < n, wx, ws, b);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) Vnext[r] = V[r];
+        if (i % R == 0 && i / R - 1 <= K - 2) store(i / R - 1);
+    }
+}
+
+template <int NC>
+struct Aff {
+    double2 h;
+    double m[NC];
+};
+
+template <int NC>
+__device__ __forceinline__ void aff_axpy(Aff<NC>& y, double s, const Aff<NC>& x) {
+    y.h.x += s * x.h.x;
+    y.h.y += s * x.h.y;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) y.m[c] += s * x.m[c];
+}
+
+__device__ __forceinline__ double2 shfl_down2(double2 v, int d) {
+    return make_double2(__shfl_down(v.x, d), __shfl_down(v.y, d));
+}
+__device__ __forceinline__ double2 shfl_up2(double2 v, int d) {
+    return make_double2(__shfl_up(v.x, d), __shfl_up(v.y, d));
+}
+
+// Lane layout: a wave holds C = 64/K adjacent columns of one parity, lane
+// = seg * C + column; blocks of 256 threads, waves ordered parity-major.
+template <int KIND, int K, int R>
+__global__ void __launch_bounds__(256) k_solve_seg(const double2* in, double2* out, const double* tab, ChebDev cd,
+                                                   ColGeom g, double alpha) {
+    using T = SegTraits<KIND>;
+    constexpr int P = T::P, Q = T::Q, NR = T::NR, S = T::S, NC = T::NC, WS = T::WS;
+    constexpr int C = 64 / K;
+    const int lane = threadIdx.x & 63;
+    const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int ngroups = (g.ncols + C - 1) / C;
+    const int p = gw / ngroups;
+    if (p >= 2) return;  // whole wave past the end
+    const int seg = lane / C;
+    const int col = (gw - p * ngroups) * C + (lane - seg * C);
+    const bool act = col < g.ncols;
+    const int ncols = g.ncols;
+    const int n = cd.npar[p];
+    const int lo = seg * R;
+    const long stride = 2L * ncols;
+    const long base = (long)p * ncols + (act ? col : 0);
+    double mu1, mu2;
+    chain_mu(g, KIND, act ? col : 0, alpha, mu1, mu2);
+
+    // 1. rows of the segment
+    double2 fr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        fr[r] = (act && lo + r < n) ? in[base + (long)(lo + r) * stride] : make_double2(0.0, 0.0);
+
+    // 2. incoming w state
+    double wx[Q][P], ws[NR][P], Vnext[NR];
+    {
+        const bool has = act && seg < K - 1 && (seg + 1) * R < n;
+        const double* t = tab + ((long)seg * 2 * ncols + (long)p * ncols + (act ? col : 0)) * WS;
+#pragma unroll
+        for (int d = 0; d < Q; ++d)
+#pragma unroll
+            for (int e = 0; e < P; ++e) wx[d][e] = has ? t[d * P + e] : 0.0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int e = 0; e < P; ++e) ws[r][e] = has ? t[(Q + r) * P + e] : 0.0;
+        double band[2 * P + 1], U[NR], V[NR];
+        const int hi = (seg + 1) * R;
+        if (S == 2 && hi < n) {
+            row_coeffs<KIND>(cd, p, hi, n, mu1, mu2, band, U, V);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) Vnext[r] = V[r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) Vnext[r] = 0.0;
+        }
+    }
+
+    // 3. symbolic bottom-up elimination: c = h + Mat c_in
+    Aff<NC> cx[Q], cs[NR];
+#pragma unroll
+    for (int d = 0; d < Q; ++d) {
+        cx[d].h = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) cx[d].m[c] = c == d ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        cs[r].h = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) cs[r].m[c] = c == Q + r ? 1.0 : 0.0;
+    }
+    double am[R][NC];
+    double bb[R][P];
+#pragma unroll
+    for (int r = R - 1; r >= 0; --r) {
+        const int i = lo + r;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) am[r][c] = 0.0;
+#pragma unroll
+        for (int e = 0; e < P; ++e) bb[r][e] = 0.0;
+        if (i < n) {
+            double band[2 * P + 1], U[NR], V[NR];
+            row_coeffs<KIND>(cd, p, i, n, mu1, mu2, band, U, V);
+            // c part of row i: cst = f - sum band_{+d} x_{i+d} - sum U_r sigma_r
+            Aff<NC> cst;
+            cst.h = fr[r];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) cst.m[c] = 0.0;
+#pragma unroll
+            for (int d = 1; d <= Q; ++d) aff_axpy(cst, -band[P + d], cx[d - 1]);
+#pragma unroll
+            for (int q = 0; q < NR; ++q) aff_axpy(cst, -U[q], cs[q]);
+            // w parts of x_{i+d} and sigma before the step
+            double w0x[Q], w0s[NR];
+#pragma unroll
+            for (int d = 0; d < Q; ++d) w0x[d] = wx[d][0];
+#pragma unroll
+            for (int q = 0; q < NR; ++q) w0s[q] = ws[q][0];
+            double b[P];
+            const double inv = w_step<KIND>(band, U, V, Vnext, (i - 1 + S) < n, wx, ws, b);
+            Aff<NC> a;
+            a.h = make_double2(cst.h.x * inv, cst.h.y * inv);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) a.m[c] = cst.m[c] * inv;
+            fr[r] = a.h;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) am[r][c] = a.m[c];
+#pragma unroll
+            for (int e = 0; e < P; ++e) bb[r][e] = b[e];
+            // c parts: x_i = a, x_{i+d} += w0 a, sigma_r += w0 a + V x_{i-1+S}
+            Aff<NC> ncx[Q];
+            ncx[0] = a;
+#pragma unroll
+            for (int d = 1; d < Q; ++d) {
+                ncx[d] = cx[d - 1];
+                aff_axpy(ncx[d], w0x[d - 1], a);
+            }
+            const bool inside = (i - 1 + S) < n;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                aff_axpy(cs[q], w0s[q], a);
+                if (inside) aff_axpy(cs[q], S == 1 ? V[q] : Vnext[q], ncx[S - 1]);
+            }
+#pragma unroll
+            for (int d = 0; d < Q; ++d) cx[d] = ncx[d];
+#pragma unroll
+            for (int q = 0; q < NR; ++q) Vnext[q] = V[q];
+        }
+    }
+
+    // 4. scan up the chain: c_in of segment s = map of segment s+1 applied to its c_in
+    double2 cin[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) cin[c] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < K - 1; ++t) {
+        double2 cout[NC];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            const Aff<NC>& src = j < Q ? cx[j] : cs[j - Q];
+            double2 v = src.h;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) { v.x += src.m[c] * cin[c].x; v.y += src.m[c] * cin[c].y; }
+            cout[j] = v;
+        }
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            const double2 v = shfl_down2(cout[j], C);
+            cin[j] = seg == K - 1 ? make_double2(0.0, 0.0) : v;
+        }
+    }
+
+    // 5. a_i, then the top-down recovery symbolic in the incoming window
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        double2 a = fr[r];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) { a.x += am[r][c] * cin[c].x; a.y += am[r][c] * cin[c].y; }
+        fr[r] = a;
+    }
+    Aff<P> win[P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+        win[e].h = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < P; ++c) win[e].m[c] = c == e ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (lo + r < n) {
+            Aff<P> x;
+            x.h = fr[r];
+#pragma unroll
+            for (int c = 0; c < P; ++c) x.m[c] = 0.0;
+#pragma unroll
+            for (int e = 0; e < P; ++e) aff_axpy(x, bb[r][e], win[e]);
+#pragma unroll
+            for (int e = P - 1; e > 0; --e) win[e] = win[e - 1];
+            win[0] = x;
+        }
+    }
+    double2 zin[P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) zin[e] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < K - 1; ++t) {
+        double2 zout[P];
+#pragma unroll
+        for (int e = 0; e < P; ++e) {
+            double2 v = win[e].h;
+#pragma unroll
+            for (int c = 0; c < P; ++c) { v.x += win[e].m[c] * zin[c].x; v.y += win[e].m[c] * zin[c].y; }
+            zout[e] = v;
+        }
+#pragma unroll
+        for (int e = 0; e < P; ++e) {
+            const double2 v = shfl_up2(zout[e], C);
+            zin[e] = seg == 0 ? make_double2(0.0, 0.0) : v;
+        }
+    }
+
+    // 6. final sweep
+    double2 w[P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) w[e] = zin[e];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = lo + r;
+        if (i < n) {
+            double2 x = fr[r];
+#pragma unroll
+            for (int e = 0; e < P; ++e) { x.x += bb[r][e] * w[e].x; x.y += bb[r][e] * w[e].y; }
+            if (act) out[base + (long)i * stride] = x;
+#pragma unroll
+            for (int e = P - 1; e > 0; --e) w[e] = w[e - 1];
+            w[0] = x;
+        }
+    }
+    // rows beyond the basis of this parity are zero
+    if (act)
+        for (int l = p + 2 * n + 2 * seg; l < cd.N; l += 2 * K) out[(long)l * ncols + col] = make_double2(0.0, 0.0);
+}
+
+template <int KIND, int K>
+hipError_t launch_seg_k(const double2* in, double2* out, const double* tab, const ChebDev& cd, const ColGeom& g,
+                        double alpha, hipStream_t s) {
+    constexpr int C = 64 / K;
+    const long waves = 2L * ((g.ncols + C - 1) / C);
+    const long blocks = (waves + 3) / 4;
+    hipLaunchKernelGGL((k_solve_seg<KIND, K, kSegRows>), dim3((unsigned)blocks), dim3(256), 0, s, in, out, tab, cd, g,
+                       alpha);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int seg_lanes(int nmax) {
+    int K = 1;
+    while (K * kSegRows < nmax) K *= 2;
+    return K <= kSegMaxLanes ? K : 0;
+}
+
+size_t seg_table_doubles(int kind, int K, int ncols) {
+    const int WS = kind == SGM_SHEN_DIRICHLET ? SegTraits<SGM_SHEN_DIRICHLET>::WS : SegTraits<SGM_SHEN_BIHARMONIC>::WS;
+    return K > 1 ? (size_t)(K - 1) * 2 * ncols * WS : 0;
+}
+
+hipError_t launch_seg_table(double* tab, const ChebDev& cd, const ColGeom& g, int kind, int K, double alpha,
+                            hipStream_t s) {
+    if (K <= 1) return hipSuccess;
+    const int blocks = (2 * g.ncols + 255) / 256;
+    if (kind == SGM_SHEN_DIRICHLET)
+        hipLaunchKernelGGL(k_seg_table<SGM_SHEN_DIRICHLET>, dim3(blocks), dim3(256), 0, s, cd, g, alpha, kSegRows, K,
+                           tab);
+    else
+        hipLaunchKernelGGL(k_seg_table<SGM_SHEN_BIHARMONIC>, dim3(blocks), dim3(256), 0, s, cd, g, alpha, kSegRows, K,
+                           tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_seg(const double2* in, double2* out, const double* tab, const ChebDev& cd, const ColGeom& g,
+                            int kind, int K, double alpha, hipStream_t s) {
+    if (kind == SGM_SHEN_DIRICHLET) {
+        switch (K) {
+            case 1: return launch_seg_k<SGM_SHEN_DIRICHLET, 1>(in, out, tab, cd, g, alpha, s);
+            case 2: return launch_seg_k<SGM_SHEN_DIRICHLET, 2>(in, out, tab, cd, g, alpha, s);
+            case 4: return launch_seg_k<SGM_SHEN_DIRICHLET, 4>(in, out, tab, cd, g, alpha, s);
+            case 8: return launch_seg_k<SGM_SHEN_DIRICHLET, 8>(in, out, tab, cd, g, alpha, s);
+            case 16: return launch_seg_k<SGM_SHEN_DIRICHLET, 16>(in, out, tab, cd, g, alpha, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (K) {
+        case 1: return launch_seg_k<SGM_SHEN_BIHARMONIC, 1>(in, out, tab, cd, g, alpha, s);
+        case 2: return launch_seg_k<SGM_SHEN_BIHARMONIC, 2>(in, out, tab, cd, g, alpha, s);
+        case 4: return launch_seg_k<SGM_SHEN_BIHARMONIC, 4>(in, out, tab, cd, g, alpha, s);
+        case 8: return launch_seg_k<SGM_SHEN_BIHARMONIC, 8>(in, out, tab, cd, g, alpha, s);
+        case 16: return launch_seg_k<SGM_SHEN_BIHARMONIC, 16>(in, out, tab, cd, g, alpha, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace sgm

@@ -202,3 +202,28 @@ def test_autotuned_plan(Plan):
     uh = host(p.forward(dev(u)))
     cols = _sample_cols(p.spec_shape, np.random.default_rng(1), n=8)
     assert rel_err(uh.reshape(256, -1)[:, cols], T.forward_columns("dirichlet", u, cols)) < TOL_T
+
+
+SOLVE_N = ([("dirichlet", n) for n in (6, 18, 35, 36, 66, 67, 130, 131, 258, 300, 515, 540)]
+           + [("biharmonic", n) for n in (8, 21, 40, 70, 133, 262, 300, 520, 600)])
+
+
+@pytest.mark.parametrize("basis,N", SOLVE_N)
+def test_solve_chain_lengths(Plan, basis, N):
+    # chain lengths covering 1..16 lanes per chain with ragged last segments and
+    # chains too long for the segmented kernel; alpha changes on one plan refill
+    # its cached boundary table
+    print(f"[case] solve lengths {basis} N={N}", flush=True)
+    p = Plan(basis, N, 6)
+    nrows = N - 2 if basis == "dirichlet" else N - 4
+    ft = synth.random_spectral(p.spec_shape, seed=300 + N, nrows=nrows)
+    if basis == "dirichlet":
+        for alpha in (0.0, 1.0, 0.0, 2.5):
+            ref = T.helmholtz_solve(basis, ft, alpha, 6)
+            assert rel_err(host(p.helmholtz_solve(dev(ft), alpha)), ref) < TOL_S, alpha
+    else:
+        ref = T.biharmonic_solve(basis, ft, 6)
+        assert rel_err(host(p.biharmonic_solve(dev(ft))), ref) < TOL_S
+        t = dev(ft)
+        p.biharmonic_solve(t, out=t)
+        assert rel_err(host(t), ref) < TOL_S
