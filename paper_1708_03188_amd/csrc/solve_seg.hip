@@ -14,10 +14,12 @@
 //     sequential sweep of the w recurrence (it depends on kappa^2 and alpha
 //     only and is cached per plan);
 //  2. each lane eliminates its segment with the incoming c state left
-//     symbolic, c = h + Mat c_in, which also yields the segment's map
-//     c_out = H + Mat c_in;
+//     symbolic, c = h + Mat c_in, which gives the segment's map
+//     c_out = H + Mat c_in (nothing is stored per row);
 //  3. a K-step scan over the lanes of the chain (wave shuffles) fixes c_in;
-//  4. the top-down recovery x_i = a_i + b_i . (x_{i-1}, ..) runs the same
+//  4. a second, concrete elimination from the exact entering state leaves
+//     a_i and b_i of every row in registers;
+//  5. the top-down recovery x_i = a_i + b_i . (x_{i-1}, ..) runs the same
 //     way: symbolic in the window entering the segment, a scan, then the
 //     final sweep that writes x.
 // f is read once and x written once: no workspace traffic.
@@ -179,6 +181,63 @@ __device__ __forceinline__ void aff_axpy(Aff<NC>& y, double s, const Aff<NC>& x)
     for (int c = 0; c < NC; ++c) y.m[c] += s * x.m[c];
 }
 
+__device__ __forceinline__ void aff_axpy(double2& y, double s, const double2& x) {
+    y.x += s * x.x;
+    y.y += s * x.y;
+}
+template <int NC>
+__device__ __forceinline__ void aff_scale(Aff<NC>& y, double s) {
+    y.h.x *= s;
+    y.h.y *= s;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) y.m[c] *= s;
+}
+__device__ __forceinline__ void aff_scale(double2& y, double s) {
+    y.x *= s;
+    y.y *= s;
+}
+
+// One row of the bottom-up elimination for either c representation (Aff: c
+// symbolic in the state entering the segment; double2: concrete).  On entry
+// cst holds f_i; on exit it holds a_i, b the window coefficients of x_i.
+template <int KIND, class CT>
+__device__ __forceinline__ void elim_row(const double* band, const double* U, const double* V,
+                                         double (&Vnext)[SegTraits<KIND>::NR], bool inside,
+                                         double (&wx)[SegTraits<KIND>::Q][SegTraits<KIND>::P],
+                                         double (&ws)[SegTraits<KIND>::NR][SegTraits<KIND>::P],
+                                         CT (&cx)[SegTraits<KIND>::Q], CT (&cs)[SegTraits<KIND>::NR], CT& cst,
+                                         double (&b)[SegTraits<KIND>::P]) {
+    constexpr int P = SegTraits<KIND>::P, Q = SegTraits<KIND>::Q, NR = SegTraits<KIND>::NR, S = SegTraits<KIND>::S;
+#pragma unroll
+    for (int d = 1; d <= Q; ++d) aff_axpy(cst, -band[P + d], cx[d - 1]);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) aff_axpy(cst, -U[q], cs[q]);
+    double w0x[Q], w0s[NR];
+#pragma unroll
+    for (int d = 0; d < Q; ++d) w0x[d] = wx[d][0];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) w0s[q] = ws[q][0];
+    const double inv = w_step<KIND>(band, U, V, Vnext, inside, wx, ws, b);
+    aff_scale(cst, inv);
+    // x_i = a, x_{i+d} += w0 a, sigma_r += w0 a + V x_{i-1+S}
+    CT ncx[Q];
+    ncx[0] = cst;
+#pragma unroll
+    for (int d = 1; d < Q; ++d) {
+        ncx[d] = cx[d - 1];
+        aff_axpy(ncx[d], w0x[d - 1], cst);
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        aff_axpy(cs[q], w0s[q], cst);
+        if (inside) aff_axpy(cs[q], S == 1 ? V[q] : Vnext[q], ncx[S - 1]);
+    }
+#pragma unroll
+    for (int d = 0; d < Q; ++d) cx[d] = ncx[d];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) Vnext[q] = V[q];
+}
+
 __device__ __forceinline__ double2 shfl_down2(double2 v, int d) {
     return make_double2(__shfl_down(v.x, d), __shfl_down(v.y, d));
 }
@@ -217,100 +276,63 @@ __global__ void __launch_bounds__(256) k_solve_seg(const double2* in, double2* o
         fr[r] = (act && lo + r < n) ? in[base + (long)(lo + r) * stride] : make_double2(0.0, 0.0);
 
     // 2. incoming w state
-    double wx[Q][P], ws[NR][P], Vnext[NR];
+    double wx0[Q][P], ws0[NR][P], Vn0[NR];
     {
         const bool has = act && seg < K - 1 && (seg + 1) * R < n;
         const double* t = tab + ((long)seg * 2 * ncols + (long)p * ncols + (act ? col : 0)) * WS;
 #pragma unroll
         for (int d = 0; d < Q; ++d)
 #pragma unroll
-            for (int e = 0; e < P; ++e) wx[d][e] = has ? t[d * P + e] : 0.0;
+            for (int e = 0; e < P; ++e) wx0[d][e] = has ? t[d * P + e] : 0.0;
 #pragma unroll
         for (int r = 0; r < NR; ++r)
 #pragma unroll
-            for (int e = 0; e < P; ++e) ws[r][e] = has ? t[(Q + r) * P + e] : 0.0;
+            for (int e = 0; e < P; ++e) ws0[r][e] = has ? t[(Q + r) * P + e] : 0.0;
         double band[2 * P + 1], U[NR], V[NR];
         const int hi = (seg + 1) * R;
         if (S == 2 && hi < n) {
             row_coeffs<KIND>(cd, p, hi, n, mu1, mu2, band, U, V);
 #pragma unroll
-            for (int r = 0; r < NR; ++r) Vnext[r] = V[r];
+            for (int r = 0; r < NR; ++r) Vn0[r] = V[r];
         } else {
 #pragma unroll
-            for (int r = 0; r < NR; ++r) Vnext[r] = 0.0;
+            for (int r = 0; r < NR; ++r) Vn0[r] = 0.0;
         }
     }
 
-    // 3. symbolic bottom-up elimination: c = h + Mat c_in
+    // 3. symbolic pass over the segment: its map c_out = H + Mat c_in
     Aff<NC> cx[Q], cs[NR];
+    {
+        double wx[Q][P], ws[NR][P], Vnext[NR];
 #pragma unroll
-    for (int d = 0; d < Q; ++d) {
-        cx[d].h = make_double2(0.0, 0.0);
+        for (int d = 0; d < Q; ++d) {
+            cx[d].h = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) cx[d].m[c] = c == d ? 1.0 : 0.0;
-    }
+            for (int c = 0; c < NC; ++c) cx[d].m[c] = c == d ? 1.0 : 0.0;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        cs[r].h = make_double2(0.0, 0.0);
+            for (int e = 0; e < P; ++e) wx[d][e] = wx0[d][e];
+        }
 #pragma unroll
-        for (int c = 0; c < NC; ++c) cs[r].m[c] = c == Q + r ? 1.0 : 0.0;
-    }
-    double am[R][NC];
-    double bb[R][P];
+        for (int r = 0; r < NR; ++r) {
+            cs[r].h = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int r = R - 1; r >= 0; --r) {
-        const int i = lo + r;
+            for (int c = 0; c < NC; ++c) cs[r].m[c] = c == Q + r ? 1.0 : 0.0;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) am[r][c] = 0.0;
+            for (int e = 0; e < P; ++e) ws[r][e] = ws0[r][e];
+            Vnext[r] = Vn0[r];
+        }
 #pragma unroll
-        for (int e = 0; e < P; ++e) bb[r][e] = 0.0;
-        if (i < n) {
-            double band[2 * P + 1], U[NR], V[NR];
-            row_coeffs<KIND>(cd, p, i, n, mu1, mu2, band, U, V);
-            // c part of row i: cst = f - sum band_{+d} x_{i+d} - sum U_r sigma_r
-            Aff<NC> cst;
-            cst.h = fr[r];
+        for (int r = R - 1; r >= 0; --r) {
+            const int i = lo + r;
+            if (i < n) {
+                double band[2 * P + 1], U[NR], V[NR], b[P];
+                row_coeffs<KIND>(cd, p, i, n, mu1, mu2, band, U, V);
+                Aff<NC> cst;
+                cst.h = fr[r];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) cst.m[c] = 0.0;
-#pragma unroll
-            for (int d = 1; d <= Q; ++d) aff_axpy(cst, -band[P + d], cx[d - 1]);
-#pragma unroll
-            for (int q = 0; q < NR; ++q) aff_axpy(cst, -U[q], cs[q]);
-            // w parts of x_{i+d} and sigma before the step
-            double w0x[Q], w0s[NR];
-#pragma unroll
-            for (int d = 0; d < Q; ++d) w0x[d] = wx[d][0];
-#pragma unroll
-            for (int q = 0; q < NR; ++q) w0s[q] = ws[q][0];
-            double b[P];
-            const double inv = w_step<KIND>(band, U, V, Vnext, (i - 1 + S) < n, wx, ws, b);
-            Aff<NC> a;
-            a.h = make_double2(cst.h.x * inv, cst.h.y * inv);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) a.m[c] = cst.m[c] * inv;
-            fr[r] = a.h;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) am[r][c] = a.m[c];
-#pragma unroll
-            for (int e = 0; e < P; ++e) bb[r][e] = b[e];
-            // c parts: x_i = a, x_{i+d} += w0 a, sigma_r += w0 a + V x_{i-1+S}
-            Aff<NC> ncx[Q];
-            ncx[0] = a;
-#pragma unroll
-            for (int d = 1; d < Q; ++d) {
-                ncx[d] = cx[d - 1];
-                aff_axpy(ncx[d], w0x[d - 1], a);
+                for (int c = 0; c < NC; ++c) cst.m[c] = 0.0;
+                elim_row<KIND>(band, U, V, Vnext, (i - 1 + S) < n, wx, ws, cx, cs, cst, b);
             }
-            const bool inside = (i - 1 + S) < n;
-#pragma unroll
-            for (int q = 0; q < NR; ++q) {
-                aff_axpy(cs[q], w0s[q], a);
-                if (inside) aff_axpy(cs[q], S == 1 ? V[q] : Vnext[q], ncx[S - 1]);
-            }
-#pragma unroll
-            for (int d = 0; d < Q; ++d) cx[d] = ncx[d];
-#pragma unroll
-            for (int q = 0; q < NR; ++q) Vnext[q] = V[q];
         }
     }
 
@@ -336,14 +358,38 @@ __global__ void __launch_bounds__(256) k_solve_seg(const double2* in, double2* o
         }
     }
 
-    // 5. a_i, then the top-down recovery symbolic in the incoming window
+    // 5. concrete pass from the exact entering state: a_i (over f_i) and b_i
+    double bb[R][P];
+    {
+        double wx[Q][P], ws[NR][P], Vnext[NR];
+        double2 cx2[Q], cs2[NR];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        double2 a = fr[r];
+        for (int d = 0; d < Q; ++d) {
+            cx2[d] = cin[d];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) { a.x += am[r][c] * cin[c].x; a.y += am[r][c] * cin[c].y; }
-        fr[r] = a;
+            for (int e = 0; e < P; ++e) wx[d][e] = wx0[d][e];
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            cs2[r] = cin[Q + r];
+#pragma unroll
+            for (int e = 0; e < P; ++e) ws[r][e] = ws0[r][e];
+            Vnext[r] = Vn0[r];
+        }
+#pragma unroll
+        for (int r = R - 1; r >= 0; --r) {
+            const int i = lo + r;
+#pragma unroll
+            for (int e = 0; e < P; ++e) bb[r][e] = 0.0;
+            if (i < n) {
+                double band[2 * P + 1], U[NR], V[NR];
+                row_coeffs<KIND>(cd, p, i, n, mu1, mu2, band, U, V);
+                elim_row<KIND>(band, U, V, Vnext, (i - 1 + S) < n, wx, ws, cx2, cs2, fr[r], bb[r]);
+            }
+        }
     }
+
+    // 6. top-down recovery, symbolic in the window entering the segment
     Aff<P> win[P];
 #pragma unroll
     for (int e = 0; e < P; ++e) {
@@ -385,7 +431,7 @@ __global__ void __launch_bounds__(256) k_solve_seg(const double2* in, double2* o
         }
     }
 
-    // 6. final sweep
+    // 7. final sweep
     double2 w[P];
 #pragma unroll
     for (int e = 0; e < P; ++e) w[e] = zin[e];
