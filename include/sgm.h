@@ -101,17 +101,21 @@ sgm_status sgm_scalar_product(sgm_plan plan, const void* f, void* f_tilde, void*
  * kappa^2 = (2pi m/Ly)^2 + (2pi n/Lz)^2, solves (-A + (kappa^2 + alpha) B) u_hat = f_tilde
  * (eq. cheb_poisson, eq. laplace), A_ml = (phi_l'', phi_m), B_ml = (phi_l, phi_m).
  * f_tilde and u_hat are spectral arrays (rows >= N-2 of f_tilde ignored); they
- * may be the same pointer (in-place).  alpha >= 0.  INVALID_ARG otherwise. */
+ * may be the same pointer (in-place).  alpha >= 0.  INVALID_ARG otherwise.  The
+ * first call with a given alpha also refreshes a plan-owned table of elimination
+ * states at chain-segment boundaries (one extra kernel on the same stream); calls
+ * that overlap on one plan race. */
 sgm_status sgm_helmholtz_solve(sgm_plan plan, double alpha, const void* f_tilde, void* u_hat, void* stream);
 
 /* Biharmonic solve lap^2 u = f for the Shen-biharmonic plan (Sec. 4): per column
  * (S - 2 kappa^2 A + kappa^4 B) u_hat = f_tilde with S_ml = (phi_l'''', phi_m).
- * Same layout and aliasing rules as sgm_helmholtz_solve. */
+ * Same layout, aliasing rules and first-call table fill as sgm_helmholtz_solve. */
 sgm_status sgm_biharmonic_solve(sgm_plan plan, const void* f_tilde, void* u_hat, void* stream);
 
-/* Per-pass timing (diagnostics).  When enabled, every pass kernel this plan
- * launches is bracketed by two hipEvents recorded on the caller's stream
- * (the events are created on first use and owned by the plan).  Pass kinds:
+/* Per-pass timing (diagnostics).  enable = 0: off; 1: every pass kernel this plan
+ * launches is bracketed by two hipEvents recorded on the caller's stream (the
+ * events are created on first use and owned by the plan); SGM_TIMING_ONLY | bits:
+ * only the pass kinds whose bit (1 << kind) is set.  Pass kinds:
  * 0 last-axis forward FFT, 1 last-axis backward FFT, 2 middle-axis forward FFT,
  * 3 middle-axis backward FFT, 4 Chebyshev forward (projection), 5 Chebyshev
  * scalar product, 6 Chebyshev backward, 7 Galerkin solve.
@@ -119,6 +123,7 @@ sgm_status sgm_biharmonic_solve(sgm_plan plan, const void* f_tilde, void* u_hat,
  * ms[SGM_NPASS] and launch counts to count[SGM_NPASS] (running totals since the
  * last reset) and, if reset != 0, clears the totals afterwards. */
 #define SGM_NPASS 8
+#define SGM_TIMING_ONLY 0x100
 sgm_status sgm_plan_timing(sgm_plan plan, int enable);
 /* Register-kernel variant in use per axis (x, y, z): 0..3, or -1 where the axis runs
  * the generic LDS kernels (diagnostics; chosen at creation, see autotune). */

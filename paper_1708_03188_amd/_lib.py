@@ -86,6 +86,7 @@ _SIGS = {
                             ctypes.c_int),
 }
 NPASS = 8
+SGM_TIMING_ONLY = 0x100
 PASS_NAMES = ["last_fwd", "last_bwd", "mid_fwd", "mid_bwd", "cheb_fwd", "cheb_scalar", "cheb_bwd", "solve"]
 
 

@@ -63,9 +63,17 @@ class Plan:
         except Exception:
             pass
 
-    def set_timing(self, enable=True):
-        """Bracket every pass kernel of this plan with hipEvents (diagnostics)."""
-        check(self._lib.sgm_plan_timing(self._h, int(bool(enable))), "sgm_plan_timing")
+    def set_timing(self, enable=True, passes=None):
+        """Bracket pass kernels of this plan with hipEvents (diagnostics): all of
+        them, or only the named passes (see PASS_NAMES)."""
+        if enable and passes is not None:
+            bits = 0
+            for name in passes:
+                bits |= 1 << _lib.PASS_NAMES.index(name)
+            flag = _lib.SGM_TIMING_ONLY | bits
+        else:
+            flag = int(bool(enable))
+        check(self._lib.sgm_plan_timing(self._h, flag), "sgm_plan_timing")
 
     def variants(self):
         """Register-kernel variant per axis (x, y, z); -1 = generic kernels."""

@@ -17,6 +17,16 @@ constexpr int kLdsBudget = 131072;
 
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 
+// Work-groups go to the 8 XCDs round-robin (block b to XCD b mod 8).  Renumber
+// them so that each XCD walks a contiguous range of tiles: neighbouring tiles
+// share the cache lines that straddle their boundary (rows of M/2+1 complex
+// values are not line aligned), and those then meet in one L2.  A bijection
+// on [0, gridDim.x) for any grid size.
+__device__ __forceinline__ int xcd_block() {
+    const int per = (int)(gridDim.x >> 3), b = (int)blockIdx.x;
+    return b < 8 * per ? (b & 7) * per + (b >> 3) : b;
+}
+
 // Launch geometry of one variant: NTMAX bounds the threads per line (so
 // E = L / NT points per thread), NB is the number of exchange buffers.
 template <int L, int NTMAX_, int NB_>
@@ -77,7 +87,7 @@ __global__ void __launch_bounds__(kThreads) kr_lines_c2r(const double2* __restri
     const int t = threadIdx.x % G::NT, g = threadIdx.x / G::NT;
     double2* b0 = lds + g * L;
     double2* b1 = lds + G::B1OFF + g * L;
-    const long l0 = ((long)blockIdx.x * G::W + g) * 2;
+    const long l0 = ((long)xcd_block() * G::W + g) * 2;
     constexpr int Lh = L / 2 + 1;
     double2 x[G::E];
 #pragma unroll
@@ -106,7 +116,7 @@ __global__ void __launch_bounds__(kThreads) kr_lines_c2c(const double2* __restri
     const int t = threadIdx.x % G::NT, g = threadIdx.x / G::NT;
     double2* b0 = lds + g * L;
     double2* b1 = lds + G::B1OFF + g * L;
-    const long ln = (long)blockIdx.x * G::W + g;
+    const long ln = (long)xcd_block() * G::W + g;
     double2 x[G::E];
 #pragma unroll
     for (int e = 0; e < G::E; ++e) x[e] = ln < nlines ? in[ln * L + t + G::NT * e] : make_double2(0.0, 0.0);
@@ -126,8 +136,9 @@ __global__ void __launch_bounds__(kThreads) kr_strided(const double2* in, double
     extern __shared__ double2 lds[];
     const int c = threadIdx.x % G::W, t = threadIdx.x / G::W;
     const int tiles = (inner + G::W - 1) / G::W;
-    const int o = blockIdx.x / tiles;
-    const int c0 = (blockIdx.x - o * tiles) * G::W;
+    const int bid = xcd_block();
+    const int o = bid / tiles;
+    const int c0 = (bid - o * tiles) * G::W;
     const bool ok = c0 + c < inner;
     const long base = (long)o * L * inner + c0 + c;
     double2 x[G::E];
@@ -204,7 +215,7 @@ __global__ void __launch_bounds__(kThreads) kr_cheb_fwd(const double2* in, doubl
     double2* B1 = lds + G::B1OFF;
     double2* SC = lds + G::NB * N * W;
     const int c = threadIdx.x % W, t = threadIdx.x / W;
-    const int c0 = blockIdx.x * W;
+    const int c0 = xcd_block() * W;
     const bool ok = c0 + c < ncols;
     double2 x[E];
 #pragma unroll
@@ -341,7 +352,7 @@ __global__ void __launch_bounds__(kThreads) kr_cheb_bwd(const double2* in, doubl
     double2* B0 = lds;
     double2* B1 = lds + G::B1OFF;
     const int c = threadIdx.x % W, t = threadIdx.x / W;
-    const int c0 = blockIdx.x * W;
+    const int c0 = xcd_block() * W;
     const bool ok = c0 + c < ncols;
     const int nb = cd.nb;
 #pragma unroll

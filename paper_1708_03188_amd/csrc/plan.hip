@@ -76,7 +76,7 @@ struct sgm_plan_s {
     bool hx = false, hy = false, hz = false;
     RegKernels rkx, rky, rkz;
     // per-pass timing
-    bool timing = false;
+    unsigned timing = 0;   // bit k: bracket passes of kind k
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
     double pass_ms[SGM_NPASS] = {0};
@@ -90,7 +90,7 @@ struct PassTimer {
     hipStream_t s;
     hipEvent_t e1 = nullptr, e2 = nullptr;
     PassTimer(sgm_plan_s* p_, int k, hipStream_t s_) : p(p_), kind(k), s(s_) {
-        if (!p->timing) return;
+        if (!((p->timing >> kind) & 1u)) return;
         e1 = take();
         e2 = take();
         if (e1) hipEventRecord(e1, s);
@@ -102,7 +102,7 @@ struct PassTimer {
         return e;
     }
     ~PassTimer() {
-        if (!p->timing || !e1 || !e2) return;
+        if (!((p->timing >> kind) & 1u) || !e1 || !e2) return;
         hipEventRecord(e2, s);
         p->pending.push_back({kind, {e1, e2}});
     }
@@ -288,7 +288,15 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
         o_qt[q] = b.add(ct.qtab[q]);
         o_rot[q] = b.add(ct.rot[q]);
         o_rt[q] = b.add(ct.rtab[q]);
-        o_sv[q] = b.add(ct.solve[q]);
+        // identity rows (T0 diagonal 1, no coupling) past the end of the chain, up to the
+        // rows covered by the segmented solve
+        std::vector<double> sv = ct.solve[q];
+        const int kseg = seg_lanes(std::max(ct.npar[0], ct.npar[1]));
+        for (int i = ct.npar[q]; i < kseg * kSegRows + 1; ++i) {
+            sv.resize(20 * (size_t)(i + 1), 0.0);
+            sv[20 * (size_t)i + 2] = 1.0;
+        }
+        o_sv[q] = b.add(sv);
     }
     hipError_t e = hipMalloc(&p->blob, b.host.size());
     if (e != hipSuccess) { set_error("hipMalloc tables: %s", hipGetErrorString(e)); delete p; return SGM_ERR_OOM; }
@@ -371,7 +379,7 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
 sgm_status sgm_plan_timing(sgm_plan p, int enable) {
     clear_error();
     SGM_CHECK_ARG(p, "null plan");
-    p->timing = enable != 0;
+    p->timing = (enable & SGM_TIMING_ONLY) ? (unsigned)(enable & 0xff) : (enable ? 0xffu : 0u);
     return SGM_OK;
 }
 

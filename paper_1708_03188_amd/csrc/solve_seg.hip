@@ -23,6 +23,8 @@
 //     way: symbolic in the window entering the segment, a scan, then the
 //     final sweep that writes x.
 // f is read once and x written once: no workspace traffic.
+#include <algorithm>
+
 #include "kernels.h"
 #include "solve_seg.h"
 
@@ -42,26 +44,46 @@ struct SegTraits {
     static constexpr int WS = NC * P;      // w-state doubles
 };
 
-// Band, tail factors of row i of the chain of parity p.
+// Band, tail factors of row i of the chain of parity p (Dirichlet in closed
+// form, biharmonic from the plan's row table, 20 doubles per row).  Rows
+// i >= n are identity rows (x_i = 0, no coupling).
 template <int KIND>
-__device__ __forceinline__ void row_coeffs(const ChebDev& cd, int p, int i, int n, double mu1, double mu2,
+__device__ __forceinline__ void row_coeffs(const double* rows, int p, int i, int n, double mu1, double mu2,
                                            double* band, double* U, double* V) {
     constexpr int P = SegTraits<KIND>::P, Q = SegTraits<KIND>::Q, NR = SegTraits<KIND>::NR;
     if constexpr (KIND == SGM_SHEN_DIRICHLET) {
+        const bool valid = i < n;
         const double k = (double)(p + 2 * i);
         const double ck = (p + 2 * i) == 0 ? 2.0 : 1.0;
-        band[0] = i >= 1 ? -mu1 * kHalfPi : 0.0;
-        band[1] = 4.0 * kHalfPi * (k + 1.0) * (k + 2.0) + mu1 * kHalfPi * (ck + 1.0);
+        band[0] = (i >= 1 && valid) ? -mu1 * kHalfPi : 0.0;
+        band[1] = valid ? 4.0 * kHalfPi * (k + 1.0) * (k + 2.0) + mu1 * kHalfPi * (ck + 1.0) : 1.0;
         band[2] = i + 1 < n ? -mu1 * kHalfPi : 0.0;
-        U[0] = 8.0 * kHalfPi * (k + 1.0);
-        V[0] = 1.0;
+        U[0] = valid ? 8.0 * kHalfPi * (k + 1.0) : 0.0;
+        V[0] = valid ? 1.0 : 0.0;
     } else {
-        const double* row = cd.solve[p] + 20 * i;
+        const double2* row = reinterpret_cast<const double2*>(rows + 20 * i);
+        double v[20];
 #pragma unroll
-        for (int d = -P; d <= Q; ++d) band[d + P] = row[d + 2] + mu1 * row[7 + d] + mu2 * row[12 + d];
+        for (int j = 0; j < 10; ++j) {
+            const double2 t = row[j];
+            v[2 * j] = t.x;
+            v[2 * j + 1] = t.y;
+        }
 #pragma unroll
-        for (int r = 0; r < NR; ++r) { U[r] = row[15 + r]; V[r] = row[17 + r]; }
+        for (int d = -P; d <= Q; ++d) band[d + P] = v[d + 2] + mu1 * v[7 + d] + mu2 * v[12 + d];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) { U[r] = v[15 + r]; V[r] = v[17 + r]; }
     }
+}
+
+// 1/a for the pivots (well scaled, never denormal): hardware estimate and two
+// Newton steps r <- r + r (1 - a r).
+__device__ __forceinline__ double recip(double a) {
+    double r = __builtin_amdgcn_rcp(a);
+    double e = __builtin_fma(-a, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-a, r, 1.0);
+    return __builtin_fma(r, e, r);
 }
 
 __device__ __forceinline__ void chain_mu(const ColGeom& g, int kind, int col, double alpha, double& mu1, double& mu2) {
@@ -92,7 +114,7 @@ __device__ __forceinline__ double w_step(const double* band, const double* U, co
     for (int r = 0; r < NR; ++r)
 #pragma unroll
         for (int e = 0; e < P; ++e) coef[e] += U[r] * ws[r][e];
-    const double inv = 1.0 / coef[0];
+    const double inv = recip(coef[0]);
 #pragma unroll
     for (int e = 0; e < P; ++e) b[e] = -coef[e + 1] * inv;
     // new w of x_i, x_{i+1}, ..; rep substitution x_i -> b . window
@@ -159,7 +181,7 @@ __global__ void __launch_bounds__(256) k_seg_table(ChebDev cd, ColGeom g, double
     for (int s = K - 2; s >= 0 && (s + 1) * R >= n; --s) store(s);
     for (int i = n - 1; i >= R; --i) {
         double band[2 * P + 1], U[NR], V[NR], b[P];
-        row_coeffs<KIND>(cd, p, i, n, mu1, mu2, band, U, V);
+        row_coeffs<KIND>(cd.solve[p], p, i, n, mu1, mu2, band, U, V);
         w_step<KIND>(band, U, V, Vnext, (i - 1 + T::S) < n, wx, ws, b);
 #pragma unroll
         for (int r = 0; r < NR; ++r) Vnext[r] = V[r];
@@ -245,19 +267,17 @@ __device__ __forceinline__ double2 shfl_up2(double2 v, int d) {
     return make_double2(__shfl_up(v.x, d), __shfl_up(v.y, d));
 }
 
-// Lane layout: a wave holds C = 64/K adjacent columns of one parity, lane
-// = seg * C + column; blocks of 256 threads, waves ordered parity-major.
 template <int KIND, int K, int R>
-__global__ void __launch_bounds__(256) k_solve_seg(const double2* in, double2* out, const double* tab, ChebDev cd,
-                                                   ColGeom g, double alpha) {
+__device__ __forceinline__ void solve_wave(int gw, const double2* in, double2* out, const double* tab,
+                                           const ChebDev& cd, const ColGeom& g, double alpha,
+                                           const double* rows0, const double* rows1) {
     using T = SegTraits<KIND>;
     constexpr int P = T::P, Q = T::Q, NR = T::NR, S = T::S, NC = T::NC, WS = T::WS;
     constexpr int C = 64 / K;
     const int lane = threadIdx.x & 63;
-    const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int ngroups = (g.ncols + C - 1) / C;
     const int p = gw / ngroups;
-    if (p >= 2) return;  // whole wave past the end
+    const double* rows = p == 0 ? rows0 : rows1;
     const int seg = lane / C;
     const int col = (gw - p * ngroups) * C + (lane - seg * C);
     const bool act = col < g.ncols;
@@ -291,7 +311,7 @@ __global__ void __launch_bounds__(256) k_solve_seg(const double2* in, double2* o
         double band[2 * P + 1], U[NR], V[NR];
         const int hi = (seg + 1) * R;
         if (S == 2 && hi < n) {
-            row_coeffs<KIND>(cd, p, hi, n, mu1, mu2, band, U, V);
+            row_coeffs<KIND>(rows, p, hi, n, mu1, mu2, band, U, V);
 #pragma unroll
             for (int r = 0; r < NR; ++r) Vn0[r] = V[r];
         } else {
@@ -326,7 +346,7 @@ __global__ void __launch_bounds__(256) k_solve_seg(const double2* in, double2* o
             const int i = lo + r;
             if (i < n) {
                 double band[2 * P + 1], U[NR], V[NR], b[P];
-                row_coeffs<KIND>(cd, p, i, n, mu1, mu2, band, U, V);
+                row_coeffs<KIND>(rows, p, i, n, mu1, mu2, band, U, V);
                 Aff<NC> cst;
                 cst.h = fr[r];
 #pragma unroll
@@ -383,7 +403,7 @@ __global__ void __launch_bounds__(256) k_solve_seg(const double2* in, double2* o
             for (int e = 0; e < P; ++e) bb[r][e] = 0.0;
             if (i < n) {
                 double band[2 * P + 1], U[NR], V[NR];
-                row_coeffs<KIND>(cd, p, i, n, mu1, mu2, band, U, V);
+                row_coeffs<KIND>(rows, p, i, n, mu1, mu2, band, U, V);
                 elim_row<KIND>(band, U, V, Vnext, (i - 1 + S) < n, wx, ws, cx2, cs2, fr[r], bb[r]);
             }
         }
@@ -399,17 +419,15 @@ __global__ void __launch_bounds__(256) k_solve_seg(const double2* in, double2* o
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        if (lo + r < n) {
-            Aff<P> x;
-            x.h = fr[r];
+        Aff<P> x;
+        x.h = fr[r];
 #pragma unroll
-            for (int c = 0; c < P; ++c) x.m[c] = 0.0;
+        for (int c = 0; c < P; ++c) x.m[c] = 0.0;
 #pragma unroll
-            for (int e = 0; e < P; ++e) aff_axpy(x, bb[r][e], win[e]);
+        for (int e = 0; e < P; ++e) aff_axpy(x, bb[r][e], win[e]);
 #pragma unroll
-            for (int e = P - 1; e > 0; --e) win[e] = win[e - 1];
-            win[0] = x;
-        }
+        for (int e = P - 1; e > 0; --e) win[e] = win[e - 1];
+        win[0] = x;
     }
     double2 zin[P];
 #pragma unroll
@@ -438,19 +456,28 @@ __global__ void __launch_bounds__(256) k_solve_seg(const double2* in, double2* o
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int i = lo + r;
-        if (i < n) {
-            double2 x = fr[r];
+        double2 x = fr[r];
 #pragma unroll
-            for (int e = 0; e < P; ++e) { x.x += bb[r][e] * w[e].x; x.y += bb[r][e] * w[e].y; }
-            if (act) out[base + (long)i * stride] = x;
+        for (int e = 0; e < P; ++e) { x.x += bb[r][e] * w[e].x; x.y += bb[r][e] * w[e].y; }
+        if (act && i < n) out[base + (long)i * stride] = x;
 #pragma unroll
-            for (int e = P - 1; e > 0; --e) w[e] = w[e - 1];
-            w[0] = x;
-        }
+        for (int e = P - 1; e > 0; --e) w[e] = w[e - 1];
+        w[0] = x;
     }
     // rows beyond the basis of this parity are zero
     if (act)
         for (int l = p + 2 * n + 2 * seg; l < cd.N; l += 2 * K) out[(long)l * ncols + col] = make_double2(0.0, 0.0);
+}
+
+// Lane layout: a wave holds C = 64/K adjacent columns of one parity, lane
+// = seg * C + column; waves ordered parity-major.
+template <int KIND, int K, int R>
+__global__ void __launch_bounds__(256) k_solve_seg(const double2* in, double2* out, const double* tab, ChebDev cd,
+                                                   ColGeom g, double alpha) {
+    constexpr int C = 64 / K;
+    const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (gw >= 2 * ((g.ncols + C - 1) / C)) return;  // whole wave past the end
+    solve_wave<KIND, K, R>(gw, in, out, tab, cd, g, alpha, cd.solve[0], cd.solve[1]);
 }
 
 template <int KIND, int K>

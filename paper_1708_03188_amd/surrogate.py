@@ -43,8 +43,11 @@ def identity_error(data):
     return float(d.mean()), float(d.max())
 
 
-def train(fno, data, steps, batch, lr=3e-3, lr_min=1e-5, seed=0, log_every=0):
-    """Adam with cosine learning-rate decay on random (snapshot, trajectory) pairs."""
+def train(fno, data, steps, batch, lr=3e-3, lr_min=1e-5, seed=0, log_every=0, start=0, total=None):
+    """Adam with cosine learning-rate decay on random (snapshot, trajectory) pairs.
+    start/total place these steps inside a longer schedule (default: one decay
+    over these steps)."""
+    total = total or steps
     gen = torch.Generator(device="cpu").manual_seed(seed)
     ns, nt = data.shape[0] - 1, data.shape[1]
     losses = []
@@ -53,7 +56,7 @@ def train(fno, data, steps, batch, lr=3e-3, lr_min=1e-5, seed=0, log_every=0):
         i = torch.randint(0, nt, (batch,), generator=gen)
         x = data[k, i].contiguous()
         y = data[k + 1, i].contiguous()
-        a = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * it / max(1, steps)))
+        a = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * (start + it) / max(1, total)))
         want = log_every and (it % log_every == 0 or it == steps - 1)
         l = fno.train_step(x, y, a, want_loss=bool(want))
         if want:
@@ -74,3 +77,43 @@ def evaluate(fno, data, batch=None):
         rels.append(fno.rel_l2(fno.infer(xb), yb))
     r = torch.cat(rels)
     return float(r.mean()), float(r.max())
+
+
+# Parameters the kernels read in fp32 (lift and biases); the rest are only ever
+# used through their bf16 mirrors, so storing them as bf16 (round to nearest
+# even, as the device mirrors are made) reproduces inference bit for bit.
+_FP32_KEYS = ("Wl", "bl", "b1", "b2")
+
+
+def _is_fp32(name):
+    return name in _FP32_KEYS or name.startswith("bp")
+
+
+def _to_bf16_bits(a):
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
+    rounded = u + 0x7FFF + ((u >> 16) & 1)
+    return (rounded >> 16).astype(np.uint16)
+
+
+def export_weights(fno, path):
+    """Write the inference weights of `fno` to an .npz file (no pickled objects)."""
+    params = fno.get_params()
+    arrays = {}
+    for k, v in params.items():
+        arrays[k] = np.asarray(v, dtype=np.float32) if _is_fp32(k) else _to_bf16_bits(v)
+    meta = np.array([fno.H, fno.W, fno.C, fno.K, fno.nl, fno.P], dtype=np.int64)
+    np.savez(path, _shape=meta, **arrays)
+
+
+def import_weights(fno, path):
+    """Load weights written by export_weights into `fno` (same architecture)."""
+    with np.load(path, allow_pickle=False) as z:
+        meta = [int(x) for x in z["_shape"]]
+        if meta != [fno.H, fno.W, fno.C, fno.K, fno.nl, fno.P]:
+            raise ValueError(f"weights are for shape {meta}")
+        params = {}
+        for k, shp in fno.param_shapes():
+            a = z[k]
+            params[k] = a if _is_fp32(k) else (a.astype(np.uint32) << 16).view(np.float32)
+            params[k] = params[k].reshape(shp)
+    fno.set_params(params)

@@ -55,3 +55,39 @@ def test_fallback_engages_and_replaces_with_solver(trained):
     # a trained network passes a loose tolerance without fallback
     st2 = f.advance_checked(gl, glc, u, nsur=2, steps_per=STRIDE, tol=0.5, seed=4)
     assert st2["n_checked"] == 4 and st2["n_fallback"] == 0
+
+
+WEIGHTS = __import__("os").path.join(__import__("os").path.dirname(__file__), "..", "paper_1708_03188_amd", "weights",
+                                     "fno_gl256.npz")
+
+
+@pytest.mark.skipif(not __import__("os").path.exists(WEIGHTS), reason="no trained 256^2 weights file")
+def test_trained_256_weights_on_fresh_trajectories(tmp_path):
+    # the shipped network (trained on the 256^2 solver trajectories): weights file
+    # round trip is exact, and on trajectories from seeds it never saw it is far
+    # ahead of the method without it and passes the FP64 checks at 3e-2
+    from paper_1708_03188_amd.api import FNO, GLBatch
+    from paper_1708_03188_amd import surrogate as S
+    import synth
+    print("[case] surrogate 256 weights", flush=True)
+    Nw = 256
+    f = FNO(Nw, Nw, width=32, modes=16, layers=4, hidden=128, max_batch=16, seed=5)
+    S.import_weights(f, WEIGHTS)
+    data = S.generate_trajectories(8, 4, Nw, seed=920000)
+    x = data[0].contiguous()
+    y0 = f.infer(x).clone()
+    S.export_weights(f, tmp_path / "w.npz")
+    g = FNO(Nw, Nw, width=32, modes=16, layers=4, hidden=128, max_batch=16, seed=9)
+    S.import_weights(g, tmp_path / "w.npz")
+    assert torch.equal(g.infer(x), y0)
+    mean, mx = S.evaluate(f, data)
+    ident, _ = S.identity_error(data)
+    print(f"256^2 held-out rel L2 mean {mean:.4f} max {mx:.4f}; persistence {ident:.4f}")
+    assert mean < 0.03 and mean < 0.1 * ident
+    B = 8
+    gl = GLBatch([Nw] * B, scheme="ifrk4", b=1.5, c=-2.0, dt=0.05, L=100.0)
+    glc = GLBatch([Nw] * 2, scheme="ifrk4", b=1.5, c=-2.0, dt=0.05, L=100.0)
+    u = gl.forward(gl.pack([synth.gl_noise(Nw, 930000 + i) for i in range(B)]))
+    gl.step(u, 200)
+    st = f.advance_checked(gl, glc, u, nsur=2, steps_per=10, tol=3e-2, seed=5)
+    assert st["n_checked"] == 4 and st["n_fallback"] == 0, st
