@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "common.h"
+#include "fno_fused.h"
 #include "fno_gemm.h"
 
 namespace sgm {
@@ -226,7 +227,7 @@ struct sgm_fno_s {
     long step = 0;
     bool mirrors_ok = false;
     // bf16 mirrors
-    bf16 *Wp16 = nullptr, *W1_16 = nullptr, *W2_16 = nullptr, *Rreal = nullptr;
+    bf16 *Wp16 = nullptr, *W1_16 = nullptr, *W2_16 = nullptr, *Rreal = nullptr, *W1T16 = nullptr;
     // DFT matrices (bf16)
     bf16 *Fx = nullptr, *Fy = nullptr, *Gy = nullptr, *Gx = nullptr;
     // activations / scratch (sized for Bmax)
@@ -302,6 +303,7 @@ extern "C" sgm_status sgm_fno_create(const sgm_fno_desc* desc, uint64_t seed, sg
         {(void**)&f->mom1, 4 * (size_t)f->npar}, {(void**)&f->mom2, 4 * (size_t)f->npar},
         {(void**)&f->Wp16, 2 * (size_t)nl * C * C}, {(void**)&f->W1_16, 2 * (size_t)C * P},
         {(void**)&f->W2_16, 2 * (size_t)2 * P}, {(void**)&f->Rreal, 2 * (size_t)nl * NM * 4 * C * C},
+        {(void**)&f->W1T16, 2 * (size_t)C * P},
         {(void**)&f->Fx, 2 * (size_t)2 * f->K * d.W}, {(void**)&f->Fy, 2 * (size_t)4 * f->K * 2 * d.H},
         {(void**)&f->Gy, 2 * (size_t)2 * d.H * 4 * f->K}, {(void**)&f->Gx, 2 * (size_t)d.W * 2 * f->K},
         {(void**)&f->acts, 2 * (size_t)(nl + 1) * act}, {(void**)&f->zsv, 2 * (size_t)nl * act},
@@ -392,6 +394,7 @@ static sgm_status refresh_mirrors(sgm_fno f, hipStream_t s) {
     hipLaunchKernelGGL(k_f32_to_bf16, dim3(nblk((long)C * P)), dim3(256), 0, s, f->par + f->oW1, f->W1_16, (long)C * P);
     hipLaunchKernelGGL(k_f32_to_bf16, dim3(nblk(2L * P)), dim3(256), 0, s, f->par + f->oW2, f->W2_16, 2L * P);
     SGM_HIP_TRY(hipGetLastError());
+    SGM_HIP_TRY(launch_transpose_bf16(f->par + f->oW1, f->W1T16, C, P, s));
     f->mirrors_ok = true;
     return SGM_OK;
 }
@@ -441,17 +444,28 @@ static int splits_for(long K) {
     return (int)s;
 }
 
-// Forward pass for `batch` samples; keeps activations for backward.
-static sgm_status fno_forward(sgm_fno f, const float* x, int B, hipStream_t s) {
+// Forward pass for `batch` samples.  Training (pred_out null) keeps the
+// activations for backward and leaves the prediction in predb; inference
+// writes pred_out.  Width 32 with 16 x-modes runs the fused row kernels
+// (lift + x-DFT; inverse x-DFT + pointwise + bias + GELU + next x-DFT;
+// projection), other shapes the GEMM sequence.
+static sgm_status fno_forward(sgm_fno f, const float* x, int B, hipStream_t s, float* pred_out = nullptr) {
     const int C = f->C, P = f->P, H = f->H, W = f->W, K = f->K, NM = f->NM;
     const long HW = (long)H * W, pix = (long)B * HW, act = (long)f->Bmax * HW * C;
-    hipLaunchKernelGGL(k_lift, dim3(nblk(pix * C)), dim3(256), 0, s, x, f->par + f->oWl, f->par + f->obl, f->acts, pix, C);
-    SGM_HIP_TRY(hipGetLastError());
+    const bool fused = fno_fused_ok(C, K, W, P);
+    if (fused) {
+        SGM_HIP_TRY(launch_fno_lift_dft(x, f->par + f->oWl, f->par + f->obl, f->Fx, f->acts, f->T, (long)B * H, W, s));
+    } else {
+        hipLaunchKernelGGL(k_lift, dim3(nblk(pix * C)), dim3(256), 0, s, x, f->par + f->oWl, f->par + f->obl, f->acts,
+                           pix, C);
+        SGM_HIP_TRY(hipGetLastError());
+    }
     for (int l = 0; l < f->nl; ++l) {
         const bf16* a = f->acts + l * act;
         bf16* an = f->acts + (l + 1) * act;
         // G1: T[(b,y)] (2K x C) = Fx (2K x W) a[(b,y)] (W x C)
-        SGM_HIP_TRY(gemm(G(B * H, 2 * K, C, W, f->Fx, 0, W, 1, 0, a, (long)W * C, C, 1, 0, f->T, 2L * K * C, C, 1), s));
+        if (!fused)
+            SGM_HIP_TRY(gemm(G(B * H, 2 * K, C, W, f->Fx, 0, W, 1, 0, a, (long)W * C, C, 1, 0, f->T, 2L * K * C, C, 1), s));
         // G2: X[b] (4K x K C) = Fy_real (4K x 2H) T[b] (2H x K C)
         SGM_HIP_TRY(gemm(G(B, 4 * K, K * C, 2 * H, f->Fy, 0, 2L * H, 1, 0, f->T, 2L * H * K * C, (long)K * C, 1, 1, f->X,
                            4L * K * K * C, (long)K * C, 1), s));
@@ -467,6 +481,18 @@ static sgm_status fno_forward(sgm_fno f, const float* x, int B, hipStream_t s) {
         // G4: U[b] (2H x K C) = Gy_real (2H x 4K) Yt[b] (4K x K C)   (U reuses T)
         SGM_HIP_TRY(gemm(G(B, 2 * H, K * C, 4 * K, f->Gy, 0, 4L * K, 1, 0, f->Yt, 4L * K * K * C, (long)K * C, 1, 1, f->T,
                            2L * H * K * C, (long)K * C, 1), s));
+        if (fused) {
+            FnoLayerArgs la{};
+            la.a = a; la.U = f->T; la.Tn = f->T; la.Gx = f->Gx; la.Fx = f->Fx;
+            la.Wp = f->Wp16 + (long)l * C * C; la.bp = f->par + f->obp[l];
+            la.a_out = an; la.zsave = pred_out ? nullptr : f->zsv + l * act;
+            la.rows = (long)B * H; la.W = W; la.act = l < f->nl - 1 ? 1 : 0;
+            la.W1T = f->W1T16; la.b1 = f->par + f->ob1; la.W2 = f->W2_16; la.b2 = f->par + f->ob2;
+            la.x = x; la.pred = pred_out; la.P = P;
+            const int mode = l < f->nl - 1 ? 0 : (pred_out ? 2 : 1);
+            SGM_HIP_TRY(launch_fno_layer(la, mode, s));
+            continue;
+        }
         // G5: s[(b,y)] (W x C) = Gx (W x 2K) U[(b,y)] (2K x C)
         SGM_HIP_TRY(gemm(G(B * H, W, C, 2 * K, f->Gx, 0, 2L * K, 1, 0, f->T, 2L * K * C, C, 1, 1, f->s32, (long)W * C, C, 1),
                          s));
@@ -477,6 +503,7 @@ static sgm_status fno_forward(sgm_fno f, const float* x, int B, hipStream_t s) {
                            (const float*)(f->par + f->obp[l]), an, f->zsv + l * act, pix * C, C, l < f->nl - 1 ? 1 : 0);
         SGM_HIP_TRY(hipGetLastError());
     }
+    if (fused && pred_out) return SGM_OK;  // projection done in the last layer kernel
     // projection
     const bf16* a = f->acts + f->nl * act;
     SGM_HIP_TRY(gemm(G(1, (int)pix, P, C, a, 0, C, 1, 0, f->W1_16, 0, P, 1, 0, f->s32, 0, P, 1), s));
@@ -579,6 +606,7 @@ extern "C" sgm_status sgm_fno_infer(sgm_fno f, const float* x, float* pred, int 
     hipStream_t s = static_cast<hipStream_t>(stream);
     sgm_status r = refresh_mirrors(f, s);
     if (r != SGM_OK) return r;
+    if (fno_fused_ok(f->C, f->K, f->W, f->P)) return fno_forward(f, x, batch, s, pred);
     if ((r = fno_forward(f, x, batch, s)) != SGM_OK) return r;
     SGM_HIP_TRY(hipMemcpyAsync(pred, f->predb, 4L * batch * f->H * f->W * 2, hipMemcpyDeviceToDevice, s));
     return SGM_OK;

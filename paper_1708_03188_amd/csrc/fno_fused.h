@@ -1,0 +1,37 @@
+// Fused FNO row kernels (width 32, 16 x-modes) - internal.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace sgm {
+
+struct FnoLayerArgs {
+    const __bf16* a;      // layer input [rows][W][32]
+    const float* U;       // inverse-y spectral rows [rows][32][32] (may alias Tn)
+    float* Tn;            // next layer's x-DFT rows [rows][32][32] (mode 0)
+    const __bf16* Gx;     // [W][32] inverse x-DFT
+    const __bf16* Fx;     // [32][W] forward x-DFT
+    const __bf16* Wp;     // [32][32] pointwise weights
+    const float* bp;      // [32]
+    __bf16* a_out;        // [rows][W][32] (modes 0, 1)
+    __bf16* zsave;        // pre-activation [rows][W][32] or null (modes 0, 1)
+    long rows;
+    int W;
+    int act;              // 1: GELU
+    // projection (mode 2)
+    const __bf16* W1T;    // [P][32]
+    const float* b1;      // [P]
+    const __bf16* W2;     // [P][2]
+    const float* b2;      // [2]
+    const float* x;       // [rows][W][2] network input (residual)
+    float* pred;          // [rows][W][2]
+    int P;
+};
+
+bool fno_fused_ok(int C, int K, int W, int P);
+hipError_t launch_fno_lift_dft(const float* x, const float* Wl, const float* bl, const __bf16* Fx, __bf16* a0,
+                               float* T, long rows, int W, hipStream_t s);
+// mode 0: a_out + next T; 1: a_out (last layer); 2: projection to pred (last layer)
+hipError_t launch_fno_layer(const FnoLayerArgs& a, int mode, hipStream_t s);
+hipError_t launch_transpose_bf16(const float* in, __bf16* out, int R, int Cc, hipStream_t s);
+
+}  // namespace sgm

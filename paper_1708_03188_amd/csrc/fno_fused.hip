@@ -1,0 +1,208 @@
+// Fused FNO row kernels for width 32 and 16 retained x-modes (2K = 32 real
+// DFT rows): one wave per activation row (b, y) of W pixels x 32 channels.
+//
+// MFMA v_mfma_f32_32x32x16_bf16 operand layout: lane i (c = i % 32,
+// g = i / 32) supplies A[c][8 g + v] and B[8 g + v][c], v = 0..7, and
+// receives C[8 r + 4 g + v][c] in accumulator 4 r + v.
+//
+//  k_fno_lift_dft : a0 = x Wl + bl (stored), T = Fx a0 (x-DFT of layer 0).
+//  k_fno_layer    : z = Gx U + a Wp + bp over the concatenated K = 2K + C,
+//                   a' = gelu(z) (not after the last layer), stored with z
+//                   when training; the next layer's x-DFT T = Fx a' is taken
+//                   from the accumulators directly (no re-read of a'), and
+//                   for inference after the last layer the projection
+//                   pred = x + gelu(a' W1 + b1) W2 + b2 runs in the same pass.
+// The next-layer DFT chains the two MFMAs without data movement: the output
+// rows x = 8 r + 4 g + v that lane group g holds are taken as that group's
+// eight K entries, and Fx is read in the same permuted order.
+#include "fno_fused.h"
+
+namespace sgm {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+namespace {
+
+constexpr int FC = 32;   // channels
+constexpr int F2K = 32;  // real x-DFT rows (Re, Im of 16 modes)
+constexpr int WAVES = 4;
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
+
+__device__ __forceinline__ bf16x8 ld8(const bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+
+__device__ __forceinline__ floatx16 zero16() {
+    floatx16 a;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) a[i] = 0.f;
+    return a;
+}
+
+__device__ __forceinline__ floatx16 mfma(bf16x8 a, bf16x8 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(64 * WAVES) k_fno_lift_dft(const float* __restrict__ x, const float* __restrict__ Wl,
+                                                           const float* __restrict__ bl, const bf16* __restrict__ Fx,
+                                                           bf16* __restrict__ a0, float* __restrict__ T, long rows,
+                                                           int W) {
+    const long row = (long)blockIdx.x * WAVES + (threadIdx.x >> 6);
+    if (row >= rows) return;  // whole wave
+    const int lane = threadIdx.x & 63, c = lane & 31, g = lane >> 5;
+    const float w0 = Wl[c], w1 = Wl[FC + c], b = bl[c];
+    const float2* xr = reinterpret_cast<const float2*>(x) + row * W;
+    bf16* ar = a0 + row * W * FC;
+    floatx16 acc = zero16();
+    for (int s = 0; s < W / 16; ++s) {
+        bf16x8 bop;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int px = 16 * s + 8 * g + v;
+            const float2 u = xr[px];
+            const bf16 val = (bf16)(u.x * w0 + u.y * w1 + b);
+            ar[px * FC + c] = val;
+            bop[v] = val;
+        }
+        acc = mfma(ld8(Fx + (long)c * W + 16 * s + 8 * g), bop, acc);
+    }
+    float* tr = T + row * F2K * FC;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) tr[(8 * r + 4 * g + v) * FC + c] = acc[4 * r + v];
+}
+
+// MODE 0: a_out and the next layer's T; 1: a_out only (last layer, training);
+// 2: projection to pred (last layer, inference).
+template <int MODE>
+__global__ void __launch_bounds__(64 * WAVES) k_fno_layer(FnoLayerArgs p) {
+    __shared__ bf16 tile[WAVES][32][FC + 8];
+    const long row = (long)blockIdx.x * WAVES + (threadIdx.x >> 6);
+    const bool live = row < p.rows;  // waves past the end still reach the barriers
+    const int wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, c = lane & 31, g = lane >> 5;
+    const long rr = live ? row : 0;
+    const int W = p.W;
+    // B operand over the concatenated K: U rows (x-spectral input) then Wp
+    bf16x8 bop[4];
+    {
+        const float* u = p.U + rr * F2K * FC;
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int v = 0; v < 8; ++v) bop[s][v] = (bf16)u[(16 * s + 8 * g + v) * FC + c];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int v = 0; v < 8; ++v) bop[2 + s][v] = p.Wp[(16 * s + 8 * g + v) * FC + c];
+    }
+    const float bias = p.bp[c];
+    const bf16* ar = p.a + rr * W * FC;
+    floatx16 tacc = zero16();
+    for (int t = 0; t < W / 32; ++t) {
+        const int x0 = 32 * t;
+        floatx16 acc = zero16();
+#pragma unroll
+        for (int s = 0; s < 2; ++s) acc = mfma(ld8(p.Gx + (long)(x0 + c) * F2K + 16 * s + 8 * g), bop[s], acc);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) acc = mfma(ld8(ar + (long)(x0 + c) * FC + 16 * s + 8 * g), bop[2 + s], acc);
+        bf16x8 yb[2];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int px = x0 + 8 * (e >> 2) + 4 * g + (e & 3);
+            const float z = acc[e] + bias;
+            if (MODE != 2 && p.zsave && live) p.zsave[(rr * W + px) * FC + c] = (bf16)z;
+            const bf16 y = (bf16)(p.act ? gelu(z) : z);
+            yb[e >> 3][e & 7] = y;
+            if (MODE != 2 && live) p.a_out[(rr * W + px) * FC + c] = y;
+        }
+        if constexpr (MODE == 0) {
+            // next x-DFT: k = 8 g + v <-> pixel x0 + 16 q + 8 (v / 4) + 4 g + v % 4
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const bf16* f = p.Fx + (long)c * W + x0 + 16 * q + 4 * g;
+                const bf16x4 lo = *reinterpret_cast<const bf16x4*>(f);
+                const bf16x4 hi = *reinterpret_cast<const bf16x4*>(f + 8);
+                bf16x8 aop;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) { aop[v] = lo[v]; aop[4 + v] = hi[v]; }
+                tacc = mfma(aop, yb[q], tacc);
+            }
+        }
+        if constexpr (MODE == 2) {
+            // a' tile [pixel][channel] through LDS, then h^T = W1T a'^T per 32 hidden units
+#pragma unroll
+            for (int e = 0; e < 16; ++e) tile[wv][8 * (e >> 2) + 4 * g + (e & 3)][c] = yb[e >> 3][e & 7];
+            __syncthreads();
+            bf16x8 bt[2];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) bt[s] = *reinterpret_cast<const bf16x8*>(&tile[wv][c][16 * s + 8 * g]);
+            float o0 = 0.f, o1 = 0.f;
+            for (int T = 0; T < p.P / 32; ++T) {
+                floatx16 h = zero16();
+#pragma unroll
+                for (int s = 0; s < 2; ++s) h = mfma(ld8(p.W1T + (long)(32 * T + c) * FC + 16 * s + 8 * g), bt[s], h);
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int hu = 32 * T + 8 * (e >> 2) + 4 * g + (e & 3);
+                    const float hv = (float)(bf16)gelu(h[e] + p.b1[hu]);
+                    o0 += hv * (float)p.W2[2 * hu];
+                    o1 += hv * (float)p.W2[2 * hu + 1];
+                }
+            }
+            o0 += __shfl_xor(o0, 32);
+            o1 += __shfl_xor(o1, 32);
+            if (live && g == 0) {
+                const long pi = rr * W + x0 + c;
+                const float2 xin = reinterpret_cast<const float2*>(p.x)[pi];
+                reinterpret_cast<float2*>(p.pred)[pi] = make_float2(xin.x + o0 + p.b2[0], xin.y + o1 + p.b2[1]);
+            }
+            __syncthreads();
+        }
+    }
+    if constexpr (MODE == 0) {
+        if (live) {
+            float* tr = p.Tn + rr * F2K * FC;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) tr[(8 * r + 4 * g + v) * FC + c] = tacc[4 * r + v];
+        }
+    }
+}
+
+__global__ void k_transpose_bf16(const float* in, bf16* out, int R, int Cc) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= R * Cc) return;
+    const int r = i / Cc, c = i - r * Cc;
+    out[(long)c * R + r] = (bf16)in[i];
+}
+
+bool fno_fused_ok(int C, int K, int W, int P) { return C == FC && 2 * K == F2K && W % 32 == 0 && P % 32 == 0; }
+
+hipError_t launch_fno_lift_dft(const float* x, const float* Wl, const float* bl, const bf16* Fx, bf16* a0, float* T,
+                               long rows, int W, hipStream_t s) {
+    hipLaunchKernelGGL(k_fno_lift_dft, dim3((unsigned)((rows + WAVES - 1) / WAVES)), dim3(64 * WAVES), 0, s, x, Wl, bl,
+                       Fx, a0, T, rows, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_fno_layer(const FnoLayerArgs& a, int mode, hipStream_t s) {
+    const dim3 grid((unsigned)((a.rows + WAVES - 1) / WAVES)), block(64 * WAVES);
+    if (mode == 0) hipLaunchKernelGGL(k_fno_layer<0>, grid, block, 0, s, a);
+    else if (mode == 1) hipLaunchKernelGGL(k_fno_layer<1>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(k_fno_layer<2>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_bf16(const float* in, bf16* out, int R, int Cc, hipStream_t s) {
+    hipLaunchKernelGGL(k_transpose_bf16, dim3((R * Cc + 255) / 256), dim3(256), 0, s, in, out, R, Cc);
+    return hipGetLastError();
+}
+
+}  // namespace sgm

@@ -18,6 +18,9 @@ def FNO():
 
 
 CFG = dict(H=32, W=32, width=8, modes=4, layers=2, hidden=16)
+# width 32 with 16 x-modes runs the fused row kernels (lift + x-DFT, layer, projection);
+# H != W to catch axis mix-ups, three layers so the middle-layer variant runs twice
+CFG32 = dict(H=32, W=64, width=32, modes=16, layers=3, hidden=64)
 
 
 def _setup(FNO, B=3, seed=0, cfg=CFG):
@@ -38,10 +41,12 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
 
 
-def test_forward_matches_oracle(FNO):
-    f, p, x, t = _setup(FNO)
+@pytest.mark.parametrize("cfg", [CFG, CFG32], ids=["gemm", "fused"])
+def test_forward_matches_oracle(FNO, cfg):
+    print(f"[case] fno forward {cfg}", flush=True)
+    f, p, x, t = _setup(FNO, cfg=cfg)
     got = f.infer(_dev(x)).cpu().numpy().astype(np.float64)
-    ref = ofno.forward(p, x, CFG["modes"])
+    ref = ofno.forward(p, x, cfg["modes"])
     # bf16 activations: compare the network output (pred - x) relative to its size
     e = np.linalg.norm(got - ref) / np.linalg.norm(ref - x)
     print("fno forward rel err (net output)", e)
@@ -49,12 +54,14 @@ def test_forward_matches_oracle(FNO):
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-2
 
 
-def test_gradients_match_oracle(FNO):
-    f, p, x, t = _setup(FNO, seed=1)
+@pytest.mark.parametrize("cfg", [CFG, CFG32], ids=["gemm", "fused"])
+def test_gradients_match_oracle(FNO, cfg):
+    print(f"[case] fno gradients {cfg}", flush=True)
+    f, p, x, t = _setup(FNO, seed=1, cfg=cfg)
     g, loss = f.grads(_dev(x), _dev(t))
-    pred, cache = ofno.forward(p, x, CFG["modes"], keep=True)
+    pred, cache = ofno.forward(p, x, cfg["modes"], keep=True)
     ref_loss = ofno.loss(pred, t)
-    gr = ofno.backward(p, x, CFG["modes"], cache, ofno.loss_grad(pred, t))
+    gr = ofno.backward(p, x, cfg["modes"], cache, ofno.loss_grad(pred, t))
     assert abs(loss - ref_loss) < 1e-2 * ref_loss
     worst = 0.0
     for k in gr:
