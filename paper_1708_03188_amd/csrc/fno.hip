@@ -23,10 +23,8 @@ namespace sgm {
 
 typedef __bf16 bf16;
 
-__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_df(float z) {
-    return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
-}
+__device__ __forceinline__ float gelu_f(float z) { return fno_gelu(z); }
+__device__ __forceinline__ float gelu_df(float z) { return fno_gelu_d(z); }
 
 // a[p, c] = x[p, 0] Wl[0, c] + x[p, 1] Wl[1, c] + bl[c]
 __global__ void k_lift(const float* x, const float* Wl, const float* bl, bf16* a, long P, int C) {

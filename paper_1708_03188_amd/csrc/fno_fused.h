@@ -4,6 +4,23 @@
 
 namespace sgm {
 
+// erf by Abramowitz & Stegun 7.1.26 (absolute error <= 1.5e-7, far below the
+// bf16 rounding every activation goes through) and the exact-form GELU on it.
+__device__ __forceinline__ float fno_erf(float x) {
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.3275911f, ax, 1.f));
+    float q = __builtin_fmaf(1.061405429f, t, -1.453152027f);
+    q = __builtin_fmaf(q, t, 1.421413741f);
+    q = __builtin_fmaf(q, t, -0.284496736f);
+    q = __builtin_fmaf(q, t, 0.254829592f);
+    const float r = 1.f - q * t * __expf(-ax * ax);
+    return copysignf(r, x);
+}
+__device__ __forceinline__ float fno_gelu(float z) { return 0.5f * z * (1.f + fno_erf(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float fno_gelu_d(float z) {
+    return 0.5f * (1.f + fno_erf(z * 0.70710678118654752f)) + z * __expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
 struct FnoLayerArgs {
     const __bf16* a;      // layer input [rows][W][32]
     const float* U;       // inverse-y spectral rows [rows][32][32] (may alias Tn)

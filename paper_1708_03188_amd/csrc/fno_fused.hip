@@ -30,7 +30,7 @@ constexpr int FC = 32;   // channels
 constexpr int F2K = 32;  // real x-DFT rows (Re, Im of 16 modes)
 constexpr int WAVES = 4;
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu(float z) { return fno_gelu(z); }
 
 __device__ __forceinline__ bf16x8 ld8(const bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
 

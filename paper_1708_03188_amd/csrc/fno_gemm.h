@@ -16,6 +16,7 @@ struct GemmDesc {
     int a_f32, b_f32;    // operand element type: 1 = float (rounded to bf16 on load), 0 = bf16
     int splitk;          // > 1: K is split over blocks and the partial sums are added
                          // atomically into C (C must hold beta * C beforehand)
+    int a_vec, b_vec;    // set by gemm(): staging along the contiguous dimension
 };
 
 // C = alpha op(A) op(B) + beta C for every batch entry.
