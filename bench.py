@@ -101,6 +101,18 @@ def measured_traffic(pass_name, variants, L):
     return None
 
 
+def pass_kernel_name(pass_name, variants, L):
+    """Kernel (template instance) that runs a pass of this plan."""
+    if pass_name not in PASS_KERNEL:
+        return None
+    name, axis = PASS_KERNEL[pass_name]
+    v = variants[axis]
+    if v < 0:
+        return f"generic LDS kernel for {pass_name}"
+    nt, nb = VARIANT_GEO[v]
+    return f"{name}<{L}, Geo<{L}, {nt}, {nb}>>"
+
+
 def cpu_baseline(N, M1, M2):
     """Time the oracle on a bounded sample of the same workload and extrapolate."""
     import synth
@@ -350,7 +362,8 @@ def main():
         "config": {"workload": "3D Poisson/Helmholtz space, Shen-Dirichlet N=256 x Fourier 256x256 R2C, "
                                "float64; step = forward + backward transform",
                    "N": N, "M1": M1, "M2": M2, "basis": "shen_dirichlet", "kind_last": "r2c"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": dom, "kernel_name": pass_kernel_name(dom, p.variants(), N),
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(dom, p.variants(), N), "algorithmic_bytes": nbytes[dom]},
         "plan_variants_xyz": p.variants(),
