@@ -17,7 +17,18 @@ struct ChebDev {
     const double* rtab[2];  // 3 * npar
     const double* qtab[2];  // 2 * mpar
     const double* solve[2]; // 20 * npar
+    // segmented biharmonic projection: per-row state coefficients (2 * npar)
+    // and per-segment 2 x 2 maps (4 * segments) of the Givens and
+    // back-substitution sweeps
+    const double* gal[2];
+    const double* gmat[2];
+    const double* bal[2];
+    const double* bmat[2];
 };
+
+// rows per segment of the parallel biharmonic projection (the plan tables
+// are built for the same value)
+constexpr int kProjSegRowsDev = 16;
 
 enum ChebFwdMode { kScalarProduct = 0, kProject = 1 };
 

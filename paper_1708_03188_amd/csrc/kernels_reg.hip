@@ -204,6 +204,154 @@ __device__ void project_givens_lane(double2* col, int es, int n, int m, int nrot
     }
 }
 
+// The same projection with every (column, parity) chain cut into segments of
+// R rows, one thread each (2 W nseg <= block threads).  The boundary-functional
+// projection is two reductions; the Givens sweep and the banded back
+// substitution are linear recurrences with a two-value state whose segment
+// maps are plan constants, so each thread runs its segment from a zero state,
+// the entering states follow from a short scan over the chain's segments, and
+// the rows are corrected with the per-row state coefficients.  SC holds two
+// complex values per segment.  Every thread of the block reaches the barriers.
+__device__ void project_segmented(double2* B0, double2* SC, int W, int nseg, const ChebDev& cd) {
+    constexpr int R = kProjSegRowsDev;
+    const int task = threadIdx.x;
+    const int ntask = 2 * W * nseg;
+    const bool on = task < ntask;
+    const int u = on ? task % nseg : 0, ch = on ? task / nseg : 0;
+    const int p = ch / W, cc = ch - p * W;
+    const int es = 2 * W;
+    double2* col = B0 + p * W + cc;
+    const int n = cd.npar[p], m = cd.mpar[p];
+    const int nsp = (n + R - 1) / R;
+    const bool seg_on = on && u < nsp;
+    const int lo = u * R, hi = min(lo + R, n);
+    const int t0 = lo, t1 = u == nsp - 1 ? m : min(lo + R, m);
+    const double* qt = cd.qtab[p];
+    double2* sc = SC + 2 * task;
+    double2* chain_sc = SC + 2 * ch * nseg;
+    // 1. projection onto the null space of the boundary functionals
+    double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
+    if (seg_on)
+        for (int tt = t0; tt < t1; ++tt) {
+            const double2 v = col[tt * es];
+            const double q1 = qt[2 * tt], q2 = qt[2 * tt + 1];
+            s1.x += q1 * v.x; s1.y += q1 * v.y;
+            s2.x += q2 * v.x; s2.y += q2 * v.y;
+        }
+    if (on) { sc[0] = s1; sc[1] = s2; }
+    __syncthreads();
+    s1 = make_double2(0.0, 0.0);
+    s2 = make_double2(0.0, 0.0);
+    if (on)
+        for (int v = 0; v < nsp; ++v) {
+            const double2 a = chain_sc[2 * v], b = chain_sc[2 * v + 1];
+            s1.x += a.x; s1.y += a.y;
+            s2.x += b.x; s2.y += b.y;
+        }
+    __syncthreads();
+    if (seg_on)
+        for (int tt = t0; tt < t1; ++tt) {
+            const double2 v = col[tt * es];
+            const double q1 = qt[2 * tt], q2 = qt[2 * tt + 1];
+            col[tt * es] = make_double2(v.x - q1 * s1.x - q2 * s2.x, v.y - q1 * s1.y - q2 * s2.y);
+        }
+    __syncthreads();
+    // 2. Givens sweep from a zero entering state; fresh input of row i is ld(i + 2)
+    double2 fr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int tt = lo + r + 2;
+        fr[r] = (seg_on && lo + r < hi && tt < m) ? col[tt * es] : make_double2(0.0, 0.0);
+    }
+    const double2 ld0 = on ? col[0] : make_double2(0.0, 0.0), ld1 = on ? col[es] : make_double2(0.0, 0.0);
+    __syncthreads();
+    const double* ro = cd.rot[p];
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = lo + r;
+        if (seg_on && i < hi) {
+            const double c1 = ro[4 * i], sn1 = ro[4 * i + 1], c2 = ro[4 * i + 2], sn2 = ro[4 * i + 3];
+            const double2 a1 = make_double2(c1 * a.x + sn1 * b.x, c1 * a.y + sn1 * b.y);
+            const double2 b1 = make_double2(-sn1 * a.x + c1 * b.x, -sn1 * a.y + c1 * b.y);
+            const double2 f = fr[r];
+            col[i * es] = make_double2(c2 * a1.x + sn2 * f.x, c2 * a1.y + sn2 * f.y);
+            a = b1;
+            b = make_double2(-sn2 * a1.x + c2 * f.x, -sn2 * a1.y + c2 * f.y);
+        }
+    }
+    if (on) { sc[0] = a; sc[1] = b; }
+    __syncthreads();
+    // 3. entering state of the segment: rows 0, 1 of the projected column, then
+    //    the maps and zero-state outputs of the segments above
+    {
+        double2 sa = ld0, sb = ld1;
+        const double* gm = cd.gmat[p];
+        if (seg_on)
+            for (int v = 0; v < u; ++v) {
+                const double2 ha = chain_sc[2 * v], hb = chain_sc[2 * v + 1];
+                const double m00 = gm[4 * v], m01 = gm[4 * v + 1], m10 = gm[4 * v + 2], m11 = gm[4 * v + 3];
+                const double2 na = make_double2(m00 * sa.x + m01 * sb.x + ha.x, m00 * sa.y + m01 * sb.y + ha.y);
+                const double2 nb = make_double2(m10 * sa.x + m11 * sb.x + hb.x, m10 * sa.y + m11 * sb.y + hb.y);
+                sa = na;
+                sb = nb;
+            }
+        const double* ga = cd.gal[p];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = lo + r;
+            if (seg_on && i < hi) {
+                const double g0 = ga[2 * i], g1 = ga[2 * i + 1];
+                const double2 v = col[i * es];
+                col[i * es] = make_double2(v.x + g0 * sa.x + g1 * sb.x, v.y + g0 * sa.y + g1 * sb.y);
+            }
+        }
+    }
+    __syncthreads();
+    // 4. banded back substitution x_i = (z_i - R_i,i+1 x_i+1 - R_i,i+2 x_i+2) / R_ii from a
+    //    zero state below the segment
+    const double* rt = cd.rtab[p];
+    double2 x1 = make_double2(0.0, 0.0), x2 = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int r = R - 1; r >= 0; --r) {
+        const int i = lo + r;
+        if (seg_on && i < hi) {
+            const double r0 = rt[3 * i], r1 = rt[3 * i + 1], r2 = rt[3 * i + 2];
+            const double2 z = col[i * es];
+            const double2 xv = make_double2((z.x - r1 * x1.x - r2 * x2.x) * r0, (z.y - r1 * x1.y - r2 * x2.y) * r0);
+            col[i * es] = xv;
+            x2 = x1;
+            x1 = xv;
+        }
+    }
+    if (on) { sc[0] = x1; sc[1] = x2; }
+    __syncthreads();
+    // 5. entering state (x_hi, x_hi+1) from the segments below, then the correction
+    {
+        double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
+        const double* bm = cd.bmat[p];
+        if (seg_on)
+            for (int v = nsp - 1; v > u; --v) {
+                const double2 ga = chain_sc[2 * v], gb = chain_sc[2 * v + 1];
+                const double m00 = bm[4 * v], m01 = bm[4 * v + 1], m10 = bm[4 * v + 2], m11 = bm[4 * v + 3];
+                const double2 na = make_double2(m00 * sa.x + m01 * sb.x + ga.x, m00 * sa.y + m01 * sb.y + ga.y);
+                const double2 nb = make_double2(m10 * sa.x + m11 * sb.x + gb.x, m10 * sa.y + m11 * sb.y + gb.y);
+                sa = na;
+                sb = nb;
+            }
+        const double* ba = cd.bal[p];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = lo + r;
+            if (seg_on && i < hi) {
+                const double b0 = ba[2 * i], b1 = ba[2 * i + 1];
+                const double2 v = col[i * es];
+                col[i * es] = make_double2(v.x + b0 * sa.x + b1 * sb.x, v.y + b0 * sa.y + b1 * sb.y);
+            }
+        }
+    }
+}
+
 template <int N, class G, int MODE>
 __global__ void __launch_bounds__(kThreads) kr_cheb_fwd(const double2* in, double2* out, ChebDev cd, int ncols,
                                                         const double2* __restrict__ tw) {
@@ -320,17 +468,24 @@ __global__ void __launch_bounds__(kThreads) kr_cheb_fwd(const double2* in, doubl
             const int l = t + NT * e;
             if (ok) out[(long)l * ncols + c0 + c] = l < nb ? B0[l * W + c] : make_double2(0.0, 0.0);
         }
-    } else {  // kProjBiharmonic: sequential Givens lanes
+    } else {  // kProjBiharmonic
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = t + NT * e;
             B0[k * W + c] = cscale(x[e], cd.bscale[k]);
         }
         __syncthreads();
-        const int lane = threadIdx.x;
-        if (lane < 2 * W) {
-            const int p = lane / W, cc = lane - p * W;
-            project_givens_lane(B0 + p * W + cc, 2 * W, cd.npar[p], cd.mpar[p], 2, cd.rot[p], cd.rtab[p], cd.qtab[p]);
+        constexpr int R = kProjSegRowsDev;
+        const int nseg = (max(cd.npar[0], cd.npar[1]) + R - 1) / R;
+        if (2 * W * nseg <= kThreads && 2 * nseg <= NT) {
+            project_segmented(B0, SC, W, nseg, cd);
+        } else {
+            const int lane = threadIdx.x;
+            if (lane < 2 * W) {
+                const int p = lane / W, cc = lane - p * W;
+                project_givens_lane(B0 + p * W + cc, 2 * W, cd.npar[p], cd.mpar[p], 2, cd.rot[p], cd.rtab[p],
+                                    cd.qtab[p]);
+            }
         }
         __syncthreads();
 #pragma unroll

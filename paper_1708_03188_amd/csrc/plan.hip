@@ -16,6 +16,8 @@
 #include "solve_seg.h"
 #include "tables.h"
 
+static_assert(sgm::kProjSegRowsDev == sgm::kProjSegRows, "projection segment length mismatch");
+
 namespace sgm {
 
 static thread_local std::string g_last_error;
@@ -283,11 +285,15 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
     size_t o_twz = b.add(twiddles(Llast));
     size_t o_theta = b.add(ct.theta), o_beta = b.add(ct.beta), o_gamma = b.add(ct.gamma);
     size_t o_bs = b.add(ct.bscale), o_fs = b.add(ct.fscale);
-    size_t o_rot[2], o_rt[2], o_sv[2], o_qt[2];
+    size_t o_rot[2], o_rt[2], o_sv[2], o_qt[2], o_gal[2], o_gm[2], o_bal[2], o_bm[2];
     for (int q = 0; q < 2; ++q) {
         o_qt[q] = b.add(ct.qtab[q]);
         o_rot[q] = b.add(ct.rot[q]);
         o_rt[q] = b.add(ct.rtab[q]);
+        o_gal[q] = b.add(ct.gal[q]);
+        o_gm[q] = b.add(ct.gmat[q]);
+        o_bal[q] = b.add(ct.bal[q]);
+        o_bm[q] = b.add(ct.bmat[q]);
         // identity rows (T0 diagonal 1, no coupling) past the end of the chain, up to the
         // rows covered by the segmented solve
         std::vector<double> sv = ct.solve[q];
@@ -314,6 +320,7 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
     for (int q = 0; q < 2; ++q) {
         cd.npar[q] = ct.npar[q]; cd.mpar[q] = ct.mpar[q];
         cd.rot[q] = D(o_rot[q]); cd.rtab[q] = D(o_rt[q]); cd.solve[q] = D(o_sv[q]); cd.qtab[q] = D(o_qt[q]);
+        cd.gal[q] = D(o_gal[q]); cd.gmat[q] = D(o_gm[q]); cd.bal[q] = D(o_bal[q]); cd.bmat[q] = D(o_bm[q]);
     }
     cd.theta = reinterpret_cast<const double2*>(base + o_theta);
     cd.beta = D(o_beta); cd.gamma = D(o_gamma); cd.bscale = D(o_bs); cd.fscale = D(o_fs);

@@ -2,6 +2,7 @@
 //
 // Everything here is computed once per plan on the host in long double
 // (x87, 64-bit significand) and rounded to binary64 when uploaded.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -9,6 +10,7 @@
 
 #include "../../include/sgm.h"
 #include "common.h"
+
 #include "tables.h"
 
 namespace sgm {
@@ -155,6 +157,43 @@ bool build_cheb_tables(int basis, int N, ChebTables& t, std::string& err) {
         }
         t.rot[p].assign(rot.begin(), rot.end());
         t.rtab[p].assign(rt.begin(), rt.end());
+        if (nrot == 2) {
+            // segment maps of both sweeps, from the binary64 factors the kernels use
+            const int R = kProjSegRows, nseg = (n + R - 1) / R;
+            const std::vector<double>& ro = t.rot[p];
+            const std::vector<double>& rr = t.rtab[p];
+            t.gal[p].assign(2 * (size_t)n, 0.0);
+            t.bal[p].assign(2 * (size_t)n, 0.0);
+            t.gmat[p].assign(4 * (size_t)nseg, 0.0);
+            t.bmat[p].assign(4 * (size_t)nseg, 0.0);
+            for (int u = 0; u < nseg; ++u) {
+                const int lo = u * R, hi = std::min(n, lo + R);
+                for (int cu = 0; cu < 2; ++cu) {
+                    // Givens sweep: state (w0, w1) entering row lo, no fresh input
+                    ld a = cu == 0, b = cu == 1;
+                    for (int i = lo; i < hi; ++i) {
+                        const ld c1 = ro[4 * i], s1 = ro[4 * i + 1], c2 = ro[4 * i + 2], s2 = ro[4 * i + 3];
+                        const ld a1 = c1 * a + s1 * b, b1 = -s1 * a + c1 * b;
+                        t.gal[p][2 * i + cu] = (double)(c2 * a1);
+                        a = b1;
+                        b = -s2 * a1;
+                    }
+                    t.gmat[p][4 * u + cu] = (double)a;
+                    t.gmat[p][4 * u + 2 + cu] = (double)b;
+                    // back substitution: (x_hi, x_hi+1) entering, rows hi-1 .. lo
+                    std::vector<ld> x((size_t)(hi - lo + 2), 0);
+                    x[hi - lo] = cu == 0;
+                    x[hi - lo + 1] = cu == 1;
+                    for (int i = hi - 1; i >= lo; --i) {
+                        const ld v = (-(ld)rr[3 * i + 1] * x[i - lo + 1] - (ld)rr[3 * i + 2] * x[i - lo + 2]) * (ld)rr[3 * i];
+                        x[i - lo] = v;
+                        t.bal[p][2 * i + cu] = (double)v;
+                    }
+                    t.bmat[p][4 * u + cu] = (double)x[0];
+                    t.bmat[p][4 * u + 2 + cu] = (double)x[1];
+                }
+            }
+        }
         // Boundary functionals of parity p: sum_k c_k (u(1) +- u(-1)) and, for the
         // biharmonic basis, sum_k k^2 c_k (u'(1) -+ u'(-1)).  Range(P) is their null
         // space; in b = D^{1/2} c coordinates the functionals are D^{-1/2} C^T, with

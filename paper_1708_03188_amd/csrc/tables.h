@@ -9,6 +9,8 @@ namespace sgm {
 // exp(-2 pi i r / L), r = 0..L-1, from the exactly reduced index r.
 std::vector<double> twiddles(int L);
 
+constexpr int kProjSegRows = 16;
+
 // Tables of one Chebyshev/Shen axis with N points; all vectors are flat
 // binary64 arrays ready for upload.
 struct ChebTables {
@@ -26,6 +28,12 @@ struct ChebTables {
     // rot[p][4i..4i+3] = (c1, s1, c2, s2), rtab[p][3i..3i+2] = (1/R_ii, R_i,i+1, R_i,i+2)
     std::vector<double> rot[2];
     std::vector<double> rtab[2];
+    // The two sweeps of that solve cut into segments of kProjSegRows rows
+    // (biharmonic): per row i, gal[p][2i..] / bal[p][2i..] = how the Givens
+    // output / back-substituted value of row i depends on the two-value state
+    // entering its segment; per segment u, gmat[p][4u..] / bmat[p][4u..] = the
+    // 2 x 2 map from the entering to the leaving state (row-major).
+    std::vector<double> gal[2], gmat[2], bal[2], bmat[2];
     // Orthonormal basis of the boundary functionals in the D^{1/2}-scaled
     // coordinates, per parity: qtab[p][2t + r], r < nrot (1 Dirichlet, 2 biharmonic).
     std::vector<double> qtab[2];
