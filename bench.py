@@ -57,7 +57,7 @@ def pass_bytes(N, M1, M2, nb):
     }
 
 
-VARIANT_GEO = {0: (32, 2), 1: (32, 1), 2: (16, 2), 3: (16, 1)}
+VARIANT_GEO = {0: (32, 2), 1: (32, 1), 2: (16, 2), 3: (16, 1), 4: (64, 1)}
 PASS_KERNEL = {"last_fwd": ("kr_lines_r2c", 2), "last_bwd": ("kr_lines_c2r", 2), "mid_fwd": ("kr_strided", 1),
                "mid_bwd": ("kr_strided", 1), "cheb_fwd": ("kr_cheb_fwd", 0), "cheb_bwd": ("kr_cheb_bwd", 0)}
 

@@ -135,7 +135,8 @@ class GLBatch:
     occupies [offsets[i], offsets[i+1]) as an N_i x N_i C-ordered array.
 
     tune: False (default launch configuration), True (time every candidate at
-    creation, keep the fastest) or an int 0 <= k < 6 pinning candidate k."""
+    creation, keep the fastest) or an int 0 <= k < 6 pinning candidate k
+    (2 * FFT tiling + grid mode)."""
 
     def __init__(self, sizes, L=100.0, b=0.0, c=1.5, dt=0.025, scheme="rk4", graph=True, tune=False):
         lib = load()

@@ -26,7 +26,7 @@ struct RegKernels {
     void (*cb)(const double2*, double2*, ChebDev, int, const double2*) = nullptr;
 };
 
-constexpr int kRegVariants = 4;
+constexpr int kRegVariants = 5;
 // Fill `k` with variant `variant` of the kernels for length L; false if L (or
 // that variant) has no compiled instance.
 bool reg_kernels_for(int L, RegKernels& k, int variant = 0);

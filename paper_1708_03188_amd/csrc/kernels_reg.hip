@@ -580,8 +580,9 @@ static void fill_g(RegKernels& k) {
 }
 
 // Variant v: 0 = (32 threads per line max, two buffers), 1 = (32, one buffer),
-// 2 = (16, two buffers), 3 = (16, one buffer).  Only the hot lengths carry all
-// four; the others have variant 0 only.
+// 2 = (16, two buffers), 3 = (16, one buffer), 4 = (64, one buffer).  The hot
+// lengths 128, 256, 512 carry 0..3 (512 and 1024 also 4); the others have
+// variant 0 only.
 template <int L>
 static bool fill_v(int v, RegKernels& k) {
     switch (v) {
@@ -591,6 +592,13 @@ static bool fill_v(int v, RegKernels& k) {
         case 3: fill_g<L, Geo<L, 16, 1>>(k); return true;
         default: return false;
     }
+}
+// Lengths whose 32-thread geometry needs E = 16: variant 4 = (64 threads per
+// line, one buffer), half the lines and LDS per block.
+template <int L>
+static bool fill_v64(int v, RegKernels& k) {
+    if (v == 4) { fill_g<L, Geo<L, 64, 1>>(k); return true; }
+    return fill_v<L>(v, k);
 }
 template <int L>
 static bool fill0(int v, RegKernels& k) {
@@ -607,8 +615,10 @@ bool reg_kernels_for(int L, RegKernels& k, int variant) {
         case 64: return fill0<64>(variant, k);
         case 128: return fill_v<128>(variant, k);
         case 256: return fill_v<256>(variant, k);
-        case 512: return fill_v<512>(variant, k);
-        case 1024: return fill0<1024>(variant, k);
+        case 512: return fill_v64<512>(variant, k);
+        case 1024:
+            if (variant == 4) { fill_g<1024, Geo<1024, 64, 1>>(k); return true; }
+            return fill0<1024>(variant, k);
         case 48: return fill0<48>(variant, k);
         case 96: return fill0<96>(variant, k);
         case 192: return fill0<192>(variant, k);

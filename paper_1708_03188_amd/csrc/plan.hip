@@ -294,15 +294,7 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
         o_gm[q] = b.add(ct.gmat[q]);
         o_bal[q] = b.add(ct.bal[q]);
         o_bm[q] = b.add(ct.bmat[q]);
-        // identity rows (T0 diagonal 1, no coupling) past the end of the chain, up to the
-        // rows covered by the segmented solve
-        std::vector<double> sv = ct.solve[q];
-        const int kseg = seg_lanes(std::max(ct.npar[0], ct.npar[1]));
-        for (int i = ct.npar[q]; i < kseg * kSegRows + 1; ++i) {
-            sv.resize(20 * (size_t)(i + 1), 0.0);
-            sv[20 * (size_t)i + 2] = 1.0;
-        }
-        o_sv[q] = b.add(sv);
+        o_sv[q] = b.add(ct.solve[q]);
     }
     hipError_t e = hipMalloc(&p->blob, b.host.size());
     if (e != hipSuccess) { set_error("hipMalloc tables: %s", hipGetErrorString(e)); delete p; return SGM_ERR_OOM; }

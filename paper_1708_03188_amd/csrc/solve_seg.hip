@@ -44,22 +44,20 @@ struct SegTraits {
     static constexpr int WS = NC * P;      // w-state doubles
 };
 
-// Band, tail factors of row i of the chain of parity p (Dirichlet in closed
-// form, biharmonic from the plan's row table, 20 doubles per row).  Rows
-// i >= n are identity rows (x_i = 0, no coupling).
+// Band, tail factors of row i < n of the chain of parity p (Dirichlet in
+// closed form, biharmonic from the plan's row table, 20 doubles per row).
 template <int KIND>
 __device__ __forceinline__ void row_coeffs(const double* rows, int p, int i, int n, double mu1, double mu2,
                                            double* band, double* U, double* V) {
     constexpr int P = SegTraits<KIND>::P, Q = SegTraits<KIND>::Q, NR = SegTraits<KIND>::NR;
     if constexpr (KIND == SGM_SHEN_DIRICHLET) {
-        const bool valid = i < n;
         const double k = (double)(p + 2 * i);
         const double ck = (p + 2 * i) == 0 ? 2.0 : 1.0;
-        band[0] = (i >= 1 && valid) ? -mu1 * kHalfPi : 0.0;
-        band[1] = valid ? 4.0 * kHalfPi * (k + 1.0) * (k + 2.0) + mu1 * kHalfPi * (ck + 1.0) : 1.0;
+        band[0] = i >= 1 ? -mu1 * kHalfPi : 0.0;
+        band[1] = 4.0 * kHalfPi * (k + 1.0) * (k + 2.0) + mu1 * kHalfPi * (ck + 1.0);
         band[2] = i + 1 < n ? -mu1 * kHalfPi : 0.0;
-        U[0] = valid ? 8.0 * kHalfPi * (k + 1.0) : 0.0;
-        V[0] = valid ? 1.0 : 0.0;
+        U[0] = 8.0 * kHalfPi * (k + 1.0);
+        V[0] = 1.0;
     } else {
         const double2* row = reinterpret_cast<const double2*>(rows + 20 * i);
         double v[20];

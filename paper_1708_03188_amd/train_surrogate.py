@@ -31,6 +31,7 @@ def main(argv=None):
     ap.add_argument("--eval-every", type=int, default=2000)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--init", default=None, help="checkpoint to continue from")
+    ap.add_argument("--export", default=None, help="also write the inference weights (.npz) at the end")
     args = ap.parse_args(argv)
     t0 = time.perf_counter()
     train = S.generate_trajectories(args.traj, args.snaps, args.N, seed=5000)
@@ -50,6 +51,8 @@ def main(argv=None):
         f.save(args.out)
         print(json.dumps({"steps": done, "heldout_rel_l2_mean": round(m, 5), "heldout_rel_l2_max": round(mx, 5),
                           "train_s": round(time.perf_counter() - t0, 1)}), flush=True)
+    if args.export:
+        S.export_weights(f, args.export)
 
 
 if __name__ == "__main__":

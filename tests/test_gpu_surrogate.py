@@ -1,5 +1,7 @@
 """The learned surrogate: trained on solver trajectories, compared with the method
 without it, and the FP64 fallback engaging (small-grid version of the C5 setup)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -57,11 +59,10 @@ def test_fallback_engages_and_replaces_with_solver(trained):
     assert st2["n_checked"] == 4 and st2["n_fallback"] == 0
 
 
-WEIGHTS = __import__("os").path.join(__import__("os").path.dirname(__file__), "..", "paper_1708_03188_amd", "weights",
-                                     "fno_gl256.npz")
+WEIGHTS = os.path.join(os.path.dirname(__file__), "..", "paper_1708_03188_amd", "weights", "fno_gl256.npz")
 
 
-@pytest.mark.skipif(not __import__("os").path.exists(WEIGHTS), reason="no trained 256^2 weights file")
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained 256^2 weights file")
 def test_trained_256_weights_on_fresh_trajectories(tmp_path):
     # the shipped network (trained on the 256^2 solver trajectories): weights file
     # round trip is exact, and on trajectories from seeds it never saw it is far
