@@ -186,7 +186,8 @@ def leg_biharmonic(steps):
             "fwd_bwd_Gdofs": round(dof / (ms * 1e-3) / 1e9, 3), "ms_fwd_bwd": round(ms, 4),
             "fwd_bwd_hbm_frac": round(pair_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "biharmonic_solves_per_s": round(1e3 / ms_s, 1),
-            "solve_hbm_frac": round(solve_bytes / (ms_s * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            "solve_hbm_frac": round(solve_bytes / (ms_s * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "plan_variants_xyz": p.variants()}
 
 
 def leg_gl(steps):

@@ -64,19 +64,43 @@ __global__ void __launch_bounds__(kThreads) kr_lines_r2c(const double* __restric
         x[e] = make_double2(re, im);
     }
     reg_fft<L, G::NTMAX, -1, G::NB>(x, b0, b1, 1, t, tw);
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < G::E; ++e) b0[t + G::NT * e] = x[e];
-    __syncthreads();
+    // Split the two real lines: X1_k = (Z_k + conj Z_{L-k}) / 2, X2_k = (Z_k - conj Z_{L-k}) / 2i.
     constexpr int Lh = L / 2 + 1;
-    for (int k = t; k < Lh; k += G::NT) {
-        double2 z = b0[k];
-        double2 zr = cconj(b0[k == 0 ? 0 : L - k]);
-        double2 x1 = make_double2(0.5 * scale * (z.x + zr.x), 0.5 * scale * (z.y + zr.y));
-        double2 d = csub(z, zr);
-        double2 x2 = make_double2(0.5 * scale * d.y, -0.5 * scale * d.x);
-        if (l0 < nlines) out[l0 * Lh + k] = x1;
-        if (l0 + 1 < nlines) out[(l0 + 1) * Lh + k] = x2;
+    if constexpr (64 % G::NT == 0) {
+        // Z_{L-k} for k = t + NT e sits in thread (NT - t) mod NT of the same line (own
+        // index E - 1 - e, or E - e for t = 0), inside the same wave: lane shuffles.
+        const int lane = threadIdx.x & 63;
+        const int src = lane - t + (G::NT - t) % G::NT;
+#pragma unroll
+        for (int e = 0; e <= G::E / 2; ++e) {
+            const double2 v = x[G::E - 1 - e];
+            double2 zr = make_double2(__shfl(v.x, src), __shfl(v.y, src));
+            if (t == 0) zr = x[(G::E - e) % G::E];
+            zr = cconj(zr);
+            const int k = t + G::NT * e;
+            if (k < Lh) {
+                const double2 z = x[e];
+                double2 x1 = make_double2(0.5 * scale * (z.x + zr.x), 0.5 * scale * (z.y + zr.y));
+                double2 d = csub(z, zr);
+                double2 x2 = make_double2(0.5 * scale * d.y, -0.5 * scale * d.x);
+                if (l0 < nlines) out[l0 * Lh + k] = x1;
+                if (l0 + 1 < nlines) out[(l0 + 1) * Lh + k] = x2;
+            }
+        }
+    } else {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < G::E; ++e) b0[t + G::NT * e] = x[e];
+        __syncthreads();
+        for (int k = t; k < Lh; k += G::NT) {
+            double2 z = b0[k];
+            double2 zr = cconj(b0[k == 0 ? 0 : L - k]);
+            double2 x1 = make_double2(0.5 * scale * (z.x + zr.x), 0.5 * scale * (z.y + zr.y));
+            double2 d = csub(z, zr);
+            double2 x2 = make_double2(0.5 * scale * d.y, -0.5 * scale * d.x);
+            if (l0 < nlines) out[l0 * Lh + k] = x1;
+            if (l0 + 1 < nlines) out[(l0 + 1) * Lh + k] = x2;
+        }
     }
 }
 
