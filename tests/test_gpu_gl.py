@@ -118,10 +118,10 @@ def test_uniform_solution_and_symmetry(GLBatch):
     assert np.linalg.norm(u - u.T) < 1e-12 * np.linalg.norm(u)
 
 
-def test_c4_batch_sampled_problems(GLBatch):
+def test_ragged_64_problem_batch_sampled(GLBatch):
     # the 64-problem ragged batch (N_i = 128, 192, 256, 384, 512 cyclically), IF-RK4,
     # dt = 0.05, L = 100, b = 1.5, c = -2; one step checked per distinct size.
-    print("[case] gl C4 batch", flush=True)
+    print("[case] gl ragged 64-problem batch", flush=True)
     sizes = synth.gl_ragged_sizes(64)
     L, b, c, dt = 100.0, 1.5, -2.0, 0.05
     g = GLBatch(sizes, L=L, b=b, c=c, dt=dt, scheme="ifrk4")

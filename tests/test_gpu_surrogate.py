@@ -1,5 +1,5 @@
 """The learned surrogate: trained on solver trajectories, compared with the method
-without it, and the FP64 fallback engaging (small-grid version of the C5 setup)."""
+without it, and the FP64 fallback engaging (small-grid version of the 256^2 setup)."""
 import os
 
 import numpy as np

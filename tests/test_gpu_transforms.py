@@ -102,7 +102,7 @@ def test_biharmonic_solve_small(Plan, shape):
     assert rel_err(host(p.biharmonic_solve(dev(ft))), ref) < TOL_S
 
 
-def test_c1_poisson_2d_closed_form(Plan):
+def test_poisson_2d_32x32_closed_form(Plan):
     # -lap u = f with the manufactured u of the 2D case: the GPU pipeline
     # scalar product -> Helmholtz (alpha = 0) -> backward reproduces u.
     x, y, u, f = synth.poisson2d_manufactured(32, 32, seed=1)
@@ -113,7 +113,7 @@ def test_c1_poisson_2d_closed_form(Plan):
     assert rel_err(host(uh), T.forward("dirichlet", u)) < TOL_S
 
 
-def test_c3_style_manufactured_biharmonic_exact_coefficients(Plan):
+def test_manufactured_biharmonic_3d_exact_coefficients(Plan):
     N, M1, M2 = 64, 16, 16
     _, _, _, u, f = synth.biharmonic3d_manufactured(N, M1, M2)
     p = Plan("biharmonic", N, M1, M2)
@@ -202,6 +202,26 @@ def test_autotuned_plan(Plan):
     uh = host(p.forward(dev(u)))
     cols = _sample_cols(p.spec_shape, np.random.default_rng(1), n=8)
     assert rel_err(uh.reshape(256, -1)[:, cols], T.forward_columns("dirichlet", u, cols)) < TOL_T
+
+
+def test_pass_timing_selection(Plan):
+    # events around every pass, then around one pass only; launch counts follow
+    p = Plan("dirichlet", 64, 32, 32)
+    u = dev(_phys((64, 32, 32), "r2c", seed=4))
+    p.set_timing(True)
+    p.pass_times(reset=True)
+    p.backward(p.forward(u))
+    allp = p.pass_times(reset=True)
+    assert set(allp) == {"last_fwd", "mid_fwd", "cheb_fwd", "cheb_bwd", "mid_bwd", "last_bwd"}
+    assert all(c == 1 and ms > 0 for ms, c in allp.values())
+    p.set_timing(True, passes=["cheb_fwd"])
+    for _ in range(3):
+        p.backward(p.forward(u))
+    one = p.pass_times(reset=True)
+    assert set(one) == {"cheb_fwd"} and one["cheb_fwd"][1] == 3
+    p.set_timing(False)
+    p.forward(u)
+    assert p.pass_times(reset=True) == {}
 
 
 SOLVE_N = ([("dirichlet", n) for n in (6, 18, 35, 36, 66, 67, 130, 131, 258, 300, 515, 540)]

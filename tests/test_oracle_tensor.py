@@ -7,7 +7,7 @@ from oracle import chebyshev as C
 from oracle import tensor as T
 
 
-def test_c1_manufactured_poisson_2d():
+def test_manufactured_poisson_2d_32x32():
     # -lap u = f on [-1,1] x [0, 2 pi) with u in the Dirichlet x Fourier space: exact up to rounding.
     x, y, u, f = synth.poisson2d_manufactured(32, 32, seed=1)
     uh = T.helmholtz_solve("dirichlet", T.scalar_product("dirichlet", f), 0.0, 32)
