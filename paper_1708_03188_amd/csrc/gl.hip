@@ -30,6 +30,10 @@
 namespace sgm {
 
 constexpr int kGlThreads = 256;
+// Minimum waves per SIMD the pass kernels are compiled for: caps the registers
+// so three 256-thread work-groups fit a CU (measured faster than the
+// unconstrained two, despite a small call-frame spill).
+constexpr int kGlWavesPerSimd = 3;
 
 constexpr int gmin(int a, int b) { return a < b ? a : b; }
 
@@ -360,7 +364,7 @@ static int reg_w(int kind) {
 // Items are taken in a grid-stride loop (a persistent grid when gridDim.x is
 // smaller than the item count, one block per item otherwise).
 template <class CF, bool GEN>
-__global__ void __launch_bounds__(kGlThreads) k_gl_rows_inv(const GLProb* probs, const GLItem* items, int nitems,
+__global__ void __launch_bounds__(kGlThreads, kGlWavesPerSimd) k_gl_rows_inv(const GLProb* probs, const GLItem* items, int nitems,
                                                             const double2* src, double2* work) {
     extern __shared__ double2 lds[];
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -378,7 +382,7 @@ __global__ void __launch_bounds__(kGlThreads) k_gl_rows_inv(const GLProb* probs,
 }
 
 template <class CF, bool GEN>
-__global__ void __launch_bounds__(kGlThreads) k_gl_cols(const GLProb* probs, const GLItem* items, int nitems,
+__global__ void __launch_bounds__(kGlThreads, kGlWavesPerSimd) k_gl_cols(const GLProb* probs, const GLItem* items, int nitems,
                                                         double2* work, double cnl) {
     extern __shared__ double2 lds[];
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -396,7 +400,7 @@ __global__ void __launch_bounds__(kGlThreads) k_gl_cols(const GLProb* probs, con
 }
 
 template <class CF, bool GEN, bool FUSE>
-__global__ void __launch_bounds__(kGlThreads) k_gl_rows_fwd(const GLProb* probs, const GLItem* items, int nitems,
+__global__ void __launch_bounds__(kGlThreads, kGlWavesPerSimd) k_gl_rows_fwd(const GLProb* probs, const GLItem* items, int nitems,
                                                             double2* work, GLStage st) {
     extern __shared__ double2 lds[];
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
