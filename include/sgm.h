@@ -248,7 +248,9 @@ sgm_status sgm_fno_unpack(const float* x, void* u_c128, int64_t n, void* stream)
  * whose relative L2 error ||pred - solver|| / ||solver|| (physical fields) exceeds
  * tol is replaced by the solver's result.  stats (may be NULL) accumulates over
  * the call.  Workspace for B samples is allocated on the first call (and when B
- * grows).  Synchronises the stream once per macro-step. */
+ * grows).  The FP64 checks run on a private second stream of the library
+ * (default priority), overlapped with the inference, and are joined to `stream`
+ * before the comparison.  Synchronises the stream once per macro-step. */
 typedef struct {
     int n_checked;     /* samples checked by the solver        */
     int n_fallback;    /* checked samples replaced             */

@@ -250,6 +250,9 @@ struct sgm_fno_s {
     // advance_checked workspace (grown on demand)
     long adv_cap = 0;       // samples
     void* adv = nullptr;
+    // second stream for the FP64 check path, overlapped with inference
+    hipStream_t adv_stream = nullptr;
+    hipEvent_t adv_ev[2] = {nullptr, nullptr};
 };
 
 static long fno_act_elems(const sgm_fno_s* f) { return (long)f->Bmax * f->H * f->W * f->C; }
@@ -259,6 +262,9 @@ extern "C" sgm_status sgm_fno_destroy(sgm_fno f) {
     if (!f) return SGM_OK;
     hipFree(f->all);
     hipFree(f->adv);
+    for (hipEvent_t e : f->adv_ev)
+        if (e) hipEventDestroy(e);
+    if (f->adv_stream) hipStreamDestroy(f->adv_stream);
     delete f;
     return SGM_OK;
 }
@@ -775,6 +781,12 @@ extern "C" sgm_status sgm_fno_advance_checked(sgm_fno f, sgm_gl gl, sgm_gl gl_ch
         SGM_HIP_TRY(hipMalloc(&f->adv, bytes));
         f->adv_cap = need;
     }
+    if (!f->adv_stream) {
+        SGM_HIP_TRY(hipStreamCreateWithFlags(&f->adv_stream, hipStreamNonBlocking));
+        SGM_HIP_TRY(hipEventCreateWithFlags(&f->adv_ev[0], hipEventDisableTiming));
+        SGM_HIP_TRY(hipEventCreateWithFlags(&f->adv_ev[1], hipEventDisableTiming));
+    }
+    hipStream_t s2 = f->adv_stream;
     char* w = static_cast<char*>(f->adv);
     double2* phys = reinterpret_cast<double2*>(w); w += (size_t)B * HW * 16;
     float* x = reinterpret_cast<float*>(w); w += (size_t)B * HW * 8;
@@ -794,19 +806,23 @@ extern "C" sgm_status sgm_fno_advance_checked(sgm_fno f, sgm_gl gl, sgm_gl gl_ch
         const int offs = (int)(rng() % (uint64_t)stride);
         std::vector<int> idx(NC);
         for (int k = 0; k < NC; ++k) idx[k] = offs + k * stride;
-        // surrogate prediction for every sample
+        // FP64 solver on the checked subset, on the second stream once the state is ready
+        SGM_HIP_TRY(hipEventRecord(f->adv_ev[0], s));
+        SGM_HIP_TRY(hipStreamWaitEvent(s2, f->adv_ev[0], 0));
+        for (int k = 0; k < NC; ++k)
+            SGM_HIP_TRY(hipMemcpyAsync(chk + (long)k * HW, uh + (long)idx[k] * HW, HW * 16, hipMemcpyDeviceToDevice, s2));
+        if ((r = sgm_gl_step(gl_check, chk, steps_per, s2)) != SGM_OK) return r;
+        if ((r = sgm_gl_backward(gl_check, chk, chkp, s2)) != SGM_OK) return r;
+        if ((r = sgm_fno_pack(chkp, xs, (int64_t)NC * HW, s2)) != SGM_OK) return r;
+        SGM_HIP_TRY(hipEventRecord(f->adv_ev[1], s2));
+        // surrogate prediction for every sample, meanwhile on the caller's stream
         if ((r = sgm_gl_backward(gl, uh, phys, s)) != SGM_OK) return r;
         if ((r = sgm_fno_pack(phys, x, (int64_t)B * HW, s)) != SGM_OK) return r;
         for (int b0 = 0; b0 < B; b0 += f->Bmax) {
             const int nb = std::min(f->Bmax, B - b0);
             if ((r = sgm_fno_infer(f, x + (long)b0 * HW * 2, pred + (long)b0 * HW * 2, nb, s)) != SGM_OK) return r;
         }
-        // FP64 solver on the checked subset
-        for (int k = 0; k < NC; ++k)
-            SGM_HIP_TRY(hipMemcpyAsync(chk + (long)k * HW, uh + (long)idx[k] * HW, HW * 16, hipMemcpyDeviceToDevice, s));
-        if ((r = sgm_gl_step(gl_check, chk, steps_per, s)) != SGM_OK) return r;
-        if ((r = sgm_gl_backward(gl_check, chk, chkp, s)) != SGM_OK) return r;
-        if ((r = sgm_fno_pack(chkp, xs, (int64_t)NC * HW, s)) != SGM_OK) return r;
+        SGM_HIP_TRY(hipStreamWaitEvent(s, f->adv_ev[1], 0));
         for (int k = 0; k < NC; ++k)
             SGM_HIP_TRY(hipMemcpyAsync(ps + (long)k * HW * 2, pred + (long)idx[k] * HW * 2, HW * 8,
                                        hipMemcpyDeviceToDevice, s));
