@@ -57,7 +57,8 @@ def pass_bytes(N, M1, M2, nb):
     }
 
 
-VARIANT_GEO = {0: (32, 2), 1: (32, 1), 2: (16, 2), 3: (16, 1), 4: (64, 1)}
+# variant -> (threads per line at most, exchange buffers, block size)
+VARIANT_GEO = {0: (32, 2, 256), 1: (32, 1, 256), 2: (16, 2, 256), 3: (16, 1, 256), 4: (64, 1, 256), 5: (32, 1, 512)}
 PASS_KERNEL = {"last_fwd": ("kr_lines_r2c", 2), "last_bwd": ("kr_lines_c2r", 2), "mid_fwd": ("kr_strided", 1),
                "mid_bwd": ("kr_strided", 1), "cheb_fwd": ("kr_cheb_fwd", 0), "cheb_bwd": ("kr_cheb_bwd", 0)}
 
@@ -84,7 +85,7 @@ def measured_traffic(pass_name, variants, L):
     v = variants[axis]
     if v < 0:
         return None
-    nt, nb = VARIANT_GEO[v]
+    nt, nb, th = VARIANT_GEO[v]
     with open(path) as fh:
         txt = fh.read()
     if f"kernel-source hash: {kernel_source_hash()}" not in txt:
@@ -92,7 +93,7 @@ def measured_traffic(pass_name, variants, L):
     sign = ""
     if name == "kr_strided":
         sign = ", -1>" if pass_name == "mid_fwd" else ", 1>"
-    key = f"sgm::{name}<{L}, sgm::Geo<{L}, {nt}, {nb}>"
+    key = f"sgm::{name}<{L}, sgm::Geo<{L}, {nt}, {nb}, {th}>"
     for line in txt.splitlines():
         if key in line and (not sign or line.split("|")[1].strip().endswith(sign)) and \
                 (name != "kr_cheb_fwd" or line.split("|")[1].strip().endswith(", 3>")):
@@ -109,8 +110,8 @@ def pass_kernel_name(pass_name, variants, L):
     v = variants[axis]
     if v < 0:
         return f"generic LDS kernel for {pass_name}"
-    nt, nb = VARIANT_GEO[v]
-    return f"{name}<{L}, Geo<{L}, {nt}, {nb}>>"
+    nt, nb, th = VARIANT_GEO[v]
+    return f"{name}<{L}, Geo<{L}, {nt}, {nb}, {th}>>"
 
 
 def cpu_baseline(N, M1, M2):

@@ -64,7 +64,7 @@ typedef struct {
                       compiled instance, generic LDS kernels otherwise); 1: time the
                       candidates once at creation and keep the fastest; 2: generic
                       LDS kernels only; 16 + v: pin register-kernel variant v
-                      (0..4) wherever it is compiled (diagnostics) */
+                      (0..5) wherever it is compiled (diagnostics) */
 } sgm_plan_desc;
 
 /* Create a plan for the tensor-product space V(x) x V^p(y) [x V^p(z)] (Sec. 4,
@@ -125,7 +125,7 @@ sgm_status sgm_biharmonic_solve(sgm_plan plan, const void* f_tilde, void* u_hat,
 #define SGM_NPASS 8
 #define SGM_TIMING_ONLY 0x100
 sgm_status sgm_plan_timing(sgm_plan plan, int enable);
-/* Register-kernel variant in use per axis (x, y, z): 0..4, or -1 where the axis runs
+/* Register-kernel variant in use per axis (x, y, z): 0..5, or -1 where the axis runs
  * the generic LDS kernels (diagnostics; chosen at creation, see autotune). */
 sgm_status sgm_plan_variants(sgm_plan plan, int variant[3]);
 sgm_status sgm_plan_pass_times(sgm_plan plan, double ms[SGM_NPASS], int64_t count[SGM_NPASS], int reset);

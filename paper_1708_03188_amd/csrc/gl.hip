@@ -858,9 +858,7 @@ static sgm_status gl_transform(sgm_gl g, const double2* in, double2* out, int si
             hipLaunchKernelGGL(sign < 0 ? k.c2c_f : k.c2c_b, dim3((N + k.W - 1) / k.W), dim3(k.threads), k.lds, s, src,
                                dst, N, g->rpN[i].tw, sc);
             SGM_HIP_TRY(hipGetLastError());
-            hipLaunchKernelGGL(sign < 0 ? k.str_f : k.str_b, dim3((N + k.W - 1) / k.W), dim3(k.threads), k.lds, s,
-                               (const double2*)dst, dst, 1, N, g->rpN[i].tw, sc);
-            SGM_HIP_TRY(hipGetLastError());
+            SGM_HIP_TRY(launch_strided(k, sign, dst, dst, 1, N, g->rpN[i].tw, sc, s));
         } else {
             int G = std::max(1, std::min(16, 2048 / N));
             SGM_HIP_TRY(launch_lines_c2c(src, dst, N, N, G, g->rpN[i], sign, sc, s));

@@ -12,6 +12,7 @@ struct RegKernels {
     int threads = 0; // block size (W * threads per line)
     size_t lds = 0;      // dynamic LDS bytes of the Fourier-line kernels
     size_t lds_cheb = 0; // dynamic LDS bytes of the Chebyshev-axis kernels (two tiles)
+    size_t lds_str = 0;  // dynamic LDS bytes of the strided kernels (exchange + twiddles)
     int variant = 0;
     void (*r2c)(const double*, double2*, int, const double2*, double) = nullptr;
     void (*c2r)(const double2*, double*, int, const double2*) = nullptr;
@@ -26,9 +27,20 @@ struct RegKernels {
     void (*cb)(const double2*, double2*, ChebDev, int, const double2*) = nullptr;
 };
 
-constexpr int kRegVariants = 5;
+constexpr int kRegVariants = 6;
 // Fill `k` with variant `variant` of the kernels for length L; false if L (or
 // that variant) has no compiled instance.
 bool reg_kernels_for(int L, RegKernels& k, int variant = 0);
+
+// Byte-offset range of the strided kernels' buffer accesses.
+constexpr long kBufRange = 0x7ffffff0;
+inline bool strided_fits(const RegKernels& k, int inner) { return (long)(k.W + 2L * inner) * k.L * 16 < kBufRange; }
+
+// Strided pass (sign -1 forward, +1 backward) over `outer` slabs of L x inner
+// complex values, line stride inner: persistent launch sized to the device's
+// occupancy.  hipErrorInvalidValue if a slab pair exceeds the kernel's 2 GB
+// buffer-offset range.
+hipError_t launch_strided(const RegKernels& k, int sign, const double2* in, double2* out, int outer, int inner,
+                          const double2* tw, double scale, hipStream_t s);
 
 }  // namespace sgm

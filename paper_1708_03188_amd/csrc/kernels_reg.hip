@@ -1,6 +1,7 @@
 // Transform passes built on the register-resident FFT (compile-time lengths).
 //
-// Every block has 256 threads = W lines x NT threads per line.  For
+// Every block has W lines x NT threads per line (256 threads, 512 for the wide
+// variant).  For
 // strided passes (middle periodic axis, Chebyshev axis) lane -> (column c =
 // lane % W, thread t = lane / W), so one warp-wide access covers W adjacent
 // columns of a row; for contiguous lines lane -> (t = lane % NT, line =
@@ -8,6 +9,9 @@
 #include "fft_reg.h"
 #include "kernels.h"
 #include "kernels_reg.h"
+
+#include <map>
+#include <mutex>
 
 namespace sgm {
 
@@ -28,17 +32,18 @@ __device__ __forceinline__ int xcd_block() {
 }
 
 // Launch geometry of one variant: NTMAX bounds the threads per line (so
-// E = L / NT points per thread), NB is the number of exchange buffers.
-template <int L, int NTMAX_, int NB_>
+// E = L / NT points per thread), NB is the number of exchange buffers, TH the
+// block size to fill.
+template <int L, int NTMAX_, int NB_, int TH = kThreads>
 struct Geo {
     static constexpr int NTMAX = NTMAX_;
     static constexpr int NB = NB_;
     static constexpr Sched sd = make_sched(L, NTMAX);
     static constexpr int NT = sd.NT;
     static constexpr int E = sd.E;
-    // lines per block: fill 256 threads unless the exchange buffers
+    // lines per block: fill TH threads unless the exchange buffers
     // (NB * W * L * 16 bytes) would exceed the LDS budget
-    static constexpr int W = cmin(kThreads / NT, kLdsBudget / (16 * NB * L)) > 0 ? cmin(kThreads / NT, kLdsBudget / (16 * NB * L)) : 1;
+    static constexpr int W = cmin(TH / NT, kLdsBudget / (16 * NB * L)) > 0 ? cmin(TH / NT, kLdsBudget / (16 * NB * L)) : 1;
     static constexpr int THREADS = W * NT;
     // offset of the second exchange buffer (elements)
     static constexpr int B1OFF = NB == 2 ? W * L : 0;
@@ -48,7 +53,7 @@ struct Geo {
 // contiguous lines
 // ---------------------------------------------------------------------------
 template <int L, class G>
-__global__ void __launch_bounds__(kThreads) kr_lines_r2c(const double* __restrict__ in, double2* __restrict__ out,
+__global__ void __launch_bounds__(G::THREADS) kr_lines_r2c(const double* __restrict__ in, double2* __restrict__ out,
                                                          int nlines, const double2* __restrict__ tw, double scale) {
     extern __shared__ double2 lds[];
     const int t = threadIdx.x % G::NT, g = threadIdx.x / G::NT;
@@ -105,7 +110,7 @@ __global__ void __launch_bounds__(kThreads) kr_lines_r2c(const double* __restric
 }
 
 template <int L, class G>
-__global__ void __launch_bounds__(kThreads) kr_lines_c2r(const double2* __restrict__ in, double* __restrict__ out,
+__global__ void __launch_bounds__(G::THREADS) kr_lines_c2r(const double2* __restrict__ in, double* __restrict__ out,
                                                          int nlines, const double2* __restrict__ tw) {
     extern __shared__ double2 lds[];
     const int t = threadIdx.x % G::NT, g = threadIdx.x / G::NT;
@@ -134,7 +139,7 @@ __global__ void __launch_bounds__(kThreads) kr_lines_c2r(const double2* __restri
 }
 
 template <int L, class G, int SIGN>
-__global__ void __launch_bounds__(kThreads) kr_lines_c2c(const double2* __restrict__ in, double2* __restrict__ out,
+__global__ void __launch_bounds__(G::THREADS) kr_lines_c2c(const double2* __restrict__ in, double2* __restrict__ out,
                                                          int nlines, const double2* __restrict__ tw, double scale) {
     extern __shared__ double2 lds[];
     const int t = threadIdx.x % G::NT, g = threadIdx.x / G::NT;
@@ -154,24 +159,95 @@ __global__ void __launch_bounds__(kThreads) kr_lines_c2c(const double2* __restri
 // ---------------------------------------------------------------------------
 // strided lines: data[o][e][c]
 // ---------------------------------------------------------------------------
+// Raw buffer access: a lane whose byte offset is kOob reads zeros and its store
+// is dropped by the hardware range check, so predicated accesses need no
+// branches and the compiler can count outstanding memory operations exactly.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kOob = 0x7fffffff;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)kBufRange, 0x00020000);
+}
+__device__ __forceinline__ double2 buf_ld(__amdgpu_buffer_rsrc_t r, int off) {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    double2 d;
+    __builtin_memcpy(&d, &v, 16);
+    return d;
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, int off, double2 d) {
+    u32x4 v;
+    __builtin_memcpy(&v, &d, 16);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 0);
+}
+
+// Persistent pass over tiles of W consecutive columns of the flattened
+// (outer, inner) column index, so no tile is ragged except the very last one
+// (a tile may straddle two slabs; each lane addresses its own slab).  With the
+// grid a multiple of 8, XCD k walks tiles [k n / 8, (k + 1) n / 8), its blocks
+// interleaved; otherwise the blocks stride over all tiles.  The next tile's
+// loads are in flight during this tile's FFT.  The launch helper checks that
+// every byte offset from a tile's first slab stays below kBufRange.
 template <int L, class G, int SIGN>
-__global__ void __launch_bounds__(kThreads) kr_strided(const double2* in, double2* out, int outer, int inner,
-                                                       const double2* __restrict__ tw, double scale) {
+__global__ void __launch_bounds__(G::THREADS) kr_strided(const double2* in, double2* out, int outer, int inner,
+                                                         const double2* __restrict__ tw, double scale) {
     extern __shared__ double2 lds[];
     const int c = threadIdx.x % G::W, t = threadIdx.x / G::W;
-    const int tiles = (inner + G::W - 1) / G::W;
-    const int bid = xcd_block();
-    const int o = bid / tiles;
-    const int c0 = (bid - o * tiles) * G::W;
-    const bool ok = c0 + c < inner;
-    const long base = (long)o * L * inner + c0 + c;
-    double2 x[G::E];
+    const long ncol = (long)outer * inner;
+    const int ntiles = (int)((ncol + G::W - 1) / G::W);
+    int nx, hi, b;
+    if ((gridDim.x & 7) == 0) {
+        const int xi = (int)(blockIdx.x & 7);
+        nx = (int)(gridDim.x >> 3);
+        hi = (int)((long)ntiles * (xi + 1) / 8);
+        b = (int)((long)ntiles * xi / 8) + (int)(blockIdx.x >> 3);
+    } else {
+        nx = (int)gridDim.x;
+        hi = ntiles;
+        b = (int)blockIdx.x;
+    }
+    // twiddles from LDS: their reads do not queue behind the prefetch
+    double2* twl = lds + G::NB * G::W * L;
+    for (int i = threadIdx.x; i < L; i += G::THREADS) twl[i] = tw[i];
+    __syncthreads();
+    const int rs = inner * 16;
+    // first slab of a tile (block-uniform) and this lane's column offset from it
+    auto slab0 = [&](int bb) { return bb < hi ? (int)((long)bb * G::W / inner) : 0; };
+    auto lane_off = [&](int bb, int o0) {
+        const long g = (long)bb * G::W + c;
+        if (bb >= hi || g >= ncol) return kOob;
+        const int o = (int)(g / inner);
+        return ((o - o0) * L * inner + (int)(g - (long)o * inner)) * 16;
+    };
+    double2 x[G::E], y[G::E];
+    int o0 = slab0(b);
+    int off = lane_off(b, o0);
+    {
+        const auto r = buf_rsrc(in + (long)o0 * L * inner);
 #pragma unroll
-    for (int e = 0; e < G::E; ++e) x[e] = ok ? in[base + (long)(t + G::NT * e) * inner] : make_double2(0.0, 0.0);
-    reg_fft<L, G::NTMAX, SIGN, G::NB>(x, lds + c, lds + G::B1OFF + c, G::W, t, tw);
-    if (ok) {
+        for (int e = 0; e < G::E; ++e) x[e] = buf_ld(r, off == kOob ? kOob : off + (t + G::NT * e) * rs);
+    }
+    while (b < hi) {
+        const int bn = b + nx;
+        const int o0n = slab0(bn);
+        const int offn = lane_off(bn, o0n);
+        {
+            const auto r = buf_rsrc(in + (long)o0n * L * inner);
 #pragma unroll
-        for (int e = 0; e < G::E; ++e) out[base + (long)(t + G::NT * e) * inner] = cscale(x[e], scale);
+            for (int e = 0; e < G::E; ++e) y[e] = buf_ld(r, offn == kOob ? kOob : offn + (t + G::NT * e) * rs);
+        }
+        reg_fft<L, G::NTMAX, SIGN, G::NB>(x, lds + c, lds + G::B1OFF + c, G::W, t, twl);
+        {
+            const auto r = buf_rsrc(out + (long)o0 * L * inner);
+#pragma unroll
+            for (int e = 0; e < G::E; ++e)
+                buf_st(r, off == kOob ? kOob : off + (t + G::NT * e) * rs, cscale(x[e], scale));
+        }
+        __syncthreads();  // every exchange read done before the next tile's first write
+#pragma unroll
+        for (int e = 0; e < G::E; ++e) x[e] = y[e];
+        off = offn;
+        o0 = o0n;
+        b = bn;
     }
 }
 
@@ -377,7 +453,7 @@ __device__ void project_segmented(double2* B0, double2* SC, int W, int nseg, con
 }
 
 template <int N, class G, int MODE>
-__global__ void __launch_bounds__(kThreads) kr_cheb_fwd(const double2* in, double2* out, ChebDev cd, int ncols,
+__global__ void __launch_bounds__(G::THREADS) kr_cheb_fwd(const double2* in, double2* out, ChebDev cd, int ncols,
                                                         const double2* __restrict__ tw) {
     constexpr int W = G::W, NT = G::NT, E = G::E;
     extern __shared__ double2 lds[];
@@ -501,7 +577,7 @@ __global__ void __launch_bounds__(kThreads) kr_cheb_fwd(const double2* in, doubl
         __syncthreads();
         constexpr int R = kProjSegRowsDev;
         const int nseg = (max(cd.npar[0], cd.npar[1]) + R - 1) / R;
-        if (2 * W * nseg <= kThreads && 2 * nseg <= NT) {
+        if (2 * W * nseg <= G::THREADS && 2 * nseg <= NT) {
             project_segmented(B0, SC, W, nseg, cd);
         } else {
             const int lane = threadIdx.x;
@@ -524,7 +600,7 @@ __global__ void __launch_bounds__(kThreads) kr_cheb_fwd(const double2* in, doubl
 // Chebyshev axis, backward (recombination + DCT-III)
 // ---------------------------------------------------------------------------
 template <int N, class G>
-__global__ void __launch_bounds__(kThreads) kr_cheb_bwd(const double2* in, double2* out, ChebDev cd, int ncols,
+__global__ void __launch_bounds__(G::THREADS) kr_cheb_bwd(const double2* in, double2* out, ChebDev cd, int ncols,
                                                         const double2* __restrict__ tw) {
     constexpr int W = G::W, NT = G::NT, E = G::E;
     extern __shared__ double2 lds[];
@@ -589,6 +665,7 @@ static void fill_g(RegKernels& k) {
     k.W = G::W;
     k.threads = G::THREADS;
     k.lds = sizeof(double2) * (size_t)G::NB * G::W * L;
+    k.lds_str = k.lds + sizeof(double2) * (size_t)L;
     k.lds_cheb = sizeof(double2) * ((size_t)G::NB * G::W * L + 2 * (size_t)G::NT * G::W);
     k.r2c = kr_lines_r2c<L, G>;
     k.c2r = kr_lines_c2r<L, G>;
@@ -604,9 +681,10 @@ static void fill_g(RegKernels& k) {
 }
 
 // Variant v: 0 = (32 threads per line max, two buffers), 1 = (32, one buffer),
-// 2 = (16, two buffers), 3 = (16, one buffer), 4 = (64, one buffer).  The hot
-// lengths 128, 256, 512 carry 0..3 (512 and 1024 also 4); the others have
-// variant 0 only.
+// 2 = (16, two buffers), 3 = (16, one buffer), 4 = (64, one buffer), 5 = (32,
+// one buffer, 512-thread blocks: twice the lines per block, so the strided
+// passes move 256-byte row segments).  The hot lengths 128, 256, 512 carry
+// 0..3 and 5 (512 and 1024 also 4); the others have variant 0 only.
 template <int L>
 static bool fill_v(int v, RegKernels& k) {
     switch (v) {
@@ -614,6 +692,7 @@ static bool fill_v(int v, RegKernels& k) {
         case 1: fill_g<L, Geo<L, 32, 1>>(k); return true;
         case 2: fill_g<L, Geo<L, 16, 2>>(k); return true;
         case 3: fill_g<L, Geo<L, 16, 1>>(k); return true;
+        case 5: fill_g<L, Geo<L, 32, 1, 512>>(k); return true;
         default: return false;
     }
 }
@@ -653,6 +732,37 @@ bool reg_kernels_for(int L, RegKernels& k, int variant) {
         case 576: return fill0<576>(variant, k);
         default: return false;
     }
+}
+
+// Occupancy-sized grid of a persistent kernel, cached per (kernel, device).
+static long resident_grid(const void* f, int threads, size_t lds) {
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, long> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 8;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({f, dev});
+    if (it != cache.end()) return it->second;
+    int per = 0, cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, threads, lds) != hipSuccess || per < 1) per = 1;
+    long g = (long)per * cus;
+    g = g < 8 ? 8 : g - g % 8;
+    cache[{f, dev}] = g;
+    return g;
+}
+
+hipError_t launch_strided(const RegKernels& k, int sign, const double2* in, double2* out, int outer, int inner,
+                          const double2* tw, double scale, hipStream_t s) {
+    const long ncol = (long)outer * inner;
+    if (ncol <= 0) return hipSuccess;
+    if (!strided_fits(k, inner)) return hipErrorInvalidValue;
+    auto f = sign < 0 ? k.str_f : k.str_b;
+    const long tiles = (ncol + k.W - 1) / k.W;
+    long grid = resident_grid(reinterpret_cast<const void*>(f), k.threads, k.lds_str);
+    if (tiles < grid) grid = (tiles + 7) / 8 * 8;
+    hipLaunchKernelGGL(f, dim3((unsigned)grid), dim3(k.threads), k.lds_str, s, in, out, outer, inner, tw, scale);
+    return hipGetLastError();
 }
 
 }  // namespace sgm

@@ -197,7 +197,8 @@ static sgm_status autotune_plan(sgm_plan p, int lds_max) {
         for (int v = 0; v < kRegVariants; ++v) {
             RegKernels cand;
             if (!reg_kernels_for(ax.L, cand, v)) continue;
-            if ((ax.idx == 0 ? cand.lds_cheb : cand.lds) > (size_t)lds_max) continue;
+            if ((ax.idx == 0 ? cand.lds_cheb : ax.idx == 1 ? cand.lds_str : cand.lds) > (size_t)lds_max) continue;
+            if (ax.idx == 1 && !strided_fits(cand, p->spec_last)) continue;
             RegKernels saved = *ax.rk;
             *ax.rk = cand;
             float t = time_ms([&]() {
@@ -355,7 +356,7 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
         p->hy = d.ndim == 3 && pick(d.M1, p->rky);
         p->hz = pick(Llast, p->rkz);
         if (p->hx && p->rkx.lds_cheb > (size_t)lds) p->hx = false;
-        if (p->hy && p->rky.lds > (size_t)lds) p->hy = false;
+        if (p->hy && (p->rky.lds_str > (size_t)lds || !strided_fits(p->rky, p->spec_last))) p->hy = false;
         if (p->hz && p->rkz.lds > (size_t)lds) p->hz = false;
         if (d.autotune == 1) {
             sgm_status st2 = autotune_plan(p, lds);
@@ -455,8 +456,7 @@ static sgm_status fourier_forward(sgm_plan p, const void* u, double2* uh, hipStr
         PassTimer t(p, 2, s);
         const RegKernels& k = p->rky;
         if (p->hy)
-            SGM_HIP_TRY(launch_k(k.str_f, (long)p->N * ((p->spec_last + k.W - 1) / k.W), k.threads, k.lds, s,
-                                 (const double2*)uh, uh, p->N, p->spec_last, p->rpy.tw, 1.0 / p->M1));
+            SGM_HIP_TRY(launch_strided(k, -1, uh, uh, p->N, p->spec_last, p->rpy.tw, 1.0 / p->M1, s));
         else
             SGM_HIP_TRY(launch_strided_c2c(uh, uh, p->M1, p->N, p->spec_last, p->W_mid, p->rpy, -1, 1.0 / p->M1, s));
     }
@@ -518,8 +518,7 @@ sgm_status sgm_backward(sgm_plan p, const void* u_hat, void* u, void* stream) {
         PassTimer t(p, 3, s);
         const RegKernels& k = p->rky;
         if (p->hy)
-            SGM_HIP_TRY(launch_k(k.str_b, (long)p->N * ((p->spec_last + k.W - 1) / k.W), k.threads, k.lds, s,
-                                 (const double2*)w, w, p->N, p->spec_last, p->rpy.tw, 1.0));
+            SGM_HIP_TRY(launch_strided(k, 1, w, w, p->N, p->spec_last, p->rpy.tw, 1.0, s));
         else
             SGM_HIP_TRY(launch_strided_c2c(w, w, p->M1, p->N, p->spec_last, p->W_mid, p->rpy, 1, 1.0, s));
     }
