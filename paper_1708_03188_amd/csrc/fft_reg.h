@@ -59,11 +59,46 @@ constexpr int sched_m(const Sched& s, int S) {
     return m;
 }
 
+// Twiddles a thread uses over the whole transform: stage S >= 1 needs p - 1
+// per butterfly q (stage 0 has m = 1 and none).
+template <int L, int NTMAX, int MAXR = 8>
+constexpr int tw_count() {
+    constexpr Sched sd = make_sched(L, NTMAX, MAXR);
+    int n = 0;
+    for (int S = 1; S < sd.nst; ++S) n += (sd.E / sd.rad[S]) * (sd.rad[S] - 1);
+    return n;
+}
+
+// Fetch those twiddles into w (stage by stage, butterfly q, then r = 1..p-1),
+// so a kernel can issue them together with its data loads.
+template <int L, int NTMAX, int SIGN, int S = 0, int MAXR = 8>
+__device__ __forceinline__ void load_twiddles(double2* w, int t, const double2* __restrict__ tw) {
+    constexpr Sched sd = make_sched(L, NTMAX, MAXR);
+    if constexpr (S < sd.nst) {
+        constexpr int p = sd.rad[S];
+        constexpr int m = sched_m(sd, S);
+        constexpr int Q = sd.E / p;
+        if constexpr (m > 1) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int k = (t + sd.NT * q) % m;
+                const int step = k * (L / (p * m));
+#pragma unroll
+                for (int r = 1; r < p; ++r) w[q * (p - 1) + r - 1] = twiddle<SIGN>(tw, r * step);
+            }
+            load_twiddles<L, NTMAX, SIGN, S + 1, MAXR>(w + Q * (p - 1), t, tw);
+        } else {
+            load_twiddles<L, NTMAX, SIGN, S + 1, MAXR>(w, t, tw);
+        }
+    }
+}
+
 // Exchange buffer addressing for one line: position v lives at base[v * ps].
 // Stages alternate between two buffers so one barrier per exchange suffices.
-template <int L, int NTMAX, int SIGN, int S, int NBUF, int MAXR>
+// With PRE, w holds this thread's twiddles in load_twiddles order.
+template <int L, int NTMAX, int SIGN, int S, int NBUF, int MAXR, bool PRE = false>
 __device__ __forceinline__ void reg_stages(double2* x, double2* b0, double2* b1, int ps, int t,
-                                           const double2* __restrict__ tw, bool act) {
+                                           const double2* __restrict__ tw, bool act, const double2* w = nullptr) {
     constexpr Sched sd = make_sched(L, NTMAX, MAXR);
     if constexpr (S < sd.nst) {
         constexpr int p = sd.rad[S];
@@ -81,9 +116,14 @@ __device__ __forceinline__ void reg_stages(double2* x, double2* b0, double2* b1,
 #pragma unroll
             for (int r = 0; r < p; ++r) y[r] = x[q + r * Q];
             if constexpr (m > 1) {
-                const int step = k * (L / (p * m));
+                if constexpr (PRE) {
 #pragma unroll
-                for (int r = 1; r < p; ++r) y[r] = cmul(y[r], twiddle<SIGN>(tw, r * step));
+                    for (int r = 1; r < p; ++r) y[r] = cmul(y[r], w[q * (p - 1) + r - 1]);
+                } else {
+                    const int step = k * (L / (p * m));
+#pragma unroll
+                    for (int r = 1; r < p; ++r) y[r] = cmul(y[r], twiddle<SIGN>(tw, r * step));
+                }
             }
             Dft<p, SIGN>::run(y);
             if constexpr (last) {
@@ -105,7 +145,8 @@ __device__ __forceinline__ void reg_stages(double2* x, double2* b0, double2* b1,
             }
             // one buffer: every thread must have read it before the next stage writes
             if constexpr (NBUF == 1 && S + 1 < sd.nst - 1) __syncthreads();
-            reg_stages<L, NTMAX, SIGN, S + 1, NBUF, MAXR>(x, b0, b1, ps, t, tw, act);
+            reg_stages<L, NTMAX, SIGN, S + 1, NBUF, MAXR, PRE>(x, b0, b1, ps, t, tw, act,
+                                                             m > 1 && PRE ? w + Q * (p - 1) : w);
         }
     }
 }
@@ -120,6 +161,12 @@ template <int L, int NTMAX, int SIGN, int NBUF = 2, int MAXR = 8>
 __device__ __forceinline__ void reg_fft(double2* x, double2* b0, double2* b1, int ps, int t,
                                         const double2* __restrict__ tw, bool act = true) {
     reg_stages<L, NTMAX, SIGN, 0, NBUF, MAXR>(x, b0, b1, ps, t, tw, act);
+}
+
+// The same with the twiddles already in w (load_twiddles<L, NTMAX, SIGN>).
+template <int L, int NTMAX, int SIGN, int NBUF = 2, int MAXR = 8>
+__device__ __forceinline__ void reg_fft_pre(double2* x, double2* b0, double2* b1, int ps, int t, const double2* w) {
+    reg_stages<L, NTMAX, SIGN, 0, NBUF, MAXR, true>(x, b0, b1, ps, t, nullptr, true, w);
 }
 
 }  // namespace sgm

@@ -49,6 +49,24 @@ struct Geo {
     static constexpr int B1OFF = NB == 2 ? W * L : 0;
 };
 
+// Register FFT of one line whose twiddles are fetched up front, with the data,
+// where they fit in registers (at most 16 per thread); otherwise each stage
+// reads them from the table.
+template <int L, class G, int SIGN, bool ALLOW = true>
+struct LineFft {
+    static constexpr int NTW = tw_count<L, G::NTMAX>();
+    static constexpr bool PRE = ALLOW && NTW <= 16;
+    double2 w[PRE ? NTW : 1];
+    __device__ __forceinline__ void load(int t, const double2* __restrict__ tw) {
+        if constexpr (PRE) load_twiddles<L, G::NTMAX, SIGN>(w, t, tw);
+    }
+    __device__ __forceinline__ void run(double2* x, double2* b0, double2* b1, int ps, int t,
+                                        const double2* __restrict__ tw) {
+        if constexpr (PRE) reg_fft_pre<L, G::NTMAX, SIGN, G::NB>(x, b0, b1, ps, t, w);
+        else reg_fft<L, G::NTMAX, SIGN, G::NB>(x, b0, b1, ps, t, tw);
+    }
+};
+
 // ---------------------------------------------------------------------------
 // contiguous lines
 // ---------------------------------------------------------------------------
@@ -68,7 +86,9 @@ __global__ void __launch_bounds__(G::THREADS) kr_lines_r2c(const double* __restr
         double im = l0 + 1 < nlines ? in[(l0 + 1) * L + v] : 0.0;
         x[e] = make_double2(re, im);
     }
-    reg_fft<L, G::NTMAX, -1, G::NB>(x, b0, b1, 1, t, tw);
+    LineFft<L, G, -1> fft;
+    fft.load(t, tw);
+    fft.run(x, b0, b1, 1, t, tw);
     // Split the two real lines: X1_k = (Z_k + conj Z_{L-k}) / 2, X2_k = (Z_k - conj Z_{L-k}) / 2i.
     constexpr int Lh = L / 2 + 1;
     if constexpr (64 % G::NT == 0) {
@@ -129,7 +149,9 @@ __global__ void __launch_bounds__(G::THREADS) kr_lines_c2r(const double2* __rest
         if (v > L / 2) { x1.y = -x1.y; x2.y = -x2.y; }
         x[e] = make_double2(x1.x - x2.y, x1.y + x2.x);
     }
-    reg_fft<L, G::NTMAX, 1, G::NB>(x, b0, b1, 1, t, tw);
+    LineFft<L, G, 1> fft;
+    fft.load(t, tw);
+    fft.run(x, b0, b1, 1, t, tw);
 #pragma unroll
     for (int e = 0; e < G::E; ++e) {
         const int v = t + G::NT * e;
@@ -149,7 +171,9 @@ __global__ void __launch_bounds__(G::THREADS) kr_lines_c2c(const double2* __rest
     double2 x[G::E];
 #pragma unroll
     for (int e = 0; e < G::E; ++e) x[e] = ln < nlines ? in[ln * L + t + G::NT * e] : make_double2(0.0, 0.0);
-    reg_fft<L, G::NTMAX, SIGN, G::NB>(x, b0, b1, 1, t, tw);
+    LineFft<L, G, SIGN> fft;
+    fft.load(t, tw);
+    fft.run(x, b0, b1, 1, t, tw);
     if (ln < nlines) {
 #pragma unroll
         for (int e = 0; e < G::E; ++e) out[ln * L + t + G::NT * e] = cscale(x[e], scale);
@@ -254,6 +278,8 @@ __global__ void __launch_bounds__(G::THREADS) kr_strided(const double2* in, doub
 // ---------------------------------------------------------------------------
 // Chebyshev axis, forward (DCT-II + scalar product / projection)
 // ---------------------------------------------------------------------------
+constexpr bool kChebTwRegs = false;  // Chebyshev kernels: twiddles from the table (registers go to the tables)
+
 __device__ __forceinline__ int makhoul_row(int v, int N) { return v < (N + 1) / 2 ? 2 * v : 2 * (N - 1 - v) + 1; }
 
 // Sequential per-(column, parity) least-squares projection used for the
@@ -471,13 +497,32 @@ __global__ void __launch_bounds__(G::THREADS) kr_cheb_fwd(const double2* in, dou
         const int v = t + NT * e;
         x[e] = ok ? in[(long)makhoul_row(v, N) * ncols + c0 + c] : make_double2(0.0, 0.0);
     }
-    reg_fft<N, G::NTMAX, -1, G::NB>(x, B0 + c, B1 + c, W, t, tw);
+    // per-position table entries fetched with the data (short lines only: registers),
+    // so their latency is not paid again after the FFT
+    constexpr bool kPre = E <= 8;
+    double2 thk[kPre ? E : 1];
+    double fsk[kPre ? E : 1], gsk[kPre && MODE == kScalarProduct ? E : 1];
+    if constexpr (kPre) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + NT * e;
+            thk[e] = cd.theta[k];
+            if constexpr (MODE == kProjCheb || MODE == kProjDirichlet) fsk[e] = cd.fscale[k];
+            if constexpr (MODE == kProjBiharmonic) fsk[e] = cd.bscale[k];
+            if constexpr (MODE == kScalarProduct) {
+                fsk[e] = (k < cd.nb && k + 2 < N) ? cd.beta[k] : 0.0;
+                gsk[e] = (k < cd.nb && k + 4 < N) ? cd.gamma[k] : 0.0;
+            }
+        }
+    }
+    LineFft<N, G, -1, kChebTwRegs> fft;
+    fft.load(t, tw);
+    fft.run(x, B0 + c, B1 + c, W, t, tw);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) B0[(t + NT * e) * W + c] = x[e];
     __syncthreads();
     // DCT-II post-processing: C_k for own k from V_k and V_{N-k}
-    const double2* th = cd.theta;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = t + NT * e;
@@ -487,7 +532,9 @@ __global__ void __launch_bounds__(G::THREADS) kr_cheb_fwd(const double2* in, dou
         double2 a = make_double2(0.5 * (V.x + cv.x), 0.5 * (V.y + cv.y));
         double2 d = csub(V, cv);
         double2 b = make_double2(0.5 * d.y, -0.5 * d.x);
-        double2 tk = th[k];
+        double2 tk;
+        if constexpr (kPre) tk = thk[e];
+        else tk = cd.theta[k];
         x[e] = make_double2(tk.x * a.x - tk.y * a.y, tk.x * b.x - tk.y * b.y);  // C_k
     }
     __syncthreads();  // every V read before B0 is reused
@@ -503,8 +550,11 @@ __global__ void __launch_bounds__(G::THREADS) kr_cheb_fwd(const double2* in, dou
             double2 v = make_double2(0.0, 0.0);
             if (l < nb) {
                 v = x[e];
-                if (l + 2 < N) { double bb = cd.beta[l]; double2 u = B0[(l + 2) * W + c]; v.x += bb * u.x; v.y += bb * u.y; }
-                if (l + 4 < N) { double gg = cd.gamma[l]; double2 u = B0[(l + 4) * W + c]; v.x += gg * u.x; v.y += gg * u.y; }
+                double bb = 0.0, gg = 0.0;
+                if constexpr (kPre) { bb = fsk[e]; gg = gsk[e]; }
+                else { bb = l + 2 < N ? cd.beta[l] : 0.0; gg = l + 4 < N ? cd.gamma[l] : 0.0; }
+                if (l + 2 < N) { double2 u = B0[(l + 2) * W + c]; v.x += bb * u.x; v.y += bb * u.y; }
+                if (l + 4 < N) { double2 u = B0[(l + 4) * W + c]; v.x += gg * u.x; v.y += gg * u.y; }
                 v = cscale(v, s);
             }
             if (ok) out[(long)l * ncols + c0 + c] = v;
@@ -513,66 +563,72 @@ __global__ void __launch_bounds__(G::THREADS) kr_cheb_fwd(const double2* in, dou
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = t + NT * e;
-            if (ok) out[(long)k * ncols + c0 + c] = cscale(x[e], cd.fscale[k]);
+            double f;
+            if constexpr (kPre) f = fsk[e];
+            else f = cd.fscale[k];
+            if (ok) out[(long)k * ncols + c0 + c] = cscale(x[e], f);
         }
     } else if constexpr (MODE == kProjDirichlet) {
-        // c_k = fscale_k C_k; per parity p: lambda_p = (sum_k c_k) / (sum_k 1/c_k);
-        // c*_k = c_k - lambda_p / c_k;  u_l = sum_{k <= l, k = l mod 2} c*_k  (prefix sum).
-        // NT is even, so all own positions of thread t have parity t & 1.
-        double2 ps = make_double2(0.0, 0.0);
+        // c_k = fscale_k C_k; per parity p: lambda_p = (sum_k c_k) / (sum_k w_k) with w_0 = 1/2
+        // and w_k = 1 otherwise; u_l = sum_{k <= l, k = l mod 2} (c_k - lambda_p w_k).  Along a
+        // parity chain (chain index i <-> position p + 2i) the w prefix is i + 1 - [p = 0]/2, so
+        // one segmented prefix sum of c yields both the chain total and every u_l.  NT is even:
+        // all own positions of thread t have parity t & 1.
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int k = t + NT * e;
-            x[e] = cscale(x[e], cd.fscale[k]);
-            ps.x += x[e].x; ps.y += x[e].y;
+            double f;
+            if constexpr (kPre) f = fsk[e];
+            else f = cd.fscale[t + NT * e];
+            B0[(t + NT * e) * W + c] = cscale(x[e], f);
         }
-        SC[t * W + c] = ps;
         __syncthreads();
-        const int p = t & 1;
-        double2 tot = make_double2(0.0, 0.0);
-        for (int tt = p; tt < NT; tt += 2) { double2 v = SC[tt * W + c]; tot.x += v.x; tot.y += v.y; }
+        // the NT/2 threads of parity p own consecutive chain segments of length seg
+        const int p = t & 1, t2 = t >> 1;
         const int mp = (N - p + 1) / 2;
-        const double wsum = (double)mp - (p == 0 ? 0.5 : 0.0);
+        constexpr int SEG = ((N + 1) / 2 + NT / 2 - 1) / (NT / 2);
+        const int seg = (mp + NT / 2 - 1) / (NT / 2);
+        const int i0 = t2 * seg;
+        double2 pre[SEG];
+        double2 run = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int r = 0; r < SEG; ++r) {
+            const int i = i0 + r;
+            if (r < seg && i < mp) {
+                const double2 v = B0[(p + 2 * i) * W + c];
+                run.x += v.x; run.y += v.y;
+            }
+            pre[r] = run;
+        }
+        SC[t * W + c] = run;
+        __syncthreads();
+        double2 below = make_double2(0.0, 0.0), tot = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < NT / 2; ++u) {
+            const double2 v = SC[(2 * u + p) * W + c];
+            if (u < t2) { below.x += v.x; below.y += v.y; }
+            tot.x += v.x; tot.y += v.y;
+        }
+        const double w0 = p == 0 ? 0.5 : 0.0;
+        const double wsum = (double)mp - w0;
         const double2 lam = make_double2(tot.x / wsum, tot.y / wsum);
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int k = t + NT * e;
-            const double ic = k == 0 ? 0.5 : 1.0;
-            x[e].x -= lam.x * ic;
-            x[e].y -= lam.y * ic;
-            B0[k * W + c] = x[e];
-        }
-        __syncthreads();
-        // prefix sums along each parity chain (chain index i <-> position p + 2i), in
-        // segments: the NT/2 threads of parity p own consecutive segments of length seg
-        const int t2 = t >> 1;
-        const int seg = (mp + NT / 2 - 1) / (NT / 2);
-        const int i0 = t2 * seg, i1 = i0 + seg < mp ? i0 + seg : mp;
-        double2 ssum = make_double2(0.0, 0.0);
-#pragma unroll 1
-        for (int i = i0; i < i1; ++i) { double2 v = B0[(p + 2 * i) * W + c]; ssum.x += v.x; ssum.y += v.y; }
-        SC[(NT + t) * W + c] = ssum;
-        __syncthreads();
-        double2 run = make_double2(0.0, 0.0);
-#pragma unroll 1
-        for (int u = 0; u < t2; ++u) { double2 v = SC[(NT + 2 * u + p) * W + c]; run.x += v.x; run.y += v.y; }
-#pragma unroll 1
-        for (int i = i0; i < i1; ++i) {
-            double2 v = B0[(p + 2 * i) * W + c];
-            run.x += v.x; run.y += v.y;
-            B0[(p + 2 * i) * W + c] = run;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int l = t + NT * e;
-            if (ok) out[(long)l * ncols + c0 + c] = l < nb ? B0[l * W + c] : make_double2(0.0, 0.0);
+        for (int r = 0; r < SEG; ++r) {
+            const int i = i0 + r;
+            if (r < seg && i < mp) {
+                const int l = p + 2 * i;
+                const double wp = (double)(i + 1) - w0;
+                const double2 u = make_double2(below.x + pre[r].x - lam.x * wp, below.y + pre[r].y - lam.y * wp);
+                if (ok) out[(long)l * ncols + c0 + c] = l < nb ? u : make_double2(0.0, 0.0);
+            }
         }
     } else {  // kProjBiharmonic
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = t + NT * e;
-            B0[k * W + c] = cscale(x[e], cd.bscale[k]);
+            double f;
+            if constexpr (kPre) f = fsk[e];
+            else f = cd.bscale[k];
+            B0[k * W + c] = cscale(x[e], f);
         }
         __syncthreads();
         constexpr int R = kProjSegRowsDev;
@@ -610,21 +666,43 @@ __global__ void __launch_bounds__(G::THREADS) kr_cheb_bwd(const double2* in, dou
     const int c0 = xcd_block() * W;
     const bool ok = c0 + c < ncols;
     const int nb = cd.nb;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int l = t + NT * e;
-        B0[l * W + c] = (ok && l < nb) ? in[(long)l * ncols + c0 + c] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
-    // Chebyshev coefficients c_k = u_k + beta_{k-2} u_{k-2} + gamma_{k-4} u_{k-4} (own k)
     const bool has_gamma = cd.basis == SGM_SHEN_BIHARMONIC;
     const bool has_beta = cd.basis != SGM_CHEBYSHEV;
     double2 x[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
+        const int l = t + NT * e;
+        x[e] = (ok && l < nb) ? in[(long)l * ncols + c0 + c] : make_double2(0.0, 0.0);
+    }
+    LineFft<N, G, 1, kChebTwRegs> fft;
+    fft.load(t, tw);
+    // table entries fetched with the data (short lines only: registers)
+    constexpr bool kPre = E <= 8;
+    double2 thk[kPre ? E : 1];
+    double bbk[kPre ? E : 1];
+    if constexpr (kPre) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + NT * e;
+            thk[e] = cd.theta[k];
+            bbk[e] = (has_beta && k >= 2) ? cd.beta[k - 2] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) B0[(t + NT * e) * W + c] = x[e];
+    __syncthreads();
+    // Chebyshev coefficients c_k = u_k + beta_{k-2} u_{k-2} + gamma_{k-4} u_{k-4} (own k)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
         const int k = t + NT * e;
-        double2 v = B0[k * W + c];
-        if (has_beta && k >= 2) { double bb = cd.beta[k - 2]; double2 u = B0[(k - 2) * W + c]; v.x += bb * u.x; v.y += bb * u.y; }
+        double2 v = x[e];
+        if (has_beta && k >= 2) {
+            double bb;
+            if constexpr (kPre) bb = bbk[e];
+            else bb = cd.beta[k - 2];
+            double2 u = B0[(k - 2) * W + c];
+            v.x += bb * u.x; v.y += bb * u.y;
+        }
         if (has_gamma && k >= 4) { double gg = cd.gamma[k - 4]; double2 u = B0[(k - 4) * W + c]; v.x += gg * u.x; v.y += gg * u.y; }
         x[e] = v;
     }
@@ -642,11 +720,14 @@ __global__ void __launch_bounds__(G::THREADS) kr_cheb_bwd(const double2* in, dou
         } else {
             const double2 cn = B0[(N - k) * W + c];
             const double2 d = make_double2(ck.x + cn.y, ck.y - cn.x);
-            x[e] = cmul(cconj(cd.theta[k]), d);
+            double2 tk;
+            if constexpr (kPre) tk = thk[e];
+            else tk = cd.theta[k];
+            x[e] = cmul(cconj(tk), d);
         }
     }
     __syncthreads();
-    reg_fft<N, G::NTMAX, 1, G::NB>(x, B0 + c, B1 + c, W, t, tw);
+    fft.run(x, B0 + c, B1 + c, W, t, tw);
     if (ok) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {

@@ -2,7 +2,6 @@
 #include <array>
 #include <cstdarg>
 #include <cstring>
-#include <functional>
 #include <tuple>
 #include <map>
 #include <mutex>
@@ -136,6 +135,7 @@ static int pick_tile(int L, int want, size_t (*bytes)(int, int), int lds_max) {
 
 static sgm_status fourier_forward(sgm_plan p, const void* u, double2* uh, hipStream_t s);
 static hipError_t cheb_forward_pass(sgm_plan p, double2* data, int mode, hipStream_t s);
+extern "C" sgm_status sgm_forward(sgm_plan p, const void* u, void* u_hat, void* stream);
 extern "C" sgm_status sgm_backward(sgm_plan p, const void* u_hat, void* u, void* stream);
 
 // Autotuner: for every axis with register kernels, time each compiled variant
@@ -150,20 +150,39 @@ struct TuneKey {
 static std::map<TuneKey, std::array<int, 3>> g_tuned;
 static std::mutex g_tune_mu;
 
-static float time_ms(const std::function<void()>& f, int reps) {
-    hipEvent_t a, b;
-    hipEventCreate(&a);
-    hipEventCreate(&b);
-    f();  // warm-up
-    hipEventRecord(a, nullptr);
-    for (int i = 0; i < reps; ++i) f();
-    hipEventRecord(b, nullptr);
-    hipEventSynchronize(b);
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, a, b);
-    hipEventDestroy(a);
-    hipEventDestroy(b);
-    return ms / reps;
+// Pass-timer bits of each axis's passes (x: forward projection and backward;
+// y: middle pair; z: last pair).
+static const unsigned kAxisPasses[3] = {(1u << 4) | (1u << 6), (1u << 2) | (1u << 3), (1u << 0) | (1u << 1)};
+
+// Time of the given passes in one forward + backward step: best of 8 steps per
+// pass (after one untimed step), so the other axes' passes add no noise.
+static float axis_pass_ms(sgm_plan p, void* u, void* uh, unsigned mask) {
+    const unsigned saved = p->timing;
+    p->timing = 0;
+    sgm_forward(p, u, uh, nullptr);
+    sgm_backward(p, uh, u, nullptr);
+    p->timing = mask;
+    for (int r = 0; r < 8; ++r) {
+        sgm_forward(p, u, uh, nullptr);
+        sgm_backward(p, uh, u, nullptr);
+    }
+    p->timing = saved;
+    float best[SGM_NPASS];
+    for (float& b : best) b = 1e30f;
+    for (auto& pe : p->pending) {
+        float t = 1e30f;
+        if (hipEventSynchronize(pe.second.second) != hipSuccess ||
+            hipEventElapsedTime(&t, pe.second.first, pe.second.second) != hipSuccess)
+            t = 1e30f;
+        best[pe.first] = std::min(best[pe.first], t);
+        p->ev_pool.push_back(pe.second.first);
+        p->ev_pool.push_back(pe.second.second);
+    }
+    p->pending.clear();
+    float sum = 0.f;
+    for (int i = 0; i < SGM_NPASS; ++i)
+        if (((mask >> i) & 1u) && best[i] < 1e29f) sum += best[i];
+    return sum;
 }
 
 static sgm_status autotune_plan(sgm_plan p, int lds_max) {
@@ -201,11 +220,7 @@ static sgm_status autotune_plan(sgm_plan p, int lds_max) {
             if (ax.idx == 1 && !strided_fits(cand, p->spec_last)) continue;
             RegKernels saved = *ax.rk;
             *ax.rk = cand;
-            float t = time_ms([&]() {
-                fourier_forward(p, u, static_cast<double2*>(uh), nullptr);
-                cheb_forward_pass(p, static_cast<double2*>(uh), kProject, nullptr);
-                sgm_backward(p, uh, u, nullptr);
-            }, 3);
+            const float t = axis_pass_ms(p, u, uh, kAxisPasses[ax.idx]);
             *ax.rk = saved;
             if (t < tbest) { tbest = t; best[ax.idx] = v; }
         }
@@ -508,7 +523,7 @@ sgm_status sgm_backward(sgm_plan p, const void* u_hat, void* u, void* stream) {
     {
         PassTimer t(p, 6, s);
         if (p->hx)
-            SGM_HIP_TRY(launch_k(p->rkx.cb, (p->geom.ncols + p->rkx.W - 1) / p->rkx.W, p->rkx.threads, p->rkx.lds_cheb, s,
+            SGM_HIP_TRY(launch_k(p->rkx.cb, (p->geom.ncols + p->rkx.W - 1) / p->rkx.W, p->rkx.threads, p->rkx.lds, s,
                                  static_cast<const double2*>(u_hat), w, p->cd, p->geom.ncols, p->rpx.tw));
         else
             SGM_HIP_TRY(launch_cheb_bwd(static_cast<const double2*>(u_hat), w, p->cd, p->geom.ncols, p->W_cheb,
