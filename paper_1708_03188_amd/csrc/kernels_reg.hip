@@ -278,6 +278,18 @@ __global__ void __launch_bounds__(G::THREADS) kr_strided(const double2* in, doub
 // ---------------------------------------------------------------------------
 // Chebyshev axis, forward (DCT-II + scalar product / projection)
 // ---------------------------------------------------------------------------
+// Waves per SIMD when a group's LDS (bytes) is the occupancy limit (160 KB per
+// CU, four SIMDs): with at most two, a thread has 256 VGPRs and the
+// per-position tables of E = 16 lines fit in registers too.
+template <class G>
+constexpr int lds_waves_per_simd(long lds_bytes) {
+    return (int)((163840 / lds_bytes) * (G::THREADS / 64) / 4);
+}
+template <class G>
+constexpr bool table_regs(long lds_bytes) {
+    return G::E <= 8 || (G::E <= 16 && lds_waves_per_simd<G>(lds_bytes) <= 2);
+}
+
 constexpr bool kChebTwRegs = false;  // Chebyshev kernels: twiddles from the table (registers go to the tables)
 
 __device__ __forceinline__ int makhoul_row(int v, int N) { return v < (N + 1) / 2 ? 2 * v : 2 * (N - 1 - v) + 1; }
@@ -499,7 +511,7 @@ __global__ void __launch_bounds__(G::THREADS) kr_cheb_fwd(const double2* in, dou
     }
     // per-position table entries fetched with the data (short lines only: registers),
     // so their latency is not paid again after the FFT
-    constexpr bool kPre = E <= 8;
+    constexpr bool kPre = MODE == kScalarProduct ? E <= 8 : table_regs<G>(16L * (G::NB * N * W + 2 * NT * W));
     double2 thk[kPre ? E : 1];
     double fsk[kPre ? E : 1], gsk[kPre && MODE == kScalarProduct ? E : 1];
     if constexpr (kPre) {
@@ -677,15 +689,16 @@ __global__ void __launch_bounds__(G::THREADS) kr_cheb_bwd(const double2* in, dou
     LineFft<N, G, 1, kChebTwRegs> fft;
     fft.load(t, tw);
     // table entries fetched with the data (short lines only: registers)
-    constexpr bool kPre = E <= 8;
+    constexpr bool kPre = table_regs<G>(16L * G::NB * N * W);
     double2 thk[kPre ? E : 1];
-    double bbk[kPre ? E : 1];
+    double bbk[kPre ? E : 1], ggk[kPre ? E : 1];
     if constexpr (kPre) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = t + NT * e;
             thk[e] = cd.theta[k];
             bbk[e] = (has_beta && k >= 2) ? cd.beta[k - 2] : 0.0;
+            ggk[e] = (has_gamma && k >= 4) ? cd.gamma[k - 4] : 0.0;
         }
     }
 #pragma unroll
@@ -703,7 +716,13 @@ __global__ void __launch_bounds__(G::THREADS) kr_cheb_bwd(const double2* in, dou
             double2 u = B0[(k - 2) * W + c];
             v.x += bb * u.x; v.y += bb * u.y;
         }
-        if (has_gamma && k >= 4) { double gg = cd.gamma[k - 4]; double2 u = B0[(k - 4) * W + c]; v.x += gg * u.x; v.y += gg * u.y; }
+        if (has_gamma && k >= 4) {
+            double gg;
+            if constexpr (kPre) gg = ggk[e];
+            else gg = cd.gamma[k - 4];
+            double2 u = B0[(k - 4) * W + c];
+            v.x += gg * u.x; v.y += gg * u.y;
+        }
         x[e] = v;
     }
     __syncthreads();
