@@ -107,6 +107,16 @@ sgm_status sgm_scalar_product(sgm_plan plan, const void* f, void* f_tilde, void*
  * that overlap on one plan race. */
 sgm_status sgm_helmholtz_solve(sgm_plan plan, double alpha, const void* f_tilde, void* u_hat, void* stream);
 
+/* The same solve from the physical right-hand side: u_hat = solve(alpha,
+ * scalar_product(f)), i.e. sgm_scalar_product followed by sgm_helmholtz_solve
+ * (Sec. 4: right-hand side scalar product, then the per-wavenumber solve).  f:
+ * physical real array (as u in sgm_forward), u_hat: spectral output; they must
+ * not overlap; f is not modified.  Where the plan allows (x axis of 256 points
+ * on 8-column tiles) the Chebyshev pass and the solve run as one kernel, the
+ * solve reading the scalar product from on-chip memory; otherwise the two
+ * calls run in turn.  Table refresh and races as sgm_helmholtz_solve. */
+sgm_status sgm_helmholtz_solve_physical(sgm_plan plan, double alpha, const void* f, void* u_hat, void* stream);
+
 /* Biharmonic solve lap^2 u = f for the Shen-biharmonic plan (Sec. 4): per column
  * (S - 2 kappa^2 A + kappa^4 B) u_hat = f_tilde with S_ml = (phi_l'''', phi_m).
  * Same layout, aliasing rules and first-call table fill as sgm_helmholtz_solve. */

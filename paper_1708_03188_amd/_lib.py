@@ -55,6 +55,7 @@ _SIGS = {
     "sgm_backward": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "sgm_scalar_product": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "sgm_helmholtz_solve": ([_vp, ctypes.c_double, _vp, _vp, _vp], ctypes.c_int),
+    "sgm_helmholtz_solve_physical": ([_vp, ctypes.c_double, _vp, _vp, _vp], ctypes.c_int),
     "sgm_biharmonic_solve": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "sgm_plan_timing": ([_vp, ctypes.c_int], ctypes.c_int),
     "sgm_plan_variants": ([_vp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),

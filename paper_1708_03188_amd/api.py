@@ -120,6 +120,16 @@ class Plan:
               "sgm_helmholtz_solve")
         return out
 
+    def helmholtz_solve_physical(self, f, alpha=0.0, out=None):
+        """alpha u - lap u = f from the physical right-hand side (scalar product
+        and solve; one fused pass where the plan allows)."""
+        _need(f, self.phys_dtype, self.phys_shape, "f")
+        out = self._out(out, self.spec_shape, torch.complex128, f.device)
+        _need(out, torch.complex128, self.spec_shape, "u_hat")
+        check(self._lib.sgm_helmholtz_solve_physical(self._h, float(alpha), _ptr(f), _ptr(out), _stream()),
+              "sgm_helmholtz_solve_physical")
+        return out
+
     def biharmonic_solve(self, f_tilde, out=None):
         _need(f_tilde, torch.complex128, self.spec_shape, "f_tilde")
         out = self._out(out, self.spec_shape, torch.complex128, f_tilde.device)

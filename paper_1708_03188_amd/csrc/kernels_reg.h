@@ -4,7 +4,16 @@
 
 namespace sgm {
 
-enum RegChebMode { kProjCheb = 2, kProjDirichlet = 3, kProjBiharmonic = 4 };
+enum RegChebMode { kProjCheb = 2, kProjDirichlet = 3, kProjBiharmonic = 4, kScalarSolve = 5 };
+
+// Extra arguments of the fused scalar-product + Dirichlet Helmholtz solve pass
+// (boundary-state table of the segmented solve for this alpha); unused by the
+// other Chebyshev-axis modes.
+struct ChebSolve {
+    const double* tab;
+    ColGeom g;
+    double alpha;
+};
 
 struct RegKernels {
     int L = 0;
@@ -20,10 +29,13 @@ struct RegKernels {
     void (*c2c_b)(const double2*, double2*, int, const double2*, double) = nullptr;
     void (*str_f)(const double2*, double2*, int, int, const double2*, double) = nullptr;
     void (*str_b)(const double2*, double2*, int, int, const double2*, double) = nullptr;
-    void (*cf_sp)(const double2*, double2*, ChebDev, int, const double2*) = nullptr;
-    void (*cf_cheb)(const double2*, double2*, ChebDev, int, const double2*) = nullptr;
-    void (*cf_dir)(const double2*, double2*, ChebDev, int, const double2*) = nullptr;
-    void (*cf_bih)(const double2*, double2*, ChebDev, int, const double2*) = nullptr;
+    void (*cf_sp)(const double2*, double2*, ChebDev, int, const double2*, ChebSolve) = nullptr;
+    void (*cf_cheb)(const double2*, double2*, ChebDev, int, const double2*, ChebSolve) = nullptr;
+    void (*cf_dir)(const double2*, double2*, ChebDev, int, const double2*, ChebSolve) = nullptr;
+    void (*cf_bih)(const double2*, double2*, ChebDev, int, const double2*, ChebSolve) = nullptr;
+    // fused scalar product + Dirichlet Helmholtz solve (L = 256 with 8-column
+    // tiles only: chains of at most 128 rows on 8 lanes; nullptr elsewhere)
+    void (*cf_spsolve)(const double2*, double2*, ChebDev, int, const double2*, ChebSolve) = nullptr;
     void (*cb)(const double2*, double2*, ChebDev, int, const double2*) = nullptr;
 };
 

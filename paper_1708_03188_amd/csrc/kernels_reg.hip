@@ -9,6 +9,8 @@
 #include "fft_reg.h"
 #include "kernels.h"
 #include "kernels_reg.h"
+#include "solve_seg.h"
+#include "solve_seg_dev.h"
 
 #include <map>
 #include <mutex>
@@ -490,9 +492,17 @@ __device__ void project_segmented(double2* B0, double2* SC, int W, int nseg, con
     }
 }
 
+// Right-hand side rows of the segmented solve from the block's LDS tile
+// (columns c0 .. c0 + W - 1, row l at B0[l W + col - c0]).
+struct TileRhs {
+    const double2* B0;
+    int W, c0;
+    __device__ __forceinline__ double2 operator()(int p, int i, int col) const { return B0[(p + 2 * i) * W + col - c0]; }
+};
+
 template <int N, class G, int MODE>
 __global__ void __launch_bounds__(G::THREADS) kr_cheb_fwd(const double2* in, double2* out, ChebDev cd, int ncols,
-                                                        const double2* __restrict__ tw) {
+                                                        const double2* __restrict__ tw, ChebSolve sv) {
     constexpr int W = G::W, NT = G::NT, E = G::E;
     extern __shared__ double2 lds[];
     // one N x W tile (B0), a second one only as the FFT's other exchange buffer,
@@ -511,9 +521,10 @@ __global__ void __launch_bounds__(G::THREADS) kr_cheb_fwd(const double2* in, dou
     }
     // per-position table entries fetched with the data (short lines only: registers),
     // so their latency is not paid again after the FFT
-    constexpr bool kPre = MODE == kScalarProduct ? E <= 8 : table_regs<G>(16L * (G::NB * N * W + 2 * NT * W));
+    constexpr bool kSP = MODE == kScalarProduct || MODE == kScalarSolve;
+    constexpr bool kPre = kSP ? E <= 8 : table_regs<G>(16L * (G::NB * N * W + 2 * NT * W));
     double2 thk[kPre ? E : 1];
-    double fsk[kPre ? E : 1], gsk[kPre && MODE == kScalarProduct ? E : 1];
+    double fsk[kPre ? E : 1], gsk[kPre && kSP ? E : 1];
     if constexpr (kPre) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -521,7 +532,7 @@ __global__ void __launch_bounds__(G::THREADS) kr_cheb_fwd(const double2* in, dou
             thk[e] = cd.theta[k];
             if constexpr (MODE == kProjCheb || MODE == kProjDirichlet) fsk[e] = cd.fscale[k];
             if constexpr (MODE == kProjBiharmonic) fsk[e] = cd.bscale[k];
-            if constexpr (MODE == kScalarProduct) {
+            if constexpr (kSP) {
                 fsk[e] = (k < cd.nb && k + 2 < N) ? cd.beta[k] : 0.0;
                 gsk[e] = (k < cd.nb && k + 4 < N) ? cd.gamma[k] : 0.0;
             }
@@ -551,7 +562,7 @@ __global__ void __launch_bounds__(G::THREADS) kr_cheb_fwd(const double2* in, dou
     }
     __syncthreads();  // every V read before B0 is reused
     const int nb = cd.nb;
-    if constexpr (MODE == kScalarProduct) {
+    if constexpr (kSP) {
 #pragma unroll
         for (int e = 0; e < E; ++e) B0[(t + NT * e) * W + c] = x[e];
         __syncthreads();
@@ -569,7 +580,27 @@ __global__ void __launch_bounds__(G::THREADS) kr_cheb_fwd(const double2* in, dou
                 if (l + 4 < N) { double2 u = B0[(l + 4) * W + c]; v.x += gg * u.x; v.y += gg * u.y; }
                 v = cscale(v, s);
             }
-            if (ok) out[(long)l * ncols + c0 + c] = v;
+            if constexpr (MODE == kScalarProduct) {
+                if (ok) out[(long)l * ncols + c0 + c] = v;
+            } else {
+                x[e] = v;
+            }
+        }
+        if constexpr (MODE == kScalarSolve) {
+            // f~ of the tile into LDS, then the Dirichlet Helmholtz solve of its chains:
+            // wave p (0, 1) takes parity p of the W = 8 columns, 8 lanes of 16 rows per chain
+            static_assert(W == 8 && G::THREADS >= 128, "fused solve needs 8-column tiles");
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < E; ++e) B0[(t + NT * e) * W + c] = x[e];
+            __syncthreads();
+            const int wv = threadIdx.x >> 6;
+            if (wv < 2) {
+                const int ngroups = (ncols + W - 1) / W;
+                segdev::solve_wave<SGM_SHEN_DIRICHLET, 8, kSegRows>(wv * ngroups + c0 / W, TileRhs{B0, W, c0}, out,
+                                                                   sv.tab, cd, sv.g, sv.alpha, cd.solve[0],
+                                                                   cd.solve[1]);
+            }
         }
     } else if constexpr (MODE == kProjCheb) {
 #pragma unroll
@@ -777,6 +808,8 @@ static void fill_g(RegKernels& k) {
     k.cf_cheb = kr_cheb_fwd<L, G, kProjCheb>;
     k.cf_dir = kr_cheb_fwd<L, G, kProjDirichlet>;
     k.cf_bih = kr_cheb_fwd<L, G, kProjBiharmonic>;
+    if constexpr (L == 256 && G::W == 8 && G::THREADS == 256) k.cf_spsolve = kr_cheb_fwd<L, G, kScalarSolve>;
+    else k.cf_spsolve = nullptr;
     k.cb = kr_cheb_bwd<L, G>;
 }
 

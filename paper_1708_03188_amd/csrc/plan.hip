@@ -485,7 +485,7 @@ static hipError_t cheb_forward_pass(sgm_plan p, double2* data, int mode, hipStre
     if (mode == kProject)
         f = p->cd.basis == SGM_SHEN_DIRICHLET ? k.cf_dir : p->cd.basis == SGM_SHEN_BIHARMONIC ? k.cf_bih : k.cf_cheb;
     return launch_k(f, (p->geom.ncols + k.W - 1) / k.W, k.threads, k.lds_cheb, s, (const double2*)data, data, p->cd,
-                    p->geom.ncols, p->rpx.tw);
+                    p->geom.ncols, p->rpx.tw, ChebSolve{nullptr, p->geom, 0.0});
 }
 
 sgm_status sgm_forward(sgm_plan p, const void* u, void* u_hat, void* stream) {
@@ -559,13 +559,12 @@ sgm_status sgm_backward(sgm_plan p, const void* u_hat, void* u, void* stream) {
 
 // Segmented solve where the chains fit, else one lane per chain.  The
 // boundary table is refilled (one extra launch) when alpha changes.
+static sgm_status seg_table_for(sgm_plan p, int kind, double alpha, hipStream_t s);
+
 static sgm_status solve_dispatch(sgm_plan p, int kind, double alpha, const void* f, void* u, hipStream_t s) {
     if (p->seg_K > 0) {
-        if (!p->seg_ok || p->seg_alpha != alpha) {
-            SGM_HIP_TRY(launch_seg_table(p->seg_tab, p->cd, p->geom, kind, p->seg_K, alpha, s));
-            p->seg_ok = true;
-            p->seg_alpha = alpha;
-        }
+        sgm_status st = seg_table_for(p, kind, alpha, s);
+        if (st != SGM_OK) return st;
         SGM_HIP_TRY(launch_solve_seg(static_cast<const double2*>(f), static_cast<double2*>(u), p->seg_tab, p->cd,
                                      p->geom, kind, p->seg_K, alpha, s));
         return SGM_OK;
@@ -573,6 +572,42 @@ static sgm_status solve_dispatch(sgm_plan p, int kind, double alpha, const void*
     SGM_HIP_TRY(launch_solve_chain(static_cast<const double2*>(f), static_cast<double2*>(u),
                                    static_cast<double*>(p->work), p->cd, p->geom, kind, alpha, s));
     return SGM_OK;
+}
+
+// Boundary-state table of the segmented solve for this alpha (refilled when alpha changes).
+static sgm_status seg_table_for(sgm_plan p, int kind, double alpha, hipStream_t s) {
+    if (!p->seg_ok || p->seg_alpha != alpha) {
+        SGM_HIP_TRY(launch_seg_table(p->seg_tab, p->cd, p->geom, kind, p->seg_K, alpha, s));
+        p->seg_ok = true;
+        p->seg_alpha = alpha;
+    }
+    return SGM_OK;
+}
+
+sgm_status sgm_helmholtz_solve_physical(sgm_plan p, double alpha, const void* f, void* u_hat, void* stream) {
+    clear_error();
+    SGM_CHECK_ARG(p && f && u_hat, "null argument");
+    SGM_CHECK_ARG(f != u_hat, "f and u_hat must not alias");
+    SGM_CHECK_ARG(p->d.basis == SGM_SHEN_DIRICHLET, "Helmholtz solve needs the Shen-Dirichlet basis");
+    SGM_CHECK_ARG(alpha >= 0.0, "alpha must be >= 0 (got %g)", alpha);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double2* uh = static_cast<double2*>(u_hat);
+    sgm_status st = fourier_forward(p, f, uh, s);
+    if (st != SGM_OK) return st;
+    if (p->hx && p->rkx.cf_spsolve && p->seg_K == 8 && p->d.autotune != 2) {
+        if ((st = seg_table_for(p, SGM_SHEN_DIRICHLET, alpha, s)) != SGM_OK) return st;
+        PassTimer t(p, 5, s);
+        const RegKernels& k = p->rkx;
+        SGM_HIP_TRY(launch_k(k.cf_spsolve, (p->geom.ncols + k.W - 1) / k.W, k.threads, k.lds_cheb, s,
+                             (const double2*)uh, uh, p->cd, p->geom.ncols, p->rpx.tw,
+                             ChebSolve{p->seg_tab, p->geom, alpha}));
+        return SGM_OK;
+    }
+    {
+        PassTimer t(p, 5, s);
+        SGM_HIP_TRY(cheb_forward_pass(p, uh, kScalarProduct, s));
+    }
+    return sgm_helmholtz_solve(p, alpha, uh, uh, stream);
 }
 
 sgm_status sgm_helmholtz_solve(sgm_plan p, double alpha, const void* f_tilde, void* u_hat, void* stream) {

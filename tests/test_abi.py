@@ -21,7 +21,8 @@ def _declared():
 
 def test_header_declares_entry_points():
     names = _declared()
-    for n in ("sgm_plan_create", "sgm_forward", "sgm_backward", "sgm_helmholtz_solve", "sgm_biharmonic_solve"):
+    for n in ("sgm_plan_create", "sgm_forward", "sgm_backward", "sgm_helmholtz_solve", "sgm_helmholtz_solve_physical",
+              "sgm_biharmonic_solve"):
         assert n in names
 
 

@@ -124,6 +124,30 @@ def test_manufactured_biharmonic_3d_exact_coefficients(Plan):
     assert np.abs(host(p.biharmonic_solve(p.scalar_product(dev(f)))) - ref).max() < 1e-14
 
 
+@pytest.mark.parametrize("alpha", [0.0, 1.0])
+@pytest.mark.parametrize("variant", [None, 1, 3])
+@pytest.mark.parametrize("shape", [(256, 64, 64), (256, 40), (128, 32, 32)])
+def test_helmholtz_solve_physical(Plan, shape, variant, alpha):
+    # the physical-RHS solve (one fused pass for N = 256 on 8-column tiles, the two
+    # calls otherwise) equals scalar product + solve, and the oracle on sampled columns
+    print(f"[case] solve from physical shape={shape} variant={variant} alpha={alpha}", flush=True)
+    p = Plan("dirichlet", *shape) if variant is None else Plan("dirichlet", *shape, variant=variant)
+    f = _phys(shape, "r2c", seed=40 + shape[0] + len(shape))
+    two = host(p.helmholtz_solve(p.scalar_product(dev(f)), alpha))
+    one = host(p.helmholtz_solve_physical(dev(f), alpha))
+    assert rel_err(one, two) < 1e-14
+    N = shape[0]
+    if len(shape) == 3:
+        cols = _sample_cols(p.spec_shape, np.random.default_rng(N), n=8)
+        ft = np.zeros(p.spec_shape, complex)
+        ft.reshape(N, -1)[:, cols] = T.scalar_product_columns("dirichlet", f, cols)
+        ref = T.helmholtz_solve("dirichlet", ft, alpha, shape[-1], cols=cols)
+        assert rel_err(one.reshape(N, -1)[:, cols], ref) < TOL_S
+    else:
+        ref = T.helmholtz_solve("dirichlet", T.scalar_product("dirichlet", f), alpha, shape[-1])
+        assert rel_err(one, ref) < TOL_S
+
+
 def _sample_cols(spec_shape, rng, n=24):
     s1, s2 = spec_shape[1], spec_shape[2]
     special = [0, s2 - 1, (s1 // 2) * s2, (s1 // 2) * s2 + s2 - 1, (s1 - 1) * s2 + 1]
