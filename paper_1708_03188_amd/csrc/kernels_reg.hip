@@ -500,6 +500,98 @@ struct TileRhs {
     __device__ __forceinline__ double2 operator()(int p, int i, int col) const { return B0[(p + 2 * i) * W + col - c0]; }
 };
 
+// Per-position tables of the backward Chebyshev pass (theta_k, beta_{k-2},
+// gamma_{k-4} for own k = t + NT e), in registers where they fit.
+template <int N, class G>
+struct BwdTables {
+    static constexpr bool PRE = table_regs<G>(16L * G::NB * N * G::W);
+    double2 th[PRE ? G::E : 1];
+    double bb[PRE ? G::E : 1], gg[PRE ? G::E : 1];
+    __device__ __forceinline__ void load(const ChebDev& cd, int t) {
+        if constexpr (PRE) {
+            const bool has_gamma = cd.basis == SGM_SHEN_BIHARMONIC;
+            const bool has_beta = cd.basis != SGM_CHEBYSHEV;
+#pragma unroll
+            for (int e = 0; e < G::E; ++e) {
+                const int k = t + G::NT * e;
+                th[e] = cd.theta[k];
+                bb[e] = (has_beta && k >= 2) ? cd.beta[k - 2] : 0.0;
+                gg[e] = (has_gamma && k >= 4) ? cd.gamma[k - 4] : 0.0;
+            }
+        }
+    }
+    __device__ __forceinline__ double2 theta(const ChebDev& cd, int e, int k) const {
+        if constexpr (PRE) return th[e];
+        else return cd.theta[k];
+    }
+    __device__ __forceinline__ double beta(const ChebDev& cd, int e, int k) const {
+        if constexpr (PRE) return bb[e];
+        else return cd.beta[k - 2];
+    }
+    __device__ __forceinline__ double gamma(const ChebDev& cd, int e, int k) const {
+        if constexpr (PRE) return gg[e];
+        else return cd.gamma[k - 4];
+    }
+};
+
+// Backward along x of one column tile: x holds the own coefficients u_hat_l
+// (l = t + NT e, zero for l >= nb) and B0 the whole tile, written before the
+// last barrier.  Recombination to Chebyshev coefficients, DCT-III (one complex
+// FFT), then the Makhoul-ordered store of the physical x values to out.
+template <int N, class G, class TB>
+__device__ __forceinline__ void cheb_bwd_tile(double2 (&x)[G::E], double2* B0, double2* B1, int c, int t, int c0,
+                                              bool ok, int ncols, double2* out, const ChebDev& cd, const TB& tb,
+                                              const double2* __restrict__ tw) {
+    constexpr int W = G::W, NT = G::NT, E = G::E;
+    const bool has_gamma = cd.basis == SGM_SHEN_BIHARMONIC;
+    const bool has_beta = cd.basis != SGM_CHEBYSHEV;
+    // Chebyshev coefficients c_k = u_k + beta_{k-2} u_{k-2} + gamma_{k-4} u_{k-4} (own k)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = t + NT * e;
+        double2 v = x[e];
+        if (has_beta && k >= 2) {
+            const double bb = tb.beta(cd, e, k);
+            double2 u = B0[(k - 2) * W + c];
+            v.x += bb * u.x; v.y += bb * u.y;
+        }
+        if (has_gamma && k >= 4) {
+            const double gg = tb.gamma(cd, e, k);
+            double2 u = B0[(k - 4) * W + c];
+            v.x += gg * u.x; v.y += gg * u.y;
+        }
+        x[e] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) B0[(t + NT * e) * W + c] = x[e];
+    __syncthreads();
+    // DCT-III input W_0 = 2 c_0, W_k = e^{i pi k/(2N)} (c_k - i c_{N-k})
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = t + NT * e;
+        const double2 ck = x[e];
+        if (k == 0) {
+            x[e] = make_double2(2.0 * ck.x, 2.0 * ck.y);
+        } else {
+            const double2 cn = B0[(N - k) * W + c];
+            const double2 d = make_double2(ck.x + cn.y, ck.y - cn.x);
+            x[e] = cmul(cconj(tb.theta(cd, e, k)), d);
+        }
+    }
+    __syncthreads();
+    LineFft<N, G, 1, kChebTwRegs> fft;
+    fft.load(t, tw);
+    fft.run(x, B0 + c, B1 + c, W, t, tw);
+    if (ok) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int v = t + NT * e;
+            out[(long)makhoul_row(v, N) * ncols + c0 + c] = cscale(x[e], 0.5);
+        }
+    }
+}
+
 template <int N, class G, int MODE>
 __global__ void __launch_bounds__(G::THREADS) kr_cheb_fwd(const double2* in, double2* out, ChebDev cd, int ncols,
                                                         const double2* __restrict__ tw, ChebSolve sv) {
@@ -595,12 +687,11 @@ __global__ void __launch_bounds__(G::THREADS) kr_cheb_fwd(const double2* in, dou
             for (int e = 0; e < E; ++e) B0[(t + NT * e) * W + c] = x[e];
             __syncthreads();
             const int wv = threadIdx.x >> 6;
-            if (wv < 2) {
-                const int ngroups = (ncols + W - 1) / W;
-                segdev::solve_wave<SGM_SHEN_DIRICHLET, 8, kSegRows>(wv * ngroups + c0 / W, TileRhs{B0, W, c0}, out,
+            if (wv < 2)
+                segdev::solve_wave<SGM_SHEN_DIRICHLET, 8, kSegRows>(wv * ((ncols + W - 1) / W) + c0 / W,
+                                                                   TileRhs{B0, W, c0}, segdev::GlobalOut{out, ncols},
                                                                    sv.tab, cd, sv.g, sv.alpha, cd.solve[0],
                                                                    cd.solve[1]);
-            }
         }
     } else if constexpr (MODE == kProjCheb) {
 #pragma unroll
@@ -709,82 +800,19 @@ __global__ void __launch_bounds__(G::THREADS) kr_cheb_bwd(const double2* in, dou
     const int c0 = xcd_block() * W;
     const bool ok = c0 + c < ncols;
     const int nb = cd.nb;
-    const bool has_gamma = cd.basis == SGM_SHEN_BIHARMONIC;
-    const bool has_beta = cd.basis != SGM_CHEBYSHEV;
     double2 x[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int l = t + NT * e;
         x[e] = (ok && l < nb) ? in[(long)l * ncols + c0 + c] : make_double2(0.0, 0.0);
     }
-    LineFft<N, G, 1, kChebTwRegs> fft;
-    fft.load(t, tw);
-    // table entries fetched with the data (short lines only: registers)
-    constexpr bool kPre = table_regs<G>(16L * G::NB * N * W);
-    double2 thk[kPre ? E : 1];
-    double bbk[kPre ? E : 1], ggk[kPre ? E : 1];
-    if constexpr (kPre) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int k = t + NT * e;
-            thk[e] = cd.theta[k];
-            bbk[e] = (has_beta && k >= 2) ? cd.beta[k - 2] : 0.0;
-            ggk[e] = (has_gamma && k >= 4) ? cd.gamma[k - 4] : 0.0;
-        }
-    }
+    // table entries fetched with the data
+    BwdTables<N, G> tb;
+    tb.load(cd, t);
 #pragma unroll
     for (int e = 0; e < E; ++e) B0[(t + NT * e) * W + c] = x[e];
     __syncthreads();
-    // Chebyshev coefficients c_k = u_k + beta_{k-2} u_{k-2} + gamma_{k-4} u_{k-4} (own k)
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int k = t + NT * e;
-        double2 v = x[e];
-        if (has_beta && k >= 2) {
-            double bb;
-            if constexpr (kPre) bb = bbk[e];
-            else bb = cd.beta[k - 2];
-            double2 u = B0[(k - 2) * W + c];
-            v.x += bb * u.x; v.y += bb * u.y;
-        }
-        if (has_gamma && k >= 4) {
-            double gg;
-            if constexpr (kPre) gg = ggk[e];
-            else gg = cd.gamma[k - 4];
-            double2 u = B0[(k - 4) * W + c];
-            v.x += gg * u.x; v.y += gg * u.y;
-        }
-        x[e] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < E; ++e) B0[(t + NT * e) * W + c] = x[e];
-    __syncthreads();
-    // DCT-III input W_0 = 2 c_0, W_k = e^{i pi k/(2N)} (c_k - i c_{N-k})
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int k = t + NT * e;
-        const double2 ck = x[e];
-        if (k == 0) {
-            x[e] = make_double2(2.0 * ck.x, 2.0 * ck.y);
-        } else {
-            const double2 cn = B0[(N - k) * W + c];
-            const double2 d = make_double2(ck.x + cn.y, ck.y - cn.x);
-            double2 tk;
-            if constexpr (kPre) tk = thk[e];
-            else tk = cd.theta[k];
-            x[e] = cmul(cconj(tk), d);
-        }
-    }
-    __syncthreads();
-    fft.run(x, B0 + c, B1 + c, W, t, tw);
-    if (ok) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int v = t + NT * e;
-            out[(long)makhoul_row(v, N) * ncols + c0 + c] = cscale(x[e], 0.5);
-        }
-    }
+    cheb_bwd_tile<N, G>(x, B0, B1, c, t, c0, ok, ncols, out, cd, tb, tw);
 }
 
 // ---------------------------------------------------------------------------

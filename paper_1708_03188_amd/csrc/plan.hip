@@ -134,6 +134,7 @@ static int pick_tile(int L, int want, size_t (*bytes)(int, int), int lds_max) {
 }
 
 static sgm_status fourier_forward(sgm_plan p, const void* u, double2* uh, hipStream_t s);
+static sgm_status fourier_backward(sgm_plan p, double2* w, void* u, hipStream_t s);
 static hipError_t cheb_forward_pass(sgm_plan p, double2* data, int mode, hipStream_t s);
 extern "C" sgm_status sgm_forward(sgm_plan p, const void* u, void* u_hat, void* stream);
 extern "C" sgm_status sgm_backward(sgm_plan p, const void* u_hat, void* u, void* stream);
@@ -529,6 +530,12 @@ sgm_status sgm_backward(sgm_plan p, const void* u_hat, void* u, void* stream) {
             SGM_HIP_TRY(launch_cheb_bwd(static_cast<const double2*>(u_hat), w, p->cd, p->geom.ncols, p->W_cheb,
                                         p->rpx, s));
     }
+    return fourier_backward(p, w, u, s);
+}
+
+// Backward Fourier passes (middle axis in place, then the last axis) from the
+// x-physical workspace w to u.
+static sgm_status fourier_backward(sgm_plan p, double2* w, void* u, hipStream_t s) {
     if (p->ndim == 3) {
         PassTimer t(p, 3, s);
         const RegKernels& k = p->rky;

@@ -88,7 +88,8 @@ __global__ void __launch_bounds__(256) k_solve_seg(const double2* in, double2* o
     constexpr int C = 64 / K;
     const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (gw >= 2 * ((g.ncols + C - 1) / C)) return;  // whole wave past the end
-    solve_wave<KIND, K, R>(gw, GlobalRhs{in, g.ncols}, out, tab, cd, g, alpha, cd.solve[0], cd.solve[1]);
+    solve_wave<KIND, K, R>(gw, GlobalRhs{in, g.ncols}, GlobalOut{out, g.ncols}, tab, cd, g, alpha, cd.solve[0],
+                           cd.solve[1]);
 }
 
 template <int KIND, int K>

@@ -205,10 +205,21 @@ struct GlobalRhs {
     }
 };
 
+// Solution rows to global memory: x of chain row i of column col, and the
+// zero rows beyond the basis.
+struct GlobalOut {
+    double2* out;
+    int ncols;
+    __device__ __forceinline__ void operator()(int p, int i, int col, double2 v) const {
+        out[(long)(p + 2 * i) * ncols + col] = v;
+    }
+    __device__ __forceinline__ void zero(int l, int col) const { out[(long)l * ncols + col] = make_double2(0.0, 0.0); }
+};
+
 // Solve the chains of wave gw (see k_solve_seg for the lane layout); f comes
-// from rhs(p, i, col).
-template <int KIND, int K, int R, class Rhs>
-__device__ __forceinline__ void solve_wave(int gw, const Rhs& rhs, double2* out, const double* tab,
+// from rhs(p, i, col), x goes to out(p, i, col, x) and out.zero(l, col).
+template <int KIND, int K, int R, class Rhs, class Out>
+__device__ __forceinline__ void solve_wave(int gw, const Rhs& rhs, const Out& out, const double* tab,
                                            const ChebDev& cd, const ColGeom& g, double alpha,
                                            const double* rows0, const double* rows1) {
     using T = SegTraits<KIND>;
@@ -224,8 +235,6 @@ __device__ __forceinline__ void solve_wave(int gw, const Rhs& rhs, double2* out,
     const int ncols = g.ncols;
     const int n = cd.npar[p];
     const int lo = seg * R;
-    const long stride = 2L * ncols;
-    const long base = (long)p * ncols + (act ? col : 0);
     double mu1, mu2;
     chain_mu(g, KIND, act ? col : 0, alpha, mu1, mu2);
 
@@ -399,14 +408,14 @@ __device__ __forceinline__ void solve_wave(int gw, const Rhs& rhs, double2* out,
         double2 x = fr[r];
 #pragma unroll
         for (int e = 0; e < P; ++e) { x.x += bb[r][e] * w[e].x; x.y += bb[r][e] * w[e].y; }
-        if (act && i < n) out[base + (long)i * stride] = x;
+        if (act && i < n) out(p, i, col, x);
 #pragma unroll
         for (int e = P - 1; e > 0; --e) w[e] = w[e - 1];
         w[0] = x;
     }
     // rows beyond the basis of this parity are zero
     if (act)
-        for (int l = p + 2 * n + 2 * seg; l < cd.N; l += 2 * K) out[(long)l * ncols + col] = make_double2(0.0, 0.0);
+        for (int l = p + 2 * n + 2 * seg; l < cd.N; l += 2 * K) out.zero(l, col);
 }
 
 }  // namespace segdev
