@@ -845,26 +845,34 @@ extern "C" sgm_status sgm_gl_step(sgm_gl g, void* u_hat, int nsteps, void* strea
     return SGM_OK;
 }
 
-// Physical <-> spectral helpers (not on the time-stepping path): per problem,
-// the contiguous y transform then the strided x transform.
+// Physical <-> spectral helpers (not on the time-stepping path): per run of
+// consecutive problems of one size (packed back to back), the contiguous y
+// transform over all their rows, then the strided x transform with the
+// problems as outer slabs: two launches per run, not per problem.
 static sgm_status gl_transform(sgm_gl g, const double2* in, double2* out, int sign, hipStream_t s) {
-    for (size_t i = 0; i < g->N.size(); ++i) {
+    const size_t np = g->N.size();
+    for (size_t i = 0; i < np;) {
         const int N = g->N[i];
+        size_t j = i + 1;
+        while (j < np && g->N[j] == N && g->off_s[j] == g->off_s[j - 1] + (int64_t)N * N) ++j;
+        const int cnt = (int)(j - i);
         const double2* src = in + g->off_s[i];
         double2* dst = out + g->off_s[i];
         const double sc = sign < 0 ? 1.0 / N : 1.0;
+        const long nlines = (long)cnt * N;
         if (g->hasN[i]) {
             const RegKernels& k = g->rkN[i];
-            hipLaunchKernelGGL(sign < 0 ? k.c2c_f : k.c2c_b, dim3((N + k.W - 1) / k.W), dim3(k.threads), k.lds, s, src,
-                               dst, N, g->rpN[i].tw, sc);
+            hipLaunchKernelGGL(sign < 0 ? k.c2c_f : k.c2c_b, dim3((unsigned)((nlines + k.W - 1) / k.W)), dim3(k.threads),
+                               k.lds, s, src, dst, (int)nlines, g->rpN[i].tw, sc);
             SGM_HIP_TRY(hipGetLastError());
-            SGM_HIP_TRY(launch_strided(k, sign, dst, dst, 1, N, g->rpN[i].tw, sc, s));
+            SGM_HIP_TRY(launch_strided(k, sign, dst, dst, cnt, N, g->rpN[i].tw, sc, s));
         } else {
             int G = std::max(1, std::min(16, 2048 / N));
-            SGM_HIP_TRY(launch_lines_c2c(src, dst, N, N, G, g->rpN[i], sign, sc, s));
+            SGM_HIP_TRY(launch_lines_c2c(src, dst, N, (int)nlines, G, g->rpN[i], sign, sc, s));
             int W = std::max(1, std::min(16, 2048 / N));
-            SGM_HIP_TRY(launch_strided_c2c(dst, dst, N, 1, N, W, g->rpN[i], sign, sc, s));
+            SGM_HIP_TRY(launch_strided_c2c(dst, dst, N, cnt, N, W, g->rpN[i], sign, sc, s));
         }
+        i = j;
     }
     return SGM_OK;
 }
