@@ -226,6 +226,7 @@ struct sgm_fno_s {
     bool mirrors_ok = false;
     // bf16 mirrors
     bf16 *Wp16 = nullptr, *W1_16 = nullptr, *W2_16 = nullptr, *Rreal = nullptr, *W1T16 = nullptr;
+    bf16* W2P = nullptr;  // W2 as MFMA A operands of the fused projection (P % 32 == 0)
     // DFT matrices (bf16)
     bf16 *Fx = nullptr, *Fy = nullptr, *Gy = nullptr, *Gx = nullptr;
     // activations / scratch (sized for Bmax)
@@ -307,7 +308,7 @@ extern "C" sgm_status sgm_fno_create(const sgm_fno_desc* desc, uint64_t seed, sg
         {(void**)&f->mom1, 4 * (size_t)f->npar}, {(void**)&f->mom2, 4 * (size_t)f->npar},
         {(void**)&f->Wp16, 2 * (size_t)nl * C * C}, {(void**)&f->W1_16, 2 * (size_t)C * P},
         {(void**)&f->W2_16, 2 * (size_t)2 * P}, {(void**)&f->Rreal, 2 * (size_t)nl * NM * 4 * C * C},
-        {(void**)&f->W1T16, 2 * (size_t)C * P},
+        {(void**)&f->W1T16, 2 * (size_t)C * P}, {(void**)&f->W2P, 2 * (size_t)(P / 16 + 1) * 512},
         {(void**)&f->Fx, 2 * (size_t)2 * f->K * d.W}, {(void**)&f->Fy, 2 * (size_t)4 * f->K * 2 * d.H},
         {(void**)&f->Gy, 2 * (size_t)2 * d.H * 4 * f->K}, {(void**)&f->Gx, 2 * (size_t)d.W * 2 * f->K},
         {(void**)&f->acts, 2 * (size_t)(nl + 1) * act}, {(void**)&f->zsv, 2 * (size_t)nl * act},
@@ -399,6 +400,7 @@ static sgm_status refresh_mirrors(sgm_fno f, hipStream_t s) {
     hipLaunchKernelGGL(k_f32_to_bf16, dim3(nblk(2L * P)), dim3(256), 0, s, f->par + f->oW2, f->W2_16, 2L * P);
     SGM_HIP_TRY(hipGetLastError());
     SGM_HIP_TRY(launch_transpose_bf16(f->par + f->oW1, f->W1T16, C, P, s));
+    if (P % 32 == 0) SGM_HIP_TRY(launch_fno_w2_operands(f->W2_16, f->W2P, P, s));
     f->mirrors_ok = true;
     return SGM_OK;
 }
@@ -491,7 +493,7 @@ static sgm_status fno_forward(sgm_fno f, const float* x, int B, hipStream_t s, f
             la.Wp = f->Wp16 + (long)l * C * C; la.bp = f->par + f->obp[l];
             la.a_out = an; la.zsave = pred_out ? nullptr : f->zsv + l * act;
             la.rows = (long)B * H; la.W = W; la.act = l < f->nl - 1 ? 1 : 0;
-            la.W1T = f->W1T16; la.b1 = f->par + f->ob1; la.W2 = f->W2_16; la.b2 = f->par + f->ob2;
+            la.W1T = f->W1T16; la.b1 = f->par + f->ob1; la.W2 = f->W2_16; la.W2P = f->W2P; la.b2 = f->par + f->ob2;
             la.x = x; la.pred = pred_out; la.P = P;
             const int mode = l < f->nl - 1 ? 0 : (pred_out ? 2 : 1);
             SGM_HIP_TRY(launch_fno_layer(la, mode, s));

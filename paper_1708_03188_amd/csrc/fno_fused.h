@@ -38,6 +38,7 @@ struct FnoLayerArgs {
     const __bf16* W1T;    // [P][32]
     const float* b1;      // [P]
     const __bf16* W2;     // [P][2]
+    const __bf16* W2P;    // [P/16][64 lanes][8]: W2 as MFMA A operands (mode 2)
     const float* b2;      // [2]
     const float* x;       // [rows][W][2] network input (residual)
     float* pred;          // [rows][W][2]
@@ -45,6 +46,8 @@ struct FnoLayerArgs {
 };
 
 bool fno_fused_ok(int C, int K, int W, int P);
+// W2 [P][2] (bf16) -> the A operands of the projection's second MFMA (P % 32 == 0).
+hipError_t launch_fno_w2_operands(const __bf16* W2, __bf16* W2P, int P, hipStream_t s);
 hipError_t launch_fno_lift_dft(const float* x, const float* Wl, const float* bl, const __bf16* Fx, __bf16* a0,
                                float* T, long rows, int W, hipStream_t s);
 // mode 0: a_out + next T; 1: a_out (last layer); 2: projection to pred (last layer)

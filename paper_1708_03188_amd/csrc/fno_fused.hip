@@ -78,7 +78,12 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_lift_dft(const float* __rest
 }
 
 // MODE 0: a_out and the next layer's T; 1: a_out only (last layer, training);
-// 2: projection to pred (last layer, inference).
+// 2: projection to pred (last layer, inference).  Both products of the
+// projection run on MFMA: the GELU'd hidden accumulators of one 32-unit block
+// are taken directly as the B operand of two 32x32x16 MFMAs for the P -> 2
+// product (lane group g's eight K entries are its own accumulator rows
+// 8 kb + v), with W2 read in that permuted order and padded to 32 output rows
+// (k_fno_w2_operands); rows 0, 1 of the result are the two outputs.
 template <int MODE>
 __global__ void __launch_bounds__(64 * WAVES) k_fno_layer(FnoLayerArgs p) {
     __shared__ bf16 tile[WAVES][32][FC + 8];
@@ -142,21 +147,25 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer(FnoLayerArgs p) {
             bf16x8 bt[2];
 #pragma unroll
             for (int s = 0; s < 2; ++s) bt[s] = *reinterpret_cast<const bf16x8*>(&tile[wv][c][16 * s + 8 * g]);
-            float o0 = 0.f, o1 = 0.f;
+            floatx16 o2 = zero16();
             for (int T = 0; T < p.P / 32; ++T) {
                 floatx16 h = zero16();
 #pragma unroll
                 for (int s = 0; s < 2; ++s) h = mfma(ld8(p.W1T + (long)(32 * T + c) * FC + 16 * s + 8 * g), bt[s], h);
 #pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    const int hu = 32 * T + 8 * (e >> 2) + 4 * g + (e & 3);
-                    const float hv = (float)(bf16)gelu(h[e] + p.b1[hu]);
-                    o0 += hv * (float)p.W2[2 * hu];
-                    o1 += hv * (float)p.W2[2 * hu + 1];
+                for (int kb = 0; kb < 2; ++kb) {
+                    bf16x8 hop;
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) {
+                        const int e = 8 * kb + v;
+                        const int hu = 32 * T + 8 * (e >> 2) + 4 * g + (e & 3);
+                        hop[v] = (bf16)gelu(h[e] + p.b1[hu]);
+                    }
+                    o2 = mfma(ld8(p.W2P + ((long)(2 * T + kb) * 64 + lane) * 8), hop, o2);
                 }
             }
-            o0 += __shfl_xor(o0, 32);
-            o1 += __shfl_xor(o1, 32);
+            // rows 0 and 1 of the padded product, in lane group 0
+            const float o0 = o2[0], o1 = o2[1];
             if (live && g == 0) {
                 const long pi = rr * W + x0 + c;
                 const float2 xin = reinterpret_cast<const float2*>(p.x)[pi];
@@ -181,6 +190,24 @@ __global__ void k_transpose_bf16(const float* in, bf16* out, int R, int Cc) {
     if (i >= R * Cc) return;
     const int r = i / Cc, c = i - r * Cc;
     out[(long)c * R + r] = (bf16)in[i];
+}
+
+// A operand of k-block kg (= 2 T + kb) for lane l (output row o = l % 32, lane
+// group g = l / 32), entry v: W2[h][o] with h = 32 T + 16 kb + 8 (v / 4) + 4 g + v % 4
+// for o < 2, zero for the padding rows.
+__global__ void k_fno_w2_operands(const bf16* W2, bf16* W2P, int P) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (P / 16) * 512) return;
+    const int kg = i / 512, l = (i / 8) % 64, v = i % 8;
+    const int o = l % 32, g = l / 32, T = kg / 2, kb = kg % 2;
+    const int h = 32 * T + 16 * kb + 8 * (v / 4) + 4 * g + (v % 4);
+    W2P[i] = o < 2 ? W2[2 * h + o] : (bf16)0.f;
+}
+
+hipError_t launch_fno_w2_operands(const bf16* W2, bf16* W2P, int P, hipStream_t s) {
+    const int n = (P / 16) * 512;
+    hipLaunchKernelGGL(k_fno_w2_operands, dim3((n + 255) / 256), dim3(256), 0, s, W2, W2P, P);
+    return hipGetLastError();
 }
 
 bool fno_fused_ok(int C, int K, int W, int P) { return C == FC && 2 * K == F2K && W % 32 == 0 && P % 32 == 0; }
