@@ -357,7 +357,10 @@ __device__ void project_segmented(double2* B0, double2* SC, int W, int nseg, con
     const int task = threadIdx.x;
     const int ntask = 2 * W * nseg;
     const bool on = task < ntask;
-    const int u = on ? task % nseg : 0, ch = on ? task / nseg : 0;
+    // chain-fastest: the threads of a wave take 2 W adjacent chains (one LDS row
+    // segment per row step) for a few segments, not one chain's segments, whose rows
+    // lie 16 rows apart and would hit the same LDS banks; task = u 2W + ch
+    const int u = on ? task / (2 * W) : 0, ch = on ? task % (2 * W) : 0;
     const int p = ch / W, cc = ch - p * W;
     const int es = 2 * W;
     double2* col = B0 + p * W + cc;
@@ -367,8 +370,11 @@ __device__ void project_segmented(double2* B0, double2* SC, int W, int nseg, con
     const int lo = u * R, hi = min(lo + R, n);
     const int t0 = lo, t1 = u == nsp - 1 ? m : min(lo + R, m);
     const double* qt = cd.qtab[p];
+    // SC segment-major: slot (v, ch) at 2 (v 2W + ch), so the 2 W chains of one
+    // segment are adjacent in the scans below
     double2* sc = SC + 2 * task;
-    double2* chain_sc = SC + 2 * ch * nseg;
+    double2* chain_sc = SC + 2 * ch;
+    const int vs = 4 * W;  // stride between a chain's segment slots
     // 1. projection onto the null space of the boundary functionals
     double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
     if (seg_on)
@@ -384,7 +390,7 @@ __device__ void project_segmented(double2* B0, double2* SC, int W, int nseg, con
     s2 = make_double2(0.0, 0.0);
     if (on)
         for (int v = 0; v < nsp; ++v) {
-            const double2 a = chain_sc[2 * v], b = chain_sc[2 * v + 1];
+            const double2 a = chain_sc[vs * v], b = chain_sc[vs * v + 1];
             s1.x += a.x; s1.y += a.y;
             s2.x += b.x; s2.y += b.y;
         }
@@ -429,7 +435,7 @@ __device__ void project_segmented(double2* B0, double2* SC, int W, int nseg, con
         const double* gm = cd.gmat[p];
         if (seg_on)
             for (int v = 0; v < u; ++v) {
-                const double2 ha = chain_sc[2 * v], hb = chain_sc[2 * v + 1];
+                const double2 ha = chain_sc[vs * v], hb = chain_sc[vs * v + 1];
                 const double m00 = gm[4 * v], m01 = gm[4 * v + 1], m10 = gm[4 * v + 2], m11 = gm[4 * v + 3];
                 const double2 na = make_double2(m00 * sa.x + m01 * sb.x + ha.x, m00 * sa.y + m01 * sb.y + ha.y);
                 const double2 nb = make_double2(m10 * sa.x + m11 * sb.x + hb.x, m10 * sa.y + m11 * sb.y + hb.y);
@@ -472,7 +478,7 @@ __device__ void project_segmented(double2* B0, double2* SC, int W, int nseg, con
         const double* bm = cd.bmat[p];
         if (seg_on)
             for (int v = nsp - 1; v > u; --v) {
-                const double2 ga = chain_sc[2 * v], gb = chain_sc[2 * v + 1];
+                const double2 ga = chain_sc[vs * v], gb = chain_sc[vs * v + 1];
                 const double m00 = bm[4 * v], m01 = bm[4 * v + 1], m10 = bm[4 * v + 2], m11 = bm[4 * v + 3];
                 const double2 na = make_double2(m00 * sa.x + m01 * sb.x + ga.x, m00 * sa.y + m01 * sb.y + ga.y);
                 const double2 nb = make_double2(m10 * sa.x + m11 * sb.x + gb.x, m10 * sa.y + m11 * sb.y + gb.y);
