@@ -10,8 +10,10 @@
  * - All array arguments are DEVICE pointers owned by the caller.  Real data
  *   are IEEE binary64; complex data are interleaved (re, im) binary64 pairs.
  * - Every call is asynchronous on the given stream (a hipStream_t passed as
- *   void*, NULL = the null stream) and never allocates device memory; plans
- *   own their workspace and tables, allocated at creation.
+ *   void*, NULL = the null stream).  Plans, GL batches and networks own their
+ *   workspace and tables, allocated at creation; the transform, solve and
+ *   time-step calls allocate nothing (sgm_fno_advance_checked sizes its
+ *   workspace on its first call, as documented there).
  * - Return value: SGM_OK (0) or a negative SGM_ERR_* code; a human-readable
  *   detail for the last failing call of the calling thread is available from
  *   sgm_last_error().  No C++ exception crosses this boundary.
