@@ -116,15 +116,32 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer(FnoLayerArgs p) {
         for (int s = 0; s < 2; ++s) acc = mfma(ld8(p.Gx + (long)(x0 + c) * F2K + 16 * s + 8 * g), bop[s], acc);
 #pragma unroll
         for (int s = 0; s < 2; ++s) acc = mfma(ld8(ar + (long)(x0 + c) * FC + 16 * s + 8 * g), bop[2 + s], acc);
-        bf16x8 yb[2];
+        bf16x8 yb[2], zb[2];
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            const int px = x0 + 8 * (e >> 2) + 4 * g + (e & 3);
             const float z = acc[e] + bias;
-            if (MODE != 2 && p.zsave && live) p.zsave[(rr * W + px) * FC + c] = (bf16)z;
-            const bf16 y = (bf16)(p.act ? gelu(z) : z);
-            yb[e >> 3][e & 7] = y;
-            if (MODE != 2 && live) p.a_out[(rr * W + px) * FC + c] = y;
+            zb[e >> 3][e & 7] = (bf16)z;
+            yb[e >> 3][e & 7] = (bf16)(p.act ? gelu(z) : z);
+        }
+        if constexpr (MODE != 2) {
+            // a' (and z) of the 32 pixels through the wave's LDS tile, so that each lane
+            // stores 16-byte runs of one pixel's channels instead of single values
+            auto store_tile = [&](const bf16x8 (&v)[2], bf16* dst) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) tile[wv][8 * (e >> 2) + 4 * g + (e & 3)][c] = v[e >> 3][e & 7];
+                __syncthreads();
+                const int pl = lane >> 1, ch = 16 * (lane & 1);
+                const bf16x8 w0 = *reinterpret_cast<const bf16x8*>(&tile[wv][pl][ch]);
+                const bf16x8 w1 = *reinterpret_cast<const bf16x8*>(&tile[wv][pl][ch + 8]);
+                if (live) {
+                    bf16* o = dst + (rr * W + x0 + pl) * FC + ch;
+                    *reinterpret_cast<bf16x8*>(o) = w0;
+                    *reinterpret_cast<bf16x8*>(o + 8) = w1;
+                }
+                __syncthreads();
+            };
+            if (p.zsave) store_tile(zb, p.zsave);
+            store_tile(yb, p.a_out);
         }
         if constexpr (MODE == 0) {
             // next x-DFT: k = 8 g + v <-> pixel x0 + 16 q + 8 (v / 4) + 4 g + v % 4
