@@ -97,6 +97,23 @@ def test_forward_backward_and_paper_initial_condition(GLBatch):
         assert rel_err(host(back[i]), us[i]) < 1e-12
 
 
+def test_forward_backward_runs_of_equal_sizes(GLBatch):
+    # consecutive problems of one size are transformed together (compiled lengths 64,
+    # 96, 128 and the generic 33), with single problems in between
+    sizes = [64, 64, 64, 33, 33, 128, 96, 128, 128, 64]
+    print(f"[case] gl forward/backward runs {sizes}", flush=True)
+    L = 100.0
+    g = GLBatch(sizes, L=L)
+    us = [synth.gl_noise(n, 500 + i) for i, n in enumerate(sizes)]
+    uh = g.forward(g.pack(us))
+    got = [host(x) for x in g.unpack(uh)]
+    for i in range(len(sizes)):
+        assert rel_err(got[i], ogl.forward(us[i])) < 1e-12, i
+    back = g.unpack(g.backward(uh))
+    for i in range(len(sizes)):
+        assert rel_err(host(back[i]), us[i]) < 1e-12, i
+
+
 def test_uniform_solution_and_symmetry(GLBatch):
     # uniform state: closed-form amplitude/phase; real symmetric IC keeps x <-> y symmetry
     L, b, c, dt = 100.0, 0.0, 1.5, 0.025
