@@ -84,8 +84,10 @@ __global__ void __launch_bounds__(G::THREADS) kr_lines_r2c(const double* __restr
 #pragma unroll
     for (int e = 0; e < G::E; ++e) {
         const int v = t + G::NT * e;
-        double re = l0 < nlines ? in[l0 * L + v] : 0.0;
-        double im = l0 + 1 < nlines ? in[(l0 + 1) * L + v] : 0.0;
+        // the physical input is read once per transform: non-temporal, so it does not
+        // displace the spectral arrays the following passes read back from the MALL
+        double re = l0 < nlines ? __builtin_nontemporal_load(&in[l0 * L + v]) : 0.0;
+        double im = l0 + 1 < nlines ? __builtin_nontemporal_load(&in[(l0 + 1) * L + v]) : 0.0;
         x[e] = make_double2(re, im);
     }
     LineFft<L, G, -1> fft;
@@ -157,8 +159,9 @@ __global__ void __launch_bounds__(G::THREADS) kr_lines_c2r(const double2* __rest
 #pragma unroll
     for (int e = 0; e < G::E; ++e) {
         const int v = t + G::NT * e;
-        if (l0 < nlines) out[l0 * L + v] = x[e].x;
-        if (l0 + 1 < nlines) out[(l0 + 1) * L + v] = x[e].y;
+        // physical output: written once, non-temporal like the forward pass's input
+        if (l0 < nlines) __builtin_nontemporal_store(x[e].x, &out[l0 * L + v]);
+        if (l0 + 1 < nlines) __builtin_nontemporal_store(x[e].y, &out[(l0 + 1) * L + v]);
     }
 }
 

@@ -99,7 +99,9 @@ struct PassTimer {
     hipEvent_t take() {
         hipEvent_t e = nullptr;
         if (!p->ev_pool.empty()) { e = p->ev_pool.back(); p->ev_pool.pop_back(); }
-        else if (hipEventCreate(&e) != hipSuccess) e = nullptr;
+        // timing-only events: no system-scope fence (no cache write-back at the
+        // record), so the interval is the pass itself
+        else if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) e = nullptr;
         return e;
     }
     ~PassTimer() {
