@@ -94,6 +94,16 @@ __device__ __forceinline__ int gwn(int q, int M) { return q < (M + 1) / 2 ? q : 
 __device__ __forceinline__ bool kept(int l, int N) { return l >= -(N / 2) && l <= (N - 1) / 2; }
 __device__ __forceinline__ int nidx(int l, int N) { return l >= 0 ? l : l + N; }
 
+// Stage operands touched once per stage (state, accumulator, stage input):
+// non-temporal, so the padded workspace, which every pass reads back, keeps the MALL.
+__device__ __forceinline__ double2 ntld(const double2* p) {
+    return make_double2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
+}
+__device__ __forceinline__ void ntst(double2* p, double2 v) {
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+}
+
 // Stage update of one retained mode.  k = N(v) = -F_trunc[(1 + i c)|u_p|^2 u_p].
 // Returns the input of the next stage (stages 0..2); stores it in s.v when
 // store_v (the explicit scheme needs it again for L v).
@@ -103,24 +113,24 @@ __device__ __forceinline__ double2 stage_update(const GLStage& s, const GLProb& 
     if (s.mode == kGlRhs || s.mode == kGlRk4) {
         const double kx = gwn(kxi, pr.N) * s.ks, ky = gwn(kyi, pr.N) * s.ks;
         const double k2 = kx * kx + ky * ky;
-        const double2 vv = s.vin[idx];
+        const double2 vv = ntld(s.vin + idx);
         // dU = (1 - (1 + i b) k^2) v + k
         const double2 du = make_double2((1.0 - k2) * vv.x + s.b * k2 * vv.y + k.x,
                                         (1.0 - k2) * vv.y - s.b * k2 * vv.x + k.y);
         if (s.mode == kGlRhs) { s.rhs[idx] = du; return vn; }
-        const double2 u0 = s.state[idx];
+        const double2 u0 = ntld(s.state + idx);
         const double dt = s.dt;
         if (s.stage == 0) {
-            s.acc[idx] = make_double2(u0.x + dt / 6 * du.x, u0.y + dt / 6 * du.y);
+            ntst(s.acc + idx, make_double2(u0.x + dt / 6 * du.x, u0.y + dt / 6 * du.y));
             vn = make_double2(u0.x + dt / 2 * du.x, u0.y + dt / 2 * du.y);
         } else if (s.stage < 3) {
-            double2 a = s.acc[idx];
-            s.acc[idx] = make_double2(a.x + dt / 3 * du.x, a.y + dt / 3 * du.y);
+            double2 a = ntld(s.acc + idx);
+            ntst(s.acc + idx, make_double2(a.x + dt / 3 * du.x, a.y + dt / 3 * du.y));
             const double bb = s.stage == 1 ? dt / 2 : dt;
             vn = make_double2(u0.x + bb * du.x, u0.y + bb * du.y);
         } else {
-            double2 a = s.acc[idx];
-            s.state[idx] = make_double2(a.x + dt / 6 * du.x, a.y + dt / 6 * du.y);
+            double2 a = ntld(s.acc + idx);
+            ntst(s.state + idx, make_double2(a.x + dt / 6 * du.x, a.y + dt / 6 * du.y));
             return vn;
         }
         if (store_v) s.v[idx] = vn;
@@ -129,28 +139,28 @@ __device__ __forceinline__ double2 stage_update(const GLStage& s, const GLProb& 
     // integrating-factor RK4; E = exp(Lhat dt/2) = e^{dt/2} ex(kx) ex(ky)
     const double2 ex = s.etab[pr.off_e + kxi], ey = s.etab[pr.off_e + kyi];
     const double2 E = cscale(cmul(ex, ey), s.edt);
-    const double2 u0 = s.state[idx];
+    const double2 u0 = ntld(s.state + idx);
     const double dt = s.dt;
     if (s.stage == 0) {
         const double2 E2 = cmul(E, E);
         const double2 a = make_double2(u0.x + dt / 6 * k.x, u0.y + dt / 6 * k.y);
-        s.acc[idx] = cmul(E2, a);
+        ntst(s.acc + idx, cmul(E2, a));
         vn = cmul(E, make_double2(u0.x + dt / 2 * k.x, u0.y + dt / 2 * k.y));
     } else if (s.stage == 1) {
         const double2 Ek = cmul(E, k);
-        double2 a = s.acc[idx];
-        s.acc[idx] = make_double2(a.x + dt / 3 * Ek.x, a.y + dt / 3 * Ek.y);
+        double2 a = ntld(s.acc + idx);
+        ntst(s.acc + idx, make_double2(a.x + dt / 3 * Ek.x, a.y + dt / 3 * Ek.y));
         const double2 Eu = cmul(E, u0);
         vn = make_double2(Eu.x + dt / 2 * k.x, Eu.y + dt / 2 * k.y);
     } else if (s.stage == 2) {
         const double2 Ek = cmul(E, k);
-        double2 a = s.acc[idx];
-        s.acc[idx] = make_double2(a.x + dt / 3 * Ek.x, a.y + dt / 3 * Ek.y);
+        double2 a = ntld(s.acc + idx);
+        ntst(s.acc + idx, make_double2(a.x + dt / 3 * Ek.x, a.y + dt / 3 * Ek.y));
         const double2 E2u = cmul(E, cmul(E, u0));
         vn = make_double2(E2u.x + dt * Ek.x, E2u.y + dt * Ek.y);
     } else {
-        double2 a = s.acc[idx];
-        s.state[idx] = make_double2(a.x + dt / 6 * k.x, a.y + dt / 6 * k.y);
+        double2 a = ntld(s.acc + idx);
+        ntst(s.state + idx, make_double2(a.x + dt / 6 * k.x, a.y + dt / 6 * k.y));
         return vn;
     }
     if (store_v) s.v[idx] = vn;
