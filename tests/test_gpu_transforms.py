@@ -38,12 +38,11 @@ def _phys(shape, kind, seed):
     return synth.random_smooth_field(shape, seed=seed, complex_last=(kind == "c2c"))
 
 
-SMALL_2D = [(32, 32), (33, 34), (8, 1), (16, 5), (7, 12), (64, 48), (40, 17)]
-SMALL_3D = [(32, 33, 34), (16, 8, 8), (24, 12, 10), (12, 6, 7)]
-
-
-SMALL_2D = SMALL_2D + [(64, 64), (96, 48), (128, 32), (192, 16), (48, 96)]
-SMALL_3D = SMALL_3D + [(64, 32, 48), (96, 16, 64), (48, 24, 32)]
+# odd, even and degenerate (M = 1) lengths, then shapes spanning several tiles
+# of the register kernels with ragged tails
+SMALL_2D = [(32, 32), (33, 34), (8, 1), (16, 5), (7, 12), (64, 48), (40, 17),
+            (64, 64), (96, 48), (128, 32), (192, 16), (48, 96)]
+SMALL_3D = [(32, 33, 34), (16, 8, 8), (24, 12, 10), (12, 6, 7), (64, 32, 48), (96, 16, 64), (48, 24, 32)]
 
 
 @pytest.mark.parametrize("generic", [False, True])
