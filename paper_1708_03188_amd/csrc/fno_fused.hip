@@ -111,7 +111,10 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer(FnoLayerArgs p) {
     floatx16 tacc = zero16();
     for (int t = 0; t < W / 32; ++t) {
         const int x0 = 32 * t;
-        floatx16 acc = zero16();
+        // every accumulator entry of a lane is output channel c: start from its bias
+        floatx16 acc;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[e] = bias;
 #pragma unroll
         for (int s = 0; s < 2; ++s) acc = mfma(ld8(p.Gx + (long)(x0 + c) * F2K + 16 * s + 8 * g), bop[s], acc);
 #pragma unroll
@@ -119,7 +122,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer(FnoLayerArgs p) {
         bf16x8 yb[2], zb[2];
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            const float z = acc[e] + bias;
+            const float z = acc[e];
             zb[e >> 3][e & 7] = (bf16)z;
             yb[e >> 3][e & 7] = (bf16)(p.act ? gelu(z) : z);
         }
@@ -166,18 +169,24 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer(FnoLayerArgs p) {
             for (int s = 0; s < 2; ++s) bt[s] = *reinterpret_cast<const bf16x8*>(&tile[wv][c][16 * s + 8 * g]);
             floatx16 o2 = zero16();
             for (int T = 0; T < p.P / 32; ++T) {
-                floatx16 h = zero16();
+                // the accumulator starts from b1: entry e is hidden unit 32 T + 8 (e / 4) + 4 g + e % 4,
+                // so each run of four entries is one 16-byte load (b1 is 16-byte aligned)
+                floatx16 h;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float4 bb = *reinterpret_cast<const float4*>(p.b1 + 32 * T + 8 * j + 4 * g);
+                    h[4 * j] = bb.x;
+                    h[4 * j + 1] = bb.y;
+                    h[4 * j + 2] = bb.z;
+                    h[4 * j + 3] = bb.w;
+                }
 #pragma unroll
                 for (int s = 0; s < 2; ++s) h = mfma(ld8(p.W1T + (long)(32 * T + c) * FC + 16 * s + 8 * g), bt[s], h);
 #pragma unroll
                 for (int kb = 0; kb < 2; ++kb) {
                     bf16x8 hop;
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) {
-                        const int e = 8 * kb + v;
-                        const int hu = 32 * T + 8 * (e >> 2) + 4 * g + (e & 3);
-                        hop[v] = (bf16)gelu(h[e] + p.b1[hu]);
-                    }
+                    for (int v = 0; v < 8; ++v) hop[v] = (bf16)gelu(h[8 * kb + v]);
                     o2 = mfma(ld8(p.W2P + ((long)(2 * T + kb) * 64 + lane) * 8), hop, o2);
                 }
             }
@@ -237,6 +246,7 @@ hipError_t launch_fno_lift_dft(const float* x, const float* Wl, const float* bl,
 }
 
 hipError_t launch_fno_layer(const FnoLayerArgs& a, int mode, hipStream_t s) {
+    if (mode == 2 && (reinterpret_cast<uintptr_t>(a.b1) & 15) != 0) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((a.rows + WAVES - 1) / WAVES)), block(64 * WAVES);
     if (mode == 0) hipLaunchKernelGGL(k_fno_layer<0>, grid, block, 0, s, a);
     else if (mode == 1) hipLaunchKernelGGL(k_fno_layer<1>, grid, block, 0, s, a);
