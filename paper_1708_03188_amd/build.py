@@ -17,6 +17,11 @@ FLAGS = [
     "-Wno-unused-result", "-I" + os.path.join(ROOT, "include"),
 ]
 
+# Per-source flags: the fused FNO row kernels keep their MFMA accumulators in
+# ordinary VGPRs, so the GELU between the projection's two products reads them
+# without accumulation-register copies.
+EXTRA = {"fno_fused.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
 
 def _run(cmd):
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -33,7 +38,7 @@ def build(verbose=False, jobs=8):
     for src in SOURCES:
         obj = os.path.join(BUILD, src.replace(".", "_") + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [HIPCC] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC] + FLAGS + EXTRA.get(src, []) + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd))
         procs.append((subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True), cmd))
