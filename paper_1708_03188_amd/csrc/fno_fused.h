@@ -16,7 +16,22 @@ __device__ __forceinline__ float fno_erf(float x) {
     const float r = 1.f - q * t * __expf(-ax * ax);
     return copysignf(r, x);
 }
-__device__ __forceinline__ float fno_gelu(float z) { return 0.5f * z * (1.f + fno_erf(z * 0.70710678118654752f)); }
+// GELU on the same approximation, written through erfc: with x = z / sqrt 2,
+// 1 - erf|x| = q(t) t exp(-x^2) and, for either sign of z,
+// z (1 + erf x) / 2 = z / 2 + |z| (1/2 - (1 - erf|x|) / 2).
+// The 1/sqrt 2, the -1/2 and log2 e are folded into the constants (10 plain
+// operations and two transcendental ones).
+__device__ __forceinline__ float fno_gelu(float z) {
+    const float az = fabsf(z);
+    const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.3275911f * 0.70710678118654752f, az, 1.f));
+    float q = __builtin_fmaf(-0.5f * 1.061405429f, t, -0.5f * -1.453152027f);
+    q = __builtin_fmaf(q, t, -0.5f * 1.421413741f);
+    q = __builtin_fmaf(q, t, -0.5f * -0.284496736f);
+    q = __builtin_fmaf(q, t, -0.5f * 0.254829592f);
+    // exp(-z^2 / 2) = 2^(-z^2 log2(e) / 2)
+    const float e = __builtin_amdgcn_exp2f(z * z * (-0.5f * 1.4426950408889634f));
+    return __builtin_fmaf(az, __builtin_fmaf(q * t, e, 0.5f), 0.5f * z);
+}
 __device__ __forceinline__ float fno_gelu_d(float z) {
     return 0.5f * (1.f + fno_erf(z * 0.70710678118654752f)) + z * __expf(-0.5f * z * z) * 0.39894228040143268f;
 }

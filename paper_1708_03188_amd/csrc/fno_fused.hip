@@ -120,11 +120,15 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer(FnoLayerArgs p) {
 #pragma unroll
         for (int s = 0; s < 2; ++s) acc = mfma(ld8(ar + (long)(x0 + c) * FC + 16 * s + 8 * g), bop[2 + s], acc);
         bf16x8 yb[2], zb[2];
+        if (p.act) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const float z = acc[e];
-            zb[e >> 3][e & 7] = (bf16)z;
-            yb[e >> 3][e & 7] = (bf16)(p.act ? gelu(z) : z);
+            for (int e = 0; e < 16; ++e) {
+                zb[e >> 3][e & 7] = (bf16)acc[e];
+                yb[e >> 3][e & 7] = (bf16)gelu(acc[e]);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) zb[e >> 3][e & 7] = yb[e >> 3][e & 7] = (bf16)acc[e];
         }
         if constexpr (MODE != 2) {
             // a' (and z) of the 32 pixels through the wave's LDS tile, so that each lane
