@@ -51,30 +51,45 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_lift_dft(const float* __rest
                                                            const float* __restrict__ bl, const bf16* __restrict__ Fx,
                                                            bf16* __restrict__ a0, float* __restrict__ T, long rows,
                                                            int W) {
+    // the row's input, 256 pixels at a time, staged by coalesced loads: each lane
+    // then reads the eight pixels it lifts from LDS instead of eight dependent
+    // broadcast loads per 16 pixels
+    constexpr int XCH = 256;
+    __shared__ float2 xs[WAVES][XCH];
     const long row = (long)blockIdx.x * WAVES + (threadIdx.x >> 6);
-    if (row >= rows) return;  // whole wave
+    const bool live = row < rows;  // waves past the end still reach the barriers
+    const int wv = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63, c = lane & 31, g = lane >> 5;
+    const long rr = live ? row : 0;
     const float w0 = Wl[c], w1 = Wl[FC + c], b = bl[c];
-    const float2* xr = reinterpret_cast<const float2*>(x) + row * W;
-    bf16* ar = a0 + row * W * FC;
+    const float2* xr = reinterpret_cast<const float2*>(x) + rr * W;
+    bf16* ar = a0 + rr * W * FC;
     floatx16 acc = zero16();
-    for (int s = 0; s < W / 16; ++s) {
-        bf16x8 bop;
+    for (int ch0 = 0; ch0 < W; ch0 += XCH) {
+        const int n = W - ch0 < XCH ? W - ch0 : XCH;  // a multiple of 32
+        for (int i = lane; i < n; i += 64) xs[wv][i] = xr[ch0 + i];
+        __syncthreads();
+        for (int s = 0; s < n / 16; ++s) {
+            bf16x8 bop;
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            const int px = 16 * s + 8 * g + v;
-            const float2 u = xr[px];
-            const bf16 val = (bf16)(u.x * w0 + u.y * w1 + b);
-            ar[px * FC + c] = val;
-            bop[v] = val;
+            for (int v = 0; v < 8; ++v) {
+                const int pl = 16 * s + 8 * g + v;
+                const float2 u = xs[wv][pl];
+                const bf16 val = (bf16)(u.x * w0 + u.y * w1 + b);
+                if (live) ar[(long)(ch0 + pl) * FC + c] = val;
+                bop[v] = val;
+            }
+            acc = mfma(ld8(Fx + (long)c * W + ch0 + 16 * s + 8 * g), bop, acc);
         }
-        acc = mfma(ld8(Fx + (long)c * W + 16 * s + 8 * g), bop, acc);
+        __syncthreads();
     }
-    float* tr = T + row * F2K * FC;
+    if (live) {
+        float* tr = T + rr * F2K * FC;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) tr[(8 * r + 4 * g + v) * FC + c] = acc[4 * r + v];
+            for (int v = 0; v < 4; ++v) tr[(8 * r + 4 * g + v) * FC + c] = acc[4 * r + v];
+    }
 }
 
 // MODE 0: a_out and the next layer's T; 1: a_out only (last layer, training);
