@@ -53,9 +53,10 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_lift_dft(const float* __rest
                                                            int W) {
     // the row's input, 256 pixels at a time, staged by coalesced loads: each lane
     // then reads the eight pixels it lifts from LDS instead of eight dependent
-    // broadcast loads per 16 pixels
+    // broadcast loads per 16 pixels; a0 leaves through an LDS tile in 16-byte runs
     constexpr int XCH = 256;
     __shared__ float2 xs[WAVES][XCH];
+    __shared__ bf16 tile[WAVES][32][FC + 8];
     const long row = (long)blockIdx.x * WAVES + (threadIdx.x >> 6);
     const bool live = row < rows;  // waves past the end still reach the barriers
     const int wv = threadIdx.x >> 6;
@@ -69,19 +70,33 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_lift_dft(const float* __rest
         const int n = W - ch0 < XCH ? W - ch0 : XCH;  // a multiple of 32
         for (int i = lane; i < n; i += 64) xs[wv][i] = xr[ch0 + i];
         __syncthreads();
-        for (int s = 0; s < n / 16; ++s) {
-            bf16x8 bop;
+        for (int s2 = 0; s2 < n / 32; ++s2) {
+            // 32 pixels: each lane lifts channel c of eight pixels per half, feeds them to
+            // the x-DFT and parks them in the wave's tile [pixel][channel] ...
 #pragma unroll
-            for (int v = 0; v < 8; ++v) {
-                const int pl = 16 * s + 8 * g + v;
-                const float2 u = xs[wv][pl];
-                const bf16 val = (bf16)(u.x * w0 + u.y * w1 + b);
-                if (live) ar[(long)(ch0 + pl) * FC + c] = val;
-                bop[v] = val;
+            for (int h = 0; h < 2; ++h) {
+                const int p0 = 32 * s2 + 16 * h + 8 * g;
+                bf16x8 bop;
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    const float2 u = xs[wv][p0 + v];
+                    bop[v] = (bf16)(u.x * w0 + u.y * w1 + b);
+                    tile[wv][16 * h + 8 * g + v][c] = bop[v];
+                }
+                acc = mfma(ld8(Fx + (long)c * W + ch0 + p0), bop, acc);
             }
-            acc = mfma(ld8(Fx + (long)c * W + ch0 + 16 * s + 8 * g), bop, acc);
+            __syncthreads();
+            // ... from which each lane stores 32 bytes: half of one pixel's channels
+            const int pl = lane >> 1, cc = 16 * (lane & 1);
+            const bf16x8 q0 = *reinterpret_cast<const bf16x8*>(&tile[wv][pl][cc]);
+            const bf16x8 q1 = *reinterpret_cast<const bf16x8*>(&tile[wv][pl][cc + 8]);
+            if (live) {
+                bf16* o = ar + (long)(ch0 + 32 * s2 + pl) * FC + cc;
+                *reinterpret_cast<bf16x8*>(o) = q0;
+                *reinterpret_cast<bf16x8*>(o + 8) = q1;
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
     if (live) {
         float* tr = T + rr * F2K * FC;
