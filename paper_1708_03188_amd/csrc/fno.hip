@@ -109,20 +109,29 @@ __global__ void k_colsum(const T* g, float* db, long P, int C) {
 }
 
 // X[b][part][j][kx][c] -> Xm[(j, kx)][b][part][c]   (and back when inv)
+// One thread per V consecutive channels (V = 4 when C % 4 == 0: 16-byte moves),
+// index arithmetic in 32 bits (the host keeps the element count below 2^31).
 __global__ void k_perm_modes(const float* in, float* out, int B, int KY, int KX, int C, int inv) {
-    long n = (long)B * 2 * KY * KX * C;
-    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const unsigned V = (C & 3) == 0 ? 4u : 1u;
+    const unsigned CV = (unsigned)C / V;
+    const unsigned n = (unsigned)B * 2u * (unsigned)KY * (unsigned)KX * CV;
+    const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    // index in the [b][part][j][kx][c] layout
-    long t = i;
-    int c = (int)(t % C); t /= C;
-    int kx = (int)(t % KX); t /= KX;
-    int j = (int)(t % KY); t /= KY;
-    int part = (int)(t % 2); t /= 2;
-    int b = (int)t;
-    long o = ((((long)(j * KX + kx) * B + b) * 2 + part) * C + c);
-    if (inv) out[i] = in[o];
-    else out[o] = in[i];
+    // element index in the [b][part][j][kx][c] layout
+    unsigned t = i;
+    const unsigned cv = t % CV; t /= CV;
+    const unsigned kx = t % (unsigned)KX; t /= (unsigned)KX;
+    const unsigned j = t % (unsigned)KY; t /= (unsigned)KY;
+    const unsigned part = t & 1u, b = t >> 1;
+    const long a = (long)i * V;
+    const long o = ((long)((j * (unsigned)KX + kx) * (unsigned)B + b) * 2 + part) * C + cv * V;
+    if (V == 4) {
+        if (inv) *reinterpret_cast<float4*>(out + a) = *reinterpret_cast<const float4*>(in + o);
+        else *reinterpret_cast<float4*>(out + o) = *reinterpret_cast<const float4*>(in + a);
+    } else {
+        if (inv) out[a] = in[o];
+        else out[o] = in[a];
+    }
 }
 
 // Rreal[m] (2C x 2C) = [[Rr, Ri], [-Ri, Rr]] as bf16, m = (j, kx)
@@ -197,6 +206,8 @@ __global__ void k_x_to_c128(const float* x, double2* u, long n) {
 }
 
 static inline unsigned nblk(long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+// threads of k_perm_modes over B x 2 x 2K x K x C values
+static inline long perm_threads(long B, long K, long C) { return B * 4 * K * K * C / ((C & 3) == 0 ? 4 : 1); }
 
 }  // namespace sgm
 
@@ -279,6 +290,8 @@ extern "C" sgm_status sgm_fno_create(const sgm_fno_desc* desc, uint64_t seed, sg
                       d.max_batch >= 1,
                   "invalid FNO sizes");
     SGM_CHECK_ARG(2 * d.modes <= d.H && 2 * d.modes <= d.W, "modes must satisfy 2*modes <= H and 2*modes <= W");
+    SGM_CHECK_ARG((long)d.max_batch * 4 * d.modes * d.modes * d.width < (1L << 31),
+                  "max_batch * 4 * modes^2 * width must stay below 2^31");
     sgm_fno_s* f = new (std::nothrow) sgm_fno_s();
     if (!f) return SGM_ERR_OOM;
     f->d = d;
@@ -476,13 +489,13 @@ static sgm_status fno_forward(sgm_fno f, const float* x, int B, hipStream_t s, f
         SGM_HIP_TRY(gemm(G(B, 4 * K, K * C, 2 * H, f->Fy, 0, 2L * H, 1, 0, f->T, 2L * H * K * C, (long)K * C, 1, 1, f->X,
                            4L * K * K * C, (long)K * C, 1), s));
         float* Xm = f->Xm + (long)l * NM * f->Bmax * 2 * C;
-        hipLaunchKernelGGL(k_perm_modes, dim3(nblk((long)B * 4 * K * K * C)), dim3(256), 0, s, (const float*)f->X, Xm,
+        hipLaunchKernelGGL(k_perm_modes, dim3(nblk(perm_threads(B, K, C))), dim3(256), 0, s, (const float*)f->X, Xm,
                            B, 2 * K, K, C, 0);
         // G3: Ym[m] (B x 2C) = Xm[m] (B x 2C) Rreal[m] (2C x 2C)
         SGM_HIP_TRY(gemm(G(NM, B, 2 * C, 2 * C, Xm, (long)B * 2 * C, 2 * C, 1, 1,
                            f->Rreal + (long)l * NM * 4 * C * C, 4L * C * C, 2 * C, 1, 0, f->Ym, (long)B * 2 * C, 2 * C, 1),
                          s));
-        hipLaunchKernelGGL(k_perm_modes, dim3(nblk((long)B * 4 * K * K * C)), dim3(256), 0, s, (const float*)f->Ym, f->Yt,
+        hipLaunchKernelGGL(k_perm_modes, dim3(nblk(perm_threads(B, K, C))), dim3(256), 0, s, (const float*)f->Ym, f->Yt,
                            B, 2 * K, K, C, 1);
         // G4: U[b] (2H x K C) = Gy_real (2H x 4K) Yt[b] (4K x K C)   (U reuses T)
         SGM_HIP_TRY(gemm(G(B, 2 * H, K * C, 4 * K, f->Gy, 0, 4L * K, 1, 0, f->Yt, 4L * K * K * C, (long)K * C, 1, 1, f->T,
