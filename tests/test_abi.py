@@ -47,3 +47,19 @@ def test_status_strings_and_argument_errors_without_gpu():
     assert lib.sgm_helmholtz_solve(None, 0.0, None, None, None) == -1
     assert lib.sgm_helmholtz_solve_physical(None, 0.0, None, None, None) == -1
     assert b"null" in lib.sgm_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsgm.so not built")
+def test_fno_create_rejects_sizes_before_any_device_call():
+    from paper_1708_03188_amd import _lib
+    lib = _lib.load()
+    out = ctypes.c_void_p()
+    # 2 * modes > H
+    d = _lib.FNODesc(H=16, W=16, width=32, modes=9, layers=4, hidden=128, max_batch=1)
+    assert lib.sgm_fno_create(ctypes.byref(d), 1, ctypes.byref(out)) == -1
+    assert b"modes" in lib.sgm_last_error()
+    # the spectral buffers' element count (max_batch * 4 * modes^2 * width) must stay below 2^31
+    d = _lib.FNODesc(H=256, W=256, width=32, modes=16, layers=4, hidden=128, max_batch=1 << 20)
+    assert lib.sgm_fno_create(ctypes.byref(d), 1, ctypes.byref(out)) == -1
+    assert b"2^31" in lib.sgm_last_error()
+    assert not out.value
