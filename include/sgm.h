@@ -224,7 +224,7 @@ typedef struct {
 
 /* Allocate parameters (seeded initialisation), Adam state and a workspace for
  * max_batch samples (about (2 layers + 3) B H W C bf16 plus B H W P).
- * SGM_ERR_ARG, before any device call, for sizes out of range or
+ * SGM_ERR_INVALID_ARG, before any device call, for sizes out of range or
  * max_batch * 4 * modes^2 * width >= 2^31 (the spectral buffers' element count). */
 sgm_status sgm_fno_create(const sgm_fno_desc* desc, uint64_t seed, sgm_fno* out);
 sgm_status sgm_fno_destroy(sgm_fno f);
