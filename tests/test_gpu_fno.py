@@ -21,6 +21,9 @@ CFG = dict(H=32, W=32, width=8, modes=4, layers=2, hidden=16)
 # width 32 with 16 x-modes runs the fused row kernels (lift + x-DFT, layer, projection);
 # H != W to catch axis mix-ups, three layers so the middle-layer variant runs twice
 CFG32 = dict(H=32, W=64, width=32, modes=16, layers=3, hidden=64)
+# fused kernels at ragged sizes: H * B = 34 rows (the last work-group has two waves past
+# the end), W = 288 (the lift stages its input in a 256-pixel and a 32-pixel chunk)
+CFG32R = dict(H=34, W=288, width=32, modes=16, layers=2, hidden=32)
 
 
 def _setup(FNO, B=3, seed=0, cfg=CFG):
@@ -41,10 +44,10 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
 
 
-@pytest.mark.parametrize("cfg", [CFG, CFG32], ids=["gemm", "fused"])
-def test_forward_matches_oracle(FNO, cfg):
-    print(f"[case] fno forward {cfg}", flush=True)
-    f, p, x, t = _setup(FNO, cfg=cfg)
+@pytest.mark.parametrize("cfg,B", [(CFG, 3), (CFG32, 3), (CFG32R, 1)], ids=["gemm", "fused", "fused-ragged"])
+def test_forward_matches_oracle(FNO, cfg, B):
+    print(f"[case] fno forward {cfg} B={B}", flush=True)
+    f, p, x, t = _setup(FNO, B=B, cfg=cfg)
     got = f.infer(_dev(x)).cpu().numpy().astype(np.float64)
     ref = ofno.forward(p, x, cfg["modes"])
     # bf16 activations: compare the network output (pred - x) relative to its size
