@@ -473,7 +473,8 @@ static sgm_status fno_forward(sgm_fno f, const float* x, int B, hipStream_t s, f
     const long HW = (long)H * W, pix = (long)B * HW, act = (long)f->Bmax * HW * C;
     const bool fused = fno_fused_ok(C, K, W, P);
     if (fused) {
-        SGM_HIP_TRY(launch_fno_lift_dft(x, f->par + f->oWl, f->par + f->obl, f->Fx, f->acts, f->T, (long)B * H, W, s));
+        SGM_HIP_TRY(launch_fno_lift_dft(x, f->par + f->oWl, f->par + f->obl, f->Fx, f->acts, reinterpret_cast<bf16*>(f->T),
+                                        (long)B * H, W, s));
     } else {
         hipLaunchKernelGGL(k_lift, dim3(nblk(pix * C)), dim3(256), 0, s, x, f->par + f->oWl, f->par + f->obl, f->acts,
                            pix, C);
@@ -485,9 +486,10 @@ static sgm_status fno_forward(sgm_fno f, const float* x, int B, hipStream_t s, f
         // G1: T[(b,y)] (2K x C) = Fx (2K x W) a[(b,y)] (W x C)
         if (!fused)
             SGM_HIP_TRY(gemm(G(B * H, 2 * K, C, W, f->Fx, 0, W, 1, 0, a, (long)W * C, C, 1, 0, f->T, 2L * K * C, C, 1), s));
-        // G2: X[b] (4K x K C) = Fy_real (4K x 2H) T[b] (2H x K C)
-        SGM_HIP_TRY(gemm(G(B, 4 * K, K * C, 2 * H, f->Fy, 0, 2L * H, 1, 0, f->T, 2L * H * K * C, (long)K * C, 1, 1, f->X,
-                           4L * K * K * C, (long)K * C, 1), s));
+        // G2: X[b] (4K x K C) = Fy_real (4K x 2H) T[b] (2H x K C).  The fused kernels keep T and U
+        // in bf16: both consumers round them to bf16 anyway, so the values are the same.
+        SGM_HIP_TRY(gemm(G(B, 4 * K, K * C, 2 * H, f->Fy, 0, 2L * H, 1, 0, f->T, 2L * H * K * C, (long)K * C, 1,
+                           fused ? 0 : 1, f->X, 4L * K * K * C, (long)K * C, 1), s));
         float* Xm = f->Xm + (long)l * NM * f->Bmax * 2 * C;
         hipLaunchKernelGGL(k_perm_modes, dim3(nblk(perm_threads(B, K, C))), dim3(256), 0, s, (const float*)f->X, Xm,
                            B, 2 * K, K, C, 0);
@@ -498,11 +500,16 @@ static sgm_status fno_forward(sgm_fno f, const float* x, int B, hipStream_t s, f
         hipLaunchKernelGGL(k_perm_modes, dim3(nblk(perm_threads(B, K, C))), dim3(256), 0, s, (const float*)f->Ym, f->Yt,
                            B, 2 * K, K, C, 1);
         // G4: U[b] (2H x K C) = Gy_real (2H x 4K) Yt[b] (4K x K C)   (U reuses T)
-        SGM_HIP_TRY(gemm(G(B, 2 * H, K * C, 4 * K, f->Gy, 0, 4L * K, 1, 0, f->Yt, 4L * K * K * C, (long)K * C, 1, 1, f->T,
-                           2L * H * K * C, (long)K * C, 1), s));
+        {
+            GemmDesc g4 = G(B, 2 * H, K * C, 4 * K, f->Gy, 0, 4L * K, 1, 0, f->Yt, 4L * K * K * C, (long)K * C, 1, 1, f->T,
+                            2L * H * K * C, (long)K * C, 1);
+            g4.c_bf16 = fused ? 1 : 0;
+            SGM_HIP_TRY(gemm(g4, s));
+        }
         if (fused) {
             FnoLayerArgs la{};
-            la.a = a; la.U = f->T; la.Tn = f->T; la.Gx = f->Gx; la.Fx = f->Fx;
+            la.a = a; la.U = reinterpret_cast<const bf16*>(f->T); la.Tn = reinterpret_cast<bf16*>(f->T);
+            la.Gx = f->Gx; la.Fx = f->Fx;
             la.Wp = f->Wp16 + (long)l * C * C; la.bp = f->par + f->obp[l];
             la.a_out = an; la.zsave = pred_out ? nullptr : f->zsv + l * act;
             la.rows = (long)B * H; la.W = W; la.act = l < f->nl - 1 ? 1 : 0;

@@ -38,8 +38,8 @@ __device__ __forceinline__ float fno_gelu_d(float z) {
 
 struct FnoLayerArgs {
     const __bf16* a;      // layer input [rows][W][32]
-    const float* U;       // inverse-y spectral rows [rows][32][32] (may alias Tn)
-    float* Tn;            // next layer's x-DFT rows [rows][32][32] (mode 0)
+    const __bf16* U;      // inverse-y spectral rows [rows][32][32] (may alias Tn)
+    __bf16* Tn;           // next layer's x-DFT rows [rows][32][32] (mode 0)
     const __bf16* Gx;     // [W][32] inverse x-DFT
     const __bf16* Fx;     // [32][W] forward x-DFT
     const __bf16* Wp;     // [32][32] pointwise weights
@@ -64,7 +64,7 @@ bool fno_fused_ok(int C, int K, int W, int P);
 // W2 [P][2] (bf16) -> the A operands of the projection's second MFMA (P % 32 == 0).
 hipError_t launch_fno_w2_operands(const __bf16* W2, __bf16* W2P, int P, hipStream_t s);
 hipError_t launch_fno_lift_dft(const float* x, const float* Wl, const float* bl, const __bf16* Fx, __bf16* a0,
-                               float* T, long rows, int W, hipStream_t s);
+                               __bf16* T, long rows, int W, hipStream_t s);
 // mode 0: a_out + next T; 1: a_out (last layer); 2: projection to pred (last layer)
 hipError_t launch_fno_layer(const FnoLayerArgs& a, int mode, hipStream_t s);
 hipError_t launch_transpose_bf16(const float* in, __bf16* out, int R, int Cc, hipStream_t s);

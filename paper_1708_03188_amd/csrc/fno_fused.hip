@@ -49,7 +49,7 @@ __device__ __forceinline__ floatx16 mfma(bf16x8 a, bf16x8 b, floatx16 c) {
 
 __global__ void __launch_bounds__(64 * WAVES) k_fno_lift_dft(const float* __restrict__ x, const float* __restrict__ Wl,
                                                            const float* __restrict__ bl, const bf16* __restrict__ Fx,
-                                                           bf16* __restrict__ a0, float* __restrict__ T, long rows,
+                                                           bf16* __restrict__ a0, bf16* __restrict__ T, long rows,
                                                            int W) {
     // the row's input, 256 pixels at a time, staged by coalesced loads: each lane
     // then reads the eight pixels it lifts from LDS instead of eight dependent
@@ -99,11 +99,11 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_lift_dft(const float* __rest
         }
     }
     if (live) {
-        float* tr = T + rr * F2K * FC;
+        bf16* tr = T + rr * F2K * FC;
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) tr[(8 * r + 4 * g + v) * FC + c] = acc[4 * r + v];
+            for (int v = 0; v < 4; ++v) tr[(8 * r + 4 * g + v) * FC + c] = (bf16)acc[4 * r + v];
     }
 }
 
@@ -126,11 +126,11 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer(FnoLayerArgs p) {
     // B operand over the concatenated K: U rows (x-spectral input) then Wp
     bf16x8 bop[4];
     {
-        const float* u = p.U + rr * F2K * FC;
+        const bf16* u = p.U + rr * F2K * FC;
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
-            for (int v = 0; v < 8; ++v) bop[s][v] = (bf16)u[(16 * s + 8 * g + v) * FC + c];
+            for (int v = 0; v < 8; ++v) bop[s][v] = u[(16 * s + 8 * g + v) * FC + c];
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -236,11 +236,11 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer(FnoLayerArgs p) {
     }
     if constexpr (MODE == 0) {
         if (live) {
-            float* tr = p.Tn + rr * F2K * FC;
+            bf16* tr = p.Tn + rr * F2K * FC;
 #pragma unroll
             for (int r = 0; r < 4; ++r)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) tr[(8 * r + 4 * g + v) * FC + c] = tacc[4 * r + v];
+                for (int v = 0; v < 4; ++v) tr[(8 * r + 4 * g + v) * FC + c] = (bf16)tacc[4 * r + v];
         }
     }
 }
@@ -272,7 +272,7 @@ hipError_t launch_fno_w2_operands(const bf16* W2, bf16* W2P, int P, hipStream_t 
 
 bool fno_fused_ok(int C, int K, int W, int P) { return C == FC && 2 * K == F2K && W % 32 == 0 && P % 32 == 0; }
 
-hipError_t launch_fno_lift_dft(const float* x, const float* Wl, const float* bl, const bf16* Fx, bf16* a0, float* T,
+hipError_t launch_fno_lift_dft(const float* x, const float* Wl, const float* bl, const bf16* Fx, bf16* a0, bf16* T,
                                long rows, int W, hipStream_t s) {
     hipLaunchKernelGGL(k_fno_lift_dft, dim3((unsigned)((rows + WAVES - 1) / WAVES)), dim3(64 * WAVES), 0, s, x, Wl, bl,
                        Fx, a0, T, rows, W);

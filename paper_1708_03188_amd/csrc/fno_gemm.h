@@ -14,6 +14,7 @@ struct GemmDesc {
     long sCb, sCm, sCn;  // element strides of C(b, m, n)
     float alpha, beta;
     int a_f32, b_f32;    // operand element type: 1 = float (rounded to bf16 on load), 0 = bf16
+    int c_bf16;          // 1: C is bf16 storage, written rounded (needs beta = 0, splitk = 1)
     int splitk;          // > 1: K is split over blocks and the partial sums are added
                          // atomically into C (C must hold beta * C beforehand)
     int a_vec, b_vec;    // set by gemm(): staging along the contiguous dimension

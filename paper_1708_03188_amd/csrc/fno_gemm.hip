@@ -131,8 +131,12 @@ __global__ void __launch_bounds__(256) k_gemm(GemmDesc d) {
         for (int v = 0; v < 4; ++v) {
             const int row = m0 + wm + 8 * r + 4 * (lane >> 5) + v;
             if (row >= d.M) continue;
-            float* cp = d.C + coff + (long)row * d.sCm;
             const float val = d.alpha * acc[4 * r + v];
+            if (d.c_bf16) {
+                reinterpret_cast<__bf16*>(d.C)[coff + (long)row * d.sCm] = (__bf16)val;
+                continue;
+            }
+            float* cp = d.C + coff + (long)row * d.sCm;
             if (d.splitk > 1) atomicAdd(cp, val);
             else *cp = d.beta == 0.f ? val : val + d.beta * *cp;
         }
@@ -140,6 +144,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmDesc d) {
 
 hipError_t gemm(const GemmDesc& d, hipStream_t s) {
     if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
+    if (d.c_bf16 && (d.beta != 0.f || d.splitk > 1)) return hipErrorInvalidValue;
     const long tiles = (long)((d.M + GBM - 1) / GBM) * ((d.N + GBN - 1) / GBN) * d.batch * (d.splitk > 1 ? d.splitk : 1);
     GemmDesc e = d;
     if (e.splitk < 1) e.splitk = 1;
