@@ -109,10 +109,13 @@ __global__ void k_colsum(const T* g, float* db, long P, int C) {
 }
 
 // X[b][part][j][kx][c] -> Xm[(j, kx)][b][part][c]   (and back when inv)
-// One thread per V consecutive channels (V = 4 when C % 4 == 0: 16-byte moves),
-// index arithmetic in 32 bits (the host keeps the element count below 2^31).
-__global__ void k_perm_modes(const float* in, float* out, int B, int KY, int KX, int C, int inv) {
-    const unsigned V = (C & 3) == 0 ? 4u : 1u;
+// One thread per V consecutive channels (V = 16 bytes of elements when C is a
+// multiple of that: 16-byte moves, else 1), index arithmetic in 32 bits (the
+// host keeps the element count below 2^31).
+template <typename T>
+__global__ void k_perm_modes(const T* in, T* out, int B, int KY, int KX, int C, int inv) {
+    constexpr unsigned VMAX = 16 / sizeof(T);
+    const unsigned V = (unsigned)C % VMAX == 0 ? VMAX : 1u;
     const unsigned CV = (unsigned)C / V;
     const unsigned n = (unsigned)B * 2u * (unsigned)KY * (unsigned)KX * CV;
     const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -125,9 +128,9 @@ __global__ void k_perm_modes(const float* in, float* out, int B, int KY, int KX,
     const unsigned part = t & 1u, b = t >> 1;
     const long a = (long)i * V;
     const long o = ((long)((j * (unsigned)KX + kx) * (unsigned)B + b) * 2 + part) * C + cv * V;
-    if (V == 4) {
-        if (inv) *reinterpret_cast<float4*>(out + a) = *reinterpret_cast<const float4*>(in + o);
-        else *reinterpret_cast<float4*>(out + o) = *reinterpret_cast<const float4*>(in + a);
+    if (V == VMAX) {
+        if (inv) *reinterpret_cast<uint4*>(out + a) = *reinterpret_cast<const uint4*>(in + o);
+        else *reinterpret_cast<uint4*>(out + o) = *reinterpret_cast<const uint4*>(in + a);
     } else {
         if (inv) out[a] = in[o];
         else out[o] = in[a];
@@ -206,8 +209,12 @@ __global__ void k_x_to_c128(const float* x, double2* u, long n) {
 }
 
 static inline unsigned nblk(long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
-// threads of k_perm_modes over B x 2 x 2K x K x C values
-static inline long perm_threads(long B, long K, long C) { return B * 4 * K * K * C / ((C & 3) == 0 ? 4 : 1); }
+// threads of k_perm_modes<T> over B x 2 x 2K x K x C values
+template <typename T>
+static inline long perm_threads(long B, long K, long C) {
+    const long v = 16 / (long)sizeof(T);
+    return B * 4 * K * K * C / (C % v == 0 ? v : 1);
+}
 
 }  // namespace sgm
 
@@ -488,20 +495,29 @@ static sgm_status fno_forward(sgm_fno f, const float* x, int B, hipStream_t s, f
             SGM_HIP_TRY(gemm(G(B * H, 2 * K, C, W, f->Fx, 0, W, 1, 0, a, (long)W * C, C, 1, 0, f->T, 2L * K * C, C, 1), s));
         // G2: X[b] (4K x K C) = Fy_real (4K x 2H) T[b] (2H x K C).  The fused kernels keep T and U
         // in bf16: both consumers round them to bf16 anyway, so the values are the same.
-        SGM_HIP_TRY(gemm(G(B, 4 * K, K * C, 2 * H, f->Fy, 0, 2L * H, 1, 0, f->T, 2L * H * K * C, (long)K * C, 1,
-                           fused ? 0 : 1, f->X, 4L * K * K * C, (long)K * C, 1), s));
-        float* Xm = f->Xm + (long)l * NM * f->Bmax * 2 * C;
-        hipLaunchKernelGGL(k_perm_modes, dim3(nblk(perm_threads(B, K, C))), dim3(256), 0, s, (const float*)f->X, Xm,
-                           B, 2 * K, K, C, 0);
+        // X, Xm, Ym and Yt are bf16 too: each is only a GEMM operand downstream (or moved by the
+        // permutation), and the GEMM rounds its operands to bf16.
+        {
+            GemmDesc g2 = G(B, 4 * K, K * C, 2 * H, f->Fy, 0, 2L * H, 1, 0, f->T, 2L * H * K * C, (long)K * C, 1,
+                            fused ? 0 : 1, f->X, 4L * K * K * C, (long)K * C, 1);
+            g2.c_bf16 = 1;
+            SGM_HIP_TRY(gemm(g2, s));
+        }
+        bf16* Xm = reinterpret_cast<bf16*>(f->Xm) + (long)l * NM * f->Bmax * 2 * C;
+        hipLaunchKernelGGL(k_perm_modes<bf16>, dim3(nblk(perm_threads<bf16>(B, K, C))), dim3(256), 0, s,
+                           reinterpret_cast<const bf16*>(f->X), Xm, B, 2 * K, K, C, 0);
         // G3: Ym[m] (B x 2C) = Xm[m] (B x 2C) Rreal[m] (2C x 2C)
-        SGM_HIP_TRY(gemm(G(NM, B, 2 * C, 2 * C, Xm, (long)B * 2 * C, 2 * C, 1, 1,
-                           f->Rreal + (long)l * NM * 4 * C * C, 4L * C * C, 2 * C, 1, 0, f->Ym, (long)B * 2 * C, 2 * C, 1),
-                         s));
-        hipLaunchKernelGGL(k_perm_modes, dim3(nblk(perm_threads(B, K, C))), dim3(256), 0, s, (const float*)f->Ym, f->Yt,
-                           B, 2 * K, K, C, 1);
+        {
+            GemmDesc g3 = G(NM, B, 2 * C, 2 * C, Xm, (long)B * 2 * C, 2 * C, 1, 0, f->Rreal + (long)l * NM * 4 * C * C,
+                            4L * C * C, 2 * C, 1, 0, f->Ym, (long)B * 2 * C, 2 * C, 1);
+            g3.c_bf16 = 1;
+            SGM_HIP_TRY(gemm(g3, s));
+        }
+        hipLaunchKernelGGL(k_perm_modes<bf16>, dim3(nblk(perm_threads<bf16>(B, K, C))), dim3(256), 0, s,
+                           reinterpret_cast<const bf16*>(f->Ym), reinterpret_cast<bf16*>(f->Yt), B, 2 * K, K, C, 1);
         // G4: U[b] (2H x K C) = Gy_real (2H x 4K) Yt[b] (4K x K C)   (U reuses T)
         {
-            GemmDesc g4 = G(B, 2 * H, K * C, 4 * K, f->Gy, 0, 4L * K, 1, 0, f->Yt, 4L * K * K * C, (long)K * C, 1, 1, f->T,
+            GemmDesc g4 = G(B, 2 * H, K * C, 4 * K, f->Gy, 0, 4L * K, 1, 0, f->Yt, 4L * K * K * C, (long)K * C, 1, 0, f->T,
                             2L * H * K * C, (long)K * C, 1);
             g4.c_bf16 = fused ? 1 : 0;
             SGM_HIP_TRY(gemm(g4, s));
@@ -599,19 +615,19 @@ static sgm_status fno_backward(sgm_fno f, const float* x, int B, hipStream_t s) 
         // gYt[b] (4K x K C) = Gy_real^T (4K x 2H) gU[b] (2H x K C)
         SGM_HIP_TRY(gemm(G(B, 4 * K, K * C, 2 * H, f->Gy, 0, 1, 4L * K, 0, f->T, 2L * H * K * C, (long)K * C, 1, 1, f->Yt,
                            4L * K * K * C, (long)K * C, 1), s));
-        hipLaunchKernelGGL(k_perm_modes, dim3(nblk((long)B * 4 * K * K * C)), dim3(256), 0, s, (const float*)f->Yt, f->Ym,
-                           B, 2 * K, K, C, 0);
-        // dRreal[m] (2C x 2C) = Xm[m]^T (2C x B) gYm[m] (B x 2C)
-        const float* Xm = f->Xm + (long)l * NM * f->Bmax * 2 * C;
-        SGM_HIP_TRY(gemm(G(NM, 2 * C, 2 * C, B, Xm, (long)B * 2 * C, 1, 2 * C, 1, f->Ym, (long)B * 2 * C, 2 * C, 1, 1, f->Rg,
+        hipLaunchKernelGGL(k_perm_modes<float>, dim3(nblk(perm_threads<float>(B, K, C))), dim3(256), 0, s,
+                           (const float*)f->Yt, f->Ym, B, 2 * K, K, C, 0);
+        // dRreal[m] (2C x 2C) = Xm[m]^T (2C x B) gYm[m] (B x 2C)   (Xm saved in bf16 by the forward pass)
+        const bf16* Xm = reinterpret_cast<const bf16*>(f->Xm) + (long)l * NM * f->Bmax * 2 * C;
+        SGM_HIP_TRY(gemm(G(NM, 2 * C, 2 * C, B, Xm, (long)B * 2 * C, 1, 2 * C, 0, f->Ym, (long)B * 2 * C, 2 * C, 1, 1, f->Rg,
                            4L * C * C, 2 * C, 1), s));
         hipLaunchKernelGGL(k_fold_rgrad, dim3(nblk((long)NM * C * C)), dim3(256), 0, s, (const float*)f->Rg,
                            f->grad + f->oRr[l], f->grad + f->oRi[l], NM, C);
         // gXm[m] (B x 2C) = gYm[m] (B x 2C) Rreal[m]^T   (into the X buffer, mode-major)
         SGM_HIP_TRY(gemm(G(NM, B, 2 * C, 2 * C, f->Ym, (long)B * 2 * C, 2 * C, 1, 1, f->Rreal + (long)l * NM * 4 * C * C,
                            4L * C * C, 1, 2 * C, 0, f->X, (long)B * 2 * C, 2 * C, 1), s));
-        hipLaunchKernelGGL(k_perm_modes, dim3(nblk((long)B * 4 * K * K * C)), dim3(256), 0, s, (const float*)f->X, f->Yt,
-                           B, 2 * K, K, C, 1);
+        hipLaunchKernelGGL(k_perm_modes<float>, dim3(nblk(perm_threads<float>(B, K, C))), dim3(256), 0, s,
+                           (const float*)f->X, f->Yt, B, 2 * K, K, C, 1);
         // gT[b] (2H x K C) = Fy_real^T (2H x 4K) gX[b] (4K x K C)
         SGM_HIP_TRY(gemm(G(B, 2 * H, K * C, 4 * K, f->Fy, 0, 1, 2L * H, 0, f->Yt, 4L * K * K * C, (long)K * C, 1, 1, f->T,
                            2L * H * K * C, (long)K * C, 1), s));
