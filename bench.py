@@ -5,11 +5,13 @@ Fourier 256 x 256 (R2C) along y, z, float64, a seeded smooth random field
 (synthetic; no dataset).  One step = one forward transform (Fourier R2C + C2C,
 DCT-II, Shen projection) plus one backward transform of the whole field;
 value = N*M1*M2 / (t_fwd + t_bwd) in Gdof/s.  Also reported: full 3D
-Helmholtz solves per second (solve kernel alone and the Poisson pipeline
-scalar product -> solve -> backward), the dominant kernel's roofline
-fraction from hipEvents around that kernel inside the timed steps (the
-per-pass breakdown comes from the warm-up steps), and the CPU oracle on a
-bounded sample.
+Helmholtz solves per second (solve kernel alone, alpha = 0 and 1, and the
+Poisson pipeline scalar product -> solve -> backward), the roofline fraction
+of the transform pair on its compulsory bytes (and of the dominant pass
+kernel, from hipEvents around that kernel inside the timed steps; the
+per-pass breakdown comes from the warm-up steps), the 2D Poisson latency,
+the biharmonic, ragged Ginzburg-Landau and surrogate legs, and the CPU
+oracle on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -25,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 
 
 def parse():
@@ -100,6 +103,49 @@ def measured_traffic(pass_name, variants, L):
             cells = [c.strip() for c in line.split("|")]
             return float(cells[4]) * 1e6
     return None
+
+
+def stored_step_traffic(variants, L):
+    """HBM bytes of one forward + backward step: the six passes' counter figures, or
+    None where any is missing or stale."""
+    tot = 0.0
+    for k in ("last_fwd", "mid_fwd", "cheb_fwd", "cheb_bwd", "mid_bwd", "last_bwd"):
+        t = measured_traffic(k, variants, L)
+        if t is None:
+            return None
+        tot += t
+    return tot
+
+
+def leg_poisson2d():
+    """2D Poisson, Shen-Dirichlet N = 32 x Fourier R2C M = 32 (the manufactured
+    problem): microseconds per call, latency-bound (8 KB of data)."""
+    import torch
+    import synth
+    from paper_1708_03188_amd.api import Plan
+    _, _, u0, f0 = synth.poisson2d_manufactured(32, 32, seed=1)
+    p = Plan("dirichlet", 32, 32)
+    u = torch.from_numpy(u0).cuda()
+    f = torch.from_numpy(f0).cuda()
+    uh = torch.empty(p.spec_shape, dtype=torch.complex128, device="cuda")
+    v = torch.empty_like(u)
+    calls = {"forward": lambda: p.forward(u, out=uh), "backward": lambda: p.backward(uh, out=v),
+             "scalar_product": lambda: p.scalar_product(f, out=uh),
+             "helmholtz_solve": lambda: p.helmholtz_solve(uh, 0.0, out=uh),
+             "poisson_f_to_u": lambda: (p.helmholtz_solve_physical(f, 0.0, out=uh), p.backward(uh, out=v))}
+    res = {"workload": "2D Poisson, Shen-Dirichlet N=32 x Fourier R2C M=32, float64"}
+    for name, fn in calls.items():
+        back_to_back = _timed(fn, 200) * 1e3
+        lat = []
+        for _ in range(50):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t0) * 1e6)
+        res[name] = {"us_per_call_back_to_back": round(back_to_back, 2),
+                     "us_per_call_synchronised_median": round(float(np.median(lat)), 2)}
+    return res
 
 
 def pass_kernel_name(pass_name, variants, L):
@@ -205,10 +251,26 @@ def leg_gl(steps):
     # compulsory bytes per IF-RK4 step: 7 state-sized reads and 4 writes of 16 B
     # (state, accumulator) per retained mode
     comp = 176 * modes
+    flop = gl_step_flop(sizes)
     return {"workload": "64 ragged complex GL problems (N_i = 128,192,256,384,512), IF-RK4 dt=0.05, 3/2 rule",
             "batch_steps_per_s": round(1e3 / ms, 1), "ms_per_step": round(ms, 4),
             "problem_steps_per_s": round(64 * 1e3 / ms, 1), "launch_variant": g.variant,
-            "compulsory_hbm_frac": round(comp / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            "compulsory_hbm_frac": round(comp / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "fp64_flop_per_step": flop,
+            "fp64_TFLOPs": round(flop / (ms * 1e-3) / 1e12, 3),
+            "fp64_frac": round(flop / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
+
+
+def gl_step_flop(sizes):
+    """Algorithmic FP64 flops of one IF-RK4 step: 4 stages x (padded backward + padded
+    forward) 2D transforms of M x M (M = floor(3N/2)), each 2 M line FFTs of
+    5 M log2 M flops (the usual radix-2 count)."""
+    import math
+    tot = 0.0
+    for n in sizes:
+        m = (3 * n) // 2
+        tot += 8 * 2 * m * 5 * m * math.log2(m)
+    return float(tot)
 
 
 SURROGATE_WEIGHTS = os.path.join(ROOT, "paper_1708_03188_amd", "weights", "fno_gl256.npz")
@@ -248,23 +310,46 @@ def leg_surrogate():
     u = gl.forward(gl.pack([synth.gl_noise(N, 9000 + i) for i in range(B)]))
     gl.step(u, 200)
     ms_plain = _timed(lambda: gl.step(u, stride), 5) / stride
-    stats = {}
-    ms_sur = _timed(lambda: stats.update(f.advance_checked(gl, glc, u, 1, stride, tol=1e-2, seed=1)), 5) / stride
+    ref = GLBatch([N] * B, L=L, b=b, c=c, dt=dt, scheme="ifrk4", tune=True)
+
+    def policy(frac, seed):
+        """Time the checked advance under one acceptance policy, then measure every
+        state of one more macro-step against the FP64 solver run from the same start."""
+        st = {}
+        ms = _timed(lambda: st.update(f.advance_checked(gl, glc, u, 1, stride, tol=1e-2, seed=seed,
+                                                        max_fail_frac=frac)), 5) / stride
+        u0 = u.clone()
+        one = f.advance_checked(gl, glc, u, 1, stride, tol=1e-2, seed=seed + 1, max_fail_frac=frac)
+        ref.step(u0, stride)
+        pu, pr = gl.backward(u), ref.backward(u0)
+        e = (torch.linalg.vector_norm((pu - pr).reshape(B, -1), dim=1) /
+             torch.linalg.vector_norm(pr.reshape(B, -1), dim=1)).cpu().numpy()
+        return ms, {"problem_steps_per_s": round(B * 1e3 / ms, 1), "speedup": round(ms_plain / ms, 3),
+                    "max_fail_frac": frac, "last_call_checks": st, "measured_call_checks": one,
+                    "all_state_rel_l2_mean": round(float(e.mean()), 6),
+                    "all_state_rel_l2_max": round(float(e.max()), 6),
+                    "all_states_within_tol": int((e <= 1e-2).sum())}
+
+    ms_sur, strict = policy(0.0, 1)
+    _, per_sample = policy(1.0, 11)
     xin = test_data[:-1].reshape(-1, N, N, 2)
     xin = xin.repeat((B + xin.shape[0] - 1) // xin.shape[0], 1, 1, 1)[:B].contiguous()
     ms_infer = _timed(lambda: f.infer(xin), 5)
     return {"workload": "GL 256^2 (L=100, b=1.5, c=-2, dt=0.05), FNO width 32, 16x16 modes, 4 layers, bf16 MFMA / "
                         f"fp32 accumulate, one surrogate step = 10 solver steps; {B} states, {NC} re-advanced by the "
-                        "FP64 solver per surrogate step (fallback above rel. L2 1e-2)",
+                        "FP64 solver per surrogate step; fallback above rel. L2 1e-2: the whole batch is re-advanced "
+                        "by the FP64 solver when any checked state fails (speed-up counts it)",
             "weights": "paper_1708_03188_amd/weights/fno_gl256.npz" if have_weights else "trained in the leg (600 steps)",
             "plain_problem_steps_per_s": round(B * 1e3 / ms_plain, 1),
             "surrogate_problem_steps_per_s": round(B * 1e3 / ms_sur, 1),
             "speedup": round(ms_plain / ms_sur, 3),
+            "strict_policy": strict,
+            "per_sample_policy": per_sample,
             "surrogate_infer_samples_per_s": round(xin.shape[0] * 1e3 / ms_infer, 1),
             "heldout_rel_l2_mean": round(mean, 5), "heldout_rel_l2_max": round(mx, 5),
             "heldout": "16 trajectories x 8 snapshot pairs, seeds disjoint from training",
             "persistence_rel_l2_mean": round(ident, 4),
-            "check_fraction": NC / B, "last_call_checks": stats,
+            "check_fraction": NC / B,
             "train_samples_per_s": round(200 * 16 / t_train, 1), "data_gen_s": round(t_gen, 2)}
 
 
@@ -326,6 +411,15 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     ms_solve = e0.elapsed_time(e1) / ks
+    for _ in range(3):
+        p.helmholtz_solve(ft, 1.0, out=sol)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(ks):
+        p.helmholtz_solve(ft, 1.0, out=sol)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_solve_a1 = e0.elapsed_time(e1) / ks
     e0.record()
     for _ in range(ks):
         p.scalar_product(u, out=ft)
@@ -360,6 +454,10 @@ def main():
                     "GBps": nbytes[k] / (t / c * 1e-3) / 1e9} for k, (t, c) in times_all.items()}
     avg_s = times[dom][0] / times[dom][1] * 1e-3
     achieved = nbytes[dom] / avg_s / 1e9
+    # compulsory bytes of the transform pair (read u, write u_hat; read u_hat, write u)
+    pair_bytes = 2 * dof * 8 + 2 * N * M1 * (M2 // 2 + 1) * 16
+    pair_gbs = pair_bytes / (ms * 1e-3) / 1e9
+    pair_traffic = stored_step_traffic(p.variants(), N)
     out = {
         "metric": "FP64 fwd+bwd transform Gdof/s; Poisson solves/s; GL steps/s surrogate vs plain",
         "value": round(gdofs, 3),
@@ -376,17 +474,28 @@ def main():
         "config": {"workload": "3D Poisson/Helmholtz space, Shen-Dirichlet N=256 x Fourier 256x256 R2C, "
                                "float64; step = forward + backward transform",
                    "N": N, "M1": M1, "M2": M2, "basis": "shen_dirichlet", "kind_last": "r2c"},
-        "roofline": {"bound": "hbm", "kernel": dom, "kernel_name": pass_kernel_name(dom, p.variants(), N),
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(dom, p.variants(), N), "algorithmic_bytes": nbytes[dom]},
+        "roofline": {"bound": "hbm", "kernel": "transform pair (forward + backward, 6 passes)",
+                     "achieved": round(pair_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(pair_gbs / HBM_PEAK_GBS, 4), "traffic": pair_traffic,
+                     "traffic_source": "stored counters (profiles/traffic_256cube_dirichlet.md, matched by kernel-"
+                                       "source hash): sum over the six passes of one step" if pair_traffic else None,
+                     "algorithmic_bytes": pair_bytes,
+                     "dominant_pass": {"pass": dom, "kernel_name": pass_kernel_name(dom, p.variants(), N),
+                                       "achieved": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                       "avg_us": round(avg_s * 1e6, 2), "algorithmic_bytes": nbytes[dom],
+                                       "traffic": measured_traffic(dom, p.variants(), N),
+                                       "traffic_source": "stored counters" if measured_traffic(dom, p.variants(), N)
+                                       else None}},
         "plan_variants_xyz": p.variants(),
         "passes_warmup": {k: {kk: round(vv, 2) for kk, vv in d.items()} for k, d in per_pass.items()},
         "helmholtz_solves_per_s": round(1e3 / ms_solve, 1),
+        "helmholtz_alpha1_solves_per_s": round(1e3 / ms_solve_a1, 1),
+        "helmholtz_hbm_frac": round(nbytes["solve"] / (ms_solve * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "poisson_pipeline_solves_per_s": round(1e3 / ms_poisson, 1),
         "poisson_pipeline_separate_calls_solves_per_s": round(1e3 / ms_poisson_calls, 1),
         "transform_pair_algorithmic_GBps": round((2 * dof * 8 + 2 * N * M1 * (M2 // 2 + 1) * 16) / (ms * 1e-3) / 1e9, 1),
     }
+    out["poisson2d_32x32"] = leg_poisson2d()
     legs = set(args.legs.split(","))
     if "biharmonic" in legs:
         out["biharmonic_512x256x256"] = leg_biharmonic(args.steps)

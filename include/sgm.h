@@ -257,22 +257,34 @@ sgm_status sgm_fno_unpack(const float* x, void* u_c128, int64_t n, void* stream)
  * FNO grid); u_hat is its packed spectral state, advanced in place by nsur
  * macro-steps of the surrogate, each standing for steps_per solver steps of gl's dt
  * (the network must have been trained for that stride).  Per macro-step a seeded
- * subset of `gl_check`->count samples (evenly spaced, random offset) is also
- * advanced by the FP64 solver `gl_check` (same N, L, b, c, dt); a checked sample
- * whose relative L2 error ||pred - solver|| / ||solver|| (physical fields) exceeds
- * tol is replaced by the solver's result.  stats (may be NULL) accumulates over
- * the call.  Workspace for B samples is allocated on the first call (and when B
- * grows).  The FP64 checks run on a private second stream of the library
- * (default priority), overlapped with the inference, and are joined to `stream`
- * before the comparison.  Synchronises the stream once per macro-step. */
+ * subset of NC = `gl_check`->count samples (evenly spaced, random offset; 1 <= NC <= B)
+ * is also advanced by the FP64 solver `gl_check` (same N, L, b, c, dt) and judges the
+ * surrogate by the relative L2 error ||pred - solver|| / ||solver|| of the physical
+ * fields.  Acceptance, per macro-step:
+ *   - more than max_fail_frac * NC checked samples above tol: the checks are taken as
+ *     evidence that the unchecked samples fail too, and the FP64 solver `gl` advances
+ *     the whole batch from the macro-step's starting state (the surrogate's prediction
+ *     is discarded); max_fail_frac = 0 re-advances on any failed check;
+ *   - otherwise every sample takes the surrogate's prediction except the failed
+ *     checked ones, which take the checking solver's result.
+ * max_fail_frac in [0, 1], else INVALID_ARG.  stats (may be NULL) accumulates into
+ * the caller's struct (zero it before the first call).  The workspace (about
+ * B H W 32 + NC H W 48 bytes) is allocated on the first call and re-allocated,
+ * after a device synchronisation, whenever a call needs more.  The FP64 checks run
+ * on a private second stream of the library (default priority), created on the
+ * first call and overlapped with the inference; they are joined to `stream` before
+ * the comparison.  Synchronises the stream once per macro-step. */
 typedef struct {
-    int n_checked;     /* samples checked by the solver        */
-    int n_fallback;    /* checked samples replaced             */
-    float max_rel_l2;  /* largest checked relative L2 error    */
-    float mean_rel_l2; /* mean checked relative L2 error       */
+    int n_checked;        /* samples checked by the solver                              */
+    int n_fallback;       /* checked samples above tol                                  */
+    float max_rel_l2;     /* largest checked relative L2 error                          */
+    float mean_rel_l2;    /* mean checked relative L2 error                             */
+    int n_batch_fallback; /* macro-steps in which the FP64 solver advanced every sample */
+    int n_replaced;       /* samples whose new state came from an FP64 solver           */
 } sgm_fno_stats;
 sgm_status sgm_fno_advance_checked(sgm_fno f, sgm_gl gl, sgm_gl gl_check, void* u_hat, int nsur, int steps_per,
-                                   double tol, uint64_t seed, sgm_fno_stats* stats, void* stream);
+                                   double tol, double max_fail_frac, uint64_t seed, sgm_fno_stats* stats,
+                                   void* stream);
 
 const char* sgm_status_string(sgm_status s);
 const char* sgm_last_error(void);

@@ -10,6 +10,8 @@ Each phase exp(+-2 pi i l j / M) is computed from the exactly reduced integer
 (l*j) mod M, so no phase error grows with l*j.  The sums are matrix products
 with those exact-phase DFT matrices.
 """
+from functools import lru_cache
+
 import numpy as np
 
 # 2 pi to the full x87 extended precision
@@ -86,12 +88,7 @@ def padded_backward(uh, Mp, axes=(0, 1)):
     u_p(x_j) = sum_{l retained} u_hat_l exp(i l 2 pi j / Mp)."""
     out = np.asarray(uh, dtype=np.complex128)
     for ax in axes:
-        N = out.shape[ax]
-        l = wavenumbers(N)
-        r = np.mod(np.outer(np.arange(Mp), l), Mp).astype(np.longdouble)
-        ang = TWO_PI_LD * r / Mp
-        E = (np.cos(ang) + 1j * np.sin(ang)).astype(np.complex128)   # Mp x N
-        out = _apply(E, out, ax)
+        out = _apply(_padded_matrix(Mp, out.shape[ax], +1), out, ax)
     return out
 
 
@@ -101,9 +98,20 @@ def padded_forward_truncate(w, N, axes=(0, 1)):
     out = np.asarray(w, dtype=np.complex128)
     for ax in axes:
         Mp = out.shape[ax]
-        l = wavenumbers(N)
-        r = np.mod(np.outer(l, np.arange(Mp)), Mp).astype(np.longdouble)
-        ang = -TWO_PI_LD * r / Mp
-        E = (np.cos(ang) + 1j * np.sin(ang)).astype(np.complex128)   # N x Mp
-        out = _apply(E, out, ax) / Mp
+        out = _apply(_padded_matrix(Mp, N, -1), out, ax) / Mp
     return out
+
+
+@lru_cache(maxsize=64)
+def _padded_matrix(Mp, N, sign):
+    """Exact-phase matrix between the N retained wavenumbers l and the Mp fine
+    grid points j: exp(+i l 2 pi j / Mp) as Mp x N (sign +1, padded backward) or
+    exp(-i l 2 pi j / Mp) as N x Mp (sign -1, forward before truncation).  Kept
+    per size (read-only), since every Runge-Kutta stage uses the same ones."""
+    l = wavenumbers(N)
+    j = np.arange(Mp)
+    r = np.mod(np.outer(j, l) if sign > 0 else np.outer(l, j), Mp).astype(np.longdouble)
+    ang = sign * TWO_PI_LD * r / Mp
+    E = (np.cos(ang) + 1j * np.sin(ang)).astype(np.complex128)
+    E.setflags(write=False)
+    return E

@@ -37,7 +37,7 @@ class FNODesc(ctypes.Structure):
 
 class FNOStats(ctypes.Structure):
     _fields_ = [("n_checked", ctypes.c_int), ("n_fallback", ctypes.c_int), ("max_rel_l2", ctypes.c_float),
-                ("mean_rel_l2", ctypes.c_float)]
+                ("mean_rel_l2", ctypes.c_float), ("n_batch_fallback", ctypes.c_int), ("n_replaced", ctypes.c_int)]
 
 
 SGM_RK4, SGM_IFRK4 = 1, 2
@@ -64,8 +64,8 @@ _SIGS = {
     "sgm_gl_offsets": ([_vp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "sgm_gl_count": ([_vp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "sgm_gl_variant": ([_vp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
-    "sgm_fno_advance_checked": ([_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_uint64,
-                                 _vp, _vp], ctypes.c_int),
+    "sgm_fno_advance_checked": ([_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_uint64, _vp, _vp], ctypes.c_int),
     "sgm_gl_forward": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "sgm_gl_backward": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "sgm_gl_rhs": ([_vp, _vp, _vp, _vp], ctypes.c_int),

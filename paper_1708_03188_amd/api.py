@@ -318,16 +318,20 @@ class FNO:
               "sgm_fno_rel_l2")
         return out
 
-    def advance_checked(self, gl, gl_check, u_hat, nsur, steps_per, tol=1e-2, seed=0):
+    def advance_checked(self, gl, gl_check, u_hat, nsur, steps_per, tol=1e-2, seed=0, max_fail_frac=0.0):
         """Advance the packed GL state u_hat by nsur surrogate macro-steps with the FP64
-        check/fallback on gl_check.count samples per macro-step; returns the stats dict."""
+        check/fallback on gl_check.count samples per macro-step (the whole batch is
+        re-advanced by the FP64 solver when more than max_fail_frac of the checks
+        fail); returns the stats dict."""
         gl._vec(u_hat, "u_hat")
-        st = _lib.FNOStats(0, 0, 0.0, 0.0)
+        st = _lib.FNOStats(0, 0, 0.0, 0.0, 0, 0)
         check(self._lib.sgm_fno_advance_checked(self._h, gl._h, gl_check._h, _ptr(u_hat), int(nsur), int(steps_per),
-                                                float(tol), ctypes.c_uint64(seed), ctypes.byref(st), _stream()),
+                                                float(tol), float(max_fail_frac), ctypes.c_uint64(seed),
+                                                ctypes.byref(st), _stream()),
               "sgm_fno_advance_checked")
         return {"n_checked": st.n_checked, "n_fallback": st.n_fallback, "max_rel_l2": st.max_rel_l2,
-                "mean_rel_l2": st.mean_rel_l2}
+                "mean_rel_l2": st.mean_rel_l2, "n_batch_fallback": st.n_batch_fallback,
+                "n_replaced": st.n_replaced}
 
     def save(self, path):
         check(self._lib.sgm_fno_save(self._h, str(path).encode()), "sgm_fno_save")

@@ -267,7 +267,7 @@ struct sgm_fno_s {
     float* rel = nullptr;   // Bmax
     void* all = nullptr;
     // advance_checked workspace (grown on demand)
-    long adv_cap = 0;       // samples
+    size_t adv_bytes = 0;   // bytes allocated at adv
     void* adv = nullptr;
     // second stream for the FP64 check path, overlapped with inference
     hipStream_t adv_stream = nullptr;
@@ -783,12 +783,23 @@ extern "C" sgm_status sgm_fno_unpack(const float* x, void* u_c128, int64_t n, vo
     return SGM_OK;
 }
 
+// Bytes of the advance_checked workspace for B states and NC checked states of HW
+// points: phys c128 [B HW], x and pred fp32 [B HW 2]; chk and chkp c128 [NC HW],
+// xs and ps fp32 [NC HW 2]; rel fp32 [NC] (each part a multiple of 256 bytes).
+static size_t adv_workspace_bytes(long B, long NC, long HW) {
+    auto up = [](size_t n) { return (n + 255) & ~(size_t)255; };
+    return up((size_t)B * HW * 16) + 2 * up((size_t)B * HW * 8) + 2 * up((size_t)NC * HW * 16) +
+           2 * up((size_t)NC * HW * 8) + up((size_t)NC * 4);
+}
+
 extern "C" sgm_status sgm_fno_advance_checked(sgm_fno f, sgm_gl gl, sgm_gl gl_check, void* u_hat, int nsur,
-                                              int steps_per, double tol, uint64_t seed, sgm_fno_stats* stats,
-                                              void* stream) {
+                                              int steps_per, double tol, double max_fail_frac, uint64_t seed,
+                                              sgm_fno_stats* stats, void* stream) {
     clear_error();
     SGM_CHECK_ARG(f && gl && gl_check && u_hat, "null argument");
     SGM_CHECK_ARG(nsur >= 0 && steps_per >= 1 && tol > 0, "invalid nsur / steps_per / tol");
+    SGM_CHECK_ARG(max_fail_frac >= 0.0 && max_fail_frac <= 1.0, "max_fail_frac must be in [0, 1] (got %g)",
+                  max_fail_frac);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const long HW = (long)f->H * f->W;
     // query the packed layout of both batches
@@ -809,15 +820,15 @@ extern "C" sgm_status sgm_fno_advance_checked(sgm_fno f, sgm_gl gl, sgm_gl gl_ch
     for (int i = 0; i < NC; ++i)
         SGM_CHECK_ARG(oc[i + 1] - oc[i] == HW, "problem %d of gl_check is not %d x %d", i, f->H, f->W);
     SGM_CHECK_ARG(NC >= 1 && NC <= B, "gl_check must hold between 1 and B problems");
-    // workspace: phys c128 [B HW], x fp32 [B HW 2], pred fp32 [B HW 2], chk c128 [NC HW] x2, xs fp32 [NC HW 2],
-    // ps fp32 [NC HW 2], rel [NC]
-    const long need = B;
-    if (f->adv_cap < need) {
+    const size_t need = adv_workspace_bytes(B, NC, HW);
+    if (f->adv_bytes < need) {
+        // the previous workspace may still be in use by queued work of an earlier call
+        if (f->adv) SGM_HIP_TRY(hipDeviceSynchronize());
         hipFree(f->adv);
         f->adv = nullptr;
-        size_t bytes = (size_t)B * HW * (16 + 8 + 8) + (size_t)NC * HW * (16 + 16 + 8 + 8) + 4096;
-        SGM_HIP_TRY(hipMalloc(&f->adv, bytes));
-        f->adv_cap = need;
+        f->adv_bytes = 0;
+        SGM_HIP_TRY(hipMalloc(&f->adv, need));
+        f->adv_bytes = need;
     }
     if (!f->adv_stream) {
         SGM_HIP_TRY(hipStreamCreateWithFlags(&f->adv_stream, hipStreamNonBlocking));
@@ -826,18 +837,24 @@ extern "C" sgm_status sgm_fno_advance_checked(sgm_fno f, sgm_gl gl, sgm_gl gl_ch
     }
     hipStream_t s2 = f->adv_stream;
     char* w = static_cast<char*>(f->adv);
-    double2* phys = reinterpret_cast<double2*>(w); w += (size_t)B * HW * 16;
-    float* x = reinterpret_cast<float*>(w); w += (size_t)B * HW * 8;
-    float* pred = reinterpret_cast<float*>(w); w += (size_t)B * HW * 8;
-    double2* chk = reinterpret_cast<double2*>(w); w += (size_t)NC * HW * 16;
-    double2* chkp = reinterpret_cast<double2*>(w); w += (size_t)NC * HW * 16;
-    float* xs = reinterpret_cast<float*>(w); w += (size_t)NC * HW * 8;
-    float* ps = reinterpret_cast<float*>(w); w += (size_t)NC * HW * 8;
-    float* reld = reinterpret_cast<float*>(w);
+    auto take = [&w](size_t n) {
+        char* p = w;
+        w += (n + 255) & ~(size_t)255;
+        return p;
+    };
+    double2* phys = reinterpret_cast<double2*>(take((size_t)B * HW * 16));
+    float* x = reinterpret_cast<float*>(take((size_t)B * HW * 8));
+    float* pred = reinterpret_cast<float*>(take((size_t)B * HW * 8));
+    double2* chk = reinterpret_cast<double2*>(take((size_t)NC * HW * 16));
+    double2* chkp = reinterpret_cast<double2*>(take((size_t)NC * HW * 16));
+    float* xs = reinterpret_cast<float*>(take((size_t)NC * HW * 8));
+    float* ps = reinterpret_cast<float*>(take((size_t)NC * HW * 8));
+    float* reld = reinterpret_cast<float*>(take((size_t)NC * 4));
     double2* uh = static_cast<double2*>(u_hat);
     std::mt19937_64 rng(seed);
     double sum_rel = 0;
-    int nchk_total = 0, nfb_total = 0;
+    int nchk_total = 0, nfb_total = 0, nbatch_total = 0;
+    long nrep_total = 0;
     float maxrel = 0.f;
     const int stride = B / NC;
     for (int it = 0; it < nsur; ++it) {
@@ -872,25 +889,42 @@ extern "C" sgm_status sgm_fno_advance_checked(sgm_fno f, sgm_gl gl, sgm_gl gl_ch
         std::vector<float> rel(NC);
         SGM_HIP_TRY(hipMemcpyAsync(rel.data(), reld, 4L * NC, hipMemcpyDeviceToHost, s));
         SGM_HIP_TRY(hipStreamSynchronize(s));
+        int nfail = 0;
+        for (int k = 0; k < NC; ++k) {
+            sum_rel += rel[k];
+            maxrel = std::max(maxrel, rel[k]);
+            if (!(rel[k] <= tol)) ++nfail;
+        }
+        nfb_total += nfail;
+        nchk_total += NC;
+        if ((double)nfail > max_fail_frac * NC) {
+            // too many checked states failed to trust the unchecked ones: u_hat still
+            // holds the macro-step's starting state, so the FP64 solver advances all of it
+            if ((r = sgm_gl_step(gl, uh, steps_per, s)) != SGM_OK) return r;
+            ++nbatch_total;
+            nrep_total += B;
+            continue;
+        }
         // new state: transform the surrogate's fields, then overwrite failed checks with the solver
         if ((r = sgm_fno_unpack(pred, phys, (int64_t)B * HW, s)) != SGM_OK) return r;
         if ((r = sgm_gl_forward(gl, phys, uh, s)) != SGM_OK) return r;
         for (int k = 0; k < NC; ++k) {
-            sum_rel += rel[k];
-            maxrel = std::max(maxrel, rel[k]);
             if (!(rel[k] <= tol)) {
-                ++nfb_total;
+                ++nrep_total;
                 SGM_HIP_TRY(hipMemcpyAsync(uh + (long)idx[k] * HW, chk + (long)k * HW, HW * 16, hipMemcpyDeviceToDevice,
                                            s));
             }
         }
-        nchk_total += NC;
     }
     if (stats) {
+        const int prev = stats->n_checked;
         stats->n_checked += nchk_total;
         stats->n_fallback += nfb_total;
+        stats->n_batch_fallback += nbatch_total;
+        stats->n_replaced += nrep_total;
         stats->max_rel_l2 = std::max(stats->max_rel_l2, maxrel);
-        stats->mean_rel_l2 = nchk_total ? (float)(sum_rel / nchk_total) : 0.f;
+        stats->mean_rel_l2 = stats->n_checked ? (float)((stats->mean_rel_l2 * (double)prev + sum_rel) / stats->n_checked)
+                                              : 0.f;
     }
     return SGM_OK;
 }

@@ -1,5 +1,7 @@
 """Pins for oracle.fno: finite-difference gradients, identity at zero output weights,
-the truncated DFT against numpy.fft, and bf16 rounding."""
+the truncated DFT against numpy.fft, the whole forward map on a case with a known
+answer (circular shift), the GELU against normal-distribution table values, and
+bf16 rounding."""
 import numpy as np
 import pytest
 
@@ -72,3 +74,39 @@ def test_bf16_rounding():
     r = fno.round_bf16(v)
     assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0 + 2 ** -7
     assert abs(r[3] - (-3.140625)) < 1e-12 and r[4] == 0.0
+
+
+@pytest.mark.parametrize("sy,sx", [(0, 0), (1, 2), (-2, 1)])
+def test_forward_with_shift_mixing_is_a_circular_shift(sy, sx):
+    # fno.forward itself, one spectral layer with every mode retained (H = 2K, odd
+    # W = 2K - 1) and mixing R[ky, kx] = exp(-2 pi i (ky sy / H + kx sx / W)) M: the
+    # spectral branch is then the input circularly shifted by (sy, sx) and mixed by
+    # M, so z = roll(a) M + a Wp + bp exactly.  The head is made the identity on z:
+    # gelu(t) = t for t >= 30 in binary64 (erf saturates), so W1 = I, b1 = 40,
+    # W2 = I, b2 = -40 gives out = z.  A wrong DFT sign, inverse weight or
+    # normalisation moves the shift or scales the result.
+    H, W, K, C = 6, 5, 3, 2
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal((2, H, W, 2))
+    M = rng.standard_normal((C, C))
+    ky = fno.ky_modes(H, K)
+    kx = np.arange(K)
+    ph = np.exp(-2j * np.pi * (np.outer(ky, np.ones(K)) * sy / H + np.outer(np.ones(2 * K), kx) * sx / W))
+    R = ph[:, :, None, None] * M[None, None]
+    p = {"Wl": rng.standard_normal((2, C)), "bl": rng.standard_normal(C),
+         "Rr0": R.real.copy(), "Ri0": R.imag.copy(),
+         "Wp0": rng.standard_normal((C, C)), "bp0": rng.standard_normal(C),
+         "W1": np.eye(C), "b1": np.full(C, 40.0), "W2": np.eye(C), "b2": np.full(2, -40.0)}
+    a = x @ p["Wl"] + p["bl"]
+    z = np.roll(a, (sy, sx), axis=(1, 2)) @ M + a @ p["Wp0"] + p["bp0"]
+    assert np.abs(z).max() < 10.0   # keeps z + 40 in the saturated range of erf
+    got = fno.forward(p, x, K)
+    assert np.abs(got - (x + z)).max() < 1e-12
+
+
+def test_gelu_at_normal_table_values():
+    # gelu(z) = z Phi(z); Phi(1) = 0.8413447460685429, Phi(2) = 0.9772498680518208,
+    # Phi(-1) = 0.15865525393145707 (standard normal distribution tables)
+    z = np.array([0.0, 1.0, 2.0, -1.0, 50.0, -50.0])
+    ref = np.array([0.0, 0.8413447460685429, 2 * 0.9772498680518208, -0.15865525393145707, 50.0, 0.0])
+    assert np.allclose(fno.gelu(z), ref, rtol=1e-15, atol=1e-300)
