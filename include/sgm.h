@@ -93,6 +93,17 @@ sgm_status sgm_forward(sgm_plan plan, const void* u, void* u_hat, void* stream);
  * the n = 0 and n = M/2 coefficients are ignored.  u_hat is not modified. */
 sgm_status sgm_backward(sgm_plan plan, const void* u_hat, void* u, void* stream);
 
+/* sgm_backward for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and result, but the x pass writes its intermediate into a library-owned
+ * static device array of 32 MiB (2^21 complex elements; one per device, held until
+ * the process ends) instead of the plan's workspace.  The call itself allocates
+ * nothing.  INVALID_ARG, before any device call, if the plan's spectral array has
+ * more than 2^21 complex elements (e.g. 3D spaces above about 128^3).  Every call on
+ * one device shares that array: calls that overlap on one device (any plan, any
+ * stream) race.  u_hat is not modified. */
+sgm_status sgm_backward_noalloc(sgm_plan plan, const void* u_hat, void* u, void* stream);
+
 /* Scalar product f_tilde_l = (f, phi_l)^N_w after the Fourier transforms
  * (Sec. 4, right-hand side formula; the (2 pi)^(d-1) factor is dropped on both
  * sides of every solve).  Same layouts as sgm_forward. */

@@ -53,6 +53,7 @@ _SIGS = {
     "sgm_plan_shapes": ([_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "sgm_forward": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "sgm_backward": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "sgm_backward_noalloc": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "sgm_scalar_product": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "sgm_helmholtz_solve": ([_vp, ctypes.c_double, _vp, _vp, _vp], ctypes.c_int),
     "sgm_helmholtz_solve_physical": ([_vp, ctypes.c_double, _vp, _vp, _vp], ctypes.c_int),

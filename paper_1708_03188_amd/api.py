@@ -105,6 +105,14 @@ class Plan:
         check(self._lib.sgm_backward(self._h, _ptr(uh), _ptr(out), _stream()), "sgm_backward")
         return out
 
+    def backward_noalloc(self, uh, out=None):
+        """backward() through the allocation-free entry point (static workspace)."""
+        _need(uh, torch.complex128, self.spec_shape, "u_hat")
+        out = self._out(out, self.phys_shape, self.phys_dtype, uh.device)
+        _need(out, self.phys_dtype, self.phys_shape, "u")
+        check(self._lib.sgm_backward_noalloc(self._h, _ptr(uh), _ptr(out), _stream()), "sgm_backward_noalloc")
+        return out
+
     def scalar_product(self, f, out=None):
         _need(f, self.phys_dtype, self.phys_shape, "f")
         out = self._out(out, self.spec_shape, torch.complex128, f.device)

@@ -55,6 +55,33 @@ static int max_lds_bytes() {
 
 using namespace sgm;
 
+// Workspace of sgm_backward_noalloc: the backward x pass writes its output here
+// instead of the plan's workspace.  One copy per device, kept until the process
+// ends; host code uses only the device address fetched by noalloc_scratch().
+static constexpr size_t kNoAllocScratchElems = ((size_t)32 << 20) / sizeof(double2);  // 32 MiB
+static __device__ __align__(256) double2 scratch[kNoAllocScratchElems];
+
+// Device address of `scratch` on the current device (looked up once per device).
+static sgm_status noalloc_scratch(double2** out) {
+    static std::mutex mu;
+    static std::map<int, double2*> addr;
+    int dev = 0;
+    SGM_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_error("hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+            return SGM_ERR_HIP;
+        }
+        it = addr.emplace(dev, static_cast<double2*>(ptr)).first;
+    }
+    *out = it->second;
+    return SGM_OK;
+}
+
 struct sgm_plan_s {
     sgm_plan_desc d;
     int N, M1, M2, ndim, r2c;
@@ -517,12 +544,9 @@ sgm_status sgm_scalar_product(sgm_plan p, const void* f, void* f_tilde, void* st
     return SGM_OK;
 }
 
-sgm_status sgm_backward(sgm_plan p, const void* u_hat, void* u, void* stream) {
-    clear_error();
-    SGM_CHECK_ARG(p && u && u_hat, "null argument");
-    SGM_CHECK_ARG(u != u_hat, "u and u_hat must not alias");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    double2* w = static_cast<double2*>(p->work);
+// Backward transform with the x pass writing into the spectral-sized workspace w
+// (the plan's own, or the allocation-free entry point's static one).
+static sgm_status backward_via(sgm_plan p, const void* u_hat, void* u, double2* w, hipStream_t s) {
     {
         PassTimer t(p, 6, s);
         if (p->hx)
@@ -533,6 +557,27 @@ sgm_status sgm_backward(sgm_plan p, const void* u_hat, void* u, void* stream) {
                                         p->rpx, s));
     }
     return fourier_backward(p, w, u, s);
+}
+
+sgm_status sgm_backward(sgm_plan p, const void* u_hat, void* u, void* stream) {
+    clear_error();
+    SGM_CHECK_ARG(p && u && u_hat, "null argument");
+    SGM_CHECK_ARG(u != u_hat, "u and u_hat must not alias");
+    return backward_via(p, u_hat, u, static_cast<double2*>(p->work), static_cast<hipStream_t>(stream));
+}
+
+sgm_status sgm_backward_noalloc(sgm_plan p, const void* u_hat, void* u, void* stream) {
+    clear_error();
+    SGM_CHECK_ARG(p && u && u_hat, "null argument");
+    SGM_CHECK_ARG(u != u_hat, "u and u_hat must not alias");
+    SGM_CHECK_ARG((size_t)p->nspec <= kNoAllocScratchElems,
+                  "spectral array of %lld complex elements exceeds the allocation-free workspace (%zu elements, "
+                  "%zu MiB)",
+                  (long long)p->nspec, kNoAllocScratchElems, kNoAllocScratchElems * sizeof(double2) >> 20);
+    double2* w = nullptr;
+    sgm_status st = noalloc_scratch(&w);
+    if (st != SGM_OK) return st;
+    return backward_via(p, u_hat, u, w, static_cast<hipStream_t>(stream));
 }
 
 // Backward Fourier passes (middle axis in place, then the last axis) from the
