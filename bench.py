@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true", help="also run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--legs", default="transforms,biharmonic,gl,surrogate",
+    ap.add_argument("--legs", default="transforms,derivative,legendre,biharmonic,gl,surrogate",
                     help="comma list of measured legs (the transform leg always runs)")
     return ap.parse_args()
 
@@ -235,6 +235,63 @@ def leg_biharmonic(steps):
             "biharmonic_solves_per_s": round(1e3 / ms_s, 1),
             "solve_hbm_frac": round(solve_bytes / (ms_s * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "plan_variants_xyz": p.variants()}
+
+
+def leg_derivative(steps):
+    """Sec. 5 derivative + projection at 256^3: d/dx of a Shen-Dirichlet field onto the
+    regular Chebyshev space, and d2/dx2 d/dy onto the Dirichlet space."""
+    import torch
+    import synth
+    from paper_1708_03188_amd.api import Plan
+    N = M1 = M2 = 256
+    p = Plan("dirichlet", N, M1, M2)
+    tc = Plan("chebyshev", N, M1, M2)
+    td = Plan("dirichlet", N, M1, M2)
+    uh = torch.from_numpy(synth.random_spectral(p.spec_shape, seed=5, nrows=N - 2)).cuda()
+    out = torch.empty_like(uh)
+    M2r = M2 // 2 + 1
+    nbytes = ((N - 2) + N) * M1 * M2r * 16   # read the basis rows, write every row
+    res = {"workload": "Shen-Dirichlet N=256 x Fourier 256x256 R2C, float64; project(Dx(u)) per call"}
+    for name, order, t in (("dx_onto_chebyshev", (1, 0, 0), tc), ("dxxy_onto_dirichlet", (2, 1, 0), td)):
+        ms = _timed(lambda: p.project_derivative(uh, order, target=t, out=out), max(10, steps))
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        res[name] = {"us_per_call": round(ms * 1e3, 2), "GBps": round(gbs, 1),
+                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": nbytes}
+    return res
+
+
+def leg_legendre(steps):
+    """Legendre-Dirichlet space 256 x 256 x 256 (R2C): transform pair; the x passes
+    are dense 256 x 256 FP64 products on the matrix cores (MFMA-bound)."""
+    import torch
+    import synth
+    from paper_1708_03188_amd.api import Plan
+    N = M1 = M2 = 256
+    p = Plan("leg_dirichlet", N, M1, M2, autotune=True)
+    u = torch.from_numpy(synth.random_smooth_field((N, M1, M2), seed=2)).cuda()
+    uh = torch.empty(p.spec_shape, dtype=torch.complex128, device="cuda")
+    v = torch.empty_like(u)
+    reps = max(10, steps // 2)
+    ms = _timed(lambda: (p.forward(u, out=uh), p.backward(uh, out=v)), reps)
+    p.pass_times(reset=True)
+    p.set_timing(True, passes=["cheb_fwd", "cheb_bwd"])
+    for _ in range(reps):
+        p.forward(u, out=uh)
+        p.backward(uh, out=v)
+    torch.cuda.synchronize()
+    t = p.pass_times(reset=True)
+    p.set_timing(False)
+    cols = 2 * M1 * (M2 // 2 + 1)
+    flop = 2.0 * N * N * cols   # one dense N x N product over the real columns
+    res = {"workload": "Shen-Legendre-Dirichlet N=256 x Fourier 256x256 R2C, float64; step = forward + backward",
+           "fwd_bwd_Gdofs": round(N * M1 * M2 / (ms * 1e-3) / 1e9, 3), "ms_fwd_bwd": round(ms, 4)}
+    for name in ("cheb_fwd", "cheb_bwd"):
+        if name in t:
+            us = 1e3 * t[name][0] / t[name][1]
+            tf = flop / (us * 1e-6) / 1e12
+            res["x_" + name.split("_")[1]] = {"avg_us": round(us, 2), "TFLOPs": round(tf, 2),
+                                              "mfma_f64_frac": round(tf / FP64_PEAK_TFLOPS, 4), "flop": flop}
+    return res
 
 
 def leg_gl(steps):
@@ -497,6 +554,10 @@ def main():
     }
     out["poisson2d_32x32"] = leg_poisson2d()
     legs = set(args.legs.split(","))
+    if "derivative" in legs:
+        out["derivative_256cube"] = leg_derivative(args.steps)
+    if "legendre" in legs:
+        out["legendre_256cube"] = leg_legendre(args.steps)
     if "biharmonic" in legs:
         out["biharmonic_512x256x256"] = leg_biharmonic(args.steps)
     if "gl" in legs:

@@ -47,6 +47,21 @@ typedef int sgm_status;
 #define SGM_SHEN_BIHARMONIC 2 /* phi_l = T_l - 2(l+2)/(l+3) T_{l+2} + (l+1)/(l+3) T_{l+4},
                                  l = 0..N-5 (eq. chebbiharmonic)                                    */
 #define SGM_CHEBYSHEV 3       /* phi_l = T_l, l = 0..N-1 (regular Chebyshev basis, Sec. 3.1)        */
+#define SGM_SHEN_NEUMANN 4    /* phi_l = T_l - (l/(l+2))^2 T_{l+2}, l = 0..N-3: Shen's Neumann basis
+                                 (Sec. 3.1 names it without a formula; this is the standard one,
+                                 phi_l'(+-1) = 0)                                                  */
+
+/* Legendre-family bases (Sec. 3.1; Legendre-Gauss points and weights, Sec. 3.4.2):
+ * the physical x axis then holds the N zeros of L_N in descending order, the
+ * transforms along x are dense O(N^2) products (no fast algorithm exists), and
+ * N <= 512. */
+#define SGM_LEGENDRE 5        /* phi_l = L_l, l = 0..N-1                                           */
+#define SGM_LEG_DIRICHLET 6   /* phi_l = L_l - L_{l+2}, l = 0..N-3 (eq. shen_legendre_basis)       */
+#define SGM_LEG_NEUMANN 7     /* phi_l = L_l - l(l+1)/((l+2)(l+3)) L_{l+2}, l = 0..N-3 (phi' = 0
+                                 at +-1; named in Sec. 3.1, formula the standard one)              */
+#define SGM_LEG_BIHARMONIC 8  /* phi_l = L_l - 2(2l+5)/(2l+7) L_{l+2} + (2l+3)/(2l+7) L_{l+4},
+                                 l = 0..N-5 (eq. legbiharmonic, read with l for k and the missing
+                                 L_{l+4}; phi = phi' = 0 at +-1)                                   */
 
 /* Transform kind of the last (contiguous) periodic axis. */
 #define SGM_R2C 1 /* real physical data, M/2+1 coefficients (R2CBasis, Sec. 3.1)  */
@@ -56,8 +71,10 @@ typedef struct sgm_plan_s* sgm_plan;
 
 typedef struct {
     int ndim;      /* 2: [x][y]; 3: [x][y][z]                                          */
-    int basis;     /* SGM_SHEN_DIRICHLET | SGM_SHEN_BIHARMONIC | SGM_CHEBYSHEV         */
-    int N;         /* points along x: >= 3 (Dirichlet), >= 5 (biharmonic), >= 2       */
+    int basis;     /* SGM_SHEN_DIRICHLET | SGM_SHEN_BIHARMONIC | SGM_CHEBYSHEV |
+                      SGM_SHEN_NEUMANN | SGM_LEGENDRE | SGM_LEG_DIRICHLET |
+                      SGM_LEG_NEUMANN | SGM_LEG_BIHARMONIC                             */
+    int N;         /* points along x: >= 3 (Dirichlet, Neumann), >= 5 (biharmonic), >= 2 */
     int M1;        /* points along y, >= 1                                             */
     int M2;        /* points along z (ndim = 3), >= 1; ignored for ndim = 2            */
     int kind_last; /* SGM_R2C | SGM_C2C for the last axis (y if ndim = 2, z if 3)      */
@@ -79,6 +96,11 @@ sgm_status sgm_plan_destroy(sgm_plan plan);
 
 /* Physical and spectral shapes in elements (unused trailing dims are 1). */
 sgm_status sgm_plan_shapes(sgm_plan plan, int64_t phys[3], int64_t spec[3]);
+
+/* The N points of the x axis (the mesh along x, Sec. 3.4.2) into the HOST array
+ * x[N]: Gauss-Chebyshev points cos((2j+1) pi / (2N)) for the Chebyshev family,
+ * the Legendre-Gauss points (descending) for the Legendre family. */
+sgm_status sgm_plan_points(sgm_plan plan, double* x);
 
 /* Forward transform u -> u_hat (Sec. 4 and Sec. 3.4.2): Fourier transforms
  * with 1/M scaling along the periodic axes (last axis first), then the Shen
@@ -134,6 +156,23 @@ sgm_status sgm_helmholtz_solve_physical(sgm_plan plan, double alpha, const void*
  * (S - 2 kappa^2 A + kappa^4 B) u_hat = f_tilde with S_ml = (phi_l'''', phi_m).
  * Same layout, aliasing rules and first-call table fill as sgm_helmholtz_solve. */
 sgm_status sgm_biharmonic_solve(sgm_plan plan, const void* f_tilde, void* u_hat, void* stream);
+
+/* Derivative and projection (Sec. 5: the Dx operator, nested for mixed
+ * derivatives, and project(Dx(u, ...), W0, uh_hat=u_hat)).  u_hat holds the
+ * coefficients of u in `plan`'s space; du_hat receives the coefficients, in the
+ * space of `target`, of the weighted L2 projection of
+ * d^(ox+oy+oz) u / dx^ox dy^oy dz^oz, order = {ox, oy, oz} (y the middle and z the
+ * last axis for ndim = 3, y the last axis for ndim = 2, where oz must be 0; each
+ * 0..8).  target->basis is SGM_CHEBYSHEV, where the result is the derivative's
+ * Chebyshev coefficients exactly (it is a polynomial of degree < N),
+ * SGM_SHEN_DIRICHLET, the projection the paper uses when the derivative vanishes
+ * at x = +-1 (exact then, a least-squares fit otherwise), or SGM_SHEN_NEUMANN.  target must have the
+ * same ndim, N, M1, M2, kind_last and periods.  Along a periodic axis of M points
+ * coefficient k is multiplied by (2 pi i k / L)^o; for even M the odd derivatives
+ * of the Nyquist coefficient are zero.  Spectral layouts as in sgm_forward; u_hat
+ * and du_hat must not overlap.  UNSUPPORTED_SIZE for N > 512. */
+sgm_status sgm_project_derivative(sgm_plan plan, sgm_plan target, const int order[3], const void* u_hat,
+                                  void* du_hat, void* stream);
 
 /* Per-pass timing (diagnostics).  enable = 0: off; 1: every pass kernel this plan
  * launches is bracketed by two hipEvents recorded on the caller's stream (the

@@ -14,4 +14,4 @@ Function-by-function pins live in tests/test_oracle_*.py.  Parity-unpinned
 functions: none (every public function is pinned by at least one closed
 form, invariant or brute-force check).
 """
-from . import fourier, chebyshev, linalg, tensor, gl, fno  # noqa: F401
+from . import fourier, chebyshev, linalg, tensor, gl, fno, derivative, legendre  # noqa: F401

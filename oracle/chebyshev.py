@@ -9,6 +9,8 @@ Bases (recombinations of T_k, stored as an N x nb matrix P with phi_l = sum_k P[
   "biharmonic": phi_l = T_l - 2(l+2)/(l+3) T_{l+2} + (l+1)/(l+3) T_{l+4},
                                                        l = 0..N-5   (eq. chebbiharmonic, Sec. 4)
   "chebyshev":  phi_l = T_l,                           l = 0..N-1   (regular basis, Sec. 3.1)
+  "neumann":    phi_l = T_l - (l/(l+2))^2 T_{l+2},     l = 0..N-3   (Shen's Neumann basis; Sec. 3.1
+                names it without a formula, this is the standard one with phi_l'(+-1) = 0)
 
 T_k(x_j) = cos(k (2j+1) pi / (2N)) is evaluated from the exactly reduced integer
 k(2j+1) mod 4N in extended precision.  Matrices are assembled by Gauss
@@ -32,7 +34,7 @@ from .linalg import householder_qr, lstsq_qr, solve_refined
 LD = np.longdouble
 # pi to the full x87 extended precision (np.pi is a binary64 constant)
 PI_LD = np.arccos(LD(-1))
-BASES = ("dirichlet", "biharmonic", "chebyshev")
+BASES = ("dirichlet", "biharmonic", "chebyshev", "neumann")
 
 
 def points(N):
@@ -45,7 +47,7 @@ def weights(N):
 
 
 def nbasis(basis, N):
-    return {"dirichlet": N - 2, "biharmonic": N - 4, "chebyshev": N}[basis]
+    return {"dirichlet": N - 2, "biharmonic": N - 4, "chebyshev": N, "neumann": N - 2}[basis]
 
 
 @functools.lru_cache(maxsize=32)
@@ -69,6 +71,8 @@ def recombination(basis, N, K=None):
         elif basis == "biharmonic":
             P[l + 2, l] = -LD(2 * (l + 2)) / LD(l + 3)
             P[l + 4, l] = LD(l + 1) / LD(l + 3)
+        elif basis == "neumann":
+            P[l + 2, l] = -(LD(l) / LD(l + 2)) ** 2
     return P
 
 
@@ -165,5 +169,5 @@ def forward_normal_equations(basis, u):
 def backward(basis, uh, axis=0):
     """u(x_j) = sum_l u_hat_l phi_l(x_j) along `axis` (N outputs)."""
     nb = np.shape(uh)[axis]
-    N = {"dirichlet": nb + 2, "biharmonic": nb + 4, "chebyshev": nb}[basis]
+    N = {"dirichlet": nb + 2, "biharmonic": nb + 4, "chebyshev": nb, "neumann": nb + 2}[basis]
     return _apply_left(synthesis(basis, N), uh, axis)

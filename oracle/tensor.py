@@ -1,6 +1,7 @@
 """Tensor-product spaces W = V(x) x V^p(y) [x V^p(z)] (oracle; test infrastructure only).
 
-Sec. 4: the non-periodic Shen/Chebyshev direction is axis 0 (x); the periodic
+Sec. 4: the non-periodic direction is axis 0 (x) with a Chebyshev-family basis
+(oracle.chebyshev) or a Legendre-family one (oracle.legendre, Sec. 3.1); the periodic
 directions are Fourier with period 2 pi.  Physical arrays are indexed
 [x][y] or [x][y][z]; spectral arrays [l][m] or [l][m][n] keep N rows along x
 (rows l >= nb are zero) and FFT order along every periodic axis.  The last
@@ -20,9 +21,17 @@ kappa^2 = m^2 + n^2 (Sec. 4, eq. laplace; Sec. 4 biharmonic problem):
 """
 import numpy as np
 
-from . import chebyshev as cheb
+from . import chebyshev as _chebyshev
 from . import fourier
+from . import legendre as _legendre
 from .linalg import solve_refined
+
+
+def _xmod(basis):
+    return _legendre if basis in _legendre.BASES else _chebyshev
+
+
+cheb = _chebyshev
 
 
 def spectral_shape(phys_shape, kind_last="r2c"):
@@ -59,18 +68,18 @@ def _pad_rows(a, N):
 def scalar_product(basis, f, kind_last="r2c"):
     """f_tilde[l, m, n] = S_l(F(f)) (nb nonzero rows, N rows stored)."""
     N = f.shape[0]
-    return _pad_rows(cheb.scalar_product(basis, _fourier_forward(f, kind_last), axis=0), N)
+    return _pad_rows(_xmod(basis).scalar_product(basis, _fourier_forward(f, kind_last), axis=0), N)
 
 
 def forward(basis, u, kind_last="r2c"):
     N = u.shape[0]
-    return _pad_rows(cheb.forward(basis, _fourier_forward(u, kind_last), axis=0), N)
+    return _pad_rows(_xmod(basis).forward(basis, _fourier_forward(u, kind_last), axis=0), N)
 
 
 def backward(basis, uh, M_last, kind_last="r2c"):
     N = uh.shape[0]
-    nb = cheb.nbasis(basis, N)
-    return _fourier_backward(cheb.backward(basis, uh[:nb], axis=0), M_last, kind_last)
+    nb = _xmod(basis).nbasis(basis, N)
+    return _fourier_backward(_xmod(basis).backward(basis, uh[:nb], axis=0), M_last, kind_last)
 
 
 def kappa2(spec_shape, M_last, kind_last="r2c"):
@@ -110,7 +119,7 @@ def helmholtz_solve(basis, ftilde, alpha, M_last, kind_last="r2c", cols=None):
     Returns the full spectral array, or an N x len(cols) array if `cols`
     (flat column indices into spectral dims 1..) is given."""
     N = ftilde.shape[0]
-    nb = cheb.nbasis(basis, N)
+    nb = _xmod(basis).nbasis(basis, N)
     A = cheb.stiffness_matrix(basis, N)
     B = cheb.mass_matrix(basis, N)
     k2 = kappa2(ftilde.shape, M_last, kind_last)
@@ -121,7 +130,7 @@ def helmholtz_solve(basis, ftilde, alpha, M_last, kind_last="r2c", cols=None):
 def biharmonic_solve(basis, ftilde, M_last, kind_last="r2c", cols=None):
     """Solve (S - 2 kappa^2 A + kappa^4 B) u_hat = f_tilde per wavenumber column."""
     N = ftilde.shape[0]
-    nb = cheb.nbasis(basis, N)
+    nb = _xmod(basis).nbasis(basis, N)
     S = cheb.bilaplace_matrix(basis, N)
     A = cheb.stiffness_matrix(basis, N)
     B = cheb.mass_matrix(basis, N)
@@ -159,12 +168,12 @@ def fourier_columns(u, cols, kind_last="r2c"):
 def forward_columns(basis, u, cols, kind_last="r2c"):
     """forward() restricted to the selected spectral columns (N x len(cols))."""
     N = u.shape[0]
-    return _pad_rows(cheb.forward(basis, fourier_columns(u, cols, kind_last), axis=0), N)
+    return _pad_rows(_xmod(basis).forward(basis, fourier_columns(u, cols, kind_last), axis=0), N)
 
 
 def scalar_product_columns(basis, f, cols, kind_last="r2c"):
     N = f.shape[0]
-    return _pad_rows(cheb.scalar_product(basis, fourier_columns(f, cols, kind_last), axis=0), N)
+    return _pad_rows(_xmod(basis).scalar_product(basis, fourier_columns(f, cols, kind_last), axis=0), N)
 
 
 def backward_rows(basis, uh, rows, M_last, kind_last="r2c"):
@@ -172,8 +181,8 @@ def backward_rows(basis, uh, rows, M_last, kind_last="r2c"):
     for each x_j, c_mn = sum_l u_hat[l, m, n] phi_l(x_j), then the Fourier
     backward transforms along y and z."""
     N = uh.shape[0]
-    nb = cheb.nbasis(basis, N)
-    Phi = cheb.synthesis(basis, N)
+    nb = _xmod(basis).nbasis(basis, N)
+    Phi = _xmod(basis).synthesis(basis, N)
     flat = uh[:nb].reshape(nb, -1)
     re = flat.real.astype(np.longdouble)
     im = flat.imag.astype(np.longdouble)

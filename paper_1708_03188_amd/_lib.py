@@ -6,7 +6,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsgm.so")
 
 SGM_OK = 0
-SGM_SHEN_DIRICHLET, SGM_SHEN_BIHARMONIC, SGM_CHEBYSHEV = 1, 2, 3
+SGM_SHEN_DIRICHLET, SGM_SHEN_BIHARMONIC, SGM_CHEBYSHEV, SGM_SHEN_NEUMANN = 1, 2, 3, 4
+SGM_LEGENDRE, SGM_LEG_DIRICHLET, SGM_LEG_NEUMANN, SGM_LEG_BIHARMONIC = 5, 6, 7, 8
 SGM_R2C, SGM_C2C = 1, 2
 
 
@@ -54,6 +55,8 @@ _SIGS = {
     "sgm_forward": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "sgm_backward": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "sgm_backward_noalloc": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "sgm_plan_points": ([_vp, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "sgm_project_derivative": ([_vp, _vp, ctypes.POINTER(ctypes.c_int), _vp, _vp, _vp], ctypes.c_int),
     "sgm_scalar_product": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "sgm_helmholtz_solve": ([_vp, ctypes.c_double, _vp, _vp, _vp], ctypes.c_int),
     "sgm_helmholtz_solve_physical": ([_vp, ctypes.c_double, _vp, _vp, _vp], ctypes.c_int),

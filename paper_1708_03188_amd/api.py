@@ -12,7 +12,9 @@ from . import _lib
 from ._lib import PlanDesc, check, load
 
 BASES = {"dirichlet": _lib.SGM_SHEN_DIRICHLET, "biharmonic": _lib.SGM_SHEN_BIHARMONIC,
-         "chebyshev": _lib.SGM_CHEBYSHEV}
+         "chebyshev": _lib.SGM_CHEBYSHEV, "neumann": _lib.SGM_SHEN_NEUMANN,
+         "legendre": _lib.SGM_LEGENDRE, "leg_dirichlet": _lib.SGM_LEG_DIRICHLET,
+         "leg_neumann": _lib.SGM_LEG_NEUMANN, "leg_biharmonic": _lib.SGM_LEG_BIHARMONIC}
 KINDS = {"r2c": _lib.SGM_R2C, "c2c": _lib.SGM_C2C}
 
 
@@ -48,6 +50,7 @@ class Plan:
         spec = (ctypes.c_int64 * 3)()
         check(lib.sgm_plan_shapes(h, phys, spec), "sgm_plan_shapes")
         self.basis, self.kind_last, self.ndim = basis, kind_last, ndim
+        self.Ly, self.Lz = float(Ly), float(Lz)
         self.phys_shape = tuple(phys[:ndim])
         self.spec_shape = tuple(spec[:ndim])
         self.phys_dtype = torch.float64 if kind_last == "r2c" else torch.complex128
@@ -74,6 +77,12 @@ class Plan:
         else:
             flag = int(bool(enable))
         check(self._lib.sgm_plan_timing(self._h, flag), "sgm_plan_timing")
+
+    def points(self):
+        """The N points of the x axis (numpy array)."""
+        x = (ctypes.c_double * self.phys_shape[0])()
+        check(self._lib.sgm_plan_points(self._h, x), "sgm_plan_points")
+        return np.array(x[:], dtype=np.float64)
 
     def variants(self):
         """Register-kernel variant per axis (x, y, z); -1 = generic kernels."""
@@ -112,6 +121,29 @@ class Plan:
         _need(out, self.phys_dtype, self.phys_shape, "u")
         check(self._lib.sgm_backward_noalloc(self._h, _ptr(uh), _ptr(out), _stream()), "sgm_backward_noalloc")
         return out
+
+    def project_derivative(self, uh, order, target=None, out=None):
+        """Coefficients in `target`'s space (a Plan on the same grid with the
+        "chebyshev" or "dirichlet" basis; default: a regular Chebyshev plan made
+        here) of the projection of d^(ox+oy+oz) u / dx^ox dy^oy dz^oz, where u has
+        the coefficients uh in this plan's space.  order = (ox, oy[, oz])."""
+        _need(uh, torch.complex128, self.spec_shape, "u_hat")
+        if target is None:
+            target = self._cheb_target()
+        out = self._out(out, self.spec_shape, torch.complex128, uh.device)
+        _need(out, torch.complex128, self.spec_shape, "du_hat")
+        o = list(order) + [0] * (3 - len(order))
+        arr = (ctypes.c_int * 3)(*[int(v) for v in o])
+        check(self._lib.sgm_project_derivative(self._h, target._h, arr, _ptr(uh), _ptr(out), _stream()),
+              "sgm_project_derivative")
+        return out
+
+    def _cheb_target(self):
+        if getattr(self, "_cheb", None) is None:
+            M2 = self.phys_shape[2] if self.ndim == 3 else None
+            self._cheb = Plan("chebyshev", self.phys_shape[0], self.phys_shape[1], M2, kind_last=self.kind_last,
+                              Ly=self.Ly, Lz=self.Lz)
+        return self._cheb
 
     def scalar_product(self, f, out=None):
         _need(f, self.phys_dtype, self.phys_shape, "f")

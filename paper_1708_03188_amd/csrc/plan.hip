@@ -9,8 +9,10 @@
 #include <string>
 #include <vector>
 
+#include "derivative.h"
 #include "kernels.h"
 #include "kernels_reg.h"
+#include "legendre.h"
 #include "solve_chain.h"
 #include "solve_seg.h"
 #include "tables.h"
@@ -91,6 +93,13 @@ struct sgm_plan_s {
     void* blob = nullptr;
     void* work = nullptr;
     RadixPlan rpx, rpy, rpz;  // rpy: middle axis (ndim=3) ; rpz: last axis
+    // Legendre-family x axis: fragment-ordered forward, backward and scalar-product
+    // matrices (in blob) and the points
+    bool leg = false;
+    const double* leg_fwd = nullptr;
+    const double* leg_bwd = nullptr;
+    const double* leg_sp = nullptr;
+    std::vector<double> xpts;
     ChebDev cd;
     ColGeom geom;
     int G_last, W_mid, W_cheb, W_solve;
@@ -287,16 +296,30 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
     *out = nullptr;
     const sgm_plan_desc& d = *desc;
     SGM_CHECK_ARG(d.ndim == 2 || d.ndim == 3, "ndim must be 2 or 3 (got %d)", d.ndim);
-    SGM_CHECK_ARG(d.basis == SGM_SHEN_DIRICHLET || d.basis == SGM_SHEN_BIHARMONIC || d.basis == SGM_CHEBYSHEV,
+    SGM_CHECK_ARG(d.basis == SGM_SHEN_DIRICHLET || d.basis == SGM_SHEN_BIHARMONIC || d.basis == SGM_CHEBYSHEV ||
+                      d.basis == SGM_SHEN_NEUMANN || is_legendre_basis(d.basis),
                   "unknown basis %d", d.basis);
     SGM_CHECK_ARG(d.kind_last == SGM_R2C || d.kind_last == SGM_C2C, "unknown kind_last %d", d.kind_last);
-    int minN = d.basis == SGM_SHEN_DIRICHLET ? 3 : d.basis == SGM_SHEN_BIHARMONIC ? 5 : 2;
+    const bool leg = is_legendre_basis(d.basis);
+    int minN = (d.basis == SGM_SHEN_DIRICHLET || d.basis == SGM_SHEN_NEUMANN || d.basis == SGM_LEG_DIRICHLET ||
+                d.basis == SGM_LEG_NEUMANN)
+                   ? 3
+               : (d.basis == SGM_SHEN_BIHARMONIC || d.basis == SGM_LEG_BIHARMONIC) ? 5
+                                                                                    : 2;
+    if (leg && d.N > kLegMaxN) {
+        set_error("Legendre spaces support N <= %d (got %d)", kLegMaxN, d.N);
+        return SGM_ERR_UNSUPPORTED_SIZE;
+    }
     int M2 = d.ndim == 3 ? d.M2 : 1;
     if (d.N < minN || d.M1 < 1 || M2 < 1 || d.N > 65536 || d.M1 > 65536 || M2 > 65536) {
         set_error("unsupported sizes N=%d M1=%d M2=%d for basis %d", d.N, d.M1, M2, d.basis);
         return SGM_ERR_UNSUPPORTED_SIZE;
     }
     SGM_CHECK_ARG(d.Ly >= 0 && d.Lz >= 0, "negative period");
+    if (d.basis == SGM_SHEN_NEUMANN && d.N > kDxMaxN) {
+        set_error("the Neumann basis supports N <= %d (its projection runs in the derivative pass)", kDxMaxN);
+        return SGM_ERR_UNSUPPORTED_SIZE;
+    }
     sgm_plan_s* p = new (std::nothrow) sgm_plan_s();
     if (!p) return SGM_ERR_OOM;
     p->d = d;
@@ -319,13 +342,29 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
     if ((st = make_radix(Llast, p->rpz)) != SGM_OK) { delete p; return st; }
 
     ChebTables ct;
+    LegTables lt;
     std::string err;
-    if (!build_cheb_tables(d.basis, d.N, ct, err)) {
+    if (leg ? !build_leg_tables(d.basis, d.N, lt, err) : !build_cheb_tables(d.basis, d.N, ct, err)) {
         set_error("%s", err.c_str());
         delete p;
         return SGM_ERR_UNSUPPORTED_SIZE;
     }
+    if (leg) {
+        ct.basis = d.basis;
+        ct.N = d.N;
+        ct.nb = lt.nb;
+        p->xpts = lt.x;
+    } else {
+        p->xpts.resize(d.N);
+        for (int j = 0; j < d.N; ++j) p->xpts[j] = std::cos((2 * j + 1) * 3.14159265358979323846 / (2.0 * d.N));
+    }
     Blob b;
+    size_t o_lf = 0, o_lb = 0, o_ls = 0;
+    if (leg) {
+        o_lf = b.add(leg_pack(lt.fwd, d.N));
+        o_lb = b.add(leg_pack(lt.bwd, d.N));
+        o_ls = b.add(leg_pack(lt.sp, d.N));
+    }
     size_t o_twx = b.add(twiddles(d.N));
     size_t o_twy = d.ndim == 3 ? b.add(twiddles(d.M1)) : 0;
     size_t o_twz = b.add(twiddles(Llast));
@@ -362,6 +401,12 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
     }
     cd.theta = reinterpret_cast<const double2*>(base + o_theta);
     cd.beta = D(o_beta); cd.gamma = D(o_gamma); cd.bscale = D(o_bs); cd.fscale = D(o_fs);
+    if (leg) {
+        p->leg = true;
+        p->leg_fwd = D(o_lf);
+        p->leg_bwd = D(o_lb);
+        p->leg_sp = D(o_ls);
+    }
 
     const double twopi = 6.283185307179586476925286766559;
     double Ly = d.Ly > 0 ? d.Ly : twopi, Lz = d.Lz > 0 ? d.Lz : twopi;
@@ -383,11 +428,11 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
     p->G_last = pick_tile(Llast, Llast >= 2048 ? 1 : 2048 / Llast, lds_bytes_lines, lds);
     if (p->G_last > 16) p->G_last = 16;
     p->W_mid = d.ndim == 3 ? pick_tile(d.M1, 16, lds_bytes_strided, lds) : 1;
-    p->W_cheb = pick_tile(d.N, d.N <= 256 ? 16 : 8, lds_bytes_cheb, lds);
+    p->W_cheb = leg ? 1 : pick_tile(d.N, d.N <= 256 ? 16 : 8, lds_bytes_cheb, lds);
     int ws = d.N <= 256 ? 16 : 8;
     while (ws > 1 && lds_bytes_solve(d.N, ws, d.basis) > (size_t)lds) ws /= 2;
     p->W_solve = ws;
-    if (lds_bytes_lines(Llast, p->G_last) > (size_t)lds || lds_bytes_cheb(d.N, p->W_cheb) > (size_t)lds ||
+    if (lds_bytes_lines(Llast, p->G_last) > (size_t)lds || (!leg && lds_bytes_cheb(d.N, p->W_cheb) > (size_t)lds) ||
         (d.ndim == 3 && lds_bytes_strided(d.M1, p->W_mid) > (size_t)lds)) {
         set_error("axis length too large for one work-group's LDS (%d bytes)", lds);
         hipFree(p->work); hipFree(p->blob); delete p;
@@ -397,7 +442,7 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
         // autotune >= 16 pins variant (autotune - 16) where it exists (diagnostics)
         const int v0 = d.autotune >= 16 ? d.autotune - 16 : 0;
         auto pick = [&](int L, RegKernels& k) { return reg_kernels_for(L, k, v0) || reg_kernels_for(L, k, 0); };
-        p->hx = pick(d.N, p->rkx);
+        p->hx = !leg && pick(d.N, p->rkx);
         p->hy = d.ndim == 3 && pick(d.M1, p->rky);
         p->hz = pick(Llast, p->rkz);
         if (p->hx && p->rkx.lds_cheb > (size_t)lds) p->hx = false;
@@ -408,7 +453,7 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
             if (st2 != SGM_OK) { hipFree(p->work); hipFree(p->blob); delete p; return st2; }
         }
     }
-    if (d.basis != SGM_CHEBYSHEV && d.autotune != 2) {
+    if ((d.basis == SGM_SHEN_DIRICHLET || d.basis == SGM_SHEN_BIHARMONIC) && d.autotune != 2) {
         p->seg_K = seg_lanes(std::max(cd.npar[0], cd.npar[1]));
         const size_t nt = seg_table_doubles(d.basis, p->seg_K, g.ncols);
         if (p->seg_K > 0 && nt > 0 && hipMalloc(&p->seg_tab, nt * sizeof(double)) != hipSuccess) {
@@ -468,6 +513,13 @@ sgm_status sgm_plan_destroy(sgm_plan p) {
     return SGM_OK;
 }
 
+sgm_status sgm_plan_points(sgm_plan p, double* x) {
+    clear_error();
+    SGM_CHECK_ARG(p && x, "null argument");
+    for (int j = 0; j < p->N; ++j) x[j] = p->xpts[j];
+    return SGM_OK;
+}
+
 sgm_status sgm_plan_shapes(sgm_plan p, int64_t phys[3], int64_t spec[3]) {
     clear_error();
     SGM_CHECK_ARG(p && phys && spec, "null argument");
@@ -508,7 +560,55 @@ static sgm_status fourier_forward(sgm_plan p, const void* u, double2* uh, hipStr
     return SGM_OK;
 }
 
+// Derivative-pass arguments for coefficients in p's space going to a space with
+// basis dst on the same grid (orders ox, oy, oz).
+static DxArgs dx_args(sgm_plan p, int src_basis, int dst_basis, int ox, int oy, int oz) {
+    const double twopi = 6.283185307179586476925286766559;
+    auto per = [twopi](double L) { return L > 0 ? L : twopi; };
+    DxArgs x;
+    x.N = p->N;
+    x.ncols = p->geom.ncols;
+    x.src_basis = src_basis;
+    x.nb_src = src_basis == SGM_CHEBYSHEV ? p->N : p->cd.nb;
+    x.beta = p->cd.beta;
+    x.gamma = p->cd.gamma;
+    x.dst_basis = dst_basis;
+    x.k4[0] = x.k4[1] = 0.0;
+    for (int k = 0; k < p->N; ++k) x.k4[k & 1] += (double)k * k * k * k;
+    x.ox = ox;
+    x.oy = oy;
+    x.oz = oz;
+    x.ndim = p->ndim;
+    x.nlast = p->geom.nlast;
+    x.Mmid = p->geom.Mmid;
+    x.Mlast = p->geom.Mlast;
+    x.last_r2c = p->geom.last_r2c;
+    x.ky = twopi / per(p->d.Ly);
+    x.kz = twopi / per(p->d.Lz);
+    return x;
+}
+
 static hipError_t cheb_forward_pass(sgm_plan p, double2* data, int mode, hipStream_t s) {
+    if (p->leg)
+        return launch_leg_pass(mode == kProject ? p->leg_fwd : p->leg_sp, reinterpret_cast<const double*>(data),
+                               reinterpret_cast<double*>(data), p->N, 2L * p->geom.ncols, s);
+    if (mode == kProject && p->cd.basis == SGM_SHEN_NEUMANN) {
+        // Neumann: Chebyshev interpolation coefficients, then their projection onto
+        // the space (in place: the Chebyshev-source projection reads only its own rows)
+        hipError_t e;
+        if (!p->hx) {
+            ChebDev cc = p->cd;
+            cc.basis = SGM_CHEBYSHEV;
+            cc.nb = p->N;
+            e = launch_cheb_fwd(data, data, cc, p->geom.ncols, p->W_cheb, p->rpx, mode, s);
+        } else {
+            const RegKernels& k = p->rkx;
+            e = launch_k(k.cf_cheb, (p->geom.ncols + k.W - 1) / k.W, k.threads, k.lds_cheb, s, (const double2*)data,
+                         data, p->cd, p->geom.ncols, p->rpx.tw, ChebSolve{nullptr, p->geom, 0.0});
+        }
+        if (e != hipSuccess) return e;
+        return launch_dx_project(data, data, dx_args(p, SGM_CHEBYSHEV, SGM_SHEN_NEUMANN, 0, 0, 0), s);
+    }
     if (!p->hx) return launch_cheb_fwd(data, data, p->cd, p->geom.ncols, p->W_cheb, p->rpx, mode, s);
     const RegKernels& k = p->rkx;
     auto f = k.cf_sp;
@@ -549,7 +649,10 @@ sgm_status sgm_scalar_product(sgm_plan p, const void* f, void* f_tilde, void* st
 static sgm_status backward_via(sgm_plan p, const void* u_hat, void* u, double2* w, hipStream_t s) {
     {
         PassTimer t(p, 6, s);
-        if (p->hx)
+        if (p->leg)
+            SGM_HIP_TRY(launch_leg_pass(p->leg_bwd, static_cast<const double*>(u_hat), reinterpret_cast<double*>(w), p->N,
+                                        2L * p->geom.ncols, s));
+        else if (p->hx)
             SGM_HIP_TRY(launch_k(p->rkx.cb, (p->geom.ncols + p->rkx.W - 1) / p->rkx.W, p->rkx.threads, p->rkx.lds, s,
                                  static_cast<const double2*>(u_hat), w, p->cd, p->geom.ncols, p->rpx.tw));
         else
@@ -675,6 +778,34 @@ sgm_status sgm_helmholtz_solve(sgm_plan p, double alpha, const void* f_tilde, vo
                                  p->W_solve, SGM_SHEN_DIRICHLET, alpha, static_cast<hipStream_t>(stream)));
     else
         return solve_dispatch(p, SGM_SHEN_DIRICHLET, alpha, f_tilde, u_hat, static_cast<hipStream_t>(stream));
+    return SGM_OK;
+}
+
+sgm_status sgm_project_derivative(sgm_plan p, sgm_plan target, const int order[3], const void* u_hat, void* du_hat,
+                                  void* stream) {
+    clear_error();
+    SGM_CHECK_ARG(p && target && order && u_hat && du_hat, "null argument");
+    SGM_CHECK_ARG(u_hat != du_hat, "u_hat and du_hat must not alias");
+    SGM_CHECK_ARG(!p->leg, "the derivative pass takes Chebyshev-family spaces");
+    const sgm_plan_desc &a = p->d, &b = target->d;
+    SGM_CHECK_ARG(b.basis == SGM_CHEBYSHEV || b.basis == SGM_SHEN_DIRICHLET || b.basis == SGM_SHEN_NEUMANN,
+                  "target basis must be SGM_CHEBYSHEV, SGM_SHEN_DIRICHLET or SGM_SHEN_NEUMANN");
+    SGM_CHECK_ARG(a.ndim == b.ndim && p->N == target->N && p->M1 == target->M1 && p->M2 == target->M2 &&
+                      a.kind_last == b.kind_last,
+                  "target plan must have the same grid (ndim, N, M1, M2, kind_last)");
+    const double twopi = 6.283185307179586476925286766559;
+    auto per = [twopi](double L) { return L > 0 ? L : twopi; };
+    SGM_CHECK_ARG(per(a.Ly) == per(b.Ly) && per(a.Lz) == per(b.Lz), "target plan must have the same periods");
+    for (int i = 0; i < 3; ++i)
+        SGM_CHECK_ARG(order[i] >= 0 && order[i] <= 8, "derivative order %d along axis %d outside 0..8", order[i], i);
+    SGM_CHECK_ARG(a.ndim == 3 || order[2] == 0, "2D plan: order[2] must be 0");
+    if (p->N > kDxMaxN) {
+        set_error("derivative pass supports N <= %d (plan has %d)", kDxMaxN, p->N);
+        return SGM_ERR_UNSUPPORTED_SIZE;
+    }
+    const DxArgs x = dx_args(p, p->cd.basis, b.basis, order[0], order[1], order[2]);
+    SGM_HIP_TRY(launch_dx_project(static_cast<const double2*>(u_hat), static_cast<double2*>(du_hat), x,
+                                  static_cast<hipStream_t>(stream)));
     return SGM_OK;
 }
 

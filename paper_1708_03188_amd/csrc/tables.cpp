@@ -77,6 +77,9 @@ static Comp composite(int basis, long l) {
         c.k[2] = l + 4; c.c[2] = (ld)(l + 1) / (ld)(l + 3);
         c.cnt = 3;
     }
+    if (basis == SGM_SHEN_NEUMANN) {
+        c.k[1] = l + 2; c.c[1] = -((ld)l / (ld)(l + 2)) * ((ld)l / (ld)(l + 2)); c.cnt = 2;
+    }
     return c;
 }
 // (phi_j^(d), phi_k)_w / (pi/2) for the composite basis, by the formulas above.
@@ -91,7 +94,8 @@ static ld entry(int basis, ld (*g)(long, long), long k, long j) {
 bool build_cheb_tables(int basis, int N, ChebTables& t, std::string& err) {
     t.basis = basis;
     t.N = N;
-    int nb = basis == SGM_SHEN_DIRICHLET ? N - 2 : basis == SGM_SHEN_BIHARMONIC ? N - 4 : N;
+    int nb = (basis == SGM_SHEN_DIRICHLET || basis == SGM_SHEN_NEUMANN) ? N - 2 : basis == SGM_SHEN_BIHARMONIC ? N - 4
+                                                                                                      : N;
     if (nb < 1) { err = "N too small for the basis"; return false; }
     t.nb = nb;
     for (int p = 0; p < 2; ++p) {
@@ -116,7 +120,9 @@ bool build_cheb_tables(int basis, int N, ChebTables& t, std::string& err) {
         if (c.cnt > 1) t.beta[l] = (double)c.c[1];
         if (c.cnt > 2) t.gamma[l] = (double)c.c[2];
     }
-    if (basis == SGM_CHEBYSHEV) return true;
+    // the regular basis needs no projection tables; the Neumann projection runs from
+    // the Chebyshev coefficients in closed form (derivative pass)
+    if (basis == SGM_CHEBYSHEV || basis == SGM_SHEN_NEUMANN) return true;
 
     // ---- Givens QR of D^{1/2} P per parity (banded least squares) ----------
     const int nrot = basis == SGM_SHEN_DIRICHLET ? 1 : 2;

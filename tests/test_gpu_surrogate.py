@@ -103,15 +103,18 @@ def test_trained_256_weights_on_fresh_trajectories(tmp_path):
     glc = GLBatch([Nw] * 2, scheme="ifrk4", b=1.5, c=-2.0, dt=0.05, L=100.0)
     u = gl.forward(gl.pack([synth.gl_noise(Nw, 930000 + i) for i in range(B)]))
     gl.step(u, 200)
-    u0 = u.clone()
-    st = f.advance_checked(gl, glc, u, nsur=2, steps_per=10, tol=1e-2, seed=5)
-    assert st["n_checked"] == 4, st
     ref = GLBatch([Nw] * B, scheme="ifrk4", b=1.5, c=-2.0, dt=0.05, L=100.0)
-    ref.step(u0, 20)
-    pu, pr = gl.backward(u), ref.backward(u0)
-    errs = [float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) for a, b in zip(gl.unpack(pu), ref.unpack(pr))]
-    print("checked advance:", st, "all-state rel L2 vs FP64:", ["%.2e" % e for e in errs])
-    if st["n_batch_fallback"] == 2:
-        assert max(errs) == 0.0   # both macro-steps re-advanced by the solver itself
-    else:
-        assert np.mean(errs) <= 1e-2
+    for it in range(2):
+        # one macro-step per call, every state compared with the FP64 solver run from
+        # the same starting state (the error the tolerance is defined on)
+        u0 = u.clone()
+        st = f.advance_checked(gl, glc, u, nsur=1, steps_per=10, tol=1e-2, seed=5 + it)
+        assert st["n_checked"] == 2, st
+        ref.step(u0, 10)
+        pu, pr = gl.backward(u), ref.backward(u0)
+        errs = [float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) for a, b in zip(gl.unpack(pu), ref.unpack(pr))]
+        print("checked advance:", st, "all-state rel L2 vs FP64:", ["%.2e" % e for e in errs])
+        if st["n_batch_fallback"] == 1:
+            assert max(errs) == 0.0   # the macro-step was re-advanced by the solver itself
+        else:
+            assert st["max_rel_l2"] <= 1e-2 and np.mean(errs) <= 1e-2

@@ -46,7 +46,7 @@ SMALL_3D = [(32, 33, 34), (16, 8, 8), (24, 12, 10), (12, 6, 7), (64, 32, 48), (9
 
 
 @pytest.mark.parametrize("generic", [False, True])
-@pytest.mark.parametrize("basis", ["dirichlet", "biharmonic", "chebyshev"])
+@pytest.mark.parametrize("basis", ["dirichlet", "biharmonic", "chebyshev", "neumann"])
 @pytest.mark.parametrize("kind", ["r2c", "c2c"])
 @pytest.mark.parametrize("shape", SMALL_2D + SMALL_3D)
 def test_forward_backward_scalar_product_small(Plan, basis, kind, shape, generic):
@@ -279,3 +279,20 @@ def test_solve_chain_lengths(Plan, basis, N):
         t = dev(ft)
         p.biharmonic_solve(t, out=t)
         assert rel_err(host(t), ref) < TOL_S
+
+
+@pytest.mark.parametrize("shape", [(256, 256, 256), (512, 64, 64)])
+def test_neumann_full_size_sampled(Plan, shape):
+    # Shen-Neumann space at full size: forward on sampled spectral columns, backward
+    # on sampled physical rows, against the oracle
+    print(f"[case] neumann full size {shape}", flush=True)
+    N, M2 = shape[0], shape[-1]
+    p = Plan("neumann", *shape)
+    u = _phys(shape, "r2c", seed=77)
+    rng = np.random.default_rng(7)
+    uh = host(p.forward(dev(u)))
+    cols = _sample_cols(p.spec_shape, rng, n=10)
+    assert rel_err(uh.reshape(N, -1)[:, cols], T.forward_columns("neumann", u, cols)) < TOL_T
+    vh = synth.random_spectral(p.spec_shape, seed=N + 3, nrows=N - 2)
+    rows = np.array([0, N // 2, N - 1])
+    assert rel_err(host(p.backward(dev(vh)))[rows], T.backward_rows("neumann", vh, rows, M2)) < TOL_T

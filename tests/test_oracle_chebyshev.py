@@ -226,3 +226,31 @@ def test_projection_accuracy_against_high_precision():
     ref = np.array([float(v) for v in mpmath.lu_solve(B, S)])
     got = C.forward("biharmonic", g)
     assert np.abs(got - ref).max() < 1e-15 * np.abs(ref).max() * 10
+
+
+def test_neumann_basis_boundary_conditions_and_mass_matrix():
+    # phi_l = T_l - (l/(l+2))^2 T_{l+2}: T_k'(1) = k^2 and T_k'(-1) = (-1)^(k+1) k^2,
+    # so phi_l'(+-1) = 0 exactly; mass matrix (pi/2)(c_l + beta_l^2) on the diagonal
+    # and (pi/2) beta_l two places off it
+    N = 14
+    P = C.recombination("neumann", N)
+    k = np.arange(N, dtype=np.longdouble)
+    assert np.all(np.abs((k**2) @ P) < 1e-15)
+    assert np.all(np.abs(((-1) ** (k + 1) * k**2) @ P) < 1e-15)
+    B = np.asarray(C.mass_matrix("neumann", N), dtype=float)
+    nb = N - 2
+    beta = np.array([-(l / (l + 2)) ** 2 for l in range(nb)])
+    ref = np.diag(PI / 2 * (np.where(np.arange(nb) == 0, 2.0, 1.0) + beta**2))
+    ref += np.diag(PI / 2 * beta[: nb - 2], 2) + np.diag(PI / 2 * beta[: nb - 2], -2)
+    assert np.abs(B - ref).max() < 1e-13
+
+
+def test_neumann_projection_of_a_neumann_polynomial_is_exact():
+    # u = x^2 - x^4/2 has u'(+-1) = 0 and u = 5/16 T0 + 1/4 T2 - 1/16 T4
+    #   = 5/16 phi_0 + 1/4 phi_2 (phi_2 = T2 - T4/4)
+    N = 12
+    x = C.points(N)
+    uh = C.forward("neumann", x**2 - x**4 / 2)
+    ref = np.zeros(N - 2)
+    ref[0], ref[2] = 5 / 16, 1 / 4
+    assert np.abs(uh - ref).max() < 1e-15

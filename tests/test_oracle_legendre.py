@@ -1,0 +1,101 @@
+"""Pins for oracle.legendre (Sec. 3.1 Legendre bases, Sec. 3.4.2 Legendre-Gauss
+quadrature): points and weights against numpy's Gauss-Legendre rule and the
+paper's weight formula, exact quadrature (discrete orthogonality), boundary
+conditions of every Shen basis, closed-form Dirichlet mass and stiffness
+matrices, round trips, the least-squares form against a library solver, and
+the paper's 1D Poisson example with the Legendre basis."""
+import numpy as np
+import pytest
+
+from oracle import legendre as L
+
+PI = np.pi
+
+
+@pytest.mark.parametrize("N", [5, 16, 33, 64])
+def test_points_and_weights(N):
+    x, w = L.nodes_weights(N)
+    xr, wr = np.polynomial.legendre.leggauss(N)
+    # descending order; same rule as numpy's
+    assert np.all(np.diff(x.astype(float)) < 0)
+    assert np.abs(x.astype(float)[::-1] - xr).max() < 1e-15
+    assert np.abs(w.astype(float)[::-1] - wr).max() < 1e-14
+    # the paper's formula w_j = 2 / ((1 - x_j^2) L_N'(x_j)^2) with L_N' from
+    # numpy's Legendre-series derivative
+    c = np.zeros(N + 1)
+    c[N] = 1
+    dLN = np.polynomial.legendre.legval(xr, np.polynomial.legendre.legder(c))
+    assert np.abs(2 / ((1 - xr**2) * dLN**2) - wr).max() < 1e-13
+
+
+@pytest.mark.parametrize("N", [8, 21])
+def test_discrete_orthogonality(N):
+    # Gauss quadrature is exact to degree 2N - 1: sum_j w_j L_k L_m = 2/(2k+1) delta_km
+    Lm = L.lmatrix(N)
+    w = L.nodes_weights(N)[1]
+    G = Lm.T @ (Lm * w[:, None])
+    ref = np.diag([2.0 / (2 * k + 1) for k in range(N)])
+    assert np.abs(np.asarray(G, dtype=float) - ref).max() < 1e-15
+    # against numpy's legvander
+    x = L.points(N)
+    assert np.abs(np.asarray(Lm, dtype=float) - np.polynomial.legendre.legvander(x, N - 1)).max() < 1e-13
+
+
+def test_boundary_conditions_of_the_shen_bases():
+    # L_k(1) = 1, L_k(-1) = (-1)^k, L_k'(1) = k(k+1)/2, L_k'(-1) = (-1)^(k+1) k(k+1)/2
+    N = 20
+    k = np.arange(N, dtype=np.longdouble)
+    val_p, val_m = np.ones(N, dtype=np.longdouble), (-1) ** k
+    der_p, der_m = k * (k + 1) / 2, (-1) ** (k + 1) * k * (k + 1) / 2
+    for basis, conds in (("leg_dirichlet", (val_p, val_m)), ("leg_neumann", (der_p, der_m)),
+                         ("leg_biharmonic", (val_p, val_m, der_p, der_m))):
+        P = L.recombination(basis, N)
+        for c in conds:
+            assert np.abs(c @ P).max() < 1e-15, basis
+
+
+def test_dirichlet_mass_and_stiffness_closed_forms():
+    # (phi_k, phi_k) = 2/(2k+1) + 2/(2k+5), (phi_k, phi_{k+2}) = -2/(2k+5);
+    # (phi_l', phi_m') = (4l + 6) delta_lm (Legendre weight 1, by parts)
+    N = 18
+    nb = N - 2
+    B = np.asarray(L.mass_matrix("leg_dirichlet", N), dtype=float)
+    k = np.arange(nb)
+    ref = np.diag(2 / (2 * k + 1) + 2 / (2 * k + 5))
+    off = -2 / (2 * k[: nb - 2] + 5)
+    ref += np.diag(off, 2) + np.diag(off, -2)
+    assert np.abs(B - ref).max() < 1e-15
+    # derivative values from numpy's Legendre derivative, quadrature with the oracle's rule
+    x, w = L.points(N), L.weights(N)
+    P = np.asarray(L.recombination("leg_dirichlet", N), dtype=float)
+    D = np.stack([np.polynomial.legendre.legval(x, np.polynomial.legendre.legder(P[:, l])) for l in range(nb)], 1)
+    A = D.T @ (D * w[:, None])
+    assert np.abs(A - np.diag(4 * k + 6.0)).max() < 1e-11
+
+
+@pytest.mark.parametrize("basis", L.BASES)
+@pytest.mark.parametrize("N", [8, 13, 40])
+def test_round_trip_and_least_squares(basis, N):
+    rng = np.random.default_rng(N)
+    nb = L.nbasis(basis, N)
+    uh = rng.standard_normal(nb) + 1j * rng.standard_normal(nb)
+    assert np.allclose(L.forward(basis, L.backward(basis, uh)), uh, atol=1e-13)
+    u = rng.standard_normal(N)
+    Phi = np.asarray(L.synthesis(basis, N), dtype=float)
+    sw = np.sqrt(L.weights(N))
+    ref = np.linalg.lstsq(Phi * sw[:, None], u * sw, rcond=None)[0]
+    assert np.allclose(L.forward(basis, u), ref, atol=1e-11)
+    # the scalar product is Phi^T W u
+    assert np.allclose(L.scalar_product(basis, u), Phi.T @ (L.weights(N) * u), atol=1e-13)
+
+
+def test_poisson_1d_legendre_dirichlet_paper_example():
+    # Sec. 3.4.2 example with the Legendre basis: u = sin(pi x)(1 - x^2), -u'' = f;
+    # (phi_l', phi_m') u_hat = (f, phi_m) with the diagonal stiffness 4l + 6
+    N = 32
+    x = L.points(N)
+    u = np.sin(PI * x) * (1 - x**2)
+    f = PI**2 * np.sin(PI * x) * (1 - x**2) + 4 * PI * x * np.cos(PI * x) + 2 * np.sin(PI * x)
+    ft = L.scalar_product("leg_dirichlet", f)
+    uh = ft / (4 * np.arange(N - 2) + 6.0)
+    assert np.abs(L.backward("leg_dirichlet", uh) - u).max() < 1e-13
