@@ -20,7 +20,10 @@ FLAGS = [
 # Per-source flags: the fused FNO row kernels keep their MFMA accumulators in
 # ordinary VGPRs, so the GELU between the projection's two products reads them
 # without accumulation-register copies.
-EXTRA = {"fno_fused.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+EXTRA = {"fno_fused.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+         # the dense Legendre pass: accumulators stay in VGPRs (no accumulation-register
+         # copies around the product loop)
+         "legendre.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _run(cmd):

@@ -30,7 +30,9 @@ bool build_leg_tables(int basis, int N, LegTables& t, std::string& err);
 
 // The matrix-core pass reads its matrix in fragment order: for k-group g (4
 // columns of the matrix) and row block r (16 rows), 64 consecutive doubles, entry
-// q holding A[16 r + q % 16][4 g + q / 16].
+// q holding A[16 r + q % 16][4 g + q / 16]; leg_row_blocks(N) row blocks per
+// k-group (a multiple of 4, rows past N zero).
+int leg_row_blocks(int N);
 std::vector<double> leg_pack(const std::vector<double>& A, int N);
 size_t leg_packed_doubles(int N);
 

@@ -2,13 +2,16 @@
 //
 // The Legendre transforms have no fast algorithm (Sec. 3.4.2): every x pass is
 // the product of a plan-constant N x N matrix with the N x C real view of the
-// spectral array.  A work-group owns TC adjacent real columns: it stages all N
-// rows of them in LDS (coalesced 8 TC-byte rows), then its four waves compute
-// the output rows in 16-row blocks with v_mfma_f64_16x16x4 (A fragment: one
-// matrix element per lane, fetched from the fragment-ordered matrix in one
-// coalesced 512-byte load; B fragment: one staged value per lane), and write
-// them back.  All reads of the block's columns precede its writes, so the pass
-// may run in place.
+// spectral array, out = A in.  A work-group owns 16 adjacent real columns: it
+// stages all N rows of them in LDS (16-byte loads, 128-byte rows), then each of
+// its four waves computes RBW 16-row blocks of the output with v_mfma_f64_16x16x4
+// (lane l: A fragment element A[16 r + l % 16][4 g + l / 16], fetched from the
+// fragment-ordered matrix in one coalesced 512-byte load per block two k-groups
+// ahead; B fragment element in[4 g + l / 16][c0 + l % 16] from LDS; result
+// elements rows 4 i + l / 16 of column l % 16).  16-column work-groups (32 KB of
+// LDS at N = 256) keep five per CU resident, which measured faster than wider
+// tiles with more reuse of the matrix.  A work-group reads all of its columns
+// before writing them, so the pass may run in place.
 #include "legendre.h"
 
 namespace sgm {
@@ -17,75 +20,89 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <int TC, int RBW>
+constexpr int kLegTC = 16;   // real columns per work-group
+constexpr int kLegRing = 2;  // k-groups of matrix fragments fetched ahead
+
+template <int RBW>
 __global__ __launch_bounds__(256) void k_leg_pass(const double* __restrict__ Apk, const double* in, double* out, int N,
                                                    long C) {
-    extern __shared__ double tile[];  // [Kp][TC]
-    constexpr int CB = TC / 16;
-    const long c0 = (long)blockIdx.x * TC;
-    const int Kp = (N + 3) & ~3;
-    for (int idx = threadIdx.x; idx < Kp * TC; idx += 256) {
-        const int r = idx / TC, c = idx - r * TC;
-        tile[idx] = (r < N && c0 + c < C) ? in[(long)r * C + c0 + c] : 0.0;
+    extern __shared__ double tile[];  // [Kp][16]
+    constexpr int RBP = 4 * RBW;      // row blocks of the packed matrix
+    const long c0 = (long)blockIdx.x * kLegTC;
+    const int Kp = (N + 3) & ~3, KG = Kp >> 2;
+    for (int idx = threadIdx.x; idx < Kp * (kLegTC / 2); idx += 256) {
+        const int r = idx / (kLegTC / 2), c = 2 * (idx - r * (kLegTC / 2));
+        double2 v = make_double2(0.0, 0.0);
+        if (r < N) {
+            const double* p = in + (long)r * C + c0 + c;
+            if (c0 + c + 1 < C) v = *reinterpret_cast<const double2*>(p);
+            else if (c0 + c < C) v.x = p[0];
+        }
+        reinterpret_cast<double2*>(tile)[idx] = v;
     }
-    __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int RB = (N + 15) >> 4;
-    d4 acc[RBW][CB];
-#pragma unroll
-    for (int rb = 0; rb < RBW; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
     const int kl = lane >> 4, cl = lane & 15;
-    for (int g = 0; g < (Kp >> 2); ++g) {
-        double b[CB];
+    // row blocks wave, wave + 4, ...; zero rows past N in the packed matrix make
+    // every load and product unconditional
+    const double* ap = Apk + (long)wave * 64 + lane;
+    double a[kLegRing][RBW];
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) b[cb] = tile[(4 * g + kl) * TC + cb * 16 + cl];
+    for (int q = 0; q < kLegRing; ++q)
 #pragma unroll
-        for (int rb = 0; rb < RBW; ++rb) {
-            const int r = wave + 4 * rb;
-            if (r < RB) {
-                const double a = Apk[((long)g * RB + r) * 64 + lane];
+        for (int rb = 0; rb < RBW; ++rb) a[q][rb] = ap[(long)(q < KG ? q : KG - 1) * RBP * 64 + rb * 256];
+    d4 acc[RBW];
 #pragma unroll
-                for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[cb], acc[rb][cb], 0, 0, 0);
+    for (int rb = 0; rb < RBW; ++rb) acc[rb] = d4{0.0, 0.0, 0.0, 0.0};
+    __syncthreads();
+    for (int g0 = 0; g0 < KG; g0 += kLegRing) {
+#pragma unroll
+        for (int q = 0; q < kLegRing; ++q) {
+            const int g = g0 + q;
+            if (g < KG) {  // uniform: only an odd KG leaves a half ring at the end
+                const double b = tile[(4 * g + kl) * kLegTC + cl];
+                const long gn = (long)(g + kLegRing < KG ? g + kLegRing : g) * RBP * 64;
+                double an[RBW];
+#pragma unroll
+                for (int rb = 0; rb < RBW; ++rb) an[rb] = ap[gn + rb * 256];
+#pragma unroll
+                for (int rb = 0; rb < RBW; ++rb) acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q][rb], b, acc[rb], 0, 0, 0);
+#pragma unroll
+                for (int rb = 0; rb < RBW; ++rb) a[q][rb] = an[rb];
             }
         }
     }
+    const long col = c0 + cl;
+    if (col >= C) return;
 #pragma unroll
     for (int rb = 0; rb < RBW; ++rb) {
         const int r = wave + 4 * rb;
-        if (r >= RB) continue;
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            const long col = c0 + cb * 16 + cl;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int row = 16 * r + 4 * i + kl;  // D element i of lane l: row 4 i + l / 16, column l % 16
-                if (row < N && col < C) out[(long)row * C + col] = acc[rb][cb][i];
-            }
+        for (int i = 0; i < 4; ++i) {
+            const int row = 16 * r + 4 * i + kl;  // D element i of lane l: row 4 i + l / 16, column l % 16
+            if (row < N) out[(long)row * C + col] = acc[rb][i];
         }
     }
 }
 
 }  // namespace
 
+int leg_row_blocks(int N) {
+    const int rb = (N + 15) / 16;
+    return rb <= 4 ? 4 : rb <= 8 ? 8 : rb <= 16 ? 16 : 32;
+}
+
+size_t leg_packed_doubles(int N) { return (size_t)((N + 3) / 4) * leg_row_blocks(N) * 64; }
+
 hipError_t launch_leg_pass(const double* Apk, const double* in, double* out, int N, long C, hipStream_t s) {
     if (C <= 0) return hipSuccess;
-    const int Kp = (N + 3) & ~3;
-    if (N <= 256) {
-        constexpr int TC = 32;
-        const long blocks = (C + TC - 1) / TC;
-        const size_t lds = (size_t)Kp * TC * sizeof(double);
-        if (N <= 64) hipLaunchKernelGGL((k_leg_pass<TC, 1>), dim3((unsigned)blocks), dim3(256), lds, s, Apk, in, out, N, C);
-        else if (N <= 128) hipLaunchKernelGGL((k_leg_pass<TC, 2>), dim3((unsigned)blocks), dim3(256), lds, s, Apk, in, out, N, C);
-        else hipLaunchKernelGGL((k_leg_pass<TC, 4>), dim3((unsigned)blocks), dim3(256), lds, s, Apk, in, out, N, C);
-    } else if (N <= kLegMaxN) {
-        constexpr int TC = 16;
-        const long blocks = (C + TC - 1) / TC;
-        const size_t lds = (size_t)Kp * TC * sizeof(double);
-        hipLaunchKernelGGL((k_leg_pass<TC, 8>), dim3((unsigned)blocks), dim3(256), lds, s, Apk, in, out, N, C);
-    } else {
-        return hipErrorInvalidValue;
+    if (N < 1 || N > kLegMaxN) return hipErrorInvalidValue;
+    const dim3 g((unsigned)((C + kLegTC - 1) / kLegTC)), b(256);
+    const size_t lds = (size_t)((N + 3) & ~3) * kLegTC * sizeof(double);
+    switch (leg_row_blocks(N)) {
+        case 4: hipLaunchKernelGGL(k_leg_pass<1>, g, b, lds, s, Apk, in, out, N, C); break;
+        case 8: hipLaunchKernelGGL(k_leg_pass<2>, g, b, lds, s, Apk, in, out, N, C); break;
+        case 16: hipLaunchKernelGGL(k_leg_pass<4>, g, b, lds, s, Apk, in, out, N, C); break;
+        default: hipLaunchKernelGGL(k_leg_pass<8>, g, b, lds, s, Apk, in, out, N, C); break;
     }
     return hipGetLastError();
 }

@@ -163,13 +163,8 @@ bool build_leg_tables(int basis, int N, LegTables& t, std::string& err) {
     return true;
 }
 
-size_t leg_packed_doubles(int N) {
-    const int KG = (N + 3) / 4, RB = (N + 15) / 16;
-    return (size_t)KG * RB * 64;
-}
-
 std::vector<double> leg_pack(const std::vector<double>& A, int N) {
-    const int KG = (N + 3) / 4, RB = (N + 15) / 16;
+    const int KG = (N + 3) / 4, RB = leg_row_blocks(N);
     std::vector<double> out(leg_packed_doubles(N), 0.0);
     for (int g = 0; g < KG; ++g)
         for (int r = 0; r < RB; ++r)
