@@ -60,8 +60,9 @@ def pass_bytes(N, M1, M2, nb):
     }
 
 
-# variant -> (threads per line at most, exchange buffers, block size)
-VARIANT_GEO = {0: (32, 2, 256), 1: (32, 1, 256), 2: (16, 2, 256), 3: (16, 1, 256), 4: (64, 1, 256), 5: (32, 1, 512)}
+# variant -> (threads per line at most, exchange buffers, block size, largest radix)
+VARIANT_GEO = {0: (32, 2, 256, 8), 1: (32, 1, 256, 8), 2: (16, 2, 256, 8), 3: (16, 1, 256, 8), 4: (64, 1, 256, 8),
+               5: (32, 1, 512, 8), 6: (32, 1, 256, 4), 7: (16, 1, 256, 4)}
 PASS_KERNEL = {"last_fwd": ("kr_lines_r2c", 2), "last_bwd": ("kr_lines_c2r", 2), "mid_fwd": ("kr_strided", 1),
                "mid_bwd": ("kr_strided", 1), "cheb_fwd": ("kr_cheb_fwd", 0), "cheb_bwd": ("kr_cheb_bwd", 0)}
 
@@ -88,7 +89,7 @@ def measured_traffic(pass_name, variants, L):
     v = variants[axis]
     if v < 0:
         return None
-    nt, nb, th = VARIANT_GEO[v]
+    nt, nb, th, mr = VARIANT_GEO[v]
     with open(path) as fh:
         txt = fh.read()
     if f"kernel-source hash: {kernel_source_hash()}" not in txt:
@@ -96,7 +97,7 @@ def measured_traffic(pass_name, variants, L):
     sign = ""
     if name == "kr_strided":
         sign = ", -1>" if pass_name == "mid_fwd" else ", 1>"
-    key = f"sgm::{name}<{L}, sgm::Geo<{L}, {nt}, {nb}, {th}>"
+    key = f"sgm::{name}<{L}, sgm::Geo<{L}, {nt}, {nb}, {th}, {mr}>"
     for line in txt.splitlines():
         if key in line and (not sign or line.split("|")[1].strip().endswith(sign)) and \
                 (name != "kr_cheb_fwd" or line.split("|")[1].strip().endswith(", 3>")):
@@ -156,8 +157,8 @@ def pass_kernel_name(pass_name, variants, L):
     v = variants[axis]
     if v < 0:
         return f"generic LDS kernel for {pass_name}"
-    nt, nb, th = VARIANT_GEO[v]
-    return f"{name}<{L}, Geo<{L}, {nt}, {nb}, {th}>>"
+    nt, nb, th, mr = VARIANT_GEO[v]
+    return f"{name}<{L}, Geo<{L}, {nt}, {nb}, {th}, {mr}>>"
 
 
 def cpu_baseline(N, M1, M2):

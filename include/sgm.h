@@ -83,7 +83,7 @@ typedef struct {
                       compiled instance, generic LDS kernels otherwise); 1: time the
                       candidates once at creation and keep the fastest; 2: generic
                       LDS kernels only; 16 + v: pin register-kernel variant v
-                      (0..5) wherever it is compiled (diagnostics) */
+                      (0..7) wherever it is compiled (diagnostics) */
 } sgm_plan_desc;
 
 /* Create a plan for the tensor-product space V(x) x V^p(y) [x V^p(z)] (Sec. 4,
@@ -187,7 +187,7 @@ sgm_status sgm_project_derivative(sgm_plan plan, sgm_plan target, const int orde
 #define SGM_NPASS 8
 #define SGM_TIMING_ONLY 0x100
 sgm_status sgm_plan_timing(sgm_plan plan, int enable);
-/* Register-kernel variant in use per axis (x, y, z): 0..5, or -1 where the axis runs
+/* Register-kernel variant in use per axis (x, y, z): 0..7, or -1 where the axis runs
  * the generic LDS kernels (diagnostics; chosen at creation, see autotune). */
 sgm_status sgm_plan_variants(sgm_plan plan, int variant[3]);
 sgm_status sgm_plan_pass_times(sgm_plan plan, double ms[SGM_NPASS], int64_t count[SGM_NPASS], int reset);
@@ -335,6 +335,20 @@ typedef struct {
 sgm_status sgm_fno_advance_checked(sgm_fno f, sgm_gl gl, sgm_gl gl_check, void* u_hat, int nsur, int steps_per,
                                    double tol, double max_fail_frac, uint64_t seed, sgm_fno_stats* stats,
                                    void* stream);
+
+/* ---- Autotuner memory ----------------------------------------------------------------
+ * Plans created with autotune = 1 and GL batches created with tune = 1 time their
+ * candidate kernels once per geometry (plan: device, ndim, basis, N, M1, M2, kind_last;
+ * batch: device, scheme, sizes) and remember the choice in the process and in a
+ * text file: $SGM_TUNE_CACHE if set ("off": no file), else
+ * $XDG_CACHE_HOME/libsgm/tune.txt, else $HOME/.cache/libsgm/tune.txt.  A stored
+ * choice is reused only if it names kernels this build compiled.  The file is
+ * read and appended without locking (the last line for a key wins).
+ * sgm_autotune_forget clears the in-process memory (the file is kept), so the next
+ * tuned plan or batch reads the file or times again; sgm_autotune_cache_path copies
+ * the file path (empty if none) into buf[len]. */
+sgm_status sgm_autotune_forget(void);
+sgm_status sgm_autotune_cache_path(char* buf, int len);
 
 const char* sgm_status_string(sgm_status s);
 const char* sgm_last_error(void);

@@ -56,6 +56,8 @@ _SIGS = {
     "sgm_backward": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "sgm_backward_noalloc": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "sgm_plan_points": ([_vp, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "sgm_autotune_forget": ([], ctypes.c_int),
+    "sgm_autotune_cache_path": ([ctypes.c_char_p, ctypes.c_int], ctypes.c_int),
     "sgm_project_derivative": ([_vp, _vp, ctypes.POINTER(ctypes.c_int), _vp, _vp, _vp], ctypes.c_int),
     "sgm_scalar_product": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "sgm_helmholtz_solve": ([_vp, ctypes.c_double, _vp, _vp, _vp], ctypes.c_int),

@@ -395,3 +395,15 @@ def unpack_states(x, out=None):
         out = torch.empty(tuple(x.shape[:-1]), dtype=torch.complex128, device=x.device)
     check(lib.sgm_fno_unpack(_ptr(x), _ptr(out), out.numel(), _stream()), "sgm_fno_unpack")
     return out
+
+
+def autotune_forget():
+    """Clear the library's in-process memory of autotuned choices (the cache file stays)."""
+    check(load().sgm_autotune_forget(), "sgm_autotune_forget")
+
+
+def autotune_cache_path():
+    """Path of the autotuner's cache file ("" if none)."""
+    buf = ctypes.create_string_buffer(4096)
+    check(load().sgm_autotune_cache_path(buf, 4096), "sgm_autotune_cache_path")
+    return buf.value.decode()

@@ -16,6 +16,7 @@
 // lines per block, exchange buffers) and grid mode (persistent grid-stride or
 // one block per item) are chosen by measurement at batch creation.
 #include <algorithm>
+#include <map>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -26,6 +27,7 @@
 #include "kernels.h"
 #include "kernels_reg.h"
 #include "tables.h"
+#include "tune_cache.h"
 
 namespace sgm {
 
@@ -96,12 +98,18 @@ __device__ __forceinline__ int nidx(int l, int N) { return l >= 0 ? l : l + N; }
 
 // Stage operands touched once per stage (state, accumulator, stage input):
 // non-temporal, so the padded workspace, which every pass reads back, keeps the MALL.
+// One 16-byte access per element (two 8-byte halves would be two partial-line
+// requests for the same line).
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ double2 ntld(const double2* p) {
-    return make_double2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
+    const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+    return make_double2(v.x, v.y);
 }
 __device__ __forceinline__ void ntst(double2* p, double2 v) {
-    __builtin_nontemporal_store(v.x, &p->x);
-    __builtin_nontemporal_store(v.y, &p->y);
+    nt_d2 w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, reinterpret_cast<nt_d2*>(p));
 }
 
 // Stage update of one retained mode.  k = N(v) = -F_trunc[(1 + i c)|u_p|^2 u_p].
@@ -563,9 +571,27 @@ static sgm_status gl_enqueue_step(sgm_gl g, double2* state, hipStream_t s) {
     return r;
 }
 
+// Cache key of a batch: device, scheme and the multiset of sizes.
+static std::string gl_tune_key(sgm_gl g) {
+    std::map<int, int> cnt;
+    for (int n : g->N) ++cnt[n];
+    std::string k = "gl " + tune_device_tag() + " scheme" + std::to_string(g->d.scheme);
+    for (auto& [n, c] : cnt) k += " " + std::to_string(n) + "x" + std::to_string(c);
+    return k;
+}
+
 // Times one step of each candidate configuration on a scratch state and keeps
-// the fastest.  Runs on the default stream before the batch is handed out.
+// the fastest (or takes the choice stored for this device and batch shape).
+// Runs on the default stream before the batch is handed out.
 static sgm_status gl_autotune(sgm_gl g, int64_t os) {
+    const std::string key = gl_tune_key(g);
+    std::vector<int> cached;
+    if (tune_cache_get(key, cached) && cached.size() == 1 && cached[0] >= 0 && cached[0] < 2 * kGlCfgs &&
+        g->cfg_ok[cached[0] / 2]) {
+        g->cfg = cached[0] / 2;
+        g->gridmode = cached[0] % 2;
+        return SGM_OK;
+    }
     double2* state = nullptr;
     if (hipMalloc(&state, (size_t)os * sizeof(double2)) != hipSuccess) {
         set_error("hipMalloc of the tuning state failed");
@@ -611,6 +637,7 @@ static sgm_status gl_autotune(sgm_gl g, int64_t os) {
     hipFree(state);
     g->cfg = bcfg;
     g->gridmode = bgrid;
+    if (r == SGM_OK) tune_cache_put(key, {2 * bcfg + bgrid});
     return r;
 }
 

@@ -39,7 +39,7 @@ struct RegKernels {
     void (*cb)(const double2*, double2*, ChebDev, int, const double2*) = nullptr;
 };
 
-constexpr int kRegVariants = 6;
+constexpr int kRegVariants = 8;
 // Fill `k` with variant `variant` of the kernels for length L; false if L (or
 // that variant) has no compiled instance.
 bool reg_kernels_for(int L, RegKernels& k, int variant = 0);

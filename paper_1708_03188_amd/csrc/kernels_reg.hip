@@ -35,12 +35,15 @@ __device__ __forceinline__ int xcd_block() {
 
 // Launch geometry of one variant: NTMAX bounds the threads per line (so
 // E = L / NT points per thread), NB is the number of exchange buffers, TH the
-// block size to fill.
-template <int L, int NTMAX_, int NB_, int TH = kThreads>
+// block size to fill, MAXR the largest radix of the stage schedule (8: radix-8
+// stages where the power of two allows; 4: radix-4/2 only, more stages with
+// fewer twiddle products each).
+template <int L, int NTMAX_, int NB_, int TH = kThreads, int MAXR_ = 8>
 struct Geo {
     static constexpr int NTMAX = NTMAX_;
     static constexpr int NB = NB_;
-    static constexpr Sched sd = make_sched(L, NTMAX);
+    static constexpr int MAXR = MAXR_;
+    static constexpr Sched sd = make_sched(L, NTMAX, MAXR);
     static constexpr int NT = sd.NT;
     static constexpr int E = sd.E;
     // lines per block: fill TH threads unless the exchange buffers
@@ -56,16 +59,16 @@ struct Geo {
 // reads them from the table.
 template <int L, class G, int SIGN, bool ALLOW = true>
 struct LineFft {
-    static constexpr int NTW = tw_count<L, G::NTMAX>();
+    static constexpr int NTW = tw_count<L, G::NTMAX, G::MAXR>();
     static constexpr bool PRE = ALLOW && NTW <= 16;
     double2 w[PRE ? NTW : 1];
     __device__ __forceinline__ void load(int t, const double2* __restrict__ tw) {
-        if constexpr (PRE) load_twiddles<L, G::NTMAX, SIGN>(w, t, tw);
+        if constexpr (PRE) load_twiddles<L, G::NTMAX, SIGN, 0, G::MAXR>(w, t, tw);
     }
     __device__ __forceinline__ void run(double2* x, double2* b0, double2* b1, int ps, int t,
                                         const double2* __restrict__ tw) {
-        if constexpr (PRE) reg_fft_pre<L, G::NTMAX, SIGN, G::NB>(x, b0, b1, ps, t, w);
-        else reg_fft<L, G::NTMAX, SIGN, G::NB>(x, b0, b1, ps, t, tw);
+        if constexpr (PRE) reg_fft_pre<L, G::NTMAX, SIGN, G::NB, G::MAXR>(x, b0, b1, ps, t, w);
+        else reg_fft<L, G::NTMAX, SIGN, G::NB, G::MAXR>(x, b0, b1, ps, t, tw);
     }
 };
 
@@ -264,7 +267,7 @@ __global__ void __launch_bounds__(G::THREADS) kr_strided(const double2* in, doub
 #pragma unroll
             for (int e = 0; e < G::E; ++e) y[e] = buf_ld(r, offn == kOob ? kOob : offn + (t + G::NT * e) * rs);
         }
-        reg_fft<L, G::NTMAX, SIGN, G::NB>(x, lds + c, lds + G::B1OFF + c, G::W, t, twl);
+        reg_fft<L, G::NTMAX, SIGN, G::NB, G::MAXR>(x, lds + c, lds + G::B1OFF + c, G::W, t, twl);
         {
             const auto r = buf_rsrc(out + (long)o0 * L * inner);
 #pragma unroll
@@ -853,8 +856,9 @@ static void fill_g(RegKernels& k) {
 // Variant v: 0 = (32 threads per line max, two buffers), 1 = (32, one buffer),
 // 2 = (16, two buffers), 3 = (16, one buffer), 4 = (64, one buffer), 5 = (32,
 // one buffer, 512-thread blocks: twice the lines per block, so the strided
-// passes move 256-byte row segments).  The hot lengths 128, 256, 512 carry
-// 0..3 and 5 (512 and 1024 also 4); the others have variant 0 only.
+// passes move 256-byte row segments), 6 = variant 1 and 7 = variant 3 with a
+// radix-4/2 stage schedule instead of radix 8.  The hot lengths 128, 256, 512
+// carry 0..3 and 5..7 (512 and 1024 also 4); the others have variant 0 only.
 template <int L>
 static bool fill_v(int v, RegKernels& k) {
     switch (v) {
@@ -863,6 +867,8 @@ static bool fill_v(int v, RegKernels& k) {
         case 2: fill_g<L, Geo<L, 16, 2>>(k); return true;
         case 3: fill_g<L, Geo<L, 16, 1>>(k); return true;
         case 5: fill_g<L, Geo<L, 32, 1, 512>>(k); return true;
+        case 6: fill_g<L, Geo<L, 32, 1, kThreads, 4>>(k); return true;
+        case 7: fill_g<L, Geo<L, 16, 1, kThreads, 4>>(k); return true;
         default: return false;
     }
 }

@@ -16,6 +16,7 @@
 #include "solve_chain.h"
 #include "solve_seg.h"
 #include "tables.h"
+#include "tune_cache.h"
 
 static_assert(sgm::kProjSegRowsDev == sgm::kProjSegRows, "projection segment length mismatch");
 
@@ -224,16 +225,45 @@ static float axis_pass_ms(sgm_plan p, void* u, void* uh, unsigned mask) {
     return sum;
 }
 
+// Take stored choices if every one names a compiled variant that fits.
+static bool apply_tuned(sgm_plan p, const std::array<int, 3>& v, int lds_max) {
+    const int Llast = p->ndim == 3 ? p->M2 : p->M1;
+    RegKernels k[3];
+    const bool has[3] = {p->hx, p->hy, p->hz};
+    const int L[3] = {p->N, p->M1, Llast};
+    for (int a = 0; a < 3; ++a) {
+        if (!has[a]) continue;
+        if (v[a] < 0 || v[a] >= kRegVariants || !reg_kernels_for(L[a], k[a], v[a])) return false;
+        if ((a == 0 ? k[a].lds_cheb : a == 1 ? k[a].lds_str : k[a].lds) > (size_t)lds_max) return false;
+        if (a == 1 && !strided_fits(k[a], p->spec_last)) return false;
+    }
+    if (p->hx) p->rkx = k[0];
+    if (p->hy) p->rky = k[1];
+    if (p->hz) p->rkz = k[2];
+    return true;
+}
+
+static std::string plan_tune_key(sgm_plan p) {
+    char b[160];
+    snprintf(b, sizeof(b), "plan %s ndim%d basis%d %dx%dx%d kind%d", tune_device_tag().c_str(), p->ndim, p->d.basis,
+             p->N, p->M1, p->M2, p->d.kind_last);
+    return b;
+}
+
 static sgm_status autotune_plan(sgm_plan p, int lds_max) {
     TuneKey key{p->ndim, p->d.basis, p->N, p->M1, p->M2, p->d.kind_last};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find(key);
-        if (it != g_tuned.end()) {
-            int Llast = p->ndim == 3 ? p->M2 : p->M1;
-            if (p->hx) reg_kernels_for(p->N, p->rkx, it->second[0]);
-            if (p->hy) reg_kernels_for(p->M1, p->rky, it->second[1]);
-            if (p->hz) reg_kernels_for(Llast, p->rkz, it->second[2]);
+        if (it != g_tuned.end() && apply_tuned(p, it->second, lds_max)) return SGM_OK;
+    }
+    const std::string fkey = plan_tune_key(p);
+    std::vector<int> cached;
+    if (tune_cache_get(fkey, cached) && cached.size() == 3) {
+        const std::array<int, 3> v{cached[0], cached[1], cached[2]};
+        if (apply_tuned(p, v, lds_max)) {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tuned[key] = v;
             return SGM_OK;
         }
     }
@@ -267,6 +297,7 @@ static sgm_status autotune_plan(sgm_plan p, int lds_max) {
     }
     hipFree(u);
     hipFree(uh);
+    tune_cache_put(fkey, {best[0], best[1], best[2]});
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[key] = best;
     return SGM_OK;
@@ -275,6 +306,22 @@ static sgm_status autotune_plan(sgm_plan p, int lds_max) {
 extern "C" {
 
 int sgm_version(void) { return 1; }
+
+sgm_status sgm_autotune_forget(void) {
+    clear_error();
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.clear();
+    return SGM_OK;
+}
+
+sgm_status sgm_autotune_cache_path(char* buf, int len) {
+    clear_error();
+    SGM_CHECK_ARG(buf && len > 0, "null buffer");
+    const std::string p = tune_cache_path();
+    SGM_CHECK_ARG((int)p.size() < len, "buffer too small (%d bytes needed)", (int)p.size() + 1);
+    std::memcpy(buf, p.c_str(), p.size() + 1);
+    return SGM_OK;
+}
 
 const char* sgm_last_error(void) { return g_last_error.c_str(); }
 

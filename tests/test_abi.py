@@ -63,3 +63,15 @@ def test_fno_create_rejects_sizes_before_any_device_call():
     assert lib.sgm_fno_create(ctypes.byref(d), 1, ctypes.byref(out)) == -1
     assert b"2^31" in lib.sgm_last_error()
     assert not out.value
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsgm.so not built")
+def test_autotune_cache_path_follows_environment(monkeypatch):
+    from paper_1708_03188_amd.api import autotune_cache_path
+    monkeypatch.setenv("SGM_TUNE_CACHE", "/tmp/some/where/tune.txt")
+    assert autotune_cache_path() == "/tmp/some/where/tune.txt"
+    monkeypatch.setenv("SGM_TUNE_CACHE", "off")
+    assert autotune_cache_path() == ""
+    monkeypatch.delenv("SGM_TUNE_CACHE")
+    monkeypatch.setenv("XDG_CACHE_HOME", "/tmp/xdg")
+    assert autotune_cache_path() == "/tmp/xdg/libsgm/tune.txt"

@@ -207,7 +207,7 @@ def test_full_size_sampled(Plan, basis, N):
     assert rel_err(back[mask], vh[mask]) < TOL_T
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("basis", ["dirichlet", "biharmonic"])
 @pytest.mark.parametrize("shape", [(128, 256, 128), (256, 128, 512), (512, 128, 256), (256, 64)])
 def test_kernel_variants(Plan, variant, basis, shape):

@@ -3,6 +3,7 @@ ordinary backward transform, through the C ABI: identical results on two calls i
 a row (the second on a smaller space), no device allocation by the call, and the
 size limit rejected before any device work."""
 import ctypes
+import gc
 
 import numpy as np
 import pytest
@@ -39,14 +40,23 @@ def test_noalloc_backward_matches_backward_on_two_calls():
         torch.cuda.synchronize()
         assert torch.equal(got, ref), (basis, shape)
     # the call allocates nothing: free device memory is unchanged across a call
+    # (objects of earlier tests are collected first, and the collector is held off
+    # meanwhile, so no release of theirs lands inside the measured interval)
     p, uh = _case("dirichlet", 48, 36, 24, seed=3)
     out = torch.empty(p.phys_shape, dtype=p.phys_dtype, device="cuda")
     p.backward_noalloc(uh, out=out)
     torch.cuda.synchronize()
-    before = _mem_free()
-    p.backward_noalloc(uh, out=out)
+    gc.collect()
     torch.cuda.synchronize()
-    assert _mem_free() == before
+    gc.disable()
+    try:
+        before = _mem_free()
+        p.backward_noalloc(uh, out=out)
+        torch.cuda.synchronize()
+        after = _mem_free()
+    finally:
+        gc.enable()
+    assert after == before
     assert torch.equal(out, p.backward(uh))
 
 
