@@ -131,10 +131,13 @@ sgm_status sgm_backward_noalloc(sgm_plan plan, const void* u_hat, void* u, void*
  * sides of every solve).  Same layouts as sgm_forward. */
 sgm_status sgm_scalar_product(sgm_plan plan, const void* f, void* f_tilde, void* stream);
 
-/* Helmholtz solve alpha u - lap u = f for the Shen-Dirichlet (or regular
- * Chebyshev is rejected) plan: per Fourier wavenumber column with
- * kappa^2 = (2pi m/Ly)^2 + (2pi n/Lz)^2, solves (-A + (kappa^2 + alpha) B) u_hat = f_tilde
- * (eq. cheb_poisson, eq. laplace), A_ml = (phi_l'', phi_m), B_ml = (phi_l, phi_m).
+/* Helmholtz solve alpha u - lap u = f for a Shen-Dirichlet plan, Chebyshev
+ * (SGM_SHEN_DIRICHLET) or Legendre (SGM_LEG_DIRICHLET); other bases are rejected:
+ * per Fourier wavenumber column with kappa^2 = (2pi m/Ly)^2 + (2pi n/Lz)^2, solves
+ * (-A + (kappa^2 + alpha) B) u_hat = f_tilde (eq. cheb_poisson, eq. laplace),
+ * A_ml = (phi_l'', phi_m), B_ml = (phi_l, phi_m) in the basis's own weighted inner
+ * product (Chebyshev weight, resp. weight 1: then -A = diag(4l + 6) and B has
+ * 2/(2l+1) + 2/(2l+5) on the diagonal and -2/(2l+5) two places off it).
  * f_tilde and u_hat are spectral arrays (rows >= N-2 of f_tilde ignored); they
  * may be the same pointer (in-place).  alpha >= 0.  INVALID_ARG otherwise.  The
  * first call with a given alpha also refreshes a plan-owned table of elimination
@@ -146,8 +149,8 @@ sgm_status sgm_helmholtz_solve(sgm_plan plan, double alpha, const void* f_tilde,
  * scalar_product(f)), i.e. sgm_scalar_product followed by sgm_helmholtz_solve
  * (Sec. 4: right-hand side scalar product, then the per-wavenumber solve).  f:
  * physical real array (as u in sgm_forward), u_hat: spectral output; they must
- * not overlap; f is not modified.  Where the plan allows (x axis of 256 points
- * on 8-column tiles) the Chebyshev pass and the solve run as one kernel, the
+ * not overlap; f is not modified.  Where the plan allows (Chebyshev x axis of 256
+ * points on 8-column tiles) the Chebyshev pass and the solve run as one kernel, the
  * solve reading the scalar product from on-chip memory; otherwise the two
  * calls run in turn.  Table refresh and races as sgm_helmholtz_solve. */
 sgm_status sgm_helmholtz_solve_physical(sgm_plan plan, double alpha, const void* f, void* u_hat, void* stream);

@@ -24,10 +24,17 @@ Newton's method on L_N started at the Chebyshev-Gauss points.
 Forward transform: the weighted least-squares projection min sum_j w_j |u_j -
 sum_l u_hat_l phi_l(x_j)|^2 (B^{-1} S(u), eq. projection), by a dense Householder
 QR in extended precision; backward: u(x_j) = sum_l u_hat_l phi_l(x_j).
+
+Galerkin matrices (Sec. 3.4, eq. cheb_poisson with the Legendre weight 1): mass
+B_ml = (phi_l, phi_m) and stiffness A_ml = (phi_l'', phi_m) by Legendre-Gauss
+quadrature in extended precision (exact: the integrands have degree <= 2N - 2);
+derivatives of the basis functions from the exact Legendre derivative relation
+(numpy.polynomial.legendre.legder on extended-precision coefficients).
 """
 import functools
 
 import numpy as np
+from numpy.polynomial import legendre as nplegendre
 
 from .linalg import householder_qr, lstsq_qr
 
@@ -112,6 +119,17 @@ def synthesis(basis, N):
     return lmatrix(N) @ recombination(basis, N)
 
 
+@functools.lru_cache(maxsize=32)
+def derivative_synthesis(basis, N, order):
+    """Phi^(order)[j, l] = phi_l^(order)(x_j) (extended precision)."""
+    P = recombination(basis, N)
+    D = np.zeros_like(P)
+    for l in range(P.shape[1]):
+        d = nplegendre.legder(P[:, l], order)
+        D[: len(d), l] = d
+    return lmatrix(N) @ D
+
+
 def _apply_left(mat, a, axis):
     a = np.moveaxis(np.asarray(a), axis, 0)
     sh = a.shape
@@ -135,6 +153,13 @@ def mass_matrix(basis, N):
     Phi = synthesis(basis, N)
     w = nodes_weights(N)[1]
     return Phi.T @ (Phi * w[:, None])
+
+
+@functools.lru_cache(maxsize=32)
+def stiffness_matrix(basis, N):
+    """A[m, l] = (phi_l'', phi_m) by Legendre-Gauss quadrature."""
+    w = nodes_weights(N)[1]
+    return synthesis(basis, N).T @ (derivative_synthesis(basis, N, 2) * w[:, None])
 
 
 @functools.lru_cache(maxsize=16)

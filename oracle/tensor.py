@@ -114,14 +114,15 @@ def _solve_columns(ftilde, k2, build, nb, cols):
 
 
 def helmholtz_solve(basis, ftilde, alpha, M_last, kind_last="r2c", cols=None):
-    """Solve (-A + (kappa^2+alpha) B) u_hat = f_tilde per wavenumber column.
+    """Solve (-A + (kappa^2+alpha) B) u_hat = f_tilde per wavenumber column
+(Chebyshev-Dirichlet with the Chebyshev weight, Legendre-Dirichlet with weight 1).
 
     Returns the full spectral array, or an N x len(cols) array if `cols`
     (flat column indices into spectral dims 1..) is given."""
     N = ftilde.shape[0]
     nb = _xmod(basis).nbasis(basis, N)
-    A = cheb.stiffness_matrix(basis, N)
-    B = cheb.mass_matrix(basis, N)
+    A = _xmod(basis).stiffness_matrix(basis, N)
+    B = _xmod(basis).mass_matrix(basis, N)
     k2 = kappa2(ftilde.shape, M_last, kind_last)
     out = _solve_columns(ftilde, k2, lambda kk: -A + (np.longdouble(kk) + np.longdouble(alpha)) * B, nb, cols)
     return out.reshape(ftilde.shape) if cols is None else out

@@ -25,6 +25,11 @@ struct LegTables {
     int basis = 0, N = 0, nb = 0;
     std::vector<double> x, w;   // points (descending) and weights
     std::vector<double> fwd, bwd, sp;
+    // Legendre-Dirichlet Galerkin rows per parity (the layout of ChebTables::solve):
+    // -A = diag(4k + 6) (A_ml = (phi_l'', phi_m) = -(phi_l', phi_m') with the Legendre
+    // weight 1), B tridiagonal per parity, no separable tail
+    int npar[2] = {0, 0}, mpar[2] = {0, 0};
+    std::vector<double> solve[2];
 };
 bool build_leg_tables(int basis, int N, LegTables& t, std::string& err);
 

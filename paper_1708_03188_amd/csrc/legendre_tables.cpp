@@ -141,6 +141,25 @@ bool build_leg_tables(int basis, int N, LegTables& t, std::string& err) {
     std::vector<ld> Lam((size_t)N * N);
     for (int k = 0; k < N; ++k)
         for (int j = 0; j < N; ++j) Lam[(size_t)k * N + j] = (ld)(2 * k + 1) / 2 * L[(size_t)j * N + k] * w[j];
+    for (int par = 0; par < 2; ++par) {
+        t.npar[par] = nb > par ? (nb - par + 1) / 2 : 0;
+        t.mpar[par] = N > par ? (N - par + 1) / 2 : 0;
+    }
+    if (basis == SGM_LEG_DIRICHLET) {
+        for (int par = 0; par < 2; ++par) {
+            const int n = t.npar[par];
+            std::vector<double>& S = t.solve[par];
+            S.assign(20 * (size_t)n, 0.0);
+            for (int i = 0; i < n; ++i) {
+                const long k = par + 2 * i;
+                double* row = &S[20 * (size_t)i];
+                row[2] = (double)(4 * k + 6);                                              // -A, diagonal
+                row[7] = (double)((ld)2 / (2 * k + 1) + (ld)2 / (2 * k + 5));              // B, diagonal
+                if (i + 1 < n) row[8] = (double)(-(ld)2 / (2 * k + 5));                   // B_{k, k+2}
+                if (i > 0) row[6] = (double)(-(ld)2 / (2 * k + 1));                       // B_{k, k-2}
+            }
+        }
+    }
     t.fwd.assign((size_t)N * N, 0.0);
     if (basis == SGM_LEGENDRE) {
         for (size_t i = 0; i < Lam.size(); ++i) t.fwd[i] = (double)Lam[i];

@@ -337,6 +337,13 @@ const char* sgm_status_string(sgm_status s) {
     }
 }
 
+// Kind of the segmented solve kernels for a basis (they evaluate the Dirichlet rows
+// in closed form, so Chebyshev- and Legendre-Dirichlet are distinct kinds); the
+// table-driven generic and chain kernels read Legendre-Dirichlet rows, which have
+// the Dirichlet shape (band + a rank-1 tail, here zero), as SGM_SHEN_DIRICHLET.
+static int solve_kind(int basis) { return basis; }
+static int table_kind(int basis) { return basis == SGM_SHEN_BIHARMONIC ? SGM_SHEN_BIHARMONIC : SGM_SHEN_DIRICHLET; }
+
 sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
     clear_error();
     SGM_CHECK_ARG(desc && out, "null argument");
@@ -400,6 +407,11 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
         ct.basis = d.basis;
         ct.N = d.N;
         ct.nb = lt.nb;
+        for (int q = 0; q < 2; ++q) {
+            ct.npar[q] = lt.npar[q];
+            ct.mpar[q] = lt.mpar[q];
+            ct.solve[q] = lt.solve[q];
+        }
         p->xpts = lt.x;
     } else {
         p->xpts.resize(d.N);
@@ -500,9 +512,10 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
             if (st2 != SGM_OK) { hipFree(p->work); hipFree(p->blob); delete p; return st2; }
         }
     }
-    if ((d.basis == SGM_SHEN_DIRICHLET || d.basis == SGM_SHEN_BIHARMONIC) && d.autotune != 2) {
+    if ((d.basis == SGM_SHEN_DIRICHLET || d.basis == SGM_SHEN_BIHARMONIC || d.basis == SGM_LEG_DIRICHLET) &&
+        d.autotune != 2) {
         p->seg_K = seg_lanes(std::max(cd.npar[0], cd.npar[1]));
-        const size_t nt = seg_table_doubles(d.basis, p->seg_K, g.ncols);
+        const size_t nt = seg_table_doubles(solve_kind(d.basis), p->seg_K, g.ncols);
         if (p->seg_K > 0 && nt > 0 && hipMalloc(&p->seg_tab, nt * sizeof(double)) != hipSuccess) {
             set_error("hipMalloc solve table failed");
             hipFree(p->work); hipFree(p->blob); delete p;
@@ -761,6 +774,8 @@ static sgm_status fourier_backward(sgm_plan p, double2* w, void* u, hipStream_t 
     return SGM_OK;
 }
 
+static bool helmholtz_basis(int basis) { return basis == SGM_SHEN_DIRICHLET || basis == SGM_LEG_DIRICHLET; }
+
 // Segmented solve where the chains fit, else one lane per chain.  The
 // boundary table is refilled (one extra launch) when alpha changes.
 static sgm_status seg_table_for(sgm_plan p, int kind, double alpha, hipStream_t s);
@@ -774,7 +789,7 @@ static sgm_status solve_dispatch(sgm_plan p, int kind, double alpha, const void*
         return SGM_OK;
     }
     SGM_HIP_TRY(launch_solve_chain(static_cast<const double2*>(f), static_cast<double2*>(u),
-                                   static_cast<double*>(p->work), p->cd, p->geom, kind, alpha, s));
+                                   static_cast<double*>(p->work), p->cd, p->geom, table_kind(kind), alpha, s));
     return SGM_OK;
 }
 
@@ -792,13 +807,13 @@ sgm_status sgm_helmholtz_solve_physical(sgm_plan p, double alpha, const void* f,
     clear_error();
     SGM_CHECK_ARG(p && f && u_hat, "null argument");
     SGM_CHECK_ARG(f != u_hat, "f and u_hat must not alias");
-    SGM_CHECK_ARG(p->d.basis == SGM_SHEN_DIRICHLET, "Helmholtz solve needs the Shen-Dirichlet basis");
+    SGM_CHECK_ARG(helmholtz_basis(p->d.basis), "Helmholtz solve needs a Shen-Dirichlet (Chebyshev or Legendre) basis");
     SGM_CHECK_ARG(alpha >= 0.0, "alpha must be >= 0 (got %g)", alpha);
     hipStream_t s = static_cast<hipStream_t>(stream);
     double2* uh = static_cast<double2*>(u_hat);
     sgm_status st = fourier_forward(p, f, uh, s);
     if (st != SGM_OK) return st;
-    if (p->hx && p->rkx.cf_spsolve && p->seg_K == 8 && p->d.autotune != 2) {
+    if (!p->leg && p->hx && p->rkx.cf_spsolve && p->seg_K == 8 && p->d.autotune != 2) {
         if ((st = seg_table_for(p, SGM_SHEN_DIRICHLET, alpha, s)) != SGM_OK) return st;
         PassTimer t(p, 5, s);
         const RegKernels& k = p->rkx;
@@ -817,14 +832,14 @@ sgm_status sgm_helmholtz_solve_physical(sgm_plan p, double alpha, const void* f,
 sgm_status sgm_helmholtz_solve(sgm_plan p, double alpha, const void* f_tilde, void* u_hat, void* stream) {
     clear_error();
     SGM_CHECK_ARG(p && f_tilde && u_hat, "null argument");
-    SGM_CHECK_ARG(p->d.basis == SGM_SHEN_DIRICHLET, "Helmholtz solve needs the Shen-Dirichlet basis");
+    SGM_CHECK_ARG(helmholtz_basis(p->d.basis), "Helmholtz solve needs a Shen-Dirichlet (Chebyshev or Legendre) basis");
     SGM_CHECK_ARG(alpha >= 0.0, "alpha must be >= 0 (got %g)", alpha);
     PassTimer t(p, 7, static_cast<hipStream_t>(stream));
     if (p->d.autotune == 2)
         SGM_HIP_TRY(launch_solve(static_cast<const double2*>(f_tilde), static_cast<double2*>(u_hat), p->cd, p->geom,
-                                 p->W_solve, SGM_SHEN_DIRICHLET, alpha, static_cast<hipStream_t>(stream)));
+                                 p->W_solve, table_kind(p->d.basis), alpha, static_cast<hipStream_t>(stream)));
     else
-        return solve_dispatch(p, SGM_SHEN_DIRICHLET, alpha, f_tilde, u_hat, static_cast<hipStream_t>(stream));
+        return solve_dispatch(p, solve_kind(p->d.basis), alpha, f_tilde, u_hat, static_cast<hipStream_t>(stream));
     return SGM_OK;
 }
 

@@ -112,7 +112,7 @@ int seg_lanes(int nmax) {
 }
 
 size_t seg_table_doubles(int kind, int K, int ncols) {
-    const int WS = kind == SGM_SHEN_DIRICHLET ? SegTraits<SGM_SHEN_DIRICHLET>::WS : SegTraits<SGM_SHEN_BIHARMONIC>::WS;
+    const int WS = kind == SGM_SHEN_BIHARMONIC ? SegTraits<SGM_SHEN_BIHARMONIC>::WS : SegTraits<SGM_SHEN_DIRICHLET>::WS;
     return K > 1 ? (size_t)(K - 1) * 2 * ncols * WS : 0;
 }
 
@@ -122,6 +122,9 @@ hipError_t launch_seg_table(double* tab, const ChebDev& cd, const ColGeom& g, in
     const int blocks = (2 * g.ncols + 255) / 256;
     if (kind == SGM_SHEN_DIRICHLET)
         hipLaunchKernelGGL(k_seg_table<SGM_SHEN_DIRICHLET>, dim3(blocks), dim3(256), 0, s, cd, g, alpha, kSegRows, K,
+                           tab);
+    else if (kind == SGM_LEG_DIRICHLET)
+        hipLaunchKernelGGL(k_seg_table<SGM_LEG_DIRICHLET>, dim3(blocks), dim3(256), 0, s, cd, g, alpha, kSegRows, K,
                            tab);
     else
         hipLaunchKernelGGL(k_seg_table<SGM_SHEN_BIHARMONIC>, dim3(blocks), dim3(256), 0, s, cd, g, alpha, kSegRows, K,
@@ -138,6 +141,16 @@ hipError_t launch_solve_seg(const double2* in, double2* out, const double* tab, 
             case 4: return launch_seg_k<SGM_SHEN_DIRICHLET, 4>(in, out, tab, cd, g, alpha, s);
             case 8: return launch_seg_k<SGM_SHEN_DIRICHLET, 8>(in, out, tab, cd, g, alpha, s);
             case 16: return launch_seg_k<SGM_SHEN_DIRICHLET, 16>(in, out, tab, cd, g, alpha, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (kind == SGM_LEG_DIRICHLET) {
+        switch (K) {
+            case 1: return launch_seg_k<SGM_LEG_DIRICHLET, 1>(in, out, tab, cd, g, alpha, s);
+            case 2: return launch_seg_k<SGM_LEG_DIRICHLET, 2>(in, out, tab, cd, g, alpha, s);
+            case 4: return launch_seg_k<SGM_LEG_DIRICHLET, 4>(in, out, tab, cd, g, alpha, s);
+            case 8: return launch_seg_k<SGM_LEG_DIRICHLET, 8>(in, out, tab, cd, g, alpha, s);
+            case 16: return launch_seg_k<SGM_LEG_DIRICHLET, 16>(in, out, tab, cd, g, alpha, s);
             default: return hipErrorInvalidValue;
         }
     }

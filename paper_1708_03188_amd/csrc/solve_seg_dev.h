@@ -13,14 +13,15 @@ __device__ __forceinline__ int wnum(int q, int M) { return q < (M + 1) / 2 ? q :
 
 template <int KIND>
 struct SegTraits {
-    static constexpr int P = KIND == SGM_SHEN_DIRICHLET ? 1 : 2;
+    static constexpr int P = (KIND == SGM_SHEN_DIRICHLET || KIND == SGM_LEG_DIRICHLET) ? 1 : 2;
     static constexpr int Q = P, S = P, NR = P;
     static constexpr int NC = Q + NR;      // c-state components
     static constexpr int WS = NC * P;      // w-state doubles
 };
 
-// Band, tail factors of row i < n of the chain of parity p (Dirichlet in
-// closed form, biharmonic from the plan's row table, 20 doubles per row).
+// Band, tail factors of row i < n of the chain of parity p (Chebyshev- and
+// Legendre-Dirichlet in closed form, biharmonic from the plan's row table, 20
+// doubles per row).
 template <int KIND>
 __device__ __forceinline__ void row_coeffs(const double* rows, int p, int i, int n, double mu1, double mu2,
                                            double* band, double* U, double* V) {
@@ -32,6 +33,16 @@ __device__ __forceinline__ void row_coeffs(const double* rows, int p, int i, int
         band[1] = 4.0 * kHalfPi * (k + 1.0) * (k + 2.0) + mu1 * kHalfPi * (ck + 1.0);
         band[2] = i + 1 < n ? -mu1 * kHalfPi : 0.0;
         U[0] = 8.0 * kHalfPi * (k + 1.0);
+        V[0] = 1.0;
+    } else if constexpr (KIND == SGM_LEG_DIRICHLET) {
+        // -A = diag(4k + 6), B: 2/(2k+1) + 2/(2k+5) on the diagonal, -2/(2k+5) and
+        // -2/(2k+1) two places right and left; no tail
+        const double k = (double)(p + 2 * i);
+        const double r1 = 2.0 / (2.0 * k + 1.0), r5 = 2.0 / (2.0 * k + 5.0);
+        band[0] = i >= 1 ? -mu1 * r1 : 0.0;
+        band[1] = 4.0 * k + 6.0 + mu1 * (r1 + r5);
+        band[2] = i + 1 < n ? -mu1 * r5 : 0.0;
+        U[0] = 0.0;
         V[0] = 1.0;
     } else {
         const double2* row = reinterpret_cast<const double2*>(rows + 20 * i);
@@ -64,8 +75,9 @@ __device__ __forceinline__ void chain_mu(const ColGeom& g, int kind, int col, do
     const double m = g.Mmid > 1 ? (double)wnum(iy, g.Mmid) : 0.0;
     const double nn = g.last_r2c ? (double)iz : (double)wnum(iz, g.Mlast);
     const double k2 = g.sy * m * m + g.sz * nn * nn;
-    mu1 = kind == SGM_SHEN_DIRICHLET ? k2 + alpha : -2.0 * k2;
-    mu2 = kind == SGM_SHEN_DIRICHLET ? 0.0 : k2 * k2;
+    const bool helm = kind == SGM_SHEN_DIRICHLET || kind == SGM_LEG_DIRICHLET;
+    mu1 = helm ? k2 + alpha : -2.0 * k2;
+    mu2 = helm ? 0.0 : k2 * k2;
 }
 
 // One step of the w recurrence (row i); returns 1/coef0 and b.

@@ -99,3 +99,31 @@ def test_poisson_1d_legendre_dirichlet_paper_example():
     ft = L.scalar_product("leg_dirichlet", f)
     uh = ft / (4 * np.arange(N - 2) + 6.0)
     assert np.abs(L.backward("leg_dirichlet", uh) - u).max() < 1e-13
+
+
+@pytest.mark.parametrize("N", [6, 17, 64])
+def test_stiffness_matrix_is_minus_the_diagonal_closed_form(N):
+    # A_ml = (phi_l'', phi_m) = -(phi_l', phi_m') = -(4l + 6) delta_lm: by parts (phi_m
+    # vanishes at +-1) and phi_l' = -(2l + 3) L_{l+1}, (L_k, L_k) = 2 / (2k + 1)
+    A = np.asarray(L.stiffness_matrix("leg_dirichlet", N), dtype=float)
+    assert np.abs(A + np.diag(4 * np.arange(N - 2) + 6.0)).max() < 1e-12
+
+
+@pytest.mark.parametrize("alpha", [0.0, 1.5])
+def test_helmholtz_2d_legendre_manufactured_exact_coefficients(alpha):
+    # u = (1 - x^2)(x^3 + 2x - 0.5) cos(2y) lies in the Legendre-Dirichlet x Fourier
+    # space, so the Galerkin solution of -lap u + alpha u = f is u itself:
+    # the solve must return the projection of u (its exact coefficients)
+    from oracle import tensor as T
+    N, M = 12, 8
+    x = L.points(N)
+    y = 2 * PI * np.arange(M) / M
+    p = (1 - x**2) * (x**3 + 2 * x - 0.5)
+    # p'' = d2/dx2 of -x^5 - x^3 + 0.5 x^2 + 2x - 0.5
+    p2 = -20 * x**3 - 6 * x + 1.0
+    u = p[:, None] * np.cos(2 * y)[None, :]
+    f = (-p2 + (4 + alpha) * p)[:, None] * np.cos(2 * y)[None, :]
+    ft = T.scalar_product("leg_dirichlet", f)
+    uh = T.helmholtz_solve("leg_dirichlet", ft, alpha, M)
+    assert np.abs(uh - T.forward("leg_dirichlet", u)).max() < 1e-13
+    assert np.abs(T.backward("leg_dirichlet", uh, M) - u).max() < 1e-13
