@@ -379,14 +379,28 @@ static int reg_w(int kind) {
     }
 }
 
-// Items are taken in a grid-stride loop (a persistent grid when gridDim.x is
-// smaller than the item count, one block per item otherwise).
+// The items of a launch in 8 contiguous chunks, chunk x taken by the blocks
+// b = x mod 8 (work-groups go to the 8 XCDs round-robin, block b to XCD b mod 8)
+// in a stride loop: neighbouring column tiles share the cache lines at their
+// edges (tiles of 4 or 5 columns are 64 or 80 bytes wide), and those then meet
+// in one XCD's L2.  A persistent grid when gridDim.x is smaller than the item
+// count, one block per item otherwise; a plain grid stride when the grid is not
+// a multiple of 8.
+struct ItemRange {
+    int it, hi, step;
+};
+__device__ __forceinline__ ItemRange item_range(int n) {
+    const int G = (int)gridDim.x, b = (int)blockIdx.x;
+    if (G & 7) return {b, n, G};
+    const int x = b & 7;
+    return {(int)((long)n * x / 8) + (b >> 3), (int)((long)n * (x + 1) / 8), G >> 3};
+}
 template <class CF, bool GEN>
 __global__ void __launch_bounds__(kGlThreads, kGlWavesPerSimd) k_gl_rows_inv(const GLProb* probs, const GLItem* items, int nitems,
                                                             const double2* src, double2* work) {
     extern __shared__ double2 lds[];
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const GLItem item = items[it];
+    for (ItemRange r = item_range(nitems); r.it < r.hi; r.it += r.step) {
+        const GLItem item = items[r.it];
         const GLProb pr = probs[item.prob];
         if constexpr (GEN) {
             rows_inv_gen(pr, item.line0, src, work, lds);
@@ -403,8 +417,8 @@ template <class CF, bool GEN>
 __global__ void __launch_bounds__(kGlThreads, kGlWavesPerSimd) k_gl_cols(const GLProb* probs, const GLItem* items, int nitems,
                                                         double2* work, double cnl) {
     extern __shared__ double2 lds[];
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const GLItem item = items[it];
+    for (ItemRange r = item_range(nitems); r.it < r.hi; r.it += r.step) {
+        const GLItem item = items[r.it];
         const GLProb pr = probs[item.prob];
         if constexpr (GEN) {
             cols_gen(pr, item.line0, work, lds, cnl);
@@ -421,8 +435,8 @@ template <class CF, bool GEN, bool FUSE>
 __global__ void __launch_bounds__(kGlThreads, kGlWavesPerSimd) k_gl_rows_fwd(const GLProb* probs, const GLItem* items, int nitems,
                                                             double2* work, GLStage st) {
     extern __shared__ double2 lds[];
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const GLItem item = items[it];
+    for (ItemRange r = item_range(nitems); r.it < r.hi; r.it += r.step) {
+        const GLItem item = items[r.it];
         const GLProb pr = probs[item.prob];
         if constexpr (GEN) {
             rows_fwd_gen(pr, item.line0, work, lds, st, FUSE);
@@ -514,7 +528,7 @@ extern "C" sgm_status sgm_gl_destroy(sgm_gl g) {
 }
 
 static int gl_grid(sgm_gl g, int k, int n) {
-    if (g->gridmode == 1) return n;
+    if (g->gridmode == 1) return (n + 7) & ~7;  // one block per item (a multiple of 8: see item_range)
     const int per_cu = std::min(8, std::max(1, (int)(g->lmax / std::max<size_t>(g->lds[k], 1))));
     return std::min(n, g->ncu * per_cu);
 }
