@@ -89,9 +89,12 @@ typedef struct {
 /* Create a plan for the tensor-product space V(x) x V^p(y) [x V^p(z)] (Sec. 4,
  * TensorProductSpace).  Uploads twiddle, recombination, projection and
  * solver tables and allocates one spectral-sized workspace on the current
- * device.  Errors: INVALID_ARG (null pointers, bad enums), UNSUPPORTED_SIZE
- * (N below the basis minimum, sizes above 65536 points per axis), OOM, HIP. */
-sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out);
+ * device.  stream (a hipStream_t, null for the default stream) carries the
+ * uploads and, with autotune = 1, the timing runs; the call synchronises that
+ * stream before it returns, and leaves other streams alone.  Errors:
+ * INVALID_ARG (null pointers, bad enums), UNSUPPORTED_SIZE (N below the basis
+ * minimum, sizes above 65536 points per axis), OOM, HIP. */
+sgm_status sgm_plan_create(const sgm_plan_desc* desc, void* stream, sgm_plan* out);
 sgm_status sgm_plan_destroy(sgm_plan plan);
 
 /* Physical and spectral shapes in elements (unused trailing dims are 1). */
@@ -229,9 +232,11 @@ typedef struct {
 
 /* Create a batch: uploads the per-problem descriptors, work lists and twiddle
  * tables and allocates two state-sized stage buffers and one padded workspace
- * (sum_i N_i floor(3 N_i / 2) complex elements).  Errors: INVALID_ARG,
+ * (sum_i N_i floor(3 N_i / 2) complex elements).  stream (hipStream_t, null for
+ * the default stream) carries the uploads and, with tune = 1, the timing runs;
+ * the call synchronises that stream before it returns.  Errors: INVALID_ARG,
  * UNSUPPORTED_SIZE, OOM, HIP. */
-sgm_status sgm_gl_create(const sgm_gl_desc* desc, sgm_gl* out);
+sgm_status sgm_gl_create(const sgm_gl_desc* desc, void* stream, sgm_gl* out);
 sgm_status sgm_gl_destroy(sgm_gl gl);
 /* Number of problems of the batch. */
 sgm_status sgm_gl_count(sgm_gl gl, int* count);

@@ -49,7 +49,7 @@ _SIGS = {
     "sgm_version": ([], ctypes.c_int),
     "sgm_last_error": ([], ctypes.c_char_p),
     "sgm_status_string": ([ctypes.c_int], ctypes.c_char_p),
-    "sgm_plan_create": ([ctypes.POINTER(PlanDesc), ctypes.POINTER(_vp)], ctypes.c_int),
+    "sgm_plan_create": ([ctypes.POINTER(PlanDesc), _vp, ctypes.POINTER(_vp)], ctypes.c_int),
     "sgm_plan_destroy": ([_vp], ctypes.c_int),
     "sgm_plan_shapes": ([_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "sgm_forward": ([_vp, _vp, _vp, _vp], ctypes.c_int),
@@ -65,7 +65,7 @@ _SIGS = {
     "sgm_biharmonic_solve": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "sgm_plan_timing": ([_vp, ctypes.c_int], ctypes.c_int),
     "sgm_plan_variants": ([_vp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
-    "sgm_gl_create": ([ctypes.POINTER(GLDesc), ctypes.POINTER(_vp)], ctypes.c_int),
+    "sgm_gl_create": ([ctypes.POINTER(GLDesc), _vp, ctypes.POINTER(_vp)], ctypes.c_int),
     "sgm_gl_destroy": ([_vp], ctypes.c_int),
     "sgm_gl_offsets": ([_vp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "sgm_gl_count": ([_vp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),

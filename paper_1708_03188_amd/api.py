@@ -44,7 +44,7 @@ class Plan:
         d = PlanDesc(ndim, BASES[basis], int(N), int(M1), int(M2 or 1), KINDS[kind_last], float(Ly), float(Lz),
                      2 if generic else (16 + int(variant)) if variant is not None else int(bool(autotune)))
         h = ctypes.c_void_p()
-        check(lib.sgm_plan_create(ctypes.byref(d), ctypes.byref(h)), "sgm_plan_create")
+        check(lib.sgm_plan_create(ctypes.byref(d), _stream(), ctypes.byref(h)), "sgm_plan_create")
         self._h = h
         phys = (ctypes.c_int64 * 3)()
         spec = (ctypes.c_int64 * 3)()
@@ -197,7 +197,7 @@ class GLBatch:
                         _lib.SGM_IFRK4 if scheme == "ifrk4" else _lib.SGM_RK4, int(bool(graph)),
                         1 if tune is True else 0 if tune is False else 16 + int(tune))
         h = ctypes.c_void_p()
-        check(lib.sgm_gl_create(ctypes.byref(d), ctypes.byref(h)), "sgm_gl_create")
+        check(lib.sgm_gl_create(ctypes.byref(d), _stream(), ctypes.byref(h)), "sgm_gl_create")
         self._h = h
         offs = (ctypes.c_int64 * (len(self.sizes) + 1))()
         check(lib.sgm_gl_offsets(h, offs), "sgm_gl_offsets")

@@ -596,8 +596,8 @@ static std::string gl_tune_key(sgm_gl g) {
 
 // Times one step of each candidate configuration on a scratch state and keeps
 // the fastest (or takes the choice stored for this device and batch shape).
-// Runs on the default stream before the batch is handed out.
-static sgm_status gl_autotune(sgm_gl g, int64_t os) {
+// Runs on the creation stream before the batch is handed out.
+static sgm_status gl_autotune(sgm_gl g, int64_t os, hipStream_t s) {
     const std::string key = gl_tune_key(g);
     std::vector<int> cached;
     if (tune_cache_get(key, cached) && cached.size() == 1 && cached[0] >= 0 && cached[0] < 2 * kGlCfgs &&
@@ -615,7 +615,7 @@ static sgm_status gl_autotune(sgm_gl g, int64_t os) {
     sgm_status r = SGM_OK;
     float best = 1e30f;
     int bcfg = 0, bgrid = 0;
-    if (hipMemset(state, 0, (size_t)os * sizeof(double2)) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+    if (hipMemsetAsync(state, 0, (size_t)os * sizeof(double2), s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
         hipEventCreate(&e1) != hipSuccess) {
         set_error("tuning set-up failed");
         r = SGM_ERR_HIP;
@@ -624,13 +624,13 @@ static sgm_status gl_autotune(sgm_gl g, int64_t os) {
         if (!g->cfg_ok[v / 2]) continue;
         g->cfg = v / 2;
         g->gridmode = v % 2;
-        r = gl_enqueue_step(g, state, nullptr);
+        r = gl_enqueue_step(g, state, s);
         float tmin = 1e30f;
         for (int rep = 0; rep < 3 && r == SGM_OK; ++rep) {
-            hipEventRecord(e0, nullptr);
-            r = gl_enqueue_step(g, state, nullptr);
-            if (r == SGM_OK) r = gl_enqueue_step(g, state, nullptr);
-            hipEventRecord(e1, nullptr);
+            hipEventRecord(e0, s);
+            r = gl_enqueue_step(g, state, s);
+            if (r == SGM_OK) r = gl_enqueue_step(g, state, s);
+            hipEventRecord(e1, s);
             if (hipEventSynchronize(e1) != hipSuccess) {
                 set_error("tuning run failed");
                 r = SGM_ERR_HIP;
@@ -646,6 +646,7 @@ static sgm_status gl_autotune(sgm_gl g, int64_t os) {
             bgrid = g->gridmode;
         }
     }
+    hipStreamSynchronize(s);
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
     hipFree(state);
@@ -655,7 +656,7 @@ static sgm_status gl_autotune(sgm_gl g, int64_t os) {
     return r;
 }
 
-extern "C" sgm_status sgm_gl_create(const sgm_gl_desc* desc, sgm_gl* out) {
+extern "C" sgm_status sgm_gl_create(const sgm_gl_desc* desc, void* stream, sgm_gl* out) {
     clear_error();
     SGM_CHECK_ARG(desc && out && desc->N, "null argument");
     *out = nullptr;
@@ -789,8 +790,10 @@ extern "C" sgm_status sgm_gl_create(const sgm_gl_desc* desc, sgm_gl* out) {
         for (int i = 0; i < n; ++i) hp[k][i].rp.tw = twptr(base, g->M[i]);
         std::memcpy(blob.data() + o_p[k], hp[k].data(), n * sizeof(GLProb));
     }
-    e = hipMemcpy(g->dev, blob.data(), blob.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) { set_error("hipMemcpy: %s", hipGetErrorString(e)); sgm_gl_destroy(g); return SGM_ERR_HIP; }
+    hipStream_t cs = static_cast<hipStream_t>(stream);
+    e = hipMemcpyAsync(g->dev, blob.data(), blob.size(), hipMemcpyHostToDevice, cs);
+    if (e == hipSuccess) e = hipStreamSynchronize(cs);  // the host staging buffer goes out of scope
+    if (e != hipSuccess) { set_error("uploading the tables: %s", hipGetErrorString(e)); sgm_gl_destroy(g); return SGM_ERR_HIP; }
     for (int k = 0; k < kGlLists; ++k) {
         g->dprobs[k] = reinterpret_cast<GLProb*>(base + o_p[k]);
         g->ditemsA[k] = reinterpret_cast<GLItem*>(base + o_A[k]);
@@ -822,7 +825,7 @@ extern "C" sgm_status sgm_gl_create(const sgm_gl_desc* desc, sgm_gl* out) {
         g->cfg = v / 2;
         g->gridmode = v % 2;
     } else if (d.tune == 1) {
-        sgm_status r = gl_autotune(g, os);
+        sgm_status r = gl_autotune(g, os, cs);
         if (r != SGM_OK) { sgm_gl_destroy(g); return r; }
     }
     *out = g;

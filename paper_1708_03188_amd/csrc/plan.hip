@@ -196,15 +196,15 @@ static const unsigned kAxisPasses[3] = {(1u << 4) | (1u << 6), (1u << 2) | (1u <
 
 // Time of the given passes in one forward + backward step: best of 8 steps per
 // pass (after one untimed step), so the other axes' passes add no noise.
-static float axis_pass_ms(sgm_plan p, void* u, void* uh, unsigned mask) {
+static float axis_pass_ms(sgm_plan p, void* u, void* uh, unsigned mask, hipStream_t s) {
     const unsigned saved = p->timing;
     p->timing = 0;
-    sgm_forward(p, u, uh, nullptr);
-    sgm_backward(p, uh, u, nullptr);
+    sgm_forward(p, u, uh, s);
+    sgm_backward(p, uh, u, s);
     p->timing = mask;
     for (int r = 0; r < 8; ++r) {
-        sgm_forward(p, u, uh, nullptr);
-        sgm_backward(p, uh, u, nullptr);
+        sgm_forward(p, u, uh, s);
+        sgm_backward(p, uh, u, s);
     }
     p->timing = saved;
     float best[SGM_NPASS];
@@ -250,7 +250,7 @@ static std::string plan_tune_key(sgm_plan p) {
     return b;
 }
 
-static sgm_status autotune_plan(sgm_plan p, int lds_max) {
+static sgm_status autotune_plan(sgm_plan p, int lds_max, hipStream_t s) {
     TuneKey key{p->ndim, p->d.basis, p->N, p->M1, p->M2, p->d.kind_last};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -272,9 +272,13 @@ static sgm_status autotune_plan(sgm_plan p, int lds_max) {
     void* uh = nullptr;
     if (hipMalloc(&u, phys_bytes) != hipSuccess) return SGM_ERR_OOM;
     if (hipMalloc(&uh, (size_t)p->nspec * sizeof(double2)) != hipSuccess) { hipFree(u); return SGM_ERR_OOM; }
-    hipMemset(u, 0, phys_bytes);
-    hipMemset(uh, 0, (size_t)p->nspec * sizeof(double2));
-    hipDeviceSynchronize();
+    if (hipMemsetAsync(u, 0, phys_bytes, s) != hipSuccess ||
+        hipMemsetAsync(uh, 0, (size_t)p->nspec * sizeof(double2), s) != hipSuccess) {
+        hipFree(u);
+        hipFree(uh);
+        set_error("tuning set-up failed");
+        return SGM_ERR_HIP;
+    }
     const int Llast = p->ndim == 3 ? p->M2 : p->M1;
     std::array<int, 3> best{0, 0, 0};
     struct Ax { bool has; RegKernels* rk; int L; int idx; };
@@ -289,12 +293,13 @@ static sgm_status autotune_plan(sgm_plan p, int lds_max) {
             if (ax.idx == 1 && !strided_fits(cand, p->spec_last)) continue;
             RegKernels saved = *ax.rk;
             *ax.rk = cand;
-            const float t = axis_pass_ms(p, u, uh, kAxisPasses[ax.idx]);
+            const float t = axis_pass_ms(p, u, uh, kAxisPasses[ax.idx], s);
             *ax.rk = saved;
             if (t < tbest) { tbest = t; best[ax.idx] = v; }
         }
         reg_kernels_for(ax.L, *ax.rk, best[ax.idx]);
     }
+    hipStreamSynchronize(s);
     hipFree(u);
     hipFree(uh);
     tune_cache_put(fkey, {best[0], best[1], best[2]});
@@ -344,7 +349,7 @@ const char* sgm_status_string(sgm_status s) {
 static int solve_kind(int basis) { return basis; }
 static int table_kind(int basis) { return basis == SGM_SHEN_BIHARMONIC ? SGM_SHEN_BIHARMONIC : SGM_SHEN_DIRICHLET; }
 
-sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
+sgm_status sgm_plan_create(const sgm_plan_desc* desc, void* stream, sgm_plan* out) {
     clear_error();
     SGM_CHECK_ARG(desc && out, "null argument");
     *out = nullptr;
@@ -442,8 +447,10 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
     }
     hipError_t e = hipMalloc(&p->blob, b.host.size());
     if (e != hipSuccess) { set_error("hipMalloc tables: %s", hipGetErrorString(e)); delete p; return SGM_ERR_OOM; }
-    e = hipMemcpy(p->blob, b.host.data(), b.host.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) { set_error("hipMemcpy tables: %s", hipGetErrorString(e)); hipFree(p->blob); delete p; return SGM_ERR_HIP; }
+    hipStream_t cs = static_cast<hipStream_t>(stream);
+    e = hipMemcpyAsync(p->blob, b.host.data(), b.host.size(), hipMemcpyHostToDevice, cs);
+    if (e == hipSuccess) e = hipStreamSynchronize(cs);  // the host staging buffer goes out of scope
+    if (e != hipSuccess) { set_error("uploading the tables: %s", hipGetErrorString(e)); hipFree(p->blob); delete p; return SGM_ERR_HIP; }
     e = hipMalloc(&p->work, (size_t)p->nspec * sizeof(double2));
     if (e != hipSuccess) { set_error("hipMalloc workspace: %s", hipGetErrorString(e)); hipFree(p->blob); delete p; return SGM_ERR_OOM; }
     char* base = static_cast<char*>(p->blob);
@@ -508,7 +515,7 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, sgm_plan* out) {
         if (p->hy && (p->rky.lds_str > (size_t)lds || !strided_fits(p->rky, p->spec_last))) p->hy = false;
         if (p->hz && p->rkz.lds > (size_t)lds) p->hz = false;
         if (d.autotune == 1) {
-            sgm_status st2 = autotune_plan(p, lds);
+            sgm_status st2 = autotune_plan(p, lds, cs);
             if (st2 != SGM_OK) { hipFree(p->work); hipFree(p->blob); delete p; return st2; }
         }
     }

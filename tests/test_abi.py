@@ -41,7 +41,7 @@ def test_status_strings_and_argument_errors_without_gpu():
     assert lib.sgm_status_string(-2) == b"unsupported size"
     assert lib.sgm_version() >= 1
     # A null descriptor is rejected before any device call.
-    assert lib.sgm_plan_create(None, None) == -1
+    assert lib.sgm_plan_create(None, None, None) == -1
     assert b"null" in lib.sgm_last_error()
     # so are null plans and arrays on the solve entry points
     assert lib.sgm_helmholtz_solve(None, 0.0, None, None, None) == -1

@@ -86,3 +86,28 @@ def test_gl_choice_persists_and_reloads(tmp_path, monkeypatch):
     for i, n in enumerate(sizes):
         ref = ogl.ifrk4_step(ogl.forward(us[i]), 0.05, 100.0, 1.5, -2.0)
         assert rel_err(out[i].cpu().numpy(), ref) < 1e-12, n
+
+
+def test_creation_on_a_side_stream(tmp_path, monkeypatch):
+    # plan and batch creation (uploads and tuning runs) enqueued on the caller's
+    # stream: results on that stream equal the oracle's
+    from paper_1708_03188_amd.api import GLBatch, Plan, autotune_forget
+    print("[case] creation on a side stream", flush=True)
+    monkeypatch.setenv("SGM_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    autotune_forget()
+    shape = (24, 16, 12)
+    u = synth.random_smooth_field(shape, seed=8)
+    st = torch.cuda.Stream()
+    us = [synth.gl_noise(16, 1), synth.gl_noise(24, 2)]
+    with torch.cuda.stream(st):
+        p = Plan("dirichlet", *shape, autotune=True)
+        g = GLBatch([16, 24], L=20.0, b=0.5, c=-1.0, dt=0.01, scheme="ifrk4", tune=True)
+        uh = p.forward(torch.from_numpy(u).cuda())
+        state = g.forward(g.pack(us))
+        g.step(state, 1)
+        out = g.unpack(state)
+    st.synchronize()
+    assert rel_err(uh.cpu().numpy(), T.forward("dirichlet", u)) < 1e-12
+    for i in range(2):
+        ref = ogl.ifrk4_step(ogl.forward(us[i]), 0.01, 20.0, 0.5, -1.0)
+        assert rel_err(out[i].cpu().numpy(), ref) < 1e-12
