@@ -86,13 +86,6 @@ __global__ __launch_bounds__(256) void k_leg_pass(const double* __restrict__ Apk
 
 }  // namespace
 
-int leg_row_blocks(int N) {
-    const int rb = (N + 15) / 16;
-    return rb <= 4 ? 4 : rb <= 8 ? 8 : rb <= 16 ? 16 : 32;
-}
-
-size_t leg_packed_doubles(int N) { return (size_t)((N + 3) / 4) * leg_row_blocks(N) * 64; }
-
 hipError_t launch_leg_pass(const double* Apk, const double* in, double* out, int N, long C, hipStream_t s) {
     if (C <= 0) return hipSuccess;
     if (N < 1 || N > kLegMaxN) return hipErrorInvalidValue;

@@ -182,6 +182,13 @@ bool build_leg_tables(int basis, int N, LegTables& t, std::string& err) {
     return true;
 }
 
+int leg_row_blocks(int N) {
+    const int rb = (N + 15) / 16;
+    return rb <= 4 ? 4 : rb <= 8 ? 8 : rb <= 16 ? 16 : 32;
+}
+
+size_t leg_packed_doubles(int N) { return (size_t)((N + 3) / 4) * leg_row_blocks(N) * 64; }
+
 std::vector<double> leg_pack(const std::vector<double>& A, int N) {
     const int KG = (N + 3) / 4, RB = leg_row_blocks(N);
     std::vector<double> out(leg_packed_doubles(N), 0.0);
