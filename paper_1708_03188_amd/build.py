@@ -11,6 +11,7 @@ BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["tables.cpp", "tune_cache.cpp", "legendre_tables.cpp", "legendre.hip", "kernels.hip", "kernels_reg.hip", "solve_chain.hip", "solve_seg.hip", "derivative.hip", "gl.hip", "fno_gemm.hip", "fno_fused.hip", "fno.hip", "plan.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ROCM_LIB = "/opt/rocm/lib"
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -55,7 +56,8 @@ def build(verbose=False, jobs=8):
     if failed:
         raise RuntimeError("HIP compilation failed")
     tmp = LIB + ".tmp"
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs +
+         ["-L" + ROCM_LIB, "-lrocprofiler-sdk-roctx", "-Wl,-rpath," + ROCM_LIB])
     os.replace(tmp, LIB)
     return LIB
 

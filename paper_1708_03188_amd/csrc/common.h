@@ -6,9 +6,20 @@
 #include <cstdio>
 #include <string>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/sgm.h"
 
 namespace sgm {
+
+// Named range around one ABI call, for profilers (rocprofv3 --marker-trace);
+// without a profiler attached the push and pop cost a few nanoseconds.
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePush(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 // Thread-local detail string behind sgm_last_error().
 void set_error(const char* fmt, ...);

@@ -290,6 +290,7 @@ extern "C" sgm_status sgm_fno_destroy(sgm_fno f) {
 
 extern "C" sgm_status sgm_fno_create(const sgm_fno_desc* desc, uint64_t seed, sgm_fno* out) {
     clear_error();
+    TraceRange trace_range("sgm_fno_create");
     SGM_CHECK_ARG(desc && out, "null argument");
     *out = nullptr;
     const sgm_fno_desc& d = *desc;
@@ -643,6 +644,7 @@ static sgm_status fno_backward(sgm_fno f, const float* x, int B, hipStream_t s) 
 
 extern "C" sgm_status sgm_fno_infer(sgm_fno f, const float* x, float* pred, int batch, void* stream) {
     clear_error();
+    TraceRange trace_range("sgm_fno_infer");
     SGM_CHECK_ARG(f && x && pred, "null argument");
     SGM_CHECK_ARG(batch >= 1 && batch <= f->Bmax, "batch must be in 1..%d", f->Bmax);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -657,6 +659,7 @@ extern "C" sgm_status sgm_fno_infer(sgm_fno f, const float* x, float* pred, int 
 extern "C" sgm_status sgm_fno_grads(sgm_fno f, const float* x, const float* target, int batch, float* grads_host,
                                     float* loss_host, void* stream) {
     clear_error();
+    TraceRange trace_range("sgm_fno_grads");
     SGM_CHECK_ARG(f && x && target, "null argument");
     SGM_CHECK_ARG(batch >= 1 && batch <= f->Bmax, "batch must be in 1..%d", f->Bmax);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -682,6 +685,7 @@ extern "C" sgm_status sgm_fno_grads(sgm_fno f, const float* x, const float* targ
 extern "C" sgm_status sgm_fno_train_step(sgm_fno f, const float* x, const float* target, int batch, float lr,
                                          float* loss_host, void* stream) {
     clear_error();
+    TraceRange trace_range("sgm_fno_train_step");
     SGM_CHECK_ARG(f && x && target, "null argument");
     SGM_CHECK_ARG(batch >= 1 && batch <= f->Bmax, "batch must be in 1..%d", f->Bmax);
     SGM_CHECK_ARG(lr > 0 && std::isfinite(lr), "lr must be positive");
@@ -796,6 +800,7 @@ extern "C" sgm_status sgm_fno_advance_checked(sgm_fno f, sgm_gl gl, sgm_gl gl_ch
                                               int steps_per, double tol, double max_fail_frac, uint64_t seed,
                                               sgm_fno_stats* stats, void* stream) {
     clear_error();
+    TraceRange trace_range("sgm_fno_advance_checked");
     SGM_CHECK_ARG(f && gl && gl_check && u_hat, "null argument");
     SGM_CHECK_ARG(nsur >= 0 && steps_per >= 1 && tol > 0, "invalid nsur / steps_per / tol");
     SGM_CHECK_ARG(max_fail_frac >= 0.0 && max_fail_frac <= 1.0, "max_fail_frac must be in [0, 1] (got %g)",

@@ -658,6 +658,7 @@ static sgm_status gl_autotune(sgm_gl g, int64_t os, hipStream_t s) {
 
 extern "C" sgm_status sgm_gl_create(const sgm_gl_desc* desc, void* stream, sgm_gl* out) {
     clear_error();
+    TraceRange trace_range("sgm_gl_create");
     SGM_CHECK_ARG(desc && out && desc->N, "null argument");
     *out = nullptr;
     const sgm_gl_desc& d = *desc;
@@ -855,6 +856,7 @@ extern "C" sgm_status sgm_gl_offsets(sgm_gl g, int64_t* offsets) {
 
 extern "C" sgm_status sgm_gl_rhs(sgm_gl g, const void* u_hat, void* rhs, void* stream) {
     clear_error();
+    TraceRange trace_range("sgm_gl_rhs");
     SGM_CHECK_ARG(g && u_hat && rhs, "null argument");
     SGM_CHECK_ARG(u_hat != rhs, "u_hat and rhs must not alias");
     GLStage st = base_stage(g);
@@ -870,6 +872,7 @@ extern "C" sgm_status sgm_gl_rhs(sgm_gl g, const void* u_hat, void* rhs, void* s
 
 extern "C" sgm_status sgm_gl_step(sgm_gl g, void* u_hat, int nsteps, void* stream) {
     clear_error();
+    TraceRange trace_range("sgm_gl_step");
     SGM_CHECK_ARG(g && u_hat, "null argument");
     SGM_CHECK_ARG(nsteps >= 0, "nsteps must be >= 0");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -933,6 +936,7 @@ static sgm_status gl_transform(sgm_gl g, const double2* in, double2* out, int si
 
 extern "C" sgm_status sgm_gl_forward(sgm_gl g, const void* u, void* u_hat, void* stream) {
     clear_error();
+    TraceRange trace_range("sgm_gl_forward");
     SGM_CHECK_ARG(g && u && u_hat, "null argument");
     SGM_CHECK_ARG(u != u_hat, "u and u_hat must not alias");
     return gl_transform(g, static_cast<const double2*>(u), static_cast<double2*>(u_hat), -1,
@@ -941,6 +945,7 @@ extern "C" sgm_status sgm_gl_forward(sgm_gl g, const void* u, void* u_hat, void*
 
 extern "C" sgm_status sgm_gl_backward(sgm_gl g, const void* u_hat, void* u, void* stream) {
     clear_error();
+    TraceRange trace_range("sgm_gl_backward");
     SGM_CHECK_ARG(g && u && u_hat, "null argument");
     SGM_CHECK_ARG(u != u_hat, "u and u_hat must not alias");
     return gl_transform(g, static_cast<const double2*>(u_hat), static_cast<double2*>(u), 1,

@@ -351,6 +351,7 @@ static int table_kind(int basis) { return basis == SGM_SHEN_BIHARMONIC ? SGM_SHE
 
 sgm_status sgm_plan_create(const sgm_plan_desc* desc, void* stream, sgm_plan* out) {
     clear_error();
+    TraceRange trace_range("sgm_plan_create");
     SGM_CHECK_ARG(desc && out, "null argument");
     *out = nullptr;
     const sgm_plan_desc& d = *desc;
@@ -687,6 +688,7 @@ static hipError_t cheb_forward_pass(sgm_plan p, double2* data, int mode, hipStre
 
 sgm_status sgm_forward(sgm_plan p, const void* u, void* u_hat, void* stream) {
     clear_error();
+    TraceRange trace_range("sgm_forward");
     SGM_CHECK_ARG(p && u && u_hat, "null argument");
     SGM_CHECK_ARG(u != u_hat, "u and u_hat must not alias");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -700,6 +702,7 @@ sgm_status sgm_forward(sgm_plan p, const void* u, void* u_hat, void* stream) {
 
 sgm_status sgm_scalar_product(sgm_plan p, const void* f, void* f_tilde, void* stream) {
     clear_error();
+    TraceRange trace_range("sgm_scalar_product");
     SGM_CHECK_ARG(p && f && f_tilde, "null argument");
     SGM_CHECK_ARG(f != f_tilde, "f and f_tilde must not alias");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -731,6 +734,7 @@ static sgm_status backward_via(sgm_plan p, const void* u_hat, void* u, double2* 
 
 sgm_status sgm_backward(sgm_plan p, const void* u_hat, void* u, void* stream) {
     clear_error();
+    TraceRange trace_range("sgm_backward");
     SGM_CHECK_ARG(p && u && u_hat, "null argument");
     SGM_CHECK_ARG(u != u_hat, "u and u_hat must not alias");
     return backward_via(p, u_hat, u, static_cast<double2*>(p->work), static_cast<hipStream_t>(stream));
@@ -812,6 +816,7 @@ static sgm_status seg_table_for(sgm_plan p, int kind, double alpha, hipStream_t 
 
 sgm_status sgm_helmholtz_solve_physical(sgm_plan p, double alpha, const void* f, void* u_hat, void* stream) {
     clear_error();
+    TraceRange trace_range("sgm_helmholtz_solve_physical");
     SGM_CHECK_ARG(p && f && u_hat, "null argument");
     SGM_CHECK_ARG(f != u_hat, "f and u_hat must not alias");
     SGM_CHECK_ARG(helmholtz_basis(p->d.basis), "Helmholtz solve needs a Shen-Dirichlet (Chebyshev or Legendre) basis");
@@ -838,6 +843,7 @@ sgm_status sgm_helmholtz_solve_physical(sgm_plan p, double alpha, const void* f,
 
 sgm_status sgm_helmholtz_solve(sgm_plan p, double alpha, const void* f_tilde, void* u_hat, void* stream) {
     clear_error();
+    TraceRange trace_range("sgm_helmholtz_solve");
     SGM_CHECK_ARG(p && f_tilde && u_hat, "null argument");
     SGM_CHECK_ARG(helmholtz_basis(p->d.basis), "Helmholtz solve needs a Shen-Dirichlet (Chebyshev or Legendre) basis");
     SGM_CHECK_ARG(alpha >= 0.0, "alpha must be >= 0 (got %g)", alpha);
@@ -853,6 +859,7 @@ sgm_status sgm_helmholtz_solve(sgm_plan p, double alpha, const void* f_tilde, vo
 sgm_status sgm_project_derivative(sgm_plan p, sgm_plan target, const int order[3], const void* u_hat, void* du_hat,
                                   void* stream) {
     clear_error();
+    TraceRange trace_range("sgm_project_derivative");
     SGM_CHECK_ARG(p && target && order && u_hat && du_hat, "null argument");
     SGM_CHECK_ARG(u_hat != du_hat, "u_hat and du_hat must not alias");
     SGM_CHECK_ARG(!p->leg, "the derivative pass takes Chebyshev-family spaces");
@@ -880,6 +887,7 @@ sgm_status sgm_project_derivative(sgm_plan p, sgm_plan target, const int order[3
 
 sgm_status sgm_biharmonic_solve(sgm_plan p, const void* f_tilde, void* u_hat, void* stream) {
     clear_error();
+    TraceRange trace_range("sgm_biharmonic_solve");
     SGM_CHECK_ARG(p && f_tilde && u_hat, "null argument");
     SGM_CHECK_ARG(p->d.basis == SGM_SHEN_BIHARMONIC, "biharmonic solve needs the Shen-biharmonic basis");
     PassTimer t(p, 7, static_cast<hipStream_t>(stream));
