@@ -25,7 +25,7 @@ def _mem_free():
 def _case(basis, N, M1, M2=None, kind="r2c", seed=0):
     from paper_1708_03188_amd.api import Plan
     p = Plan(basis, N, M1, M2, kind_last=kind)
-    nb = N - 2 if basis == "dirichlet" else N - 4 if basis == "biharmonic" else N
+    nb = {"dirichlet": N - 2, "neumann": N - 2, "leg_dirichlet": N - 2, "biharmonic": N - 4}.get(basis, N)
     uh = torch.from_numpy(synth.random_spectral(p.spec_shape, seed=seed, nrows=nb)).cuda()
     return p, uh
 
@@ -58,6 +58,19 @@ def test_noalloc_backward_matches_backward_on_two_calls():
         gc.enable()
     assert after == before
     assert torch.equal(out, p.backward(uh))
+
+
+@pytest.mark.parametrize("basis", ["chebyshev", "neumann", "legendre", "leg_dirichlet", "leg_biharmonic"])
+def test_noalloc_backward_every_basis_family(basis):
+    # the other x-pass kinds (table-driven Chebyshev backward, the dense Legendre pass)
+    # into the static workspace, twice in a row with the second space smaller
+    print(f"[case] sgm_backward_noalloc {basis}", flush=True)
+    for shape, seed in (((40, 24, 18), 11), ((24, 10), 12)):
+        p, uh = _case(basis, *shape, seed=seed)
+        ref = p.backward(uh)
+        got = p.backward_noalloc(uh)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), (basis, shape)
 
 
 def test_noalloc_backward_rejects_oversized_space():
