@@ -163,6 +163,33 @@ def _sample_cols(spec_shape, rng, n=24):
     return np.array(sorted(set(special + rnd)))
 
 
+@pytest.mark.parametrize("basis,N", [("dirichlet", 256), ("biharmonic", 512)])
+def test_full_size_benchmark_configuration(Plan, basis, N):
+    # the benchmark's own plans: autotuned (the kernel variants the benchmark times),
+    # the same synthetic fields; sampled columns and rows against the oracle, and
+    # the solves the benchmark times (alpha 0 and 1 / biharmonic)
+    print(f"[case] benchmark configuration {basis} N={N}", flush=True)
+    M1 = M2 = 256
+    p = Plan(basis, N, M1, M2, autotune=True)
+    u = synth.random_smooth_field((N, M1, M2), seed=2 if basis == "dirichlet" else 3)
+    rng = np.random.default_rng(N + 1)
+    cols = _sample_cols(p.spec_shape, rng, n=16)
+    uh = host(p.forward(dev(u))).reshape(N, -1)
+    assert rel_err(uh[:, cols], T.forward_columns(basis, u, cols)) < TOL_T
+    nb = C.nbasis(basis, N)
+    vh = synth.random_spectral(p.spec_shape, seed=N + 21, nrows=nb)
+    rows = np.array([0, N // 2, N - 1])
+    assert rel_err(host(p.backward(dev(vh)))[rows], T.backward_rows(basis, vh, rows, M2)) < TOL_T
+    fts = synth.random_spectral(p.spec_shape, seed=N + 23, nrows=nb)
+    if basis == "dirichlet":
+        for alpha in (0.0, 1.0):
+            out = host(p.helmholtz_solve(dev(fts), alpha)).reshape(N, -1)[:, cols]
+            assert rel_err(out, T.helmholtz_solve(basis, fts, alpha, M2, cols=cols)) < TOL_S
+    else:
+        out = host(p.biharmonic_solve(dev(fts))).reshape(N, -1)[:, cols]
+        assert rel_err(out, T.biharmonic_solve(basis, fts, M2, cols=cols)) < TOL_S
+
+
 @pytest.mark.parametrize("basis,N", [("dirichlet", 256), ("biharmonic", 512), ("chebyshev", 256)])
 def test_full_size_sampled(Plan, basis, N):
     # The bench shapes: 256^3 Shen-Dirichlet and 512 x 256^2 Shen-biharmonic, R2C.
