@@ -41,6 +41,7 @@ typedef int sgm_status;
 #define SGM_ERR_HIP (-3)
 #define SGM_ERR_OOM (-4)
 #define SGM_ERR_UNIMPLEMENTED (-5)
+#define SGM_ERR_SINGULAR (-6)     /* the requested system has no unique solution (see the solve) */
 
 /* Basis along the non-periodic axis 0. */
 #define SGM_SHEN_DIRICHLET 1  /* phi_l = T_l - T_{l+2}, l = 0..N-3 (eq. chebdirichlet)              */
@@ -135,12 +136,18 @@ sgm_status sgm_backward_noalloc(sgm_plan plan, const void* u_hat, void* u, void*
 sgm_status sgm_scalar_product(sgm_plan plan, const void* f, void* f_tilde, void* stream);
 
 /* Helmholtz solve alpha u - lap u = f for a Shen-Dirichlet plan, Chebyshev
- * (SGM_SHEN_DIRICHLET) or Legendre (SGM_LEG_DIRICHLET); other bases are rejected:
- * per Fourier wavenumber column with kappa^2 = (2pi m/Ly)^2 + (2pi n/Lz)^2, solves
+ * (SGM_SHEN_DIRICHLET) or Legendre (SGM_LEG_DIRICHLET), or a Chebyshev Shen-Neumann
+ * plan (SGM_SHEN_NEUMANN: homogeneous Neumann conditions u'(+-1) = 0); other bases
+ * are rejected: per Fourier wavenumber column with
+ * kappa^2 = (2pi m/Ly)^2 + (2pi n/Lz)^2, solves
  * (-A + (kappa^2 + alpha) B) u_hat = f_tilde (eq. cheb_poisson, eq. laplace),
  * A_ml = (phi_l'', phi_m), B_ml = (phi_l, phi_m) in the basis's own weighted inner
  * product (Chebyshev weight, resp. weight 1: then -A = diag(4l + 6) and B has
- * 2/(2l+1) + 2/(2l+5) on the diagonal and -2/(2l+5) two places off it).
+ * 2/(2l+1) + 2/(2l+5) on the diagonal and -2/(2l+5) two places off it).  Neumann:
+ * with r_l = (l/(l+2))^2, -A_ll = 2 pi l^2 (l+1)/(l+2), -A_ml = pi (1 - r_m) l^2
+ * for l >= m + 2 of the same parity, B_ll = (pi/2)(c_l + r_l^2), B_{l,l+2} =
+ * -(pi/2) r_l; alpha = 0 returns SGM_ERR_SINGULAR before any device work (the
+ * constant mode of the zero wavenumber is then undetermined).
  * f_tilde and u_hat are spectral arrays (rows >= N-2 of f_tilde ignored); they
  * may be the same pointer (in-place).  alpha >= 0.  INVALID_ARG otherwise.  The
  * first call with a given alpha also refreshes a plan-owned table of elimination

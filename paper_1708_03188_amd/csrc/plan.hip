@@ -338,6 +338,7 @@ const char* sgm_status_string(sgm_status s) {
         case SGM_ERR_HIP: return "HIP runtime error";
         case SGM_ERR_OOM: return "out of device memory";
         case SGM_ERR_UNIMPLEMENTED: return "not implemented";
+        case SGM_ERR_SINGULAR: return "singular system";
         default: return "unknown status";
     }
 }
@@ -520,7 +521,8 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, void* stream, sgm_plan* ou
             if (st2 != SGM_OK) { hipFree(p->work); hipFree(p->blob); delete p; return st2; }
         }
     }
-    if ((d.basis == SGM_SHEN_DIRICHLET || d.basis == SGM_SHEN_BIHARMONIC || d.basis == SGM_LEG_DIRICHLET) &&
+    if ((d.basis == SGM_SHEN_DIRICHLET || d.basis == SGM_SHEN_BIHARMONIC || d.basis == SGM_LEG_DIRICHLET ||
+         d.basis == SGM_SHEN_NEUMANN) &&
         d.autotune != 2) {
         p->seg_K = seg_lanes(std::max(cd.npar[0], cd.npar[1]));
         const size_t nt = seg_table_doubles(solve_kind(d.basis), p->seg_K, g.ncols);
@@ -785,7 +787,23 @@ static sgm_status fourier_backward(sgm_plan p, double2* w, void* u, hipStream_t 
     return SGM_OK;
 }
 
-static bool helmholtz_basis(int basis) { return basis == SGM_SHEN_DIRICHLET || basis == SGM_LEG_DIRICHLET; }
+static bool helmholtz_basis(int basis) {
+    return basis == SGM_SHEN_DIRICHLET || basis == SGM_LEG_DIRICHLET || basis == SGM_SHEN_NEUMANN;
+}
+
+// Checks shared by the Helmholtz entry points: the basis, alpha >= 0, and for the
+// Neumann basis alpha > 0 (at kappa = 0 and alpha = 0 the constant leaves the
+// system singular).
+static sgm_status helmholtz_args(sgm_plan p, double alpha) {
+    SGM_CHECK_ARG(helmholtz_basis(p->d.basis),
+                  "Helmholtz solve needs a Shen-Dirichlet (Chebyshev or Legendre) or Shen-Neumann basis");
+    SGM_CHECK_ARG(alpha >= 0.0, "alpha must be >= 0 (got %g)", alpha);
+    if (p->d.basis == SGM_SHEN_NEUMANN && alpha == 0.0) {
+        set_error("Neumann basis: alpha = 0 leaves the constant mode of the zero wavenumber undetermined");
+        return SGM_ERR_SINGULAR;
+    }
+    return SGM_OK;
+}
 
 // Segmented solve where the chains fit, else one lane per chain.  The
 // boundary table is refilled (one extra launch) when alpha changes.
@@ -819,13 +837,13 @@ sgm_status sgm_helmholtz_solve_physical(sgm_plan p, double alpha, const void* f,
     TraceRange trace_range("sgm_helmholtz_solve_physical");
     SGM_CHECK_ARG(p && f && u_hat, "null argument");
     SGM_CHECK_ARG(f != u_hat, "f and u_hat must not alias");
-    SGM_CHECK_ARG(helmholtz_basis(p->d.basis), "Helmholtz solve needs a Shen-Dirichlet (Chebyshev or Legendre) basis");
-    SGM_CHECK_ARG(alpha >= 0.0, "alpha must be >= 0 (got %g)", alpha);
+    sgm_status st = helmholtz_args(p, alpha);
+    if (st != SGM_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     double2* uh = static_cast<double2*>(u_hat);
-    sgm_status st = fourier_forward(p, f, uh, s);
+    st = fourier_forward(p, f, uh, s);
     if (st != SGM_OK) return st;
-    if (!p->leg && p->hx && p->rkx.cf_spsolve && p->seg_K == 8 && p->d.autotune != 2) {
+    if (p->d.basis == SGM_SHEN_DIRICHLET && p->hx && p->rkx.cf_spsolve && p->seg_K == 8 && p->d.autotune != 2) {
         if ((st = seg_table_for(p, SGM_SHEN_DIRICHLET, alpha, s)) != SGM_OK) return st;
         PassTimer t(p, 5, s);
         const RegKernels& k = p->rkx;
@@ -845,8 +863,10 @@ sgm_status sgm_helmholtz_solve(sgm_plan p, double alpha, const void* f_tilde, vo
     clear_error();
     TraceRange trace_range("sgm_helmholtz_solve");
     SGM_CHECK_ARG(p && f_tilde && u_hat, "null argument");
-    SGM_CHECK_ARG(helmholtz_basis(p->d.basis), "Helmholtz solve needs a Shen-Dirichlet (Chebyshev or Legendre) basis");
-    SGM_CHECK_ARG(alpha >= 0.0, "alpha must be >= 0 (got %g)", alpha);
+    {
+        const sgm_status st = helmholtz_args(p, alpha);
+        if (st != SGM_OK) return st;
+    }
     PassTimer t(p, 7, static_cast<hipStream_t>(stream));
     if (p->d.autotune == 2)
         SGM_HIP_TRY(launch_solve(static_cast<const double2*>(f_tilde), static_cast<double2*>(u_hat), p->cd, p->geom,

@@ -13,15 +13,15 @@ __device__ __forceinline__ int wnum(int q, int M) { return q < (M + 1) / 2 ? q :
 
 template <int KIND>
 struct SegTraits {
-    static constexpr int P = (KIND == SGM_SHEN_DIRICHLET || KIND == SGM_LEG_DIRICHLET) ? 1 : 2;
+    static constexpr int P = KIND == SGM_SHEN_BIHARMONIC ? 2 : 1;
     static constexpr int Q = P, S = P, NR = P;
     static constexpr int NC = Q + NR;      // c-state components
     static constexpr int WS = NC * P;      // w-state doubles
 };
 
-// Band, tail factors of row i < n of the chain of parity p (Chebyshev- and
-// Legendre-Dirichlet in closed form, biharmonic from the plan's row table, 20
-// doubles per row).
+// Band, tail factors of row i < n of the chain of parity p (Chebyshev-Dirichlet,
+// Chebyshev-Neumann and Legendre-Dirichlet in closed form, biharmonic from the
+// plan's row table, 20 doubles per row).
 template <int KIND>
 __device__ __forceinline__ void row_coeffs(const double* rows, int p, int i, int n, double mu1, double mu2,
                                            double* band, double* U, double* V) {
@@ -34,6 +34,18 @@ __device__ __forceinline__ void row_coeffs(const double* rows, int p, int i, int
         band[2] = i + 1 < n ? -mu1 * kHalfPi : 0.0;
         U[0] = 8.0 * kHalfPi * (k + 1.0);
         V[0] = 1.0;
+    } else if constexpr (KIND == SGM_SHEN_NEUMANN) {
+        // r_k = (k/(k+2))^2: -A_kk = 4 (pi/2) k^2 (k+1)/(k+2), tail pi (1 - r_k) j^2;
+        // B: (pi/2)(c_k + r_k^2) on the diagonal, -(pi/2) r_k right, -(pi/2) r_{k-2} left
+        const double k = (double)(p + 2 * i);
+        const double ck = (p + 2 * i) == 0 ? 2.0 : 1.0;
+        const double q = k / (k + 2.0), rk = q * q;
+        const double qm = (k - 2.0) / k;
+        band[0] = i >= 1 ? -mu1 * kHalfPi * qm * qm : 0.0;
+        band[1] = 4.0 * kHalfPi * k * k * (k + 1.0) / (k + 2.0) + mu1 * kHalfPi * (ck + rk * rk);
+        band[2] = i + 1 < n ? -mu1 * kHalfPi * rk : 0.0;
+        U[0] = 2.0 * kHalfPi * (1.0 - rk);
+        V[0] = k * k;
     } else if constexpr (KIND == SGM_LEG_DIRICHLET) {
         // -A = diag(4k + 6), B: 2/(2k+1) + 2/(2k+5) on the diagonal, -2/(2k+5) and
         // -2/(2k+1) two places right and left; no tail
@@ -75,7 +87,7 @@ __device__ __forceinline__ void chain_mu(const ColGeom& g, int kind, int col, do
     const double m = g.Mmid > 1 ? (double)wnum(iy, g.Mmid) : 0.0;
     const double nn = g.last_r2c ? (double)iz : (double)wnum(iz, g.Mlast);
     const double k2 = g.sy * m * m + g.sz * nn * nn;
-    const bool helm = kind == SGM_SHEN_DIRICHLET || kind == SGM_LEG_DIRICHLET;
+    const bool helm = kind != SGM_SHEN_BIHARMONIC;
     mu1 = helm ? k2 + alpha : -2.0 * k2;
     mu2 = helm ? 0.0 : k2 * k2;
 }

@@ -120,6 +120,35 @@ bool build_cheb_tables(int basis, int N, ChebTables& t, std::string& err) {
         if (c.cnt > 1) t.beta[l] = (double)c.c[1];
         if (c.cnt > 2) t.gamma[l] = (double)c.c[2];
     }
+    if (basis == SGM_SHEN_NEUMANN) {
+        // Galerkin rows (layout of the solver rows below), Chebyshev weight, with
+        // r_k = (k / (k+2))^2: -A_kk = 2 pi k^2 (k+1) / (k+2), -A_kj = pi (1 - r_k) j^2
+        // for j >= k + 2 (rank one: U = pi (1 - r_k), V = j^2), B_kk = (pi/2)(c_k + r_k^2),
+        // B_{k,k+2} = B_{k+2,k} = -(pi/2) r_k
+        const ld h = PI_L / 2;
+        for (int p = 0; p < 2; ++p) {
+            const int n = t.npar[p];
+            std::vector<double>& S = t.solve[p];
+            S.assign(20 * (size_t)n, 0.0);
+            for (int i = 0; i < n; ++i) {
+                const long k = p + 2 * i;
+                const ld rk = ((ld)k / (ld)(k + 2)) * ((ld)k / (ld)(k + 2));
+                const ld ck = k == 0 ? 2 : 1;
+                double* row = &S[20 * (size_t)i];
+                row[2] = (double)(2 * PI_L * (ld)k * (ld)k * (ld)(k + 1) / (ld)(k + 2));
+                row[7] = (double)(h * (ck + rk * rk));
+                if (i + 1 < n) row[8] = (double)(-h * rk);
+                if (i > 0) {
+                    const ld rm = ((ld)(k - 2) / (ld)k) * ((ld)(k - 2) / (ld)k);
+                    row[6] = (double)(-h * rm);
+                }
+                row[15] = (double)(PI_L * (1 - rk));
+                row[17] = (double)((ld)k * (ld)k);
+            }
+        }
+        t.solve_s = 1;
+        t.solve_rank = 1;
+    }
     // the regular basis needs no projection tables; the Neumann projection runs from
     // the Chebyshev coefficients in closed form (derivative pass)
     if (basis == SGM_CHEBYSHEV || basis == SGM_SHEN_NEUMANN) return true;

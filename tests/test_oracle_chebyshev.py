@@ -254,3 +254,35 @@ def test_neumann_projection_of_a_neumann_polynomial_is_exact():
     ref = np.zeros(N - 2)
     ref[0], ref[2] = 5 / 16, 1 / 4
     assert np.abs(uh - ref).max() < 1e-15
+
+
+def test_neumann_stiffness_closed_form():
+    # A_kj = (phi_j'', phi_k)_w with phi_l = T_l - r_l T_{l+2}, r_l = (l/(l+2))^2, from
+    # (T_m'', T_n)_w = (pi/2) m (m^2 - n^2) for n <= m - 2 of the parity of m (zero
+    # otherwise): A_kk = -2 pi k^2 (k+1)/(k+2); for j >= k+2 the four terms collapse
+    # (k^2 - r_k (k+2)^2 = 0) to A_kj = -pi (1 - r_k) j^2
+    N = 22
+    nb = N - 2
+    A = np.asarray(C.stiffness_matrix("neumann", N), dtype=float)
+    r = lambda l: (l / (l + 2.0)) ** 2
+    ref = np.zeros((nb, nb))
+    for k in range(nb):
+        ref[k, k] = -2 * PI * k * k * (k + 1) / (k + 2)
+        for j in range(k + 2, nb, 2):
+            ref[k, j] = -PI * (1 - r(k)) * j * j
+    assert np.abs(A - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("alpha", [0.5, 3.0])
+def test_neumann_helmholtz_2d_manufactured(alpha):
+    # alpha u - lap u = f on [-1, 1] x [0, 2 pi) with u = cos(pi x) sin(2y), which has
+    # u'(+-1) = 0: the Galerkin solution in the Neumann space converges spectrally
+    # (cos(pi x) is entire), so at N = 40 it reproduces u to rounding
+    from oracle import tensor as T
+    N, M = 40, 16
+    x = C.points(N)
+    y = 2 * PI * np.arange(M) / M
+    u = np.cos(PI * x)[:, None] * np.sin(2 * y)[None, :]
+    f = (alpha + PI**2 + 4) * u
+    uh = T.helmholtz_solve("neumann", T.scalar_product("neumann", f), alpha, M)
+    assert np.abs(T.backward("neumann", uh, M) - u).max() < 1e-12
