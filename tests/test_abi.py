@@ -39,6 +39,7 @@ def test_status_strings_and_argument_errors_without_gpu():
     lib = _lib.load()
     assert lib.sgm_status_string(0) == b"ok"
     assert lib.sgm_status_string(-2) == b"unsupported size"
+    assert lib.sgm_status_string(-6) == b"singular system"
     assert lib.sgm_version() >= 1
     # A null descriptor is rejected before any device call.
     assert lib.sgm_plan_create(None, None, None) == -1
