@@ -136,9 +136,9 @@ sgm_status sgm_backward_noalloc(sgm_plan plan, const void* u_hat, void* u, void*
 sgm_status sgm_scalar_product(sgm_plan plan, const void* f, void* f_tilde, void* stream);
 
 /* Helmholtz solve alpha u - lap u = f for a Shen-Dirichlet plan, Chebyshev
- * (SGM_SHEN_DIRICHLET) or Legendre (SGM_LEG_DIRICHLET), or a Chebyshev Shen-Neumann
- * plan (SGM_SHEN_NEUMANN: homogeneous Neumann conditions u'(+-1) = 0); other bases
- * are rejected: per Fourier wavenumber column with
+ * (SGM_SHEN_DIRICHLET) or Legendre (SGM_LEG_DIRICHLET), or a Shen-Neumann plan
+ * (SGM_SHEN_NEUMANN, SGM_LEG_NEUMANN: homogeneous Neumann conditions u'(+-1) = 0);
+ * other bases are rejected: per Fourier wavenumber column with
  * kappa^2 = (2pi m/Ly)^2 + (2pi n/Lz)^2, solves
  * (-A + (kappa^2 + alpha) B) u_hat = f_tilde (eq. cheb_poisson, eq. laplace),
  * A_ml = (phi_l'', phi_m), B_ml = (phi_l, phi_m) in the basis's own weighted inner
@@ -146,8 +146,10 @@ sgm_status sgm_scalar_product(sgm_plan plan, const void* f, void* f_tilde, void*
  * 2/(2l+1) + 2/(2l+5) on the diagonal and -2/(2l+5) two places off it).  Neumann:
  * with r_l = (l/(l+2))^2, -A_ll = 2 pi l^2 (l+1)/(l+2), -A_ml = pi (1 - r_m) l^2
  * for l >= m + 2 of the same parity, B_ll = (pi/2)(c_l + r_l^2), B_{l,l+2} =
- * -(pi/2) r_l; alpha = 0 returns SGM_ERR_SINGULAR before any device work (the
- * constant mode of the zero wavenumber is then undetermined).
+ * -(pi/2) r_l; Legendre-Neumann: with s_l = l(l+1)/((l+2)(l+3)), -A = diag((4l + 6)
+ * s_l), B_ll = 2/(2l+1) + s_l^2 2/(2l+5), B_{l,l+2} = -s_l 2/(2l+5).  Neumann bases:
+ * alpha = 0 returns SGM_ERR_SINGULAR before any device work (the constant mode of
+ * the zero wavenumber is then undetermined).
  * f_tilde and u_hat are spectral arrays (rows >= N-2 of f_tilde ignored); they
  * may be the same pointer (in-place).  alpha >= 0.  INVALID_ARG otherwise.  The
  * first call with a given alpha also refreshes a plan-owned table of elimination
@@ -165,9 +167,12 @@ sgm_status sgm_helmholtz_solve(sgm_plan plan, double alpha, const void* f_tilde,
  * calls run in turn.  Table refresh and races as sgm_helmholtz_solve. */
 sgm_status sgm_helmholtz_solve_physical(sgm_plan plan, double alpha, const void* f, void* u_hat, void* stream);
 
-/* Biharmonic solve lap^2 u = f for the Shen-biharmonic plan (Sec. 4): per column
- * (S - 2 kappa^2 A + kappa^4 B) u_hat = f_tilde with S_ml = (phi_l'''', phi_m).
- * Same layout, aliasing rules and first-call table fill as sgm_helmholtz_solve. */
+/* Biharmonic solve lap^2 u = f for a Shen-biharmonic plan, Chebyshev
+ * (SGM_SHEN_BIHARMONIC) or Legendre (SGM_LEG_BIHARMONIC) (Sec. 4): per column
+ * (S - 2 kappa^2 A + kappa^4 B) u_hat = f_tilde with S_ml = (phi_l'''', phi_m) in the
+ * basis's weighted inner product (Legendre: S = diag(2 (2l+3)^2 (2l+5)), A and B
+ * banded).  Same layout, aliasing rules and first-call table fill as
+ * sgm_helmholtz_solve; other bases are rejected (INVALID_ARG). */
 sgm_status sgm_biharmonic_solve(sgm_plan plan, const void* f_tilde, void* u_hat, void* stream);
 
 /* Derivative and projection (Sec. 5: the Dx operator, nested for mixed

@@ -26,7 +26,8 @@ sum_l u_hat_l phi_l(x_j)|^2 (B^{-1} S(u), eq. projection), by a dense Householde
 QR in extended precision; backward: u(x_j) = sum_l u_hat_l phi_l(x_j).
 
 Galerkin matrices (Sec. 3.4, eq. cheb_poisson with the Legendre weight 1): mass
-B_ml = (phi_l, phi_m) and stiffness A_ml = (phi_l'', phi_m) by Legendre-Gauss
+B_ml = (phi_l, phi_m), stiffness A_ml = (phi_l'', phi_m) and, for the biharmonic
+problem, S_ml = (phi_l^(4), phi_m) by Legendre-Gauss
 quadrature in extended precision (exact: the integrands have degree <= 2N - 2);
 derivatives of the basis functions from the exact Legendre derivative relation
 (numpy.polynomial.legendre.legder on extended-precision coefficients).
@@ -160,6 +161,13 @@ def stiffness_matrix(basis, N):
     """A[m, l] = (phi_l'', phi_m) by Legendre-Gauss quadrature."""
     w = nodes_weights(N)[1]
     return synthesis(basis, N).T @ (derivative_synthesis(basis, N, 2) * w[:, None])
+
+
+@functools.lru_cache(maxsize=32)
+def bilaplace_matrix(basis, N):
+    """S[m, l] = (phi_l^(4), phi_m) by Legendre-Gauss quadrature (Sec. 4, biharmonic problem)."""
+    w = nodes_weights(N)[1]
+    return synthesis(basis, N).T @ (derivative_synthesis(basis, N, 4) * w[:, None])
 
 
 @functools.lru_cache(maxsize=16)

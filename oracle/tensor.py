@@ -132,9 +132,9 @@ def biharmonic_solve(basis, ftilde, M_last, kind_last="r2c", cols=None):
     """Solve (S - 2 kappa^2 A + kappa^4 B) u_hat = f_tilde per wavenumber column."""
     N = ftilde.shape[0]
     nb = _xmod(basis).nbasis(basis, N)
-    S = cheb.bilaplace_matrix(basis, N)
-    A = cheb.stiffness_matrix(basis, N)
-    B = cheb.mass_matrix(basis, N)
+    S = _xmod(basis).bilaplace_matrix(basis, N)
+    A = _xmod(basis).stiffness_matrix(basis, N)
+    B = _xmod(basis).mass_matrix(basis, N)
     k2 = kappa2(ftilde.shape, M_last, kind_last)
     LD = np.longdouble
     out = _solve_columns(ftilde, k2, lambda kk: S - 2 * LD(kk) * A + LD(kk) ** 2 * B, nb, cols)

@@ -25,9 +25,9 @@ struct LegTables {
     int basis = 0, N = 0, nb = 0;
     std::vector<double> x, w;   // points (descending) and weights
     std::vector<double> fwd, bwd, sp;
-    // Legendre-Dirichlet Galerkin rows per parity (the layout of ChebTables::solve):
-    // -A = diag(4k + 6) (A_ml = (phi_l'', phi_m) = -(phi_l', phi_m') with the Legendre
-    // weight 1), B tridiagonal per parity, no separable tail
+    // Galerkin rows per parity (the layout of ChebTables::solve), weight 1, banded
+    // (no separable tail): Dirichlet and Neumann -A (diagonal) and B (tridiagonal per
+    // parity); biharmonic S (diagonal), A (tridiagonal), B (pentadiagonal)
     int npar[2] = {0, 0}, mpar[2] = {0, 0};
     std::vector<double> solve[2];
 };

@@ -85,6 +85,64 @@ static void lstsq(std::vector<ld>& A, int m, int n, std::vector<ld>& B, int r, s
         }
 }
 
+// Legendre series in extended precision: derivative of a coefficient vector,
+// d_m = (2m + 1) sum_{k > m, k - m odd} c_k.
+static std::vector<ld> leg_series_der(const std::vector<ld>& c) {
+    const int n = (int)c.size();
+    std::vector<ld> d(n, 0);
+    ld s[2] = {0, 0};
+    for (int k = n - 1; k >= 1; --k) {
+        s[k & 1] += c[k];
+        d[k - 1] = (ld)(2 * (k - 1) + 1) * s[k & 1];
+    }
+    return d;
+}
+
+// Galerkin rows per parity in the layout of the solver rows (20 doubles per row,
+// offsets -2..2 in units of two modes): the Helmholtz bases (Dirichlet, Neumann)
+// store -A, B; the biharmonic basis stores S, A, B with S_mj = (phi_j^(4), phi_m),
+// A_mj = (phi_j'', phi_m), B_mj = (phi_j, phi_m), all with the Legendre weight 1:
+// (L_k, L_n) = 2/(2n+1) delta_kn, derivatives exact in coefficient space.  No
+// separable tail for these bases (the matrices are banded).
+static void galerkin_rows(int basis, int N, int nb, LegTables& t) {
+    const bool bih = basis == SGM_LEG_BIHARMONIC;
+    std::vector<std::vector<ld>> d0(nb), d2(nb), d4(nb);
+    for (int l = 0; l < nb; ++l) {
+        std::vector<ld> c(N, 0);
+        for (int k = l; k <= l + 4 && k < N; ++k) c[k] = recomb(basis, k, l);
+        d2[l] = leg_series_der(leg_series_der(c));
+        if (bih) d4[l] = leg_series_der(leg_series_der(d2[l]));
+        d0[l] = std::move(c);
+    }
+    // (f, phi_m) for a Legendre series f
+    auto inner = [&](const std::vector<ld>& f, int m) {
+        ld s = 0;
+        for (int k = m; k <= m + 4 && k < N; ++k) s += f[k] * recomb(basis, k, m) * (ld)2 / (ld)(2 * k + 1);
+        return s;
+    };
+    for (int par = 0; par < 2; ++par) {
+        const int n = t.npar[par];
+        std::vector<double>& S = t.solve[par];
+        S.assign(20 * (size_t)n, 0.0);
+        for (int i = 0; i < n; ++i) {
+            const int m = par + 2 * i;
+            double* row = &S[20 * (size_t)i];
+            for (int d = -2; d <= 2; ++d) {
+                const int ii = i + d, j = m + 2 * d;
+                if (ii < 0 || ii >= n) continue;
+                if (bih) {
+                    row[0 + d + 2] = (double)inner(d4[j], m);
+                    row[5 + d + 2] = (double)inner(d2[j], m);
+                    row[10 + d + 2] = (double)inner(d0[j], m);
+                } else {
+                    row[0 + d + 2] = (double)(-inner(d2[j], m));
+                    row[5 + d + 2] = (double)inner(d0[j], m);
+                }
+            }
+        }
+    }
+}
+
 bool build_leg_tables(int basis, int N, LegTables& t, std::string& err) {
     if (!is_legendre_basis(basis)) { err = "not a Legendre basis"; return false; }
     const int nb = legendre_nbasis(basis, N);
@@ -145,21 +203,7 @@ bool build_leg_tables(int basis, int N, LegTables& t, std::string& err) {
         t.npar[par] = nb > par ? (nb - par + 1) / 2 : 0;
         t.mpar[par] = N > par ? (N - par + 1) / 2 : 0;
     }
-    if (basis == SGM_LEG_DIRICHLET) {
-        for (int par = 0; par < 2; ++par) {
-            const int n = t.npar[par];
-            std::vector<double>& S = t.solve[par];
-            S.assign(20 * (size_t)n, 0.0);
-            for (int i = 0; i < n; ++i) {
-                const long k = par + 2 * i;
-                double* row = &S[20 * (size_t)i];
-                row[2] = (double)(4 * k + 6);                                              // -A, diagonal
-                row[7] = (double)((ld)2 / (2 * k + 1) + (ld)2 / (2 * k + 5));              // B, diagonal
-                if (i + 1 < n) row[8] = (double)(-(ld)2 / (2 * k + 5));                   // B_{k, k+2}
-                if (i > 0) row[6] = (double)(-(ld)2 / (2 * k + 1));                       // B_{k, k-2}
-            }
-        }
-    }
+    if (basis != SGM_LEGENDRE) galerkin_rows(basis, N, nb, t);
     t.fwd.assign((size_t)N * N, 0.0);
     if (basis == SGM_LEGENDRE) {
         for (size_t i = 0; i < Lam.size(); ++i) t.fwd[i] = (double)Lam[i];

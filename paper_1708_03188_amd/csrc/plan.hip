@@ -343,12 +343,15 @@ const char* sgm_status_string(sgm_status s) {
     }
 }
 
-// Kind of the segmented solve kernels for a basis (they evaluate the Dirichlet rows
-// in closed form, so Chebyshev- and Legendre-Dirichlet are distinct kinds); the
-// table-driven generic and chain kernels read Legendre-Dirichlet rows, which have
-// the Dirichlet shape (band + a rank-1 tail, here zero), as SGM_SHEN_DIRICHLET.
-static int solve_kind(int basis) { return basis; }
-static int table_kind(int basis) { return basis == SGM_SHEN_BIHARMONIC ? SGM_SHEN_BIHARMONIC : SGM_SHEN_DIRICHLET; }
+// Kind of the segmented solve kernels for a basis: the Helmholtz kinds evaluate
+// their rows in closed form, so each basis is its own kind; the biharmonic kind
+// reads its rows from the plan's table, Chebyshev and Legendre alike.  The
+// table-driven generic and chain kernels read every Helmholtz basis's rows, which
+// have the Dirichlet shape (band + a rank-1 tail, zero for the Legendre bases), as
+// SGM_SHEN_DIRICHLET.
+static bool biharmonic_basis(int basis) { return basis == SGM_SHEN_BIHARMONIC || basis == SGM_LEG_BIHARMONIC; }
+static int solve_kind(int basis) { return biharmonic_basis(basis) ? SGM_SHEN_BIHARMONIC : basis; }
+static int table_kind(int basis) { return biharmonic_basis(basis) ? SGM_SHEN_BIHARMONIC : SGM_SHEN_DIRICHLET; }
 
 sgm_status sgm_plan_create(const sgm_plan_desc* desc, void* stream, sgm_plan* out) {
     clear_error();
@@ -498,7 +501,7 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, void* stream, sgm_plan* ou
     p->W_mid = d.ndim == 3 ? pick_tile(d.M1, 16, lds_bytes_strided, lds) : 1;
     p->W_cheb = leg ? 1 : pick_tile(d.N, d.N <= 256 ? 16 : 8, lds_bytes_cheb, lds);
     int ws = d.N <= 256 ? 16 : 8;
-    while (ws > 1 && lds_bytes_solve(d.N, ws, d.basis) > (size_t)lds) ws /= 2;
+    while (ws > 1 && lds_bytes_solve(d.N, ws, table_kind(d.basis)) > (size_t)lds) ws /= 2;
     p->W_solve = ws;
     if (lds_bytes_lines(Llast, p->G_last) > (size_t)lds || (!leg && lds_bytes_cheb(d.N, p->W_cheb) > (size_t)lds) ||
         (d.ndim == 3 && lds_bytes_strided(d.M1, p->W_mid) > (size_t)lds)) {
@@ -521,9 +524,7 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, void* stream, sgm_plan* ou
             if (st2 != SGM_OK) { hipFree(p->work); hipFree(p->blob); delete p; return st2; }
         }
     }
-    if ((d.basis == SGM_SHEN_DIRICHLET || d.basis == SGM_SHEN_BIHARMONIC || d.basis == SGM_LEG_DIRICHLET ||
-         d.basis == SGM_SHEN_NEUMANN) &&
-        d.autotune != 2) {
+    if (d.basis != SGM_CHEBYSHEV && d.basis != SGM_LEGENDRE && d.autotune != 2) {
         p->seg_K = seg_lanes(std::max(cd.npar[0], cd.npar[1]));
         const size_t nt = seg_table_doubles(solve_kind(d.basis), p->seg_K, g.ncols);
         if (p->seg_K > 0 && nt > 0 && hipMalloc(&p->seg_tab, nt * sizeof(double)) != hipSuccess) {
@@ -788,7 +789,8 @@ static sgm_status fourier_backward(sgm_plan p, double2* w, void* u, hipStream_t 
 }
 
 static bool helmholtz_basis(int basis) {
-    return basis == SGM_SHEN_DIRICHLET || basis == SGM_LEG_DIRICHLET || basis == SGM_SHEN_NEUMANN;
+    return basis == SGM_SHEN_DIRICHLET || basis == SGM_LEG_DIRICHLET || basis == SGM_SHEN_NEUMANN ||
+           basis == SGM_LEG_NEUMANN;
 }
 
 // Checks shared by the Helmholtz entry points: the basis, alpha >= 0, and for the
@@ -796,9 +798,9 @@ static bool helmholtz_basis(int basis) {
 // system singular).
 static sgm_status helmholtz_args(sgm_plan p, double alpha) {
     SGM_CHECK_ARG(helmholtz_basis(p->d.basis),
-                  "Helmholtz solve needs a Shen-Dirichlet (Chebyshev or Legendre) or Shen-Neumann basis");
+                  "Helmholtz solve needs a Shen-Dirichlet or Shen-Neumann basis (Chebyshev or Legendre)");
     SGM_CHECK_ARG(alpha >= 0.0, "alpha must be >= 0 (got %g)", alpha);
-    if (p->d.basis == SGM_SHEN_NEUMANN && alpha == 0.0) {
+    if ((p->d.basis == SGM_SHEN_NEUMANN || p->d.basis == SGM_LEG_NEUMANN) && alpha == 0.0) {
         set_error("Neumann basis: alpha = 0 leaves the constant mode of the zero wavenumber undetermined");
         return SGM_ERR_SINGULAR;
     }
@@ -909,7 +911,7 @@ sgm_status sgm_biharmonic_solve(sgm_plan p, const void* f_tilde, void* u_hat, vo
     clear_error();
     TraceRange trace_range("sgm_biharmonic_solve");
     SGM_CHECK_ARG(p && f_tilde && u_hat, "null argument");
-    SGM_CHECK_ARG(p->d.basis == SGM_SHEN_BIHARMONIC, "biharmonic solve needs the Shen-biharmonic basis");
+    SGM_CHECK_ARG(biharmonic_basis(p->d.basis), "biharmonic solve needs a Shen-biharmonic basis (Chebyshev or Legendre)");
     PassTimer t(p, 7, static_cast<hipStream_t>(stream));
     if (p->d.autotune == 2)
         SGM_HIP_TRY(launch_solve(static_cast<const double2*>(f_tilde), static_cast<double2*>(u_hat), p->cd, p->geom,

@@ -129,6 +129,9 @@ hipError_t launch_seg_table(double* tab, const ChebDev& cd, const ColGeom& g, in
     else if (kind == SGM_SHEN_NEUMANN)
         hipLaunchKernelGGL(k_seg_table<SGM_SHEN_NEUMANN>, dim3(blocks), dim3(256), 0, s, cd, g, alpha, kSegRows, K,
                            tab);
+    else if (kind == SGM_LEG_NEUMANN)
+        hipLaunchKernelGGL(k_seg_table<SGM_LEG_NEUMANN>, dim3(blocks), dim3(256), 0, s, cd, g, alpha, kSegRows, K,
+                           tab);
     else
         hipLaunchKernelGGL(k_seg_table<SGM_SHEN_BIHARMONIC>, dim3(blocks), dim3(256), 0, s, cd, g, alpha, kSegRows, K,
                            tab);
@@ -144,6 +147,16 @@ hipError_t launch_solve_seg(const double2* in, double2* out, const double* tab, 
             case 4: return launch_seg_k<SGM_SHEN_DIRICHLET, 4>(in, out, tab, cd, g, alpha, s);
             case 8: return launch_seg_k<SGM_SHEN_DIRICHLET, 8>(in, out, tab, cd, g, alpha, s);
             case 16: return launch_seg_k<SGM_SHEN_DIRICHLET, 16>(in, out, tab, cd, g, alpha, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (kind == SGM_LEG_NEUMANN) {
+        switch (K) {
+            case 1: return launch_seg_k<SGM_LEG_NEUMANN, 1>(in, out, tab, cd, g, alpha, s);
+            case 2: return launch_seg_k<SGM_LEG_NEUMANN, 2>(in, out, tab, cd, g, alpha, s);
+            case 4: return launch_seg_k<SGM_LEG_NEUMANN, 4>(in, out, tab, cd, g, alpha, s);
+            case 8: return launch_seg_k<SGM_LEG_NEUMANN, 8>(in, out, tab, cd, g, alpha, s);
+            case 16: return launch_seg_k<SGM_LEG_NEUMANN, 16>(in, out, tab, cd, g, alpha, s);
             default: return hipErrorInvalidValue;
         }
     }

@@ -46,6 +46,18 @@ __device__ __forceinline__ void row_coeffs(const double* rows, int p, int i, int
         band[2] = i + 1 < n ? -mu1 * kHalfPi * rk : 0.0;
         U[0] = 2.0 * kHalfPi * (1.0 - rk);
         V[0] = k * k;
+    } else if constexpr (KIND == SGM_LEG_NEUMANN) {
+        // s_k = k(k+1)/((k+2)(k+3)): -A = diag((4k + 6) s_k), B: 2/(2k+1) + s_k^2 2/(2k+5)
+        // on the diagonal, -s_k 2/(2k+5) right, -s_{k-2} 2/(2k+1) left; no tail
+        const double k = (double)(p + 2 * i);
+        const double sk = k * (k + 1.0) / ((k + 2.0) * (k + 3.0));
+        const double sm = (k - 2.0) * (k - 1.0) / (k * (k + 1.0));
+        const double r1 = 2.0 / (2.0 * k + 1.0), r5 = 2.0 / (2.0 * k + 5.0);
+        band[0] = i >= 1 ? -mu1 * sm * r1 : 0.0;
+        band[1] = (4.0 * k + 6.0) * sk + mu1 * (r1 + sk * sk * r5);
+        band[2] = i + 1 < n ? -mu1 * sk * r5 : 0.0;
+        U[0] = 0.0;
+        V[0] = 1.0;
     } else if constexpr (KIND == SGM_LEG_DIRICHLET) {
         // -A = diag(4k + 6), B: 2/(2k+1) + 2/(2k+5) on the diagonal, -2/(2k+5) and
         // -2/(2k+1) two places right and left; no tail

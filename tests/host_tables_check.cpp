@@ -91,9 +91,26 @@ int main() {
             CHECK(std::fabs(wsum - 2.0) < 1e-13, "leg weights sum %d %d", basis, N);
             const std::vector<double> pk = leg_pack(t.fwd, N);
             CHECK(pk.size() == leg_packed_doubles(N) && finite(pk), "leg pack %d %d", basis, N);
-            if (basis == SGM_LEG_DIRICHLET)
-                for (int p = 0; p < 2; ++p)
-                    CHECK(t.solve[p].size() == 20 * (size_t)t.npar[p] && finite(t.solve[p]), "leg solve %d", N);
+            if (basis == SGM_LEGENDRE) continue;
+            // Galerkin rows against their closed forms (k the row's mode):
+            // Dirichlet -A = 4k + 6; Neumann -A = (4k + 6) s_k with s_k = k(k+1)/((k+2)(k+3));
+            // biharmonic S = 2 (2k+3)^2 (2k+5); Dirichlet / Neumann B diagonal
+            for (int p = 0; p < 2; ++p) {
+                CHECK(t.solve[p].size() == 20 * (size_t)t.npar[p] && finite(t.solve[p]), "leg solve %d %d", basis, N);
+                for (int i = 0; i < t.npar[p]; ++i) {
+                    const double k = p + 2 * i, *row = &t.solve[p][20 * (size_t)i];
+                    const double sk = k * (k + 1) / ((k + 2) * (k + 3));
+                    double want = 0, bdiag = 0;
+                    if (basis == SGM_LEG_DIRICHLET) { want = 4 * k + 6; bdiag = 2 / (2 * k + 1) + 2 / (2 * k + 5); }
+                    if (basis == SGM_LEG_NEUMANN) { want = (4 * k + 6) * sk; bdiag = 2 / (2 * k + 1) + sk * sk * 2 / (2 * k + 5); }
+                    if (basis == SGM_LEG_BIHARMONIC) want = 2 * (2 * k + 3) * (2 * k + 3) * (2 * k + 5);
+                    CHECK(std::fabs(row[2] - want) <= 1e-12 * std::fabs(want) + 1e-14, "leg row %d %d %d: %g vs %g", basis,
+                          N, (int)k, row[2], want);
+                    if (bdiag != 0) CHECK(std::fabs(row[7] - bdiag) <= 1e-13, "leg B %d %d %d", basis, N, (int)k);
+                    for (int d : {0, 1, 3, 4}) CHECK(basis == SGM_LEG_BIHARMONIC || row[d] == 0.0 || std::fabs(row[d]) < 1e-12,
+                                                     "leg -A off-diagonal %d %d %d", basis, N, (int)k);
+                }
+            }
         }
     if (fails) {
         std::printf("FAILED %d checks\n", fails);

@@ -127,3 +127,60 @@ def test_helmholtz_2d_legendre_manufactured_exact_coefficients(alpha):
     uh = T.helmholtz_solve("leg_dirichlet", ft, alpha, M)
     assert np.abs(uh - T.forward("leg_dirichlet", u)).max() < 1e-13
     assert np.abs(T.backward("leg_dirichlet", uh, M) - u).max() < 1e-13
+
+
+def test_neumann_galerkin_closed_forms():
+    # phi_k = L_k - s_k L_{k+2}, s_k = k(k+1)/((k+2)(k+3)): phi_k'(+-1) = 0, so by parts
+    # A_mk = -(phi_k', phi_m'); with L_{n+1}' - L_{n-1}' = (2n+1) L_n this is diagonal,
+    # -A_kk = (4k+6) s_k; B_kk = 2/(2k+1) + s_k^2 2/(2k+5), B_{k,k+2} = -s_k 2/(2k+5)
+    N = 20
+    nb = N - 2
+    k = np.arange(nb, dtype=float)
+    s = k * (k + 1) / ((k + 2) * (k + 3))
+    A = np.asarray(L.stiffness_matrix("leg_neumann", N), dtype=float)
+    B = np.asarray(L.mass_matrix("leg_neumann", N), dtype=float)
+    assert np.abs(A + np.diag((4 * k + 6) * s)).max() < 1e-12
+    Bref = np.diag(2 / (2 * k + 1) + s**2 * 2 / (2 * k + 5))
+    off = -s[: nb - 2] * 2 / (2 * k[: nb - 2] + 5)
+    Bref += np.diag(off, 2) + np.diag(off, -2)
+    assert np.abs(B - Bref).max() < 1e-15
+
+
+def test_biharmonic_galerkin_matrices():
+    # S = (phi_l'''', phi_m) is diagonal, 2 (2k+3)^2 (2k+5) (by parts twice: (phi_l'', phi_m'')
+    # with phi_k'' proportional to L_{k+2}); A and B against numpy's own Gauss-Legendre rule
+    # and Legendre-series derivative (an independent implementation)
+    from numpy.polynomial import legendre as npl
+    N = 18
+    nb = N - 4
+    k = np.arange(nb, dtype=float)
+    S = np.asarray(L.bilaplace_matrix("leg_biharmonic", N), dtype=float)
+    assert np.abs(S - np.diag(2 * (2 * k + 3) ** 2 * (2 * k + 5))).max() < 1e-12 * S.max()
+    P = np.asarray(L.recombination("leg_biharmonic", N), dtype=float)
+    x, w = npl.leggauss(N + 2)
+    Phi = np.stack([npl.legval(x, P[:, l]) for l in range(nb)], 1)
+    D2 = np.stack([npl.legval(x, npl.legder(P[:, l], 2)) for l in range(nb)], 1)
+    A = np.asarray(L.stiffness_matrix("leg_biharmonic", N), dtype=float)
+    B = np.asarray(L.mass_matrix("leg_biharmonic", N), dtype=float)
+    assert np.abs(A - Phi.T @ (D2 * w[:, None])).max() < 1e-12 * np.abs(A).max()
+    assert np.abs(B - Phi.T @ (Phi * w[:, None])).max() < 1e-14
+
+
+def test_neumann_and_biharmonic_2d_manufactured():
+    from oracle import tensor as T
+    N, M = 40, 16
+    x = L.points(N)
+    y = 2 * PI * np.arange(M) / M
+    # Neumann: alpha u - lap u = f, u = cos(pi x) sin(2y) (u'(+-1) = 0): spectral accuracy
+    alpha = 0.5
+    u = np.cos(PI * x)[:, None] * np.sin(2 * y)[None, :]
+    uh = T.helmholtz_solve("leg_neumann", T.scalar_product("leg_neumann", (alpha + PI**2 + 4) * u), alpha, M)
+    assert np.abs(T.backward("leg_neumann", uh, M) - u).max() < 1e-12
+    # biharmonic: lap^2 u = f, u = (1 - x^2)^2 sin(y) lies in the space: exact coefficients
+    g = (1 - x**2) ** 2
+    g2 = 12 * x**2 - 4
+    u = g[:, None] * np.sin(y)[None, :]
+    f = (24 - 2 * g2 + g)[:, None] * np.sin(y)[None, :]
+    uh = T.biharmonic_solve("leg_biharmonic", T.scalar_product("leg_biharmonic", f), M)
+    assert np.abs(uh - T.forward("leg_biharmonic", u)).max() < 1e-13
+    assert np.abs(T.backward("leg_biharmonic", uh, M) - u).max() < 1e-13
