@@ -181,10 +181,14 @@ sgm_status sgm_biharmonic_solve(sgm_plan plan, const void* f_tilde, void* u_hat,
  * space of `target`, of the weighted L2 projection of
  * d^(ox+oy+oz) u / dx^ox dy^oy dz^oz, order = {ox, oy, oz} (y the middle and z the
  * last axis for ndim = 3, y the last axis for ndim = 2, where oz must be 0; each
- * 0..8).  target->basis is SGM_CHEBYSHEV, where the result is the derivative's
- * Chebyshev coefficients exactly (it is a polynomial of degree < N),
- * SGM_SHEN_DIRICHLET, the projection the paper uses when the derivative vanishes
- * at x = +-1 (exact then, a least-squares fit otherwise), or SGM_SHEN_NEUMANN.  target must have the
+ * 0..8).  For a Chebyshev-family plan target->basis is SGM_CHEBYSHEV, where the
+ * result is the derivative's Chebyshev coefficients exactly (it is a polynomial of
+ * degree < N), SGM_SHEN_DIRICHLET, the projection the paper uses when the
+ * derivative vanishes at x = +-1 (exact then, a least-squares fit otherwise), or
+ * SGM_SHEN_NEUMANN; for a Legendre-family plan (every Legendre basis may be the
+ * source) it is SGM_LEGENDRE, SGM_LEG_DIRICHLET or SGM_LEG_NEUMANN, the same
+ * projections in the Legendre inner product (weight 1).  Other targets, and a
+ * target of the other family, are rejected (INVALID_ARG).  target must have the
  * same ndim, N, M1, M2, kind_last and periods.  Along a periodic axis of M points
  * coefficient k is multiplied by (2 pi i k / L)^o; for even M the odd derivatives
  * of the Nyquist coefficient are zero.  Spectral layouts as in sgm_forward; u_hat

@@ -10,6 +10,8 @@ W = V(x) x V^p(y) [x V^p(z)] this is, axis by axis:
   x (Chebyshev/Shen axis): the values of d^k u / dx^k at the Gauss-Chebyshev
       points, sum_l u_hat_l phi_l^(k)(x_j), followed by the target space's
       forward transform (its weighted least-squares projection, Sec. 3.4.2).
+      A Legendre-family space does the same at its Legendre-Gauss points with
+      the Legendre weight 1, onto a Legendre-family target.
       Gauss quadrature with N points is exact for the degree <= 2N - 2 products
       involved, so this equals the paper's route through the spectral matrix
       (phi_l^(k), psi_m)^N_w and the target mass matrix.  A regular Chebyshev
@@ -27,6 +29,7 @@ import numpy as np
 
 from . import chebyshev as cheb
 from . import fourier
+from . import legendre as leg
 
 
 def fourier_factor(M, n_coef, order, L=0.0):
@@ -63,17 +66,21 @@ def _axis_factors(order, spec_shape, M_last, kind_last, Ly, Lz):
 def _x_part(basis, target, cols, ox):
     """Target coefficients of d^ox/dx^ox along axis 0 of an N x k array of columns."""
     N = cols.shape[0]
-    nb = cheb.nbasis(basis, N)
-    D = cheb.derivative_synthesis(basis, N, ox) if ox > 0 else cheb.synthesis(basis, N)
-    g = cheb._apply_left(D, cols[:nb], 0)
-    res = cheb.forward(target, g, axis=0)
+    mod = leg if basis in leg.BASES else cheb
+    if (target in leg.BASES) != (mod is leg):
+        raise ValueError("source and target bases must be of one family (Chebyshev or Legendre)")
+    nb = mod.nbasis(basis, N)
+    D = mod.derivative_synthesis(basis, N, ox) if ox > 0 else mod.synthesis(basis, N)
+    g = mod._apply_left(D, cols[:nb], 0)
+    res = mod.forward(target, g, axis=0)
     out = np.zeros(cols.shape, dtype=np.complex128)
     out[: res.shape[0]] = res
     return out
 
 
 def project_dx(basis, uh, order, target, M_last, kind_last="r2c", Ly=0.0, Lz=0.0):
-    """Coefficients in the `target` basis ("chebyshev" or "dirichlet") of the
+    """Coefficients in the `target` basis ("chebyshev", "dirichlet" or "neumann";
+    "legendre", "leg_dirichlet" or "leg_neumann" for a Legendre-family source) of the
     projection of d^(ox+oy[+oz]) u / dx^ox dy^oy [dz^oz], where u has the
     spectral coefficients uh ([N][M1] or [N][M1][M2c], rows >= nbasis zero) in
     `basis`.  order = (ox, oy) or (ox, oy, oz).  Returns an array shaped like uh

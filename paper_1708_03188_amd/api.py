@@ -124,8 +124,9 @@ class Plan:
 
     def project_derivative(self, uh, order, target=None, out=None):
         """Coefficients in `target`'s space (a Plan on the same grid with the
-        "chebyshev" or "dirichlet" basis; default: a regular Chebyshev plan made
-        here) of the projection of d^(ox+oy+oz) u / dx^ox dy^oy dz^oz, where u has
+        "chebyshev", "dirichlet" or "neumann" basis, or for a Legendre-family plan
+        "legendre", "leg_dirichlet" or "leg_neumann"; default: the regular space of
+        this plan's family, made here) of the projection of d^(ox+oy+oz) u / dx^ox dy^oy dz^oz, where u has
         the coefficients uh in this plan's space.  order = (ox, oy[, oz])."""
         _need(uh, torch.complex128, self.spec_shape, "u_hat")
         if target is None:
@@ -141,7 +142,8 @@ class Plan:
     def _cheb_target(self):
         if getattr(self, "_cheb", None) is None:
             M2 = self.phys_shape[2] if self.ndim == 3 else None
-            self._cheb = Plan("chebyshev", self.phys_shape[0], self.phys_shape[1], M2, kind_last=self.kind_last,
+            regular = "legendre" if self.basis.startswith("leg") else "chebyshev"
+            self._cheb = Plan(regular, self.phys_shape[0], self.phys_shape[1], M2, kind_last=self.kind_last,
                               Ly=self.Ly, Lz=self.Lz)
         return self._cheb
 

@@ -1,5 +1,6 @@
 // Spectral derivative and projection pass (Sec. 5: the Dx operator, nested for
-// mixed derivatives, and project onto a regular Chebyshev or Shen-Dirichlet space).
+// mixed derivatives, and project onto a regular, Shen-Dirichlet or Shen-Neumann
+// space of the Chebyshev or the Legendre family).
 //
 // One work-group takes 16 adjacent spectral columns; each column is split into
 // 16 chunks of E consecutive rows, one thread per chunk, so every row access of a
@@ -23,6 +24,16 @@
 //      mu_p = sum_{k in p} k^2 b_k / sum_{k in p} k^4, then
 //      u_l = (1 / l^2) sum_{k <= l, k = l mod 2} k^2 a_k (l >= 1; u_0 = a_0), which
 //      inverts a_k = u_k - ((k-2)/k)^2 u_{k-2}.
+// The Legendre family (coefficients of L_k, weight 1) takes the same steps with
+// its own constants: d/dx gives b_k = (2k + 1) sum_{p > k, p - k odd} a_p; the
+// functions orthogonal to the Dirichlet space L_l - L_{l+2} have coefficients
+// proportional per parity to h_k = (2k + 1) / 2 (the inverse squared norm of L_k;
+// Chebyshev: w_k above), and those orthogonal to the Neumann space
+// L_l - (l(l+1) / ((l+2)(l+3))) L_{l+2} to q_k h_k with q_k = k(k+1)
+// (L_k'(1) = q_k / 2; Chebyshev: q_k = k^2, h_k = 1).  So the Dirichlet target
+// subtracts lambda_p h_k, lambda_p = sum_{k in p} b_k / sum_{k in p} h_k, and the
+// Neumann target subtracts mu_p q_k h_k, mu_p = sum_{k in p} q_k b_k /
+// sum_{k in p} q_k^2 h_k, then u_l = (1 / q_l) sum_{k <= l, k = l mod 2} q_k a_k.
 // The cross-chunk sums go through LDS: one thread per (parity, column) scans the
 // 16 chunk partials serially.
 #include "derivative.h"
@@ -74,8 +85,10 @@ __global__ __launch_bounds__(256) void k_dx_project(const double2* __restrict__ 
         const int k = r0 + e;
         v[e] = (live && k < nb) ? in[k * ld + col] : make_double2(0.0, 0.0);
     }
-    // 1. Chebyshev coefficients (descending, so u_{k-2} and u_{k-4} are still the inputs)
-    if (a.src_basis != SGM_CHEBYSHEV) {
+    const bool leg = a.leg != 0;
+    // 1. Chebyshev (Legendre) coefficients (descending, so u_{k-2} and u_{k-4} are
+    //    still the inputs)
+    if (a.src_basis != SGM_CHEBYSHEV && a.src_basis != SGM_LEGENDRE) {
         double2 h[4];  // u_{r0-4} .. u_{r0-1}
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -98,7 +111,7 @@ __global__ __launch_bounds__(256) void k_dx_project(const double2* __restrict__ 
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = r0 + e;
-            const double2 w = cscale((double)k, v[e]);
+            const double2 w = cscale(leg ? 1.0 : (double)k, v[e]);
             if (k & 1) t1 = cadd(t1, w);
             else t0 = cadd(t0, w);
         }
@@ -121,9 +134,10 @@ __global__ __launch_bounds__(256) void k_dx_project(const double2* __restrict__ 
         for (int e = E - 1; e >= 0; --e) {
             const int k = r0 + e;
             const double2 ak = v[e];
-            v[e] = cscale(k == 0 ? 1.0 : 2.0, (k & 1) ? R0 : R1);
-            if (k & 1) R1 = cadd(R1, cscale((double)k, ak));
-            else R0 = cadd(R0, cscale((double)k, ak));
+            const double pk = leg ? 1.0 : (double)k;
+            v[e] = cscale(leg ? 2.0 * k + 1.0 : (k == 0 ? 1.0 : 2.0), (k & 1) ? R0 : R1);
+            if (k & 1) R1 = cadd(R1, cscale(pk, ak));
+            else R0 = cadd(R0, cscale(pk, ak));
         }
     }
     // 3. Fourier factors of the column
@@ -139,7 +153,7 @@ __global__ __launch_bounds__(256) void k_dx_project(const double2* __restrict__ 
         for (int e = 0; e < E; ++e) v[e] = cmul(f, v[e]);
     }
     // 4. projection onto the Shen-Dirichlet space
-    if (a.dst_basis == SGM_SHEN_DIRICHLET) {
+    if (a.dst_basis == SGM_SHEN_DIRICHLET || a.dst_basis == SGM_LEG_DIRICHLET) {
         double2 s0 = make_double2(0.0, 0.0), s1 = s0;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -164,31 +178,37 @@ __global__ __launch_bounds__(256) void k_dx_project(const double2* __restrict__ 
         }
         __syncthreads();
         const double2 P0 = part[0][j][c], P1 = part[1][j][c], T0 = total[0][c], T1 = total[1][c];
-        const double W0 = (double)((N + 1) / 2) - 0.5, W1 = (double)(N / 2);
+        // sums of h_k over the even / odd k < N (W) and k < r0 (pw), in closed form
+        const double me = (double)((N + 1) / 2), mo = (double)(N / 2);
+        const double pe = (double)((r0 + 1) / 2), po = (double)(r0 / 2);
+        const double W0 = leg ? me * (2.0 * me - 1.0) / 2.0 : me - 0.5;
+        const double W1 = leg ? mo * (2.0 * mo + 1.0) / 2.0 : mo;
+        const double pw0 = leg ? pe * (2.0 * pe - 1.0) / 2.0 : (r0 > 0 ? pe - 0.5 : 0.0);
+        const double pw1 = leg ? po * (2.0 * po + 1.0) / 2.0 : po;
         const double2 lam0 = cscale(1.0 / W0, T0), lam1 = cscale(1.0 / W1, T1);
-        const double pw0 = r0 > 0 ? (double)((r0 + 1) / 2) - 0.5 : 0.0, pw1 = (double)(r0 / 2);
         double2 D0 = cadd(P0, cscale(-pw0, lam0)), D1 = cadd(P1, cscale(-pw1, lam1));
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = r0 + e;
+            const double hk = leg ? (2.0 * k + 1.0) / 2.0 : (k == 0 ? 0.5 : 1.0);
             if (k & 1) {
-                D1 = cadd(D1, cadd(v[e], cscale(-1.0, lam1)));
+                D1 = cadd(D1, cadd(v[e], cscale(-hk, lam1)));
                 v[e] = D1;
             } else {
-                D0 = cadd(D0, cadd(v[e], cscale(k == 0 ? -0.5 : -1.0, lam0)));
+                D0 = cadd(D0, cadd(v[e], cscale(-hk, lam0)));
                 v[e] = D0;
             }
             if (k >= N - 2) v[e] = make_double2(0.0, 0.0);
         }
     }
     // 4'. projection onto the Shen-Neumann space
-    if (a.dst_basis == SGM_SHEN_NEUMANN) {
+    if (a.dst_basis == SGM_SHEN_NEUMANN || a.dst_basis == SGM_LEG_NEUMANN) {
         double2 s0 = make_double2(0.0, 0.0), s1 = s0;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = r0 + e;
             if (k < N) {
-                const double2 w = cscale((double)k * (double)k, v[e]);
+                const double2 w = cscale(leg ? (double)k * (k + 1.0) : (double)k * (double)k, v[e]);
                 if (k & 1) s1 = cadd(s1, w);
                 else s0 = cadd(s0, w);
             }
@@ -208,9 +228,10 @@ __global__ __launch_bounds__(256) void k_dx_project(const double2* __restrict__ 
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = r0 + e;
-            const double k2 = (double)k * (double)k;
+            const double k2 = leg ? (double)k * (k + 1.0) : (double)k * (double)k;
+            const double hk = leg ? (2.0 * k + 1.0) / 2.0 : 1.0;
             if (k < N) {
-                v[e] = cadd(v[e], cscale(-k2, (k & 1) ? mu1 : mu0));
+                v[e] = cadd(v[e], cscale(-k2 * hk, (k & 1) ? mu1 : mu0));
                 if (k & 1) t1 = cadd(t1, cscale(k2, v[e]));
                 else t0 = cadd(t0, cscale(k2, v[e]));
             }
@@ -233,7 +254,7 @@ __global__ __launch_bounds__(256) void k_dx_project(const double2* __restrict__ 
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = r0 + e;
-            const double k2 = (double)k * (double)k;
+            const double k2 = leg ? (double)k * (k + 1.0) : (double)k * (double)k;
             if (k & 1) {
                 P1 = cadd(P1, cscale(k2, v[e]));
                 v[e] = cscale(1.0 / k2, P1);

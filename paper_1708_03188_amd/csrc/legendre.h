@@ -30,6 +30,9 @@ struct LegTables {
     // parity); biharmonic S (diagonal), A (tridiagonal), B (pentadiagonal)
     int npar[2] = {0, 0}, mpar[2] = {0, 0};
     std::vector<double> solve[2];
+    // recombination coefficients of L_{l+2} and L_{l+4} in phi_l (N each, zero past
+    // the basis), for the derivative pass
+    std::vector<double> beta, gamma;
 };
 bool build_leg_tables(int basis, int N, LegTables& t, std::string& err);
 

@@ -204,6 +204,12 @@ bool build_leg_tables(int basis, int N, LegTables& t, std::string& err) {
         t.mpar[par] = N > par ? (N - par + 1) / 2 : 0;
     }
     if (basis != SGM_LEGENDRE) galerkin_rows(basis, N, nb, t);
+    t.beta.assign(N, 0.0);
+    t.gamma.assign(N, 0.0);
+    for (int l = 0; l < nb; ++l) {
+        if (l + 2 < N) t.beta[l] = (double)recomb(basis, l + 2, l);
+        if (l + 4 < N) t.gamma[l] = (double)recomb(basis, l + 4, l);
+    }
     t.fwd.assign((size_t)N * N, 0.0);
     if (basis == SGM_LEGENDRE) {
         for (size_t i = 0; i < Lam.size(); ++i) t.fwd[i] = (double)Lam[i];

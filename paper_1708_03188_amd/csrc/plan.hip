@@ -422,6 +422,8 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, void* stream, sgm_plan* ou
             ct.mpar[q] = lt.mpar[q];
             ct.solve[q] = lt.solve[q];
         }
+        ct.beta = lt.beta;
+        ct.gamma = lt.gamma;
         p->xpts = lt.x;
     } else {
         p->xpts.resize(d.N);
@@ -644,8 +646,13 @@ static DxArgs dx_args(sgm_plan p, int src_basis, int dst_basis, int ox, int oy, 
     x.beta = p->cd.beta;
     x.gamma = p->cd.gamma;
     x.dst_basis = dst_basis;
+    x.leg = is_legendre_basis(src_basis) ? 1 : 0;
+    // Neumann targets: sum over each parity of q_k^2 h_k (see DxArgs)
     x.k4[0] = x.k4[1] = 0.0;
-    for (int k = 0; k < p->N; ++k) x.k4[k & 1] += (double)k * k * k * k;
+    for (int k = 0; k < p->N; ++k) {
+        const double q = x.leg ? (double)k * (k + 1) : (double)k * k, h = x.leg ? (2.0 * k + 1.0) / 2.0 : 1.0;
+        x.k4[k & 1] += q * q * h;
+    }
     x.ox = ox;
     x.oy = oy;
     x.oz = oz;
@@ -884,10 +891,14 @@ sgm_status sgm_project_derivative(sgm_plan p, sgm_plan target, const int order[3
     TraceRange trace_range("sgm_project_derivative");
     SGM_CHECK_ARG(p && target && order && u_hat && du_hat, "null argument");
     SGM_CHECK_ARG(u_hat != du_hat, "u_hat and du_hat must not alias");
-    SGM_CHECK_ARG(!p->leg, "the derivative pass takes Chebyshev-family spaces");
     const sgm_plan_desc &a = p->d, &b = target->d;
-    SGM_CHECK_ARG(b.basis == SGM_CHEBYSHEV || b.basis == SGM_SHEN_DIRICHLET || b.basis == SGM_SHEN_NEUMANN,
-                  "target basis must be SGM_CHEBYSHEV, SGM_SHEN_DIRICHLET or SGM_SHEN_NEUMANN");
+    if (p->leg)
+        SGM_CHECK_ARG(b.basis == SGM_LEGENDRE || b.basis == SGM_LEG_DIRICHLET || b.basis == SGM_LEG_NEUMANN,
+                      "target basis of a Legendre-family space must be SGM_LEGENDRE, SGM_LEG_DIRICHLET or "
+                      "SGM_LEG_NEUMANN");
+    else
+        SGM_CHECK_ARG(b.basis == SGM_CHEBYSHEV || b.basis == SGM_SHEN_DIRICHLET || b.basis == SGM_SHEN_NEUMANN,
+                      "target basis must be SGM_CHEBYSHEV, SGM_SHEN_DIRICHLET or SGM_SHEN_NEUMANN");
     SGM_CHECK_ARG(a.ndim == b.ndim && p->N == target->N && p->M1 == target->M1 && p->M2 == target->M2 &&
                       a.kind_last == b.kind_last,
                   "target plan must have the same grid (ndim, N, M1, M2, kind_last)");

@@ -137,3 +137,87 @@ def test_columns_form_matches_full_form():
     part = D.project_dx_columns("biharmonic", uh.reshape(N, -1)[:, cols], (2, 1, 3), "dirichlet", cols, sh, M2,
                                 "r2c", Ly=3.0, Lz=5.0)
     assert np.array_equal(part, full.reshape(N, -1)[:, cols])
+
+
+# ---- Legendre family (same Dx / project, Legendre-Gauss points, weight 1) ----
+from oracle import legendre as L  # noqa: E402
+
+
+def _lcol(basis, vals):
+    N = len(vals)
+    out = np.zeros((N, 1), complex)
+    c = L.forward(basis, vals)
+    out[: len(c), 0] = c
+    return out
+
+
+def test_legendre_derivative_values_satisfy_the_ode():
+    # L_n^(k) from L_n, L_n' = n (L_{n-1} - x L_n) / (1 - x^2) and the differentiated
+    # Legendre equation (1 - x^2) y^(k+2) - 2(k+1) x y^(k+1) + (n(n+1) - k(k+1)) y^(k) = 0
+    N = 11
+    x = L.points(N).astype(np.longdouble)
+    P = [np.ones_like(x), x]
+    for n in range(1, N):
+        P.append(((2 * n + 1) * x * P[n] - n * P[n - 1]) / (n + 1))
+    for n in range(N):
+        ys = [P[n], n * ((P[n - 1] if n > 0 else 0 * x) - x * P[n]) / (1 - x * x)]
+        for k in range(3):
+            ys.append((2 * (k + 1) * x * ys[k + 1] - (n * (n + 1) - k * (k + 1)) * ys[k]) / (1 - x * x))
+        for k in range(1, 5):
+            got = L.derivative_synthesis("legendre", N, k)[:, n]
+            assert np.abs(got - ys[k]).max() <= 1e-12 * max(1.0, float(np.abs(ys[k]).max())), (n, k)
+
+
+def test_legendre_closed_form_derivatives():
+    N = 14
+    x = L.points(N)
+    # u = (1 - x^2) x^3 in the Dirichlet space: u' = 3x^2 - 5x^4 = -(6/7) L2 - (8/7) L4,
+    # u'' = 6x - 20x^3 = -6 L1 - 8 L3
+    uh = _lcol("leg_dirichlet", (1 - x**2) * x**3)
+    d1 = D.project_dx("leg_dirichlet", uh, (1, 0), "legendre", 1, "c2c")[:, 0]
+    d2 = D.project_dx("leg_dirichlet", uh, (2, 0), "legendre", 1, "c2c")[:, 0]
+    ref1 = np.zeros(N); ref1[[2, 4]] = [-6 / 7, -8 / 7]
+    ref2 = np.zeros(N); ref2[[1, 3]] = [-6, -8]
+    assert np.abs(d1 - ref1).max() < 1e-13 and np.abs(d2 - ref2).max() < 1e-13
+    # u = (1 - x^2)^2 (biharmonic space): u' = 4x^3 - 4x vanishes at +-1, so its
+    # Dirichlet projection reproduces it exactly
+    bh = _lcol("leg_biharmonic", (1 - x**2) ** 2)
+    dd = D.project_dx("leg_biharmonic", bh, (1, 0), "leg_dirichlet", 1, "c2c")[:, 0]
+    assert np.abs(L.backward("leg_dirichlet", dd[: N - 2]) - (4 * x**3 - 4 * x)).max() < 1e-13
+    # u = x - 2x^3/3 + x^5/5 (regular space): u' = (1 - x^2)^2 has u''(+-1) = 0, so its
+    # Neumann projection reproduces it exactly
+    rg = _lcol("legendre", x - 2 * x**3 / 3 + x**5 / 5)
+    dn = D.project_dx("legendre", rg, (1, 0), "leg_neumann", 1, "c2c")[:, 0]
+    assert np.abs(L.backward("leg_neumann", dn[: N - 2]) - (1 - x**2) ** 2).max() < 1e-13
+
+
+@pytest.mark.parametrize("target", ["leg_dirichlet", "leg_neumann"])
+def test_legendre_projection_residual_is_orthogonal_to_the_target(target):
+    # the L2 (weight 1) projection f -> Pf leaves f - Pf orthogonal to every basis
+    # function of the target: sum_j w_j (f - Pf)(x_j) phi_m(x_j) = 0, and Pf satisfies
+    # the target's boundary conditions
+    rng = np.random.default_rng(11)
+    N = 16
+    uh = np.zeros((N, 2), complex)
+    nb = L.nbasis("leg_biharmonic", N)
+    uh[:nb] = rng.standard_normal((nb, 2)) + 1j * rng.standard_normal((nb, 2))
+    f = L.backward("legendre", D.project_dx("leg_biharmonic", uh, (1, 0), "legendre", 2, "c2c"))
+    Pf = D.project_dx("leg_biharmonic", uh, (1, 0), target, 2, "c2c")[: N - 2]
+    r = f - L.backward(target, Pf)
+    w = L.weights(N)
+    G = L.synthesis(target, N).astype(np.float64)
+    assert np.abs(G.T @ (w[:, None] * r)).max() < 1e-12 * np.abs(f).max()
+    ends = np.array([1.0, -1.0])
+    from numpy.polynomial import legendre as npl
+    for c in range(2):
+        coef = L.recombination(target, N).astype(np.float64) @ Pf[:, c]
+        vals = npl.legval(ends, coef) if target == "leg_dirichlet" else npl.legval(ends, npl.legder(coef))
+        assert np.abs(vals).max() < 1e-12 * np.abs(f).max()
+
+
+def test_legendre_and_chebyshev_families_do_not_mix():
+    uh = np.zeros((8, 1), complex)
+    with pytest.raises(ValueError):
+        D.project_dx("leg_dirichlet", uh, (1, 0), "chebyshev", 1, "c2c")
+    with pytest.raises(ValueError):
+        D.project_dx("dirichlet", uh, (1, 0), "leg_dirichlet", 1, "c2c")
