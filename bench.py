@@ -241,7 +241,8 @@ def leg_biharmonic(steps):
 
 def leg_derivative(steps):
     """Sec. 5 derivative + projection at 256^3: d/dx of a Shen-Dirichlet field onto the
-    regular Chebyshev space, and d2/dx2 d/dy onto the Dirichlet space."""
+    regular Chebyshev space, d2/dx2 d/dy onto the Dirichlet space, and d/dx of a
+    Legendre-Dirichlet field onto the Legendre-Neumann space."""
     import torch
     import synth
     from paper_1708_03188_amd.api import Plan
@@ -259,6 +260,12 @@ def leg_derivative(steps):
         gbs = nbytes / (ms * 1e-3) / 1e9
         res[name] = {"us_per_call": round(ms * 1e3, 2), "GBps": round(gbs, 1),
                      "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": nbytes}
+    lp = Plan("leg_dirichlet", N, M1, M2)
+    ln = Plan("leg_neumann", N, M1, M2)
+    ms = _timed(lambda: lp.project_derivative(uh, (1, 0, 0), target=ln, out=out), max(10, steps))
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    res["legendre_dx_onto_leg_neumann"] = {"us_per_call": round(ms * 1e3, 2), "GBps": round(gbs, 1),
+                                           "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": nbytes}
     return res
 
 
