@@ -71,7 +71,7 @@ def test_project_derivative_small(Plan, basis, target, kind, shape):
         assert err < TOL, (order, err)
 
 
-LEG_SHAPES = [(12, 10), (33, 7), (5, 9), (100, 18), (257, 6), (20, 6, 8), (17, 9, 14), (130, 12, 10)]
+LEG_SHAPES = [(12, 10), (33, 7), (3, 6), (5, 9), (100, 18), (257, 6), (512, 4), (20, 6, 8), (17, 9, 14), (130, 12, 10)]
 
 
 @pytest.mark.parametrize("kind", ["r2c", "c2c"])
@@ -80,6 +80,8 @@ LEG_SHAPES = [(12, 10), (33, 7), (5, 9), (100, 18), (257, 6), (20, 6, 8), (17, 9
 @pytest.mark.parametrize("shape", LEG_SHAPES)
 def test_project_derivative_legendre(Plan, basis, target, kind, shape):
     N = shape[0]
+    if basis == "leg_biharmonic" and N < 5:
+        pytest.skip("the Legendre-biharmonic basis needs N >= 5")
     print(f"[case] derivative {basis}->{target} {kind} {shape}", flush=True)
     Ly, Lz = (3.0, 5.0) if N == 17 else (0.0, 0.0)
     p = Plan(basis, *shape, kind_last=kind, Ly=Ly, Lz=Lz)
