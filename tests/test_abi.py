@@ -76,3 +76,22 @@ def test_autotune_cache_path_follows_environment(monkeypatch):
     monkeypatch.delenv("SGM_TUNE_CACHE")
     monkeypatch.setenv("XDG_CACHE_HOME", "/tmp/xdg")
     assert autotune_cache_path() == "/tmp/xdg/libsgm/tune.txt"
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsgm.so not built")
+def test_plain_c_consumer_compiles_links_and_runs(tmp_path):
+    # The header must be valid C99 (no C++ or HIP types across the boundary) and the
+    # library usable from C alone; the program only makes calls that need no GPU.
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    exe = str(tmp_path / "abi_consumer")
+    libdir = os.path.dirname(LIB)
+    subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I" + os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "abi_consumer.c"), "-L" + libdir, "-lsgm", "-Wl,-rpath," + libdir,
+                    "-o", exe], check=True)
+    r = subprocess.run([exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    assert "ok" in r.stdout
