@@ -306,8 +306,22 @@ sgm_status sgm_fno_num_params(sgm_fno f, int64_t* n);
 /* Host copies of the flat fp32 parameter vector (set also resets Adam). */
 sgm_status sgm_fno_set_params(sgm_fno f, const float* host);
 sgm_status sgm_fno_get_params(sgm_fno f, float* host);
-/* pred = net(x) for `batch` samples (device arrays [batch][H][W][2]). */
+/* pred = net(x) for `batch` samples (device arrays [batch][H][W][2]); with an
+ * ensemble set (sgm_fno_set_ensemble) the average of its members.  With more than
+ * one member pred must not overlap x. */
 sgm_status sgm_fno_infer(sgm_fno f, const float* x, float* pred, int batch, void* stream);
+/* Inference averaged over reflections of the periodic square (not in the paper;
+ * the GL equation of Sec. 6, u_t = u + (1 + i b) lap u - (1 + i c)|u|^2 u on a
+ * doubly periodic square, commutes with them, and so does its solution map):
+ * pred = (1/m) sum_R R^{-1} net(R x) over m = `members` reflections R of the
+ * H x W grid, (R u)[i][j] = u[s(i, j)]: 1 = the network alone, 4 = the identity and
+ * the flips of rows (i -> H-1-i), of columns (j -> W-1-j) and of both, 2 = the
+ * identity and the transpose, 8 = all eight (flips, then transpose).  Transposes
+ * need H = W (else INVALID_ARG); other member counts are INVALID_ARG.  The first
+ * call with members > 1 allocates two B_max x H x W x 2 float buffers, owned by
+ * the network; inference then runs the network `members` times.  Applies to
+ * sgm_fno_infer and to sgm_fno_advance_checked; training is unaffected. */
+sgm_status sgm_fno_set_ensemble(sgm_fno f, int members);
 /* Forward + loss + backward without an update: gradients to grads_host (num_params
  * floats, may be NULL) and the mean relative L2 loss to loss_host (may be NULL).
  * Synchronises the stream. */

@@ -106,6 +106,44 @@ def forward(p, x, K, keep=False):
     return pred
 
 
+def reflect(u, t, fx, fy):
+    """(R u)[b, i, j] for the reflection R = (transpose if t) after (flip rows if fx,
+    flip columns if fy) of the H x W grid: the flips first, then the transpose."""
+    v = u
+    if fx:
+        v = v[:, ::-1, :]
+    if fy:
+        v = v[:, :, ::-1]
+    if t:
+        v = np.swapaxes(v, 1, 2)
+    return np.ascontiguousarray(v)
+
+
+def unreflect(u, t, fx, fy):
+    """R^{-1} u: the steps of reflect undone in reverse order."""
+    v = u
+    if t:
+        v = np.swapaxes(v, 1, 2)
+    if fy:
+        v = v[:, :, ::-1]
+    if fx:
+        v = v[:, ::-1, :]
+    return np.ascontiguousarray(v)
+
+
+ENSEMBLES = {1: [(0, 0, 0)], 2: [(0, 0, 0), (1, 0, 0)],
+             4: [(0, 0, 0), (0, 1, 0), (0, 0, 1), (0, 1, 1)],
+             8: [(t, fx, fy) for t in (0, 1) for fx in (0, 1) for fy in (0, 1)]}
+
+
+def forward_ensemble(p, x, K, members):
+    """(1/m) sum_R R^{-1} forward(R x) over the m reflections of ENSEMBLES[m]: the
+    network averaged over symmetries of the periodic square, which the
+    Ginzburg-Landau equation (isotropic Laplacian, square periodic domain) has."""
+    ops = ENSEMBLES[members]
+    return sum(unreflect(forward(p, reflect(x, *op), K), *op) for op in ops) / len(ops)
+
+
 def loss(pred, tgt):
     """mean_b ||pred_b - tgt_b|| / ||tgt_b||."""
     B = pred.shape[0]

@@ -82,6 +82,7 @@ _SIGS = {
     "sgm_fno_set_params": ([_vp, _vp], ctypes.c_int),
     "sgm_fno_get_params": ([_vp, _vp], ctypes.c_int),
     "sgm_fno_infer": ([_vp, _vp, _vp, ctypes.c_int, _vp], ctypes.c_int),
+    "sgm_fno_set_ensemble": ([_vp, ctypes.c_int], ctypes.c_int),
     "sgm_fno_grads": ([_vp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp], ctypes.c_int),
     "sgm_fno_train_step": ([_vp, _vp, _vp, ctypes.c_int, ctypes.c_float, _vp, _vp], ctypes.c_int),
     "sgm_fno_rel_l2": ([_vp, _vp, _vp, ctypes.c_int, _vp, _vp], ctypes.c_int),

@@ -280,6 +280,7 @@ class FNO:
         check(lib.sgm_fno_num_params(h, ctypes.byref(n)), "sgm_fno_num_params")
         self.num_params = n.value
         self.H, self.W, self.C, self.K, self.nl, self.P, self.max_batch = H, W, width, modes, layers, hidden, max_batch
+        self.ensemble = 1
 
     def close(self):
         if getattr(self, "_h", None):
@@ -328,6 +329,12 @@ class FNO:
             raise ValueError(f"{name}: expected contiguous float32 device tensor [B, {self.H}, {self.W}, 2]")
         if not 1 <= x.shape[0] <= self.max_batch:
             raise ValueError(f"{name}: batch must be in 1..{self.max_batch}")
+
+    def set_ensemble(self, members):
+        """Average inference over 1, 2, 4 or 8 reflections of the periodic grid
+        (sgm_fno_set_ensemble); applies to infer() and advance_checked()."""
+        check(self._lib.sgm_fno_set_ensemble(self._h, int(members)), "sgm_fno_set_ensemble")
+        self.ensemble = int(members)
 
     def infer(self, x, out=None):
         self._x(x, "x")

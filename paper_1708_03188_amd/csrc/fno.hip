@@ -195,6 +195,37 @@ __global__ void k_adam(float* w, const float* g, float* m, float* v, long n, flo
 }
 
 // complex128 packed N x N states [x][y] -> fp32 [b][y?]... channels-last [b][x][y][2]
+// Reflections of the square grid: pixel (i, j) of the reflected field takes
+// pixel s(i, j) of the field, s = (transpose?) o (flip rows?, flip columns?):
+// (i1, j1) = (fx ? H-1-i : i, fy ? W-1-j : j), s = t ? (j1, i1) : (i1, j1)
+// (t needs H = W).  bits of op: 1 flip rows, 2 flip columns, 4 transpose.
+__device__ __forceinline__ long refl_src(long p, int H, int W, int op) {
+    const long HW = (long)H * W;
+    const long b = p / HW;
+    const int r = (int)(p - b * HW);
+    const int i = r / W, j = r - i * W;
+    const int i1 = (op & 1) ? H - 1 - i : i, j1 = (op & 2) ? W - 1 - j : j;
+    return b * HW + ((op & 4) ? (long)j1 * W + i1 : (long)i1 * W + j1);
+}
+
+// out = R in (gather), over npix pixels of 2 channels
+__global__ void k_reflect(const float2* in, float2* out, long npix, int H, int W, int op) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < npix) out[p] = in[refl_src(p, H, W, op)];
+}
+
+// acc (=|+=) w R^{-1} p: the reflected-frame pixel p goes back to s(p)
+__global__ void k_unreflect_acc(const float2* pr, float2* acc, long npix, int H, int W, int op, float w, int first) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    const long q = refl_src(p, H, W, op);
+    const float2 v = pr[p];
+    float2 a = first ? make_float2(0.f, 0.f) : acc[q];
+    a.x += w * v.x;
+    a.y += w * v.y;
+    acc[q] = a;
+}
+
 __global__ void k_c128_to_x(const double2* u, float* x, long n) {
     long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -272,6 +303,11 @@ struct sgm_fno_s {
     // second stream for the FP64 check path, overlapped with inference
     hipStream_t adv_stream = nullptr;
     hipEvent_t adv_ev[2] = {nullptr, nullptr};
+    // inference averaged over ens reflections of the periodic square (1 = the plain
+    // network); ens_x / ens_p hold one member's input and prediction (Bmax x H x W x 2)
+    int ens = 1;
+    float* ens_x = nullptr;
+    float* ens_p = nullptr;
 };
 
 static long fno_act_elems(const sgm_fno_s* f) { return (long)f->Bmax * f->H * f->W * f->C; }
@@ -281,6 +317,8 @@ extern "C" sgm_status sgm_fno_destroy(sgm_fno f) {
     if (!f) return SGM_OK;
     hipFree(f->all);
     hipFree(f->adv);
+    hipFree(f->ens_x);
+    hipFree(f->ens_p);
     for (hipEvent_t e : f->adv_ev)
         if (e) hipEventDestroy(e);
     if (f->adv_stream) hipStreamDestroy(f->adv_stream);
@@ -642,6 +680,22 @@ static sgm_status fno_backward(sgm_fno f, const float* x, int B, hipStream_t s) 
     return SGM_OK;
 }
 
+// One pass of the network over batch states (mirrors current).
+static sgm_status infer_once(sgm_fno f, const float* x, float* pred, int batch, hipStream_t s) {
+    if (fno_fused_ok(f->C, f->K, f->W, f->P)) return fno_forward(f, x, batch, s, pred);
+    sgm_status r = fno_forward(f, x, batch, s);
+    if (r != SGM_OK) return r;
+    SGM_HIP_TRY(hipMemcpyAsync(pred, f->predb, 4L * batch * f->H * f->W * 2, hipMemcpyDeviceToDevice, s));
+    return SGM_OK;
+}
+
+// Reflections averaged by an ensemble of 2 (identity, transpose), 4 (the row and
+// column flips) or 8 (all of them) members.
+static int ens_op(int ens, int m) {
+    if (ens == 2) return m ? 4 : 0;
+    return m;  // 4: ops 0..3 (flips), 8: ops 0..7
+}
+
 extern "C" sgm_status sgm_fno_infer(sgm_fno f, const float* x, float* pred, int batch, void* stream) {
     clear_error();
     TraceRange trace_range("sgm_fno_infer");
@@ -650,9 +704,44 @@ extern "C" sgm_status sgm_fno_infer(sgm_fno f, const float* x, float* pred, int 
     hipStream_t s = static_cast<hipStream_t>(stream);
     sgm_status r = refresh_mirrors(f, s);
     if (r != SGM_OK) return r;
-    if (fno_fused_ok(f->C, f->K, f->W, f->P)) return fno_forward(f, x, batch, s, pred);
-    if ((r = fno_forward(f, x, batch, s)) != SGM_OK) return r;
-    SGM_HIP_TRY(hipMemcpyAsync(pred, f->predb, 4L * batch * f->H * f->W * 2, hipMemcpyDeviceToDevice, s));
+    if (f->ens == 1) return infer_once(f, x, pred, batch, s);
+    SGM_CHECK_ARG(x != pred, "pred must not alias x for an ensemble of %d members", f->ens);
+    const long npix = (long)batch * f->H * f->W;
+    for (int m = 0; m < f->ens; ++m) {
+        const int op = ens_op(f->ens, m);
+        const float* xin = x;
+        if (op) {
+            hipLaunchKernelGGL(k_reflect, dim3(nblk(npix)), dim3(256), 0, s, reinterpret_cast<const float2*>(x),
+                               reinterpret_cast<float2*>(f->ens_x), npix, f->H, f->W, op);
+            SGM_HIP_TRY(hipGetLastError());
+            xin = f->ens_x;
+        }
+        if ((r = infer_once(f, xin, f->ens_p, batch, s)) != SGM_OK) return r;
+        hipLaunchKernelGGL(k_unreflect_acc, dim3(nblk(npix)), dim3(256), 0, s, reinterpret_cast<const float2*>(f->ens_p),
+                           reinterpret_cast<float2*>(pred), npix, f->H, f->W, op, 1.0f / (float)f->ens, m == 0 ? 1 : 0);
+        SGM_HIP_TRY(hipGetLastError());
+    }
+    return SGM_OK;
+}
+
+extern "C" sgm_status sgm_fno_set_ensemble(sgm_fno f, int members) {
+    clear_error();
+    SGM_CHECK_ARG(f, "null network");
+    SGM_CHECK_ARG(members == 1 || members == 2 || members == 4 || members == 8,
+                  "members must be 1, 2, 4 or 8 (got %d)", members);
+    SGM_CHECK_ARG(members == 1 || members == 4 || f->H == f->W,
+                  "an ensemble with transposes (2 or 8 members) needs a square grid (H = %d, W = %d)", f->H, f->W);
+    if (members > 1 && !f->ens_x) {
+        const size_t bytes = (size_t)f->Bmax * f->H * f->W * 2 * sizeof(float);
+        if (hipMalloc(&f->ens_x, bytes) != hipSuccess || hipMalloc(&f->ens_p, bytes) != hipSuccess) {
+            hipFree(f->ens_x);
+            f->ens_x = nullptr;
+            f->ens_p = nullptr;
+            set_error("hipMalloc ensemble buffers (%zu bytes each) failed", bytes);
+            return SGM_ERR_OOM;
+        }
+    }
+    f->ens = members;
     return SGM_OK;
 }
 

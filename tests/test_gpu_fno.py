@@ -65,6 +65,41 @@ def test_forward_matches_oracle(FNO, cfg, B):
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-2
 
 
+@pytest.mark.parametrize("cfg,B,members", [(CFG, 3, 2), (CFG, 3, 8), (CFG32, 3, 4), (CFG32R, 1, 4), (CFG_C5, 1, 8)],
+                         ids=["gemm-2", "gemm-8", "fused-4", "fused-ragged-4", "surrogate-256-8"])
+def test_ensemble_forward_matches_oracle(FNO, cfg, B, members):
+    # inference averaged over reflections of the grid against the oracle's average
+    # of the FP64 network over the same reflections
+    print(f"[case] fno ensemble {members} {cfg} B={B}", flush=True)
+    f, p, x, t = _setup(FNO, B=B, cfg=cfg)
+    f.set_ensemble(members)
+    got = f.infer(_dev(x)).cpu().numpy().astype(np.float64)
+    ref = ofno.forward_ensemble(p, x, cfg["modes"], members)
+    e = np.linalg.norm(got - ref) / np.linalg.norm(ref - x)
+    print("fno ensemble rel err (net output)", e)
+    assert e < 3e-2
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-2
+    # back to the plain network: the same numbers as before any ensemble
+    f.set_ensemble(1)
+    plain = f.infer(_dev(x)).cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(plain - ofno.forward(p, x, cfg["modes"])) / np.linalg.norm(ref) < 1e-2
+
+
+def test_ensemble_arguments(FNO):
+    from paper_1708_03188_amd._lib import SgmError
+    f, p, x, t = _setup(FNO, B=1, cfg=CFG32)  # 32 x 64: no transposes
+    for m in (2, 8):
+        with pytest.raises(SgmError, match="square"):
+            f.set_ensemble(m)
+    for m in (0, 3, 16):
+        with pytest.raises(SgmError, match="members"):
+            f.set_ensemble(m)
+    f.set_ensemble(4)
+    xd = _dev(x)
+    with pytest.raises(SgmError, match="alias"):
+        f.infer(xd, out=xd)
+
+
 @pytest.mark.parametrize("cfg,B", [(CFG, 3), (CFG32, 3), (CFG_SK, 3), (CFG32_SK, 4)],
                          ids=["gemm", "fused", "gemm-splitk", "fused-splitk"])
 def test_gradients_match_oracle(FNO, cfg, B):

@@ -118,3 +118,21 @@ def test_trained_256_weights_on_fresh_trajectories(tmp_path):
             assert max(errs) == 0.0   # the macro-step was re-advanced by the solver itself
         else:
             assert st["max_rel_l2"] <= 1e-2 and np.mean(errs) <= 1e-2
+    # the network averaged over the four flips of the periodic square (symmetries of
+    # the equation): a smaller held-out error than the network alone, and the same
+    # acceptance guarantees in the checked advance
+    f.set_ensemble(4)
+    mean4, mx4 = S.evaluate(f, data)
+    print(f"256^2 held-out rel L2 with the 4-flip ensemble: mean {mean4:.4f} max {mx4:.4f}")
+    assert mean4 < mean and mx4 < 1e-2
+    for it in range(2):
+        u0 = u.clone()
+        st = f.advance_checked(gl, glc, u, nsur=1, steps_per=10, tol=1e-2, seed=15 + it)
+        ref.step(u0, 10)
+        pu, pr = gl.backward(u), ref.backward(u0)
+        errs = [float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) for a, b in zip(gl.unpack(pu), ref.unpack(pr))]
+        print("checked advance (ensemble):", st, "all-state rel L2 vs FP64:", ["%.2e" % e for e in errs])
+        if st["n_batch_fallback"] == 1:
+            assert max(errs) == 0.0
+        else:
+            assert st["max_rel_l2"] <= 1e-2 and np.mean(errs) <= 1e-2

@@ -110,3 +110,34 @@ def test_gelu_at_normal_table_values():
     z = np.array([0.0, 1.0, 2.0, -1.0, 50.0, -50.0])
     ref = np.array([0.0, 0.8413447460685429, 2 * 0.9772498680518208, -0.15865525393145707, 50.0, 0.0])
     assert np.allclose(fno.gelu(z), ref, rtol=1e-15, atol=1e-300)
+
+
+def test_reflections_form_the_square_symmetry_group():
+    # the eight reflections of ENSEMBLES[8] are distinct, each is undone by its
+    # unreflect, and the 2- and 4-member sets are closed under composition
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal((1, 6, 6, 2))
+    outs = [fno.reflect(u, *op) for op in fno.ENSEMBLES[8]]
+    assert len({o.tobytes() for o in outs}) == 8
+    for op in fno.ENSEMBLES[8]:
+        assert np.array_equal(fno.unreflect(fno.reflect(u, *op), *op), u)
+    for m in (2, 4):
+        images = {fno.reflect(u, *op).tobytes() for op in fno.ENSEMBLES[m]}
+        for a in fno.ENSEMBLES[m]:
+            for b in fno.ENSEMBLES[m]:
+                assert fno.reflect(fno.reflect(u, *a), *b).tobytes() in images
+
+
+@pytest.mark.parametrize("members", [2, 4, 8])
+def test_ensemble_is_equivariant_and_reduces_to_the_network(members):
+    # E(x) = (1/m) sum_R R^-1 net(R x) over a group commutes with every R of the
+    # group (a wrong inverse would break it); one member is the network itself
+    p, x, _, _ = _small(seed=4)  # an 8 x 8 grid, square for the transposes
+    assert np.array_equal(fno.forward_ensemble(p, x, 2, 1), fno.forward(p, x, 2))
+    e = fno.forward_ensemble(p, x, 2, members)
+    for op in fno.ENSEMBLES[members]:
+        lhs = fno.forward_ensemble(p, fno.reflect(x, *op), 2, members)
+        assert np.abs(lhs - fno.reflect(e, *op)).max() < 1e-12
+    # the network alone is not equivariant, so the pin has teeth
+    assert np.abs(fno.forward(p, fno.reflect(x, *fno.ENSEMBLES[members][1]), 2) -
+                  fno.reflect(fno.forward(p, x, 2), *fno.ENSEMBLES[members][1])).max() > 1e-6
