@@ -236,7 +236,7 @@ def leg_biharmonic(steps):
             "fwd_bwd_hbm_frac": round(pair_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "biharmonic_solves_per_s": round(1e3 / ms_s, 1),
             "solve_hbm_frac": round(solve_bytes / (ms_s * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "plan_variants_xyz": p.variants()}
+            "plan_variants_xyz": p.variants(), "solve_lanes_rows": list(p.solve_layout())}
 
 
 def leg_derivative(steps):
@@ -596,6 +596,7 @@ def main():
                                        "traffic_source": "stored counters" if measured_traffic(dom, p.variants(), N)
                                        else None}},
         "plan_variants_xyz": p.variants(),
+        "solve_lanes_rows": list(p.solve_layout()),
         "passes_warmup": {k: {kk: round(vv, 2) for kk, vv in d.items()} for k, d in per_pass.items()},
         "helmholtz_solves_per_s": round(1e3 / ms_solve, 1),
         "helmholtz_alpha1_solves_per_s": round(1e3 / ms_solve_a1, 1),

@@ -82,7 +82,8 @@ typedef struct {
     double Ly, Lz; /* periods of y and z; 0 means 2 pi.  Used only by the solves.      */
     int autotune;  /* 0: default kernels (register-resident FFTs for lengths 2^a 3^b with a
                       compiled instance, generic LDS kernels otherwise); 1: time the
-                      candidates once at creation and keep the fastest; 2: generic
+                      candidates once at creation and keep the fastest (register
+                      kernels per axis, rows per lane of the solves); 2: generic
                       LDS kernels only; 16 + v: pin register-kernel variant v
                       (0..7) wherever it is compiled (diagnostics) */
 } sgm_plan_desc;
@@ -212,6 +213,16 @@ sgm_status sgm_plan_timing(sgm_plan plan, int enable);
 /* Register-kernel variant in use per axis (x, y, z): 0..7, or -1 where the axis runs
  * the generic LDS kernels (diagnostics; chosen at creation, see autotune). */
 sgm_status sgm_plan_variants(sgm_plan plan, int variant[3]);
+/* Layout of the plan's Galerkin solves (diagnostics): each (column, parity) chain is
+ * split over `lanes` lanes of a wave with `rows` rows each (16 by default; plans
+ * created with autotune = 1 time 16 and 8 rows per lane and keep the faster);
+ * lanes = rows = 0 where the solves run one chain per lane or the basis has none. */
+sgm_status sgm_plan_solve_layout(sgm_plan plan, int* lanes, int* rows);
+/* Set the rows per lane (8 or 16) of the plan's segmented solves: re-sizes the
+ * boundary table (a device synchronisation, then a new allocation owned by the plan).
+ * INVALID_ARG for other values, for plans without segmented solves and where the
+ * chains would need more than 16 lanes. */
+sgm_status sgm_plan_set_solve_rows(sgm_plan plan, int rows);
 sgm_status sgm_plan_pass_times(sgm_plan plan, double ms[SGM_NPASS], int64_t count[SGM_NPASS], int reset);
 
 /* ---- Complex Ginzburg-Landau, ragged batch (Sec. 6) ------------------------------

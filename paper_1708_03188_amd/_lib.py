@@ -81,6 +81,8 @@ _SIGS = {
     "sgm_fno_num_params": ([_vp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "sgm_fno_set_params": ([_vp, _vp], ctypes.c_int),
     "sgm_fno_get_params": ([_vp, _vp], ctypes.c_int),
+    "sgm_plan_solve_layout": ([_vp, _vp, _vp], ctypes.c_int),
+    "sgm_plan_set_solve_rows": ([_vp, ctypes.c_int], ctypes.c_int),
     "sgm_fno_infer": ([_vp, _vp, _vp, ctypes.c_int, _vp], ctypes.c_int),
     "sgm_fno_set_ensemble": ([_vp, ctypes.c_int], ctypes.c_int),
     "sgm_fno_grads": ([_vp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp], ctypes.c_int),

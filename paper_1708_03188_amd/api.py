@@ -90,6 +90,15 @@ class Plan:
         check(self._lib.sgm_plan_variants(self._h, v), "sgm_plan_variants")
         return list(v)
 
+    def solve_layout(self):
+        """(lanes per chain, rows per lane) of the segmented solves; (0, 0) if none."""
+        k, r = ctypes.c_int(), ctypes.c_int()
+        check(self._lib.sgm_plan_solve_layout(self._h, ctypes.byref(k), ctypes.byref(r)), "sgm_plan_solve_layout")
+        return k.value, r.value
+
+    def set_solve_rows(self, rows):
+        check(self._lib.sgm_plan_set_solve_rows(self._h, int(rows)), "sgm_plan_set_solve_rows")
+
     def pass_times(self, reset=False):
         """{pass name: (total ms, launches)} accumulated since the last reset."""
         ms = (ctypes.c_double * _lib.NPASS)()

@@ -107,6 +107,7 @@ struct sgm_plan_s {
     // segmented solves: lanes per chain (0 = chains too long), boundary table
     // valid for seg_alpha once seg_ok
     int seg_K = 0;
+    int seg_R = kSegRows;  // rows per lane (chosen by the autotuner: 16 or 8)
     double* seg_tab = nullptr;
     bool seg_ok = false;
     double seg_alpha = 0.0;
@@ -187,7 +188,7 @@ struct TuneKey {
         return std::tie(ndim, basis, N, M1, M2, kind) < std::tie(o.ndim, o.basis, o.N, o.M1, o.M2, o.kind);
     }
 };
-static std::map<TuneKey, std::array<int, 3>> g_tuned;
+static std::map<TuneKey, std::array<int, 4>> g_tuned;
 static std::mutex g_tune_mu;
 
 // Pass-timer bits of each axis's passes (x: forward projection and backward;
@@ -226,7 +227,7 @@ static float axis_pass_ms(sgm_plan p, void* u, void* uh, unsigned mask, hipStrea
 }
 
 // Take stored choices if every one names a compiled variant that fits.
-static bool apply_tuned(sgm_plan p, const std::array<int, 3>& v, int lds_max) {
+static bool apply_tuned(sgm_plan p, const std::array<int, 4>& v, int lds_max) {
     const int Llast = p->ndim == 3 ? p->M2 : p->M1;
     RegKernels k[3];
     const bool has[3] = {p->hx, p->hy, p->hz};
@@ -237,10 +238,53 @@ static bool apply_tuned(sgm_plan p, const std::array<int, 3>& v, int lds_max) {
         if ((a == 0 ? k[a].lds_cheb : a == 1 ? k[a].lds_str : k[a].lds) > (size_t)lds_max) return false;
         if (a == 1 && !strided_fits(k[a], p->spec_last)) return false;
     }
+    if (v[3] != 8 && v[3] != kSegRows) return false;
     if (p->hx) p->rkx = k[0];
     if (p->hy) p->rky = k[1];
     if (p->hz) p->rkz = k[2];
+    p->seg_R = v[3];
     return true;
+}
+
+static bool biharmonic_basis(int basis) { return basis == SGM_SHEN_BIHARMONIC || basis == SGM_LEG_BIHARMONIC; }
+static int solve_kind(int basis) { return biharmonic_basis(basis) ? SGM_SHEN_BIHARMONIC : basis; }
+static int table_kind(int basis) { return biharmonic_basis(basis) ? SGM_SHEN_BIHARMONIC : SGM_SHEN_DIRICHLET; }
+// Bases whose solves run the segmented kernels.
+static bool seg_basis(int basis) { return basis != SGM_CHEBYSHEV && basis != SGM_LEGENDRE; }
+
+// Time of the segmented solve at R rows per lane (table filled, best of three
+// launches in place on uh); 1e30 where the chains are too long for R.
+static float solve_rows_ms(sgm_plan p, void* uh, int R, hipStream_t s) {
+    const int nmax = std::max(p->cd.npar[0], p->cd.npar[1]);
+    const int K = seg_lanes(nmax, R);
+    if (K <= 0) return 1e30f;
+    const int kind = solve_kind(p->d.basis);
+    const double alpha = kind == SGM_SHEN_BIHARMONIC ? 0.0 : 1.0;
+    const size_t nt = seg_table_doubles(kind, K, p->geom.ncols);
+    double* tab = nullptr;
+    if (nt > 0 && hipMalloc(&tab, nt * sizeof(double)) != hipSuccess) return 1e30f;
+    float best = 1e30f;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+        launch_seg_table(tab, p->cd, p->geom, kind, K, R, alpha, s) == hipSuccess) {
+        double2* d = static_cast<double2*>(uh);
+        if (launch_solve_seg(d, d, tab, p->cd, p->geom, kind, K, R, alpha, s) == hipSuccess) {
+            for (int r = 0; r < 3; ++r) {
+                float t = 1e30f;
+                if (hipEventRecord(e0, s) != hipSuccess ||
+                    launch_solve_seg(d, d, tab, p->cd, p->geom, kind, K, R, alpha, s) != hipSuccess ||
+                    hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+                    t = 1e30f;
+                best = std::min(best, t);
+            }
+        }
+    }
+    hipStreamSynchronize(s);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipFree(tab);
+    return best;
 }
 
 static std::string plan_tune_key(sgm_plan p) {
@@ -259,8 +303,9 @@ static sgm_status autotune_plan(sgm_plan p, int lds_max, hipStream_t s) {
     }
     const std::string fkey = plan_tune_key(p);
     std::vector<int> cached;
-    if (tune_cache_get(fkey, cached) && cached.size() == 3) {
-        const std::array<int, 3> v{cached[0], cached[1], cached[2]};
+    if (tune_cache_get(fkey, cached) && (cached.size() == 3 || cached.size() == 4)) {
+        // three values: an entry from before the solve was tuned (16 rows per lane)
+        const std::array<int, 4> v{cached[0], cached[1], cached[2], cached.size() == 4 ? cached[3] : kSegRows};
         if (apply_tuned(p, v, lds_max)) {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             g_tuned[key] = v;
@@ -280,7 +325,7 @@ static sgm_status autotune_plan(sgm_plan p, int lds_max, hipStream_t s) {
         return SGM_ERR_HIP;
     }
     const int Llast = p->ndim == 3 ? p->M2 : p->M1;
-    std::array<int, 3> best{0, 0, 0};
+    std::array<int, 4> best{0, 0, 0, kSegRows};
     struct Ax { bool has; RegKernels* rk; int L; int idx; };
     Ax axes[3] = {{p->hx, &p->rkx, p->N, 0}, {p->hy, &p->rky, p->M1, 1}, {p->hz, &p->rkz, Llast, 2}};
     for (auto& ax : axes) {
@@ -299,10 +344,19 @@ static sgm_status autotune_plan(sgm_plan p, int lds_max, hipStream_t s) {
         }
         reg_kernels_for(ax.L, *ax.rk, best[ax.idx]);
     }
+    // rows per lane of the segmented solve (lanes per chain follow from the chain length)
+    if (seg_basis(p->d.basis)) {
+        float tbest = 1e30f;
+        for (int R : {kSegRows, 8}) {
+            const float t = solve_rows_ms(p, uh, R, s);
+            if (t < tbest) { tbest = t; best[3] = R; }
+        }
+        p->seg_R = best[3];
+    }
     hipStreamSynchronize(s);
     hipFree(u);
     hipFree(uh);
-    tune_cache_put(fkey, {best[0], best[1], best[2]});
+    tune_cache_put(fkey, {best[0], best[1], best[2], best[3]});
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[key] = best;
     return SGM_OK;
@@ -349,9 +403,6 @@ const char* sgm_status_string(sgm_status s) {
 // table-driven generic and chain kernels read every Helmholtz basis's rows, which
 // have the Dirichlet shape (band + a rank-1 tail, zero for the Legendre bases), as
 // SGM_SHEN_DIRICHLET.
-static bool biharmonic_basis(int basis) { return basis == SGM_SHEN_BIHARMONIC || basis == SGM_LEG_BIHARMONIC; }
-static int solve_kind(int basis) { return biharmonic_basis(basis) ? SGM_SHEN_BIHARMONIC : basis; }
-static int table_kind(int basis) { return biharmonic_basis(basis) ? SGM_SHEN_BIHARMONIC : SGM_SHEN_DIRICHLET; }
 
 sgm_status sgm_plan_create(const sgm_plan_desc* desc, void* stream, sgm_plan* out) {
     clear_error();
@@ -527,7 +578,7 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, void* stream, sgm_plan* ou
         }
     }
     if (d.basis != SGM_CHEBYSHEV && d.basis != SGM_LEGENDRE && d.autotune != 2) {
-        p->seg_K = seg_lanes(std::max(cd.npar[0], cd.npar[1]));
+        p->seg_K = seg_lanes(std::max(cd.npar[0], cd.npar[1]), p->seg_R);
         const size_t nt = seg_table_doubles(solve_kind(d.basis), p->seg_K, g.ncols);
         if (p->seg_K > 0 && nt > 0 && hipMalloc(&p->seg_tab, nt * sizeof(double)) != hipSuccess) {
             set_error("hipMalloc solve table failed");
@@ -543,6 +594,38 @@ sgm_status sgm_plan_timing(sgm_plan p, int enable) {
     clear_error();
     SGM_CHECK_ARG(p, "null plan");
     p->timing = (enable & SGM_TIMING_ONLY) ? (unsigned)(enable & 0xff) : (enable ? 0xffu : 0u);
+    return SGM_OK;
+}
+
+sgm_status sgm_plan_solve_layout(sgm_plan p, int* lanes, int* rows) {
+    clear_error();
+    SGM_CHECK_ARG(p && lanes && rows, "null argument");
+    *lanes = p->seg_K;
+    *rows = p->seg_K > 0 ? p->seg_R : 0;
+    return SGM_OK;
+}
+
+sgm_status sgm_plan_set_solve_rows(sgm_plan p, int rows) {
+    clear_error();
+    SGM_CHECK_ARG(p, "null plan");
+    SGM_CHECK_ARG(rows == 8 || rows == kSegRows, "rows per lane must be 8 or %d (got %d)", kSegRows, rows);
+    SGM_CHECK_ARG(seg_basis(p->d.basis) && p->d.autotune != 2, "the plan has no segmented solve");
+    const int K = seg_lanes(std::max(p->cd.npar[0], p->cd.npar[1]), rows);
+    SGM_CHECK_ARG(K > 0, "chains of %d rows are too long for %d rows per lane",
+                  std::max(p->cd.npar[0], p->cd.npar[1]), rows);
+    const size_t nt = seg_table_doubles(solve_kind(p->d.basis), K, p->geom.ncols);
+    // the old table may still be read by queued solves
+    if (p->seg_tab) SGM_HIP_TRY(hipDeviceSynchronize());
+    double* tab = nullptr;
+    if (nt > 0 && hipMalloc(&tab, nt * sizeof(double)) != hipSuccess) {
+        set_error("hipMalloc solve table failed");
+        return SGM_ERR_OOM;
+    }
+    hipFree(p->seg_tab);
+    p->seg_tab = tab;
+    p->seg_K = K;
+    p->seg_R = rows;
+    p->seg_ok = false;
     return SGM_OK;
 }
 
@@ -823,7 +906,7 @@ static sgm_status solve_dispatch(sgm_plan p, int kind, double alpha, const void*
         sgm_status st = seg_table_for(p, kind, alpha, s);
         if (st != SGM_OK) return st;
         SGM_HIP_TRY(launch_solve_seg(static_cast<const double2*>(f), static_cast<double2*>(u), p->seg_tab, p->cd,
-                                     p->geom, kind, p->seg_K, alpha, s));
+                                     p->geom, kind, p->seg_K, p->seg_R, alpha, s));
         return SGM_OK;
     }
     SGM_HIP_TRY(launch_solve_chain(static_cast<const double2*>(f), static_cast<double2*>(u),
@@ -834,7 +917,7 @@ static sgm_status solve_dispatch(sgm_plan p, int kind, double alpha, const void*
 // Boundary-state table of the segmented solve for this alpha (refilled when alpha changes).
 static sgm_status seg_table_for(sgm_plan p, int kind, double alpha, hipStream_t s) {
     if (!p->seg_ok || p->seg_alpha != alpha) {
-        SGM_HIP_TRY(launch_seg_table(p->seg_tab, p->cd, p->geom, kind, p->seg_K, alpha, s));
+        SGM_HIP_TRY(launch_seg_table(p->seg_tab, p->cd, p->geom, kind, p->seg_K, p->seg_R, alpha, s));
         p->seg_ok = true;
         p->seg_alpha = alpha;
     }
@@ -852,7 +935,8 @@ sgm_status sgm_helmholtz_solve_physical(sgm_plan p, double alpha, const void* f,
     double2* uh = static_cast<double2*>(u_hat);
     st = fourier_forward(p, f, uh, s);
     if (st != SGM_OK) return st;
-    if (p->d.basis == SGM_SHEN_DIRICHLET && p->hx && p->rkx.cf_spsolve && p->seg_K == 8 && p->d.autotune != 2) {
+    if (p->d.basis == SGM_SHEN_DIRICHLET && p->hx && p->rkx.cf_spsolve && p->seg_K == 8 && p->seg_R == kSegRows &&
+        p->d.autotune != 2) {
         if ((st = seg_table_for(p, SGM_SHEN_DIRICHLET, alpha, s)) != SGM_OK) return st;
         PassTimer t(p, 5, s);
         const RegKernels& k = p->rkx;

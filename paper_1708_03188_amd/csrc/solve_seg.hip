@@ -92,22 +92,43 @@ __global__ void __launch_bounds__(256) k_solve_seg(const double2* in, double2* o
                            cd.solve[1]);
 }
 
-template <int KIND, int K>
+template <int KIND, int K, int R>
 hipError_t launch_seg_k(const double2* in, double2* out, const double* tab, const ChebDev& cd, const ColGeom& g,
                         double alpha, hipStream_t s) {
     constexpr int C = 64 / K;
     const long waves = 2L * ((g.ncols + C - 1) / C);
     const long blocks = (waves + 3) / 4;
-    hipLaunchKernelGGL((k_solve_seg<KIND, K, kSegRows>), dim3((unsigned)blocks), dim3(256), 0, s, in, out, tab, cd, g,
-                       alpha);
+    hipLaunchKernelGGL((k_solve_seg<KIND, K, R>), dim3((unsigned)blocks), dim3(256), 0, s, in, out, tab, cd, g, alpha);
     return hipGetLastError();
+}
+
+template <int KIND, int R>
+hipError_t launch_seg_lanes(int K, const double2* in, double2* out, const double* tab, const ChebDev& cd,
+                            const ColGeom& g, double alpha, hipStream_t s) {
+    switch (K) {
+        case 1: return launch_seg_k<KIND, 1, R>(in, out, tab, cd, g, alpha, s);
+        case 2: return launch_seg_k<KIND, 2, R>(in, out, tab, cd, g, alpha, s);
+        case 4: return launch_seg_k<KIND, 4, R>(in, out, tab, cd, g, alpha, s);
+        case 8: return launch_seg_k<KIND, 8, R>(in, out, tab, cd, g, alpha, s);
+        case 16: return launch_seg_k<KIND, 16, R>(in, out, tab, cd, g, alpha, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int KIND>
+hipError_t launch_seg_rows(int K, int R, const double2* in, double2* out, const double* tab, const ChebDev& cd,
+                           const ColGeom& g, double alpha, hipStream_t s) {
+    if (R == 16) return launch_seg_lanes<KIND, 16>(K, in, out, tab, cd, g, alpha, s);
+    if (R == 8) return launch_seg_lanes<KIND, 8>(K, in, out, tab, cd, g, alpha, s);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-int seg_lanes(int nmax) {
+int seg_lanes(int nmax, int R) {
+    if (R != 8 && R != 16) return 0;
     int K = 1;
-    while (K * kSegRows < nmax) K *= 2;
+    while (K * R < nmax) K *= 2;
     return K <= kSegMaxLanes ? K : 0;
 }
 
@@ -116,77 +137,39 @@ size_t seg_table_doubles(int kind, int K, int ncols) {
     return K > 1 ? (size_t)(K - 1) * 2 * ncols * WS : 0;
 }
 
-hipError_t launch_seg_table(double* tab, const ChebDev& cd, const ColGeom& g, int kind, int K, double alpha,
+hipError_t launch_seg_table(double* tab, const ChebDev& cd, const ColGeom& g, int kind, int K, int R, double alpha,
                             hipStream_t s) {
     if (K <= 1) return hipSuccess;
     const int blocks = (2 * g.ncols + 255) / 256;
-    if (kind == SGM_SHEN_DIRICHLET)
-        hipLaunchKernelGGL(k_seg_table<SGM_SHEN_DIRICHLET>, dim3(blocks), dim3(256), 0, s, cd, g, alpha, kSegRows, K,
-                           tab);
-    else if (kind == SGM_LEG_DIRICHLET)
-        hipLaunchKernelGGL(k_seg_table<SGM_LEG_DIRICHLET>, dim3(blocks), dim3(256), 0, s, cd, g, alpha, kSegRows, K,
-                           tab);
-    else if (kind == SGM_SHEN_NEUMANN)
-        hipLaunchKernelGGL(k_seg_table<SGM_SHEN_NEUMANN>, dim3(blocks), dim3(256), 0, s, cd, g, alpha, kSegRows, K,
-                           tab);
-    else if (kind == SGM_LEG_NEUMANN)
-        hipLaunchKernelGGL(k_seg_table<SGM_LEG_NEUMANN>, dim3(blocks), dim3(256), 0, s, cd, g, alpha, kSegRows, K,
-                           tab);
-    else
-        hipLaunchKernelGGL(k_seg_table<SGM_SHEN_BIHARMONIC>, dim3(blocks), dim3(256), 0, s, cd, g, alpha, kSegRows, K,
-                           tab);
+    switch (kind) {
+        case SGM_SHEN_DIRICHLET:
+            hipLaunchKernelGGL(k_seg_table<SGM_SHEN_DIRICHLET>, dim3(blocks), dim3(256), 0, s, cd, g, alpha, R, K, tab);
+            break;
+        case SGM_LEG_DIRICHLET:
+            hipLaunchKernelGGL(k_seg_table<SGM_LEG_DIRICHLET>, dim3(blocks), dim3(256), 0, s, cd, g, alpha, R, K, tab);
+            break;
+        case SGM_SHEN_NEUMANN:
+            hipLaunchKernelGGL(k_seg_table<SGM_SHEN_NEUMANN>, dim3(blocks), dim3(256), 0, s, cd, g, alpha, R, K, tab);
+            break;
+        case SGM_LEG_NEUMANN:
+            hipLaunchKernelGGL(k_seg_table<SGM_LEG_NEUMANN>, dim3(blocks), dim3(256), 0, s, cd, g, alpha, R, K, tab);
+            break;
+        default:
+            hipLaunchKernelGGL(k_seg_table<SGM_SHEN_BIHARMONIC>, dim3(blocks), dim3(256), 0, s, cd, g, alpha, R, K,
+                               tab);
+            break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_solve_seg(const double2* in, double2* out, const double* tab, const ChebDev& cd, const ColGeom& g,
-                            int kind, int K, double alpha, hipStream_t s) {
-    if (kind == SGM_SHEN_DIRICHLET) {
-        switch (K) {
-            case 1: return launch_seg_k<SGM_SHEN_DIRICHLET, 1>(in, out, tab, cd, g, alpha, s);
-            case 2: return launch_seg_k<SGM_SHEN_DIRICHLET, 2>(in, out, tab, cd, g, alpha, s);
-            case 4: return launch_seg_k<SGM_SHEN_DIRICHLET, 4>(in, out, tab, cd, g, alpha, s);
-            case 8: return launch_seg_k<SGM_SHEN_DIRICHLET, 8>(in, out, tab, cd, g, alpha, s);
-            case 16: return launch_seg_k<SGM_SHEN_DIRICHLET, 16>(in, out, tab, cd, g, alpha, s);
-            default: return hipErrorInvalidValue;
-        }
-    }
-    if (kind == SGM_LEG_NEUMANN) {
-        switch (K) {
-            case 1: return launch_seg_k<SGM_LEG_NEUMANN, 1>(in, out, tab, cd, g, alpha, s);
-            case 2: return launch_seg_k<SGM_LEG_NEUMANN, 2>(in, out, tab, cd, g, alpha, s);
-            case 4: return launch_seg_k<SGM_LEG_NEUMANN, 4>(in, out, tab, cd, g, alpha, s);
-            case 8: return launch_seg_k<SGM_LEG_NEUMANN, 8>(in, out, tab, cd, g, alpha, s);
-            case 16: return launch_seg_k<SGM_LEG_NEUMANN, 16>(in, out, tab, cd, g, alpha, s);
-            default: return hipErrorInvalidValue;
-        }
-    }
-    if (kind == SGM_SHEN_NEUMANN) {
-        switch (K) {
-            case 1: return launch_seg_k<SGM_SHEN_NEUMANN, 1>(in, out, tab, cd, g, alpha, s);
-            case 2: return launch_seg_k<SGM_SHEN_NEUMANN, 2>(in, out, tab, cd, g, alpha, s);
-            case 4: return launch_seg_k<SGM_SHEN_NEUMANN, 4>(in, out, tab, cd, g, alpha, s);
-            case 8: return launch_seg_k<SGM_SHEN_NEUMANN, 8>(in, out, tab, cd, g, alpha, s);
-            case 16: return launch_seg_k<SGM_SHEN_NEUMANN, 16>(in, out, tab, cd, g, alpha, s);
-            default: return hipErrorInvalidValue;
-        }
-    }
-    if (kind == SGM_LEG_DIRICHLET) {
-        switch (K) {
-            case 1: return launch_seg_k<SGM_LEG_DIRICHLET, 1>(in, out, tab, cd, g, alpha, s);
-            case 2: return launch_seg_k<SGM_LEG_DIRICHLET, 2>(in, out, tab, cd, g, alpha, s);
-            case 4: return launch_seg_k<SGM_LEG_DIRICHLET, 4>(in, out, tab, cd, g, alpha, s);
-            case 8: return launch_seg_k<SGM_LEG_DIRICHLET, 8>(in, out, tab, cd, g, alpha, s);
-            case 16: return launch_seg_k<SGM_LEG_DIRICHLET, 16>(in, out, tab, cd, g, alpha, s);
-            default: return hipErrorInvalidValue;
-        }
-    }
-    switch (K) {
-        case 1: return launch_seg_k<SGM_SHEN_BIHARMONIC, 1>(in, out, tab, cd, g, alpha, s);
-        case 2: return launch_seg_k<SGM_SHEN_BIHARMONIC, 2>(in, out, tab, cd, g, alpha, s);
-        case 4: return launch_seg_k<SGM_SHEN_BIHARMONIC, 4>(in, out, tab, cd, g, alpha, s);
-        case 8: return launch_seg_k<SGM_SHEN_BIHARMONIC, 8>(in, out, tab, cd, g, alpha, s);
-        case 16: return launch_seg_k<SGM_SHEN_BIHARMONIC, 16>(in, out, tab, cd, g, alpha, s);
-        default: return hipErrorInvalidValue;
+                            int kind, int K, int R, double alpha, hipStream_t s) {
+    switch (kind) {
+        case SGM_SHEN_DIRICHLET: return launch_seg_rows<SGM_SHEN_DIRICHLET>(K, R, in, out, tab, cd, g, alpha, s);
+        case SGM_LEG_DIRICHLET: return launch_seg_rows<SGM_LEG_DIRICHLET>(K, R, in, out, tab, cd, g, alpha, s);
+        case SGM_SHEN_NEUMANN: return launch_seg_rows<SGM_SHEN_NEUMANN>(K, R, in, out, tab, cd, g, alpha, s);
+        case SGM_LEG_NEUMANN: return launch_seg_rows<SGM_LEG_NEUMANN>(K, R, in, out, tab, cd, g, alpha, s);
+        default: return launch_seg_rows<SGM_SHEN_BIHARMONIC>(K, R, in, out, tab, cd, g, alpha, s);
     }
 }
 

@@ -38,14 +38,26 @@ def test_plan_choices_persist_and_reload(tmp_path, monkeypatch):
     autotune_forget()
     shape = (128, 128, 256)
     p = Plan("dirichlet", *shape, autotune=True)
-    first = p.variants()
+    first = p.variants() + [p.solve_layout()[1]]
+    assert first[3] in (8, 16)
     lines = _lines(path, "plan ")
     assert len(lines) == 1 and [int(v) for v in lines[0].split("=")[1].split()] == first
-    # another compiled choice in the file: the next tuned plan takes it
-    _rewrite(path, "plan ", [6, 7, 2])
+    # another compiled choice in the file (register variants per axis, rows per lane of
+    # the solves): the next tuned plan takes it
+    _rewrite(path, "plan ", [6, 7, 2, 8])
     autotune_forget()
     q = Plan("dirichlet", *shape, autotune=True)
-    assert q.variants() == [6, 7, 2]
+    assert q.variants() == [6, 7, 2] and q.solve_layout() == (8, 8)
+    ft = synth.random_spectral(q.spec_shape, seed=32, nrows=shape[0] - 2)
+    sol = q.helmholtz_solve(torch.from_numpy(ft).cuda(), 1.0)
+    torch.cuda.synchronize()
+    scols = np.array([0, 7, 129 * 5 + 3, 128 * 129 - 1])
+    ref = T.helmholtz_solve("dirichlet", ft, 1.0, shape[-1], cols=scols)
+    assert rel_err(sol.cpu().numpy().reshape(shape[0], -1)[:, scols], ref) < 1e-10
+    # an entry from before the solve was tuned (three values): 16 rows per lane
+    _rewrite(path, "plan ", [6, 7, 2])
+    autotune_forget()
+    assert Plan("dirichlet", *shape, autotune=True).solve_layout() == (4, 16)
     u = synth.random_smooth_field(shape, seed=31)
     uh = q.forward(torch.from_numpy(u).cuda())
     torch.cuda.synchronize()
@@ -58,7 +70,7 @@ def test_plan_choices_persist_and_reload(tmp_path, monkeypatch):
     torch.cuda.synchronize()
     assert rel_err(back.cpu().numpy()[rows], T.backward_rows("dirichlet", vh, rows, shape[-1])) < 1e-12
     # a stored choice naming no compiled kernel (variant 4 does not exist at 128) is ignored
-    _rewrite(path, "plan ", [4, 4, 4])
+    _rewrite(path, "plan ", [4, 4, 4, 16])
     autotune_forget()
     r = Plan("dirichlet", *shape, autotune=True)
     assert 4 not in r.variants()[:2]

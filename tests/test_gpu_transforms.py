@@ -372,3 +372,51 @@ def test_neumann_full_size_sampled(Plan, shape):
     fts = synth.random_spectral(p.spec_shape, seed=N + 5, nrows=N - 2)
     out = host(p.helmholtz_solve(dev(fts), 1.0)).reshape(N, -1)[:, cols]
     assert rel_err(out, T.helmholtz_solve("neumann", fts, 1.0, M2, cols=cols)) < TOL_S
+
+
+ROWS8 = ([(b, n) for b in ("dirichlet", "neumann", "leg_dirichlet", "leg_neumann") for n in (6, 19, 35, 66, 131, 258)]
+         + [(b, n) for b in ("biharmonic", "leg_biharmonic") for n in (9, 21, 40, 70, 133, 260)])
+
+
+@pytest.mark.parametrize("basis,N", ROWS8)
+def test_solves_at_eight_rows_per_lane(Plan, basis, N):
+    # the segmented solves with 8 rows per lane (the autotuner's other choice): chains
+    # of 1..16 lanes per parity with ragged last segments, every solve kind, against
+    # the oracle; switching back to 16 rows gives the same answers
+    print(f"[case] solve 8 rows per lane {basis} N={N}", flush=True)
+    p = Plan(basis, N, 6)
+    p.set_solve_rows(8)
+    lanes, rows = p.solve_layout()
+    nb = N - 4 if "biharmonic" in basis else N - 2
+    nmax = (nb + 1) // 2  # rows of the longer parity chain
+    assert rows == 8 and lanes * 8 >= nmax and (lanes == 1 or lanes * 4 < nmax)
+    nrows = N - 4 if "biharmonic" in basis else N - 2
+    ft = synth.random_spectral(p.spec_shape, seed=900 + N, nrows=nrows)
+    if "biharmonic" in basis:
+        ref = T.biharmonic_solve(basis, ft, 6)
+        got = host(p.biharmonic_solve(dev(ft)))
+        assert rel_err(got, ref) < TOL_S
+        p.set_solve_rows(16)
+        assert rel_err(host(p.biharmonic_solve(dev(ft))), got) < TOL_S
+    else:
+        for alpha in (1.0, 2.5):
+            ref = T.helmholtz_solve(basis, ft, alpha, 6)
+            assert rel_err(host(p.helmholtz_solve(dev(ft), alpha)), ref) < TOL_S, alpha
+        p.set_solve_rows(16)
+        assert rel_err(host(p.helmholtz_solve(dev(ft), 2.5)), ref) < TOL_S
+    assert p.solve_layout()[1] == 16
+
+
+def test_solve_rows_arguments(Plan):
+    from paper_1708_03188_amd._lib import SgmError
+    p = Plan("dirichlet", 16, 6)
+    for r in (0, 4, 12, 32):
+        with pytest.raises(SgmError, match="rows per lane"):
+            p.set_solve_rows(r)
+    with pytest.raises(SgmError, match="no segmented solve"):
+        Plan("chebyshev", 16, 6).set_solve_rows(8)
+    assert Plan("chebyshev", 16, 6).solve_layout() == (0, 0)
+    # chains of 257 rows need 33 lanes at 8 rows per lane
+    big = Plan("dirichlet", 516, 4)
+    with pytest.raises(SgmError, match="too long"):
+        big.set_solve_rows(8)
