@@ -251,7 +251,7 @@ typedef struct {
                        and stream) and replays it; 0: launches the kernels directly      */
     int tune;       /* launch configuration of the time-stepping kernels: 0 default;
                        1 time every candidate on one step at creation (on the current
-                       device, default stream) and keep the fastest; 16 + k pin
+                       device, on the creation stream) and keep the fastest; 16 + k pin
                        candidate k, 0 <= k < SGM_GL_NVARIANT                             */
 } sgm_gl_desc;
 #define SGM_GL_NVARIANT 6 /* candidate = 2 * geometry (3 FFT tilings) + grid mode
