@@ -95,3 +95,16 @@ def test_plain_c_consumer_compiles_links_and_runs(tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
     assert "ok" in r.stdout
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    # the product path has no fallback: without the built library every entry into
+    # the binding raises instead of computing anything another way
+    from paper_1708_03188_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libsgm.so"))
+    with pytest.raises(_lib.SgmError, match="not found"):
+        _lib.load()
+    from paper_1708_03188_amd import api
+    with pytest.raises(_lib.SgmError, match="not found"):
+        api.Plan("dirichlet", 8, 4)
