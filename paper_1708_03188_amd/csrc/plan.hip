@@ -180,8 +180,11 @@ extern "C" sgm_status sgm_forward(sgm_plan p, const void* u, void* u_hat, void* 
 extern "C" sgm_status sgm_backward(sgm_plan p, const void* u_hat, void* u, void* stream);
 
 // Autotuner: for every axis with register kernels, time each compiled variant
-// (tile width and exchange-buffer count) on the plan's own passes and keep the
-// fastest.  Choices are remembered per process, keyed by the plan geometry.
+// (threads per line, exchange buffers, block size, radix schedule) on the plan's
+// own passes and keep the fastest; then the rows per lane of the segmented
+// solves.  Choices (three variants and the rows per lane) are remembered per
+// process, keyed by the plan geometry, and in the tune-cache file keyed by the
+// device and the geometry.
 struct TuneKey {
     int ndim, basis, N, M1, M2, kind;
     bool operator<(const TuneKey& o) const {

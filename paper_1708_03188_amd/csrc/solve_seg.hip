@@ -8,8 +8,9 @@
 // kept as affine functions c + w . (x_i, .., x_{i-P+1}) of the window.  The
 // w parts depend on the matrix only; the c parts are linear in f.
 //
-// Here the n rows of a chain are cut into K segments of at most R rows, one
-// lane each, with the segment's rows held in registers:
+// Here the n rows of a chain are cut into K segments of at most R rows (R = 16
+// or 8, chosen per plan), one lane each, with the segment's rows held in
+// registers:
 //  1. w at the bottom of every segment comes from a table filled by a plain
 //     sequential sweep of the w recurrence (it depends on kappa^2 and alpha
 //     only and is cached per plan);
