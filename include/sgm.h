@@ -197,7 +197,11 @@ sgm_status sgm_biharmonic_solve(sgm_plan plan, const void* f_tilde, void* u_hat,
 sgm_status sgm_project_derivative(sgm_plan plan, sgm_plan target, const int order[3], const void* u_hat,
                                   void* du_hat, void* stream);
 
-/* Per-pass timing (diagnostics).  enable = 0: off; 1: every pass kernel this plan
+/* Small 2D spaces (ndim = 2, N <= 64, M1 <= 64, not biharmonic) with autotune 0 or 1
+ * run every forward / backward / scalar-product call as one kernel (dense products in
+ * one work-group's LDS); their pass timing then records the whole call as the x pass
+ * (kind 4, 5 or 6).
+ * Per-pass timing (diagnostics).  enable = 0: off; 1: every pass kernel this plan
  * launches is bracketed by two hipEvents recorded on the caller's stream (the
  * events are created on first use and owned by the plan); SGM_TIMING_ONLY | bits:
  * only the pass kinds whose bit (1 << kind) is set.  Pass kinds:

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsgm.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["tables.cpp", "tune_cache.cpp", "legendre_tables.cpp", "legendre.hip", "kernels.hip", "kernels_reg.hip", "solve_chain.hip", "solve_seg.hip", "derivative.hip", "gl.hip", "fno_gemm.hip", "fno_fused.hip", "fno.hip", "plan.hip"]
+SOURCES = ["tables.cpp", "tune_cache.cpp", "legendre_tables.cpp", "small_tables.cpp", "small.hip", "legendre.hip", "kernels.hip", "kernels_reg.hip", "solve_chain.hip", "solve_seg.hip", "derivative.hip", "gl.hip", "fno_gemm.hip", "fno_fused.hip", "fno.hip", "plan.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ROCM_LIB = "/opt/rocm/lib"
 FLAGS = [

@@ -14,6 +14,7 @@
 #include "kernels_reg.h"
 #include "legendre.h"
 #include "solve_chain.h"
+#include "small.h"
 #include "solve_seg.h"
 #include "tables.h"
 #include "tune_cache.h"
@@ -108,6 +109,9 @@ struct sgm_plan_s {
     // valid for seg_alpha once seg_ok
     int seg_K = 0;
     int seg_R = kSegRows;  // rows per lane (chosen by the autotuner: 16 or 8)
+    // small 2D spaces: every transform in one kernel (tables in the blob)
+    bool small = false;
+    SmallDev sd{};
     double* seg_tab = nullptr;
     bool seg_ok = false;
     double seg_alpha = 0.0;
@@ -332,7 +336,7 @@ static sgm_status autotune_plan(sgm_plan p, int lds_max, hipStream_t s) {
     struct Ax { bool has; RegKernels* rk; int L; int idx; };
     Ax axes[3] = {{p->hx, &p->rkx, p->N, 0}, {p->hy, &p->rky, p->M1, 1}, {p->hz, &p->rkz, Llast, 2}};
     for (auto& ax : axes) {
-        if (!ax.has) continue;
+        if (!ax.has || p->small) continue;  // a small space runs no per-axis pass
         float tbest = 1e30f;
         for (int v = 0; v < kRegVariants; ++v) {
             RegKernels cand;
@@ -484,6 +488,22 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, void* stream, sgm_plan* ou
         for (int j = 0; j < d.N; ++j) p->xpts[j] = std::cos((2 * j + 1) * 3.14159265358979323846 / (2.0 * d.N));
     }
     Blob b;
+    // Small 2D spaces (N, M <= 64, not biharmonic: its projection matrix is
+    // ill-conditioned) run every transform in one kernel, except where the plan
+    // pins register-kernel variants or asks for the generic kernels.
+    const bool small = d.ndim == 2 && d.N <= kSmallMaxN && d.M1 <= kSmallMaxM && !biharmonic_basis(d.basis) &&
+                       (d.autotune == 0 || d.autotune == 1);
+    size_t o_small = 0;
+    if (small) {
+        std::vector<double> sv;
+        if (!build_small_tables(d.basis, d.N, d.M1, p->r2c, leg ? &lt.fwd : nullptr, leg ? &lt.sp : nullptr,
+                                leg ? &lt.bwd : nullptr, sv, err)) {
+            set_error("%s", err.c_str());
+            delete p;
+            return SGM_ERR_UNSUPPORTED_SIZE;
+        }
+        o_small = b.add(sv);
+    }
     size_t o_lf = 0, o_lb = 0, o_ls = 0;
     if (leg) {
         o_lf = b.add(leg_pack(lt.fwd, d.N));
@@ -533,6 +553,18 @@ sgm_status sgm_plan_create(const sgm_plan_desc* desc, void* stream, sgm_plan* ou
         p->leg_fwd = D(o_lf);
         p->leg_bwd = D(o_lb);
         p->leg_sp = D(o_ls);
+    }
+    if (small) {
+        SmallDev& sd = p->sd;
+        sd.N = d.N;
+        sd.M = d.M1;
+        sd.r2c = p->r2c ? 1 : 0;
+        sd.Mc = p->spec_last;
+        const size_t nF = 2 * (size_t)sd.M * sd.Mc;
+        sd.F = reinterpret_cast<const double2*>(base + o_small);
+        sd.G = reinterpret_cast<const double2*>(base + o_small + nF * sizeof(double));
+        for (int m = 0; m < 3; ++m) sd.P[m] = D(o_small + (2 * nF + (size_t)m * d.N * d.N) * sizeof(double));
+        p->small = true;
     }
 
     const double twopi = 6.283185307179586476925286766559;
@@ -789,6 +821,11 @@ sgm_status sgm_forward(sgm_plan p, const void* u, void* u_hat, void* stream) {
     SGM_CHECK_ARG(u != u_hat, "u and u_hat must not alias");
     hipStream_t s = static_cast<hipStream_t>(stream);
     double2* uh = static_cast<double2*>(u_hat);
+    if (p->small) {
+        PassTimer t(p, 4, s);
+        SGM_HIP_TRY(launch_small_pass(u, uh, p->sd, kSmallForward, s));
+        return SGM_OK;
+    }
     sgm_status st = fourier_forward(p, u, uh, s);
     if (st != SGM_OK) return st;
     PassTimer t(p, 4, s);
@@ -803,6 +840,11 @@ sgm_status sgm_scalar_product(sgm_plan p, const void* f, void* f_tilde, void* st
     SGM_CHECK_ARG(f != f_tilde, "f and f_tilde must not alias");
     hipStream_t s = static_cast<hipStream_t>(stream);
     double2* ft = static_cast<double2*>(f_tilde);
+    if (p->small) {
+        PassTimer t(p, 5, s);
+        SGM_HIP_TRY(launch_small_pass(f, ft, p->sd, kSmallScalar, s));
+        return SGM_OK;
+    }
     sgm_status st = fourier_forward(p, f, ft, s);
     if (st != SGM_OK) return st;
     PassTimer t(p, 5, s);
@@ -813,6 +855,11 @@ sgm_status sgm_scalar_product(sgm_plan p, const void* f, void* f_tilde, void* st
 // Backward transform with the x pass writing into the spectral-sized workspace w
 // (the plan's own, or the allocation-free entry point's static one).
 static sgm_status backward_via(sgm_plan p, const void* u_hat, void* u, double2* w, hipStream_t s) {
+    if (p->small) {
+        PassTimer t(p, 6, s);
+        SGM_HIP_TRY(launch_small_pass(u_hat, u, p->sd, kSmallBackward, s));
+        return SGM_OK;
+    }
     {
         PassTimer t(p, 6, s);
         if (p->leg)
@@ -936,6 +983,13 @@ sgm_status sgm_helmholtz_solve_physical(sgm_plan p, double alpha, const void* f,
     if (st != SGM_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     double2* uh = static_cast<double2*>(u_hat);
+    if (p->small) {
+        {
+            PassTimer t(p, 5, s);
+            SGM_HIP_TRY(launch_small_pass(f, uh, p->sd, kSmallScalar, s));
+        }
+        return sgm_helmholtz_solve(p, alpha, uh, uh, stream);
+    }
     st = fourier_forward(p, f, uh, s);
     if (st != SGM_OK) return st;
     if (p->d.basis == SGM_SHEN_DIRICHLET && p->hx && p->rkx.cf_spsolve && p->seg_K == 8 && p->seg_R == kSegRows &&
