@@ -92,7 +92,79 @@ __global__ void k_act_bwd(const float* da, const bf16* z, bf16* dz, long n, int 
     dz[i] = (bf16)g;
 }
 
-// db[c] += sum_p g[p, c]  (g bf16 or fp32)
+// dz = da gelu'(z) (act) or da, four elements per thread (n a multiple of 4)
+__global__ void k_act_bwd4(const float* da, const bf16* z, bf16* dz, long n4, int act) {
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= n4) return;
+    const float4 g4 = reinterpret_cast<const float4*>(da)[i];
+    float g[4] = {g4.x, g4.y, g4.z, g4.w};
+    typedef __bf16 bf16x4v __attribute__((ext_vector_type(4)));
+    if (act) {
+        const bf16x4v zz = reinterpret_cast<const bf16x4v*>(z)[i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) g[j] *= gelu_df((float)zz[j]);
+    }
+    bf16x4v o;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = (bf16)g[j];
+    reinterpret_cast<bf16x4v*>(dz)[i] = o;
+}
+
+// The projection's hidden-layer gradient in one pass: dh = dpred W2^T (the two
+// dpred channels rounded to bf16, as the product's operands are), then
+// dhp = dh gelu'(hp) to bf16; eight hidden units per thread.
+__global__ void k_proj_act_bwd(const float* dpred, const bf16* W2, const bf16* hpz, bf16* dhp, long pix, int P) {
+    const int G8 = P / 8;
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= pix * G8) return;
+    const long p = i / G8;
+    const int j0 = (int)(i - p * G8) * 8;
+    const float d0 = (float)(bf16)dpred[2 * p], d1 = (float)(bf16)dpred[2 * p + 1];
+    typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+    const bf16x8v z = *reinterpret_cast<const bf16x8v*>(hpz + p * P + j0);
+    bf16x8v o;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const float w0 = (float)W2[2 * (j0 + j)], w1 = (float)W2[2 * (j0 + j) + 1];
+        o[j] = (bf16)((d0 * w0 + d1 * w1) * gelu_df((float)z[j]));
+    }
+    *reinterpret_cast<bf16x8v*>(dhp + p * P + j0) = o;
+}
+
+// db[c] += sum_p g[p, c] with 8 consecutive columns per thread (C a multiple of
+// 8): one 16-byte (bf16) or two (fp32) loads per row, so a wave reads whole
+// rows; per-block partials reduced in LDS, one atomic add per column and block.
+template <typename T>
+__global__ void __launch_bounds__(256) k_colsum8(const T* g, float* db, long P, int C) {
+    extern __shared__ float sh[];
+    const int G8 = C / 8;                     // threads per row
+    const int c8 = threadIdx.x % G8, r = threadIdx.x / G8, R = blockDim.x / G8;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (long p = blockIdx.x * (long)R + r; p < P; p += (long)gridDim.x * R) {
+        const T* q = g + p * C + 8 * c8;
+        if constexpr (sizeof(T) == 2) {
+            typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+            const bf16x8v v = *reinterpret_cast<const bf16x8v*>(q);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] += (float)v[j];
+        } else {
+            const float4 u = reinterpret_cast<const float4*>(q)[0], w = reinterpret_cast<const float4*>(q)[1];
+            acc[0] += u.x; acc[1] += u.y; acc[2] += u.z; acc[3] += u.w;
+            acc[4] += w.x; acc[5] += w.y; acc[6] += w.z; acc[7] += w.w;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sh[threadIdx.x * 8 + j] = acc[j];
+    __syncthreads();
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+        const int cg = c / 8, j = c % 8;
+        float sum = 0.f;
+        for (int q = 0; q < R; ++q) sum += sh[(q * G8 + cg) * 8 + j];
+        atomicAdd(&db[c], sum);
+    }
+}
+
+// db[c] += sum_p g[p, c]  (g bf16 or fp32), any C
 template <typename T>
 __global__ void k_colsum(const T* g, float* db, long P, int C) {
     extern __shared__ float sh[];
@@ -503,7 +575,9 @@ static GemmDesc G(int batch, int M, int N, int K, const void* A, long sAb, long 
 }
 
 static int splits_for(long K) {
-    long s = K / 4096;
+    // one split per 1024 rows of the reduction: enough work-groups to cover the
+    // device when the output is one 64 x 64 tile
+    long s = K / 1024;
     if (s < 1) s = 1;
     if (s > 1024) s = 1024;
     return (int)s;
@@ -609,11 +683,25 @@ static sgm_status fno_loss(sgm_fno f, const float* tgt, int B, bool grad, hipStr
 }
 
 static hipError_t colsum_bf16(const bf16* g, float* db, long P, int C, hipStream_t s) {
+    if (C % 8 == 0 && C <= 256 * 8 && (reinterpret_cast<uintptr_t>(g) & 15) == 0) {
+        const int G8 = C / 8, R = std::max(1, 256 / G8);
+        const long blocks = std::min(2048L, std::max(1L, (P + R - 1) / R));
+        hipLaunchKernelGGL(k_colsum8<bf16>, dim3((unsigned)blocks), dim3(R * G8), (size_t)R * G8 * 8 * 4, s, g, db, P,
+                           C);
+        return hipGetLastError();
+    }
     int R = std::max(1, 256 / C);
     hipLaunchKernelGGL(k_colsum<bf16>, dim3(512), dim3(R * C), (size_t)R * C * 4, s, g, db, P, C);
     return hipGetLastError();
 }
 static hipError_t colsum_f32(const float* g, float* db, long P, int C, hipStream_t s) {
+    if (C % 8 == 0 && C <= 256 * 8 && (reinterpret_cast<uintptr_t>(g) & 31) == 0) {
+        const int G8 = C / 8, R = std::max(1, 256 / G8);
+        const long blocks = std::min(2048L, std::max(1L, (P + R - 1) / R));
+        hipLaunchKernelGGL(k_colsum8<float>, dim3((unsigned)blocks), dim3(R * G8), (size_t)R * G8 * 8 * 4, s, g, db, P,
+                           C);
+        return hipGetLastError();
+    }
     int R = std::max(1, 256 / C);
     hipLaunchKernelGGL(k_colsum<float>, dim3(512), dim3(R * C), (size_t)R * C * 4, s, g, db, P, C);
     return hipGetLastError();
@@ -630,9 +718,15 @@ static sgm_status fno_backward(sgm_fno f, const float* x, int B, hipStream_t s) 
     SGM_HIP_TRY(gemm(G(1, P, 2, (int)pix, f->hbuf, 0, 1, P, 0, dpred, 0, 2, 1, 1, f->grad + f->oW2, 0, 2, 1, 0.f, sk), s));
     SGM_HIP_TRY(colsum_f32(dpred, f->grad + f->ob2, pix, 2, s));
     // dh = dpred W2^T ; dhp = dh gelu'(hp)
-    SGM_HIP_TRY(gemm(G(1, (int)pix, P, 2, dpred, 0, 2, 1, 1, f->W2_16, 0, 1, 2, 0, f->s32, 0, P, 1), s));
-    hipLaunchKernelGGL(k_act_bwd, dim3(nblk(pix * P)), dim3(256), 0, s, (const float*)f->s32, (const bf16*)f->hpz,
-                       f->d16, pix * P, 1);
+    if (P % 8 == 0) {
+        hipLaunchKernelGGL(k_proj_act_bwd, dim3(nblk(pix * (P / 8))), dim3(256), 0, s, dpred, (const bf16*)f->W2_16,
+                           (const bf16*)f->hpz, f->d16, pix, P);
+    } else {
+        SGM_HIP_TRY(gemm(G(1, (int)pix, P, 2, dpred, 0, 2, 1, 1, f->W2_16, 0, 1, 2, 0, f->s32, 0, P, 1), s));
+        hipLaunchKernelGGL(k_act_bwd, dim3(nblk(pix * P)), dim3(256), 0, s, (const float*)f->s32, (const bf16*)f->hpz,
+                           f->d16, pix * P, 1);
+    }
+    SGM_HIP_TRY(hipGetLastError());
     const bf16* alast = f->acts + f->nl * act;
     SGM_HIP_TRY(gemm(G(1, C, P, (int)pix, alast, 0, 1, C, 0, f->d16, 0, P, 1, 0, f->grad + f->oW1, 0, P, 1, 0.f, sk), s));
     SGM_HIP_TRY(colsum_bf16(f->d16, f->grad + f->ob1, pix, P, s));
@@ -641,8 +735,12 @@ static sgm_status fno_backward(sgm_fno f, const float* x, int B, hipStream_t s) 
     for (int l = f->nl - 1; l >= 0; --l) {
         const bf16* aprev = f->acts + l * act;
         // dz = da gelu'(z)
-        hipLaunchKernelGGL(k_act_bwd, dim3(nblk(pix * C)), dim3(256), 0, s, (const float*)f->da32,
-                           (const bf16*)(f->zsv + l * act), f->d16, pix * C, l < f->nl - 1 ? 1 : 0);
+        if ((pix * C) % 4 == 0 && act % 4 == 0)  // whole 4-element groups, 8-byte aligned z rows
+            hipLaunchKernelGGL(k_act_bwd4, dim3(nblk(pix * C / 4)), dim3(256), 0, s, (const float*)f->da32,
+                               (const bf16*)(f->zsv + l * act), f->d16, pix * C / 4, l < f->nl - 1 ? 1 : 0);
+        else
+            hipLaunchKernelGGL(k_act_bwd, dim3(nblk(pix * C)), dim3(256), 0, s, (const float*)f->da32,
+                               (const bf16*)(f->zsv + l * act), f->d16, pix * C, l < f->nl - 1 ? 1 : 0);
         const bf16* dz = f->d16;
         SGM_HIP_TRY(gemm(G(1, C, C, (int)pix, aprev, 0, 1, C, 0, dz, 0, C, 1, 0, f->grad + f->oWp[l], 0, C, 1, 0.f, sk),
                          s));

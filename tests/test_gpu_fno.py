@@ -27,8 +27,8 @@ CFG32R = dict(H=34, W=288, width=32, modes=16, layers=2, hidden=32)
 # the surrogate's full shape: 256 x 256, width 32, 16 modes, 4 layers, hidden 128
 CFG_C5 = dict(H=256, W=256, width=32, modes=16, layers=4, hidden=128)
 # gradient cases large enough for the split-K weight-gradient products (one split
-# per 4096 pixels, partial products accumulated atomically): 3 splits for the
-# general-GEMM network, 4 for the fused one
+# per 1024 pixels, partial products accumulated atomically): 12 splits for the
+# general-GEMM network (3 x 64 x 64 pixels), 16 for the fused one (4 x 64 x 64)
 CFG_SK = dict(H=64, W=64, width=8, modes=4, layers=2, hidden=16)
 CFG32_SK = dict(H=64, W=64, width=32, modes=16, layers=2, hidden=64)
 
