@@ -588,10 +588,16 @@ static int splits_for(long K) {
 // writes pred_out.  Width 32 with 16 x-modes runs the fused row kernels
 // (lift + x-DFT; inverse x-DFT + pointwise + bias + GELU + next x-DFT;
 // projection), other shapes the GEMM sequence.
+// Training with the fused row kernels keeps no hidden projection layer: the last
+// layer kernel also projects to the prediction, and the backward recomputes the
+// hidden pre-activation from the last layer's output.
+static bool proj_fused(sgm_fno f) { return fno_fused_ok(f->C, f->K, f->W, f->P) && fno_proj_bwd_ok(f->C, f->P); }
+
 static sgm_status fno_forward(sgm_fno f, const float* x, int B, hipStream_t s, float* pred_out = nullptr) {
     const int C = f->C, P = f->P, H = f->H, W = f->W, K = f->K, NM = f->NM;
     const long HW = (long)H * W, pix = (long)B * HW, act = (long)f->Bmax * HW * C;
     const bool fused = fno_fused_ok(C, K, W, P);
+    const bool projf = proj_fused(f);
     if (fused) {
         SGM_HIP_TRY(launch_fno_lift_dft(x, f->par + f->oWl, f->par + f->obl, f->Fx, f->acts, reinterpret_cast<bf16*>(f->T),
                                         (long)B * H, W, s));
@@ -643,8 +649,8 @@ static sgm_status fno_forward(sgm_fno f, const float* x, int B, hipStream_t s, f
             la.a_out = an; la.zsave = pred_out ? nullptr : f->zsv + l * act;
             la.rows = (long)B * H; la.W = W; la.act = l < f->nl - 1 ? 1 : 0;
             la.W1T = f->W1T16; la.b1 = f->par + f->ob1; la.W2 = f->W2_16; la.W2P = f->W2P; la.b2 = f->par + f->ob2;
-            la.x = x; la.pred = pred_out; la.P = P;
-            const int mode = l < f->nl - 1 ? 0 : (pred_out ? 2 : 1);
+            la.x = x; la.pred = pred_out ? pred_out : f->predb; la.P = P;
+            const int mode = l < f->nl - 1 ? 0 : (pred_out ? 2 : (projf ? 3 : 1));
             SGM_HIP_TRY(launch_fno_layer(la, mode, s));
             continue;
         }
@@ -658,7 +664,7 @@ static sgm_status fno_forward(sgm_fno f, const float* x, int B, hipStream_t s, f
                            (const float*)(f->par + f->obp[l]), an, f->zsv + l * act, pix * C, C, l < f->nl - 1 ? 1 : 0);
         SGM_HIP_TRY(hipGetLastError());
     }
-    if (fused && pred_out) return SGM_OK;  // projection done in the last layer kernel
+    if (fused && (pred_out || projf)) return SGM_OK;  // projection done in the last layer kernel
     // projection
     const bf16* a = f->acts + f->nl * act;
     SGM_HIP_TRY(gemm(G(1, (int)pix, P, C, a, 0, C, 1, 0, f->W1_16, 0, P, 1, 0, f->s32, 0, P, 1), s));
@@ -708,12 +714,24 @@ static hipError_t colsum_f32(const float* g, float* db, long P, int C, hipStream
 }
 
 // Backward pass; dpred (fp32 [B H W 2]) is in f->outb.  Gradients -> f->grad.
+static sgm_status fno_backward_layers(sgm_fno f, const float* x, int B, hipStream_t s);
+
 static sgm_status fno_backward(sgm_fno f, const float* x, int B, hipStream_t s) {
     const int C = f->C, P = f->P, H = f->H, W = f->W, K = f->K, NM = f->NM;
     const long HW = (long)H * W, pix = (long)B * HW, act = (long)f->Bmax * HW * C;
     hipLaunchKernelGGL(k_fill, dim3(nblk(f->npar)), dim3(256), 0, s, f->grad, 0.f, f->npar);
     const float* dpred = f->outb;
     const int sk = splits_for(pix);
+    if (proj_fused(f)) {
+        FnoProjBwdArgs pa{};
+        pa.a = f->acts + f->nl * act; pa.dpred = dpred;
+        pa.W1T = f->W1T16; pa.W1 = f->W1_16; pa.b1 = f->par + f->ob1; pa.W2 = f->W2_16;
+        pa.da = f->da32; pa.gW1 = f->grad + f->oW1; pa.gb1 = f->grad + f->ob1; pa.gW2 = f->grad + f->oW2;
+        pa.pix = pix; pa.P = P;
+        SGM_HIP_TRY(launch_fno_proj_bwd(pa, s));
+        SGM_HIP_TRY(colsum_f32(dpred, f->grad + f->ob2, pix, 2, s));
+        return fno_backward_layers(f, x, B, s);
+    }
     // W2, b2
     SGM_HIP_TRY(gemm(G(1, P, 2, (int)pix, f->hbuf, 0, 1, P, 0, dpred, 0, 2, 1, 1, f->grad + f->oW2, 0, 2, 1, 0.f, sk), s));
     SGM_HIP_TRY(colsum_f32(dpred, f->grad + f->ob2, pix, 2, s));
@@ -732,6 +750,15 @@ static sgm_status fno_backward(sgm_fno f, const float* x, int B, hipStream_t s) 
     SGM_HIP_TRY(colsum_bf16(f->d16, f->grad + f->ob1, pix, P, s));
     // da = dhp W1^T
     SGM_HIP_TRY(gemm(G(1, (int)pix, C, P, f->d16, 0, P, 1, 0, f->W1_16, 0, 1, P, 0, f->da32, 0, C, 1), s));
+    return fno_backward_layers(f, x, B, s);
+}
+
+// Backward through the layers and the lift, from da (fp32, last layer's output
+// gradient) in f->da32.
+static sgm_status fno_backward_layers(sgm_fno f, const float* x, int B, hipStream_t s) {
+    const int C = f->C, H = f->H, W = f->W, K = f->K, NM = f->NM;
+    const long HW = (long)H * W, pix = (long)B * HW, act = (long)f->Bmax * HW * C;
+    const int sk = splits_for(pix);
     for (int l = f->nl - 1; l >= 0; --l) {
         const bf16* aprev = f->acts + l * act;
         // dz = da gelu'(z)

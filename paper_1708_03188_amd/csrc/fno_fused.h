@@ -44,12 +44,12 @@ struct FnoLayerArgs {
     const __bf16* Fx;     // [32][W] forward x-DFT
     const __bf16* Wp;     // [32][32] pointwise weights
     const float* bp;      // [32]
-    __bf16* a_out;        // [rows][W][32] (modes 0, 1)
-    __bf16* zsave;        // pre-activation [rows][W][32] or null (modes 0, 1)
+    __bf16* a_out;        // [rows][W][32] (modes 0, 1, 3)
+    __bf16* zsave;        // pre-activation [rows][W][32] or null (modes 0, 1, 3)
     long rows;
     int W;
     int act;              // 1: GELU
-    // projection (mode 2)
+    // projection (modes 2, 3)
     const __bf16* W1T;    // [P][32]
     const float* b1;      // [P]
     const __bf16* W2;     // [P][2]
@@ -60,12 +60,36 @@ struct FnoLayerArgs {
     int P;
 };
 
+// Backward of the projection pred = x + gelu(a W1 + b1) W2 + b2 over tiles of
+// 32 pixels, with the hidden pre-activation recomputed from a (it is not kept):
+// da = dz W1^T (overwritten) and the parameter gradients gW1 (+= a^T dz, [32][P]),
+// gb1 (+= sum dz), gW2 (+= h^T dpred, [P][2]), with dz = (dpred W2^T) gelu'(z)
+// rounded to bf16 and dpred rounded to bf16 as the products' operands.
+struct FnoProjBwdArgs {
+    const __bf16* a;      // last layer output [pix][32]
+    const float* dpred;   // [pix][2]
+    const __bf16* W1T;    // [P][32]
+    const __bf16* W1;     // [32][P]
+    const float* b1;      // [P]
+    const __bf16* W2;     // [P][2]
+    float* da;            // [pix][32]
+    float* gW1;           // [32][P]
+    float* gb1;           // [P]
+    float* gW2;           // [P][2]
+    long pix;             // multiple of 32
+    int P;                // 32, 64 or 128
+};
+
 bool fno_fused_ok(int C, int K, int W, int P);
+// The fused projection backward handles width 32 with P in {32, 64, 128}.
+bool fno_proj_bwd_ok(int C, int P);
+hipError_t launch_fno_proj_bwd(const FnoProjBwdArgs& a, hipStream_t s);
 // W2 [P][2] (bf16) -> the A operands of the projection's second MFMA (P % 32 == 0).
 hipError_t launch_fno_w2_operands(const __bf16* W2, __bf16* W2P, int P, hipStream_t s);
 hipError_t launch_fno_lift_dft(const float* x, const float* Wl, const float* bl, const __bf16* Fx, __bf16* a0,
                                __bf16* T, long rows, int W, hipStream_t s);
-// mode 0: a_out + next T; 1: a_out (last layer); 2: projection to pred (last layer)
+// mode 0: a_out + next T; 1: a_out (last layer); 2: projection to pred (last
+// layer); 3: a_out, z and the projection to pred (last layer, training)
 hipError_t launch_fno_layer(const FnoLayerArgs& a, int mode, hipStream_t s);
 hipError_t launch_transpose_bf16(const float* in, __bf16* out, int R, int Cc, hipStream_t s);
 

@@ -17,6 +17,8 @@
 // eight K entries, and Fx is read in the same permuted order.
 #include "fno_fused.h"
 
+#include <algorithm>
+
 namespace sgm {
 
 typedef __bf16 bf16;
@@ -193,7 +195,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer(FnoLayerArgs p) {
                 tacc = mfma(aop, yb[q], tacc);
             }
         }
-        if constexpr (MODE == 2) {
+        if constexpr (MODE >= 2) {
             // a' tile [pixel][channel] through LDS, then h^T = W1T a'^T per 32 hidden units
 #pragma unroll
             for (int e = 0; e < 16; ++e) tile[wv][8 * (e >> 2) + 4 * g + (e & 3)][c] = yb[e >> 3][e & 7];
@@ -280,11 +282,157 @@ hipError_t launch_fno_lift_dft(const float* x, const float* Wl, const float* bl,
 }
 
 hipError_t launch_fno_layer(const FnoLayerArgs& a, int mode, hipStream_t s) {
-    if (mode == 2 && (reinterpret_cast<uintptr_t>(a.b1) & 15) != 0) return hipErrorInvalidValue;
+    if (mode >= 2 && (reinterpret_cast<uintptr_t>(a.b1) & 15) != 0) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((a.rows + WAVES - 1) / WAVES)), block(64 * WAVES);
     if (mode == 0) hipLaunchKernelGGL(k_fno_layer<0>, grid, block, 0, s, a);
     else if (mode == 1) hipLaunchKernelGGL(k_fno_layer<1>, grid, block, 0, s, a);
-    else hipLaunchKernelGGL(k_fno_layer<2>, grid, block, 0, s, a);
+    else if (mode == 2) hipLaunchKernelGGL(k_fno_layer<2>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(k_fno_layer<3>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+// Projection backward, one wave per tile of 32 pixels (persistent work-groups,
+// uniform trip count so the barriers are reached by every wave).  Per hidden
+// block of 32 units T:
+//   z  = a W1 + b1      rows = pixels (A = a), cols = hidden units (B = W1T rows)
+//   dz = (dpred W2^T) gelu'(z), h = gelu(z)   per accumulator entry
+//   gW1^T += dz^T a     A = dz straight from the accumulators (K = the lane's
+//                       16 pixels in accumulator order), B = a^T from LDS in
+//                       the same pixel order
+//   da  += dz W1^T      A = dz rows through LDS, B = W1 rows
+// gW2 and gb1 are per-lane sums over the lane's pixels of one hidden unit.
+template <int NT>
+__global__ void __launch_bounds__(64 * WAVES) k_fno_proj_bwd(FnoProjBwdArgs p) {
+    constexpr int LD = FC + 8;
+    __shared__ bf16 sm[WAVES][1 + NT][32][LD];  // [0]: a tile [pixel][channel]; [1 + T]: dz [pixel][unit]
+    const int wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, c = lane & 31, g = lane >> 5;
+    const int P = p.P;
+    const long ntiles = p.pix / 32, nbt = (ntiles + WAVES - 1) / WAVES;
+    floatx16 gw1[NT];
+    float gw2a[NT], gw2b[NT], gb[NT];
+#pragma unroll
+    for (int T = 0; T < NT; ++T) { gw1[T] = zero16(); gw2a[T] = gw2b[T] = gb[T] = 0.f; }
+    float w2a[NT], w2b[NT], bb[NT];
+#pragma unroll
+    for (int T = 0; T < NT; ++T) {
+        w2a[T] = (float)p.W2[2 * (32 * T + c)];
+        w2b[T] = (float)p.W2[2 * (32 * T + c) + 1];
+        bb[T] = p.b1[32 * T + c];
+    }
+    for (long bt = blockIdx.x; bt < nbt; bt += gridDim.x) {
+        const long tile = bt * WAVES + wv;
+        const bool live = tile < ntiles;
+        const long p0 = live ? tile * 32 : 0;
+        const bf16* ar = p.a + p0 * FC;
+        bf16x8 aop[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) aop[s] = ld8(ar + (long)c * FC + 16 * s + 8 * g);
+        // dpred of the lane's 16 pixels (entry e <-> pixel 8 (e / 4) + 4 g + e % 4), zero on a dead tile
+        float d0[16], d1[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const float2 d = live ? reinterpret_cast<const float2*>(p.dpred)[p0 + 8 * (e >> 2) + 4 * g + (e & 3)]
+                                  : make_float2(0.f, 0.f);
+            d0[e] = (float)(bf16)d.x;
+            d1[e] = (float)(bf16)d.y;
+        }
+        __syncthreads();  // the previous tile's LDS reads are done
+#pragma unroll
+        for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(&sm[wv][0][c][16 * s + 8 * g]) = aop[s];
+        __syncthreads();
+        // a^T in accumulator pixel order: K entry 8 g + v of step q <-> pixel 16 q + 8 (v / 4) + 4 g + v % 4
+        bf16x8 at[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int v = 0; v < 8; ++v) at[q][v] = sm[wv][0][16 * q + 8 * (v >> 2) + 4 * g + (v & 3)][c];
+#pragma unroll
+        for (int T = 0; T < NT; ++T) {
+            floatx16 h;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) h[e] = bb[T];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) h = mfma(aop[s], ld8(p.W1T + (long)(32 * T + c) * FC + 16 * s + 8 * g), h);
+            bf16x8 dz[2];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const float z = h[e];
+                const float hv = (float)(bf16)gelu(z);
+                const bf16 dzv = (bf16)((d0[e] * w2a[T] + d1[e] * w2b[T]) * fno_gelu_d(z));
+                dz[e >> 3][e & 7] = dzv;
+                gw2a[T] += hv * d0[e];
+                gw2b[T] += hv * d1[e];
+                gb[T] += (float)dzv;
+                sm[wv][1 + T][8 * (e >> 2) + 4 * g + (e & 3)][c] = dzv;
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q) gw1[T] = mfma(dz[q], at[q], gw1[T]);
+        }
+        __syncthreads();
+        floatx16 da = zero16();
+#pragma unroll
+        for (int T = 0; T < NT; ++T)
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+                da = mfma(*reinterpret_cast<const bf16x8*>(&sm[wv][1 + T][c][16 * s + 8 * g]),
+                          ld8(p.W1 + (long)c * P + 32 * T + 16 * s + 8 * g), da);
+        if (live) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) p.da[(p0 + 8 * (e >> 2) + 4 * g + (e & 3)) * FC + c] = da[e];
+        }
+    }
+    // block reduction of the parameter gradients through LDS, then one atomic add per value
+    __syncthreads();
+    float* red = reinterpret_cast<float*>(&sm[0][0][0][0]);  // >= WAVES * 64 * 16 floats
+    static_assert(sizeof(sm) >= sizeof(float) * WAVES * 64 * 16, "reduction buffer");
+#pragma unroll
+    for (int T = 0; T < NT; ++T) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) red[(wv * 64 + lane) * 16 + e] = gw1[T][e];
+        __syncthreads();
+        for (int i = threadIdx.x; i < 64 * 16; i += 64 * WAVES) {
+            float sum = 0.f;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) sum += red[w * 64 * 16 + i];
+            const int ln = i >> 4, e = i & 15;
+            // entry e of lane (channel ln % 32, group ln / 32): unit 32 T + 8 (e / 4) + 4 g + e % 4
+            const int unit = 32 * T + 8 * (e >> 2) + 4 * (ln >> 5) + (e & 3);
+            atomicAdd(&p.gW1[(long)(ln & 31) * P + unit], sum);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int T = 0; T < NT; ++T) {
+        red[(wv * 64 + lane) * 3 * NT + 3 * T] = gw2a[T];
+        red[(wv * 64 + lane) * 3 * NT + 3 * T + 1] = gw2b[T];
+        red[(wv * 64 + lane) * 3 * NT + 3 * T + 2] = gb[T];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 32 * 3 * NT; i += 64 * WAVES) {
+        // unit 32 T + cc: lanes cc and cc + 32 of every wave
+        const int cc = i / (3 * NT), k = i % (3 * NT), T = k / 3, which = k % 3;
+        float sum = 0.f;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) sum += red[(w * 64 + cc) * 3 * NT + k] + red[(w * 64 + cc + 32) * 3 * NT + k];
+        const int unit = 32 * T + cc;
+        if (which == 2) atomicAdd(&p.gb1[unit], sum);
+        else atomicAdd(&p.gW2[2 * unit + which], sum);
+    }
+}
+
+bool fno_proj_bwd_ok(int C, int P) { return C == FC && (P == 32 || P == 64 || P == 128); }
+
+hipError_t launch_fno_proj_bwd(const FnoProjBwdArgs& a, hipStream_t s) {
+    if (!fno_proj_bwd_ok(FC, a.P) || a.pix % 32 != 0 || a.pix <= 0) return hipErrorInvalidValue;
+    if ((reinterpret_cast<uintptr_t>(a.a) & 15) || (reinterpret_cast<uintptr_t>(a.W1T) & 15) ||
+        (reinterpret_cast<uintptr_t>(a.W1) & 15) || (reinterpret_cast<uintptr_t>(a.dpred) & 7))
+        return hipErrorInvalidValue;
+    const long nbt = (a.pix / 32 + WAVES - 1) / WAVES;
+    const dim3 grid((unsigned)std::min(nbt, 512L)), block(64 * WAVES);
+    if (a.P == 32) hipLaunchKernelGGL(k_fno_proj_bwd<1>, grid, block, 0, s, a);
+    else if (a.P == 64) hipLaunchKernelGGL(k_fno_proj_bwd<2>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(k_fno_proj_bwd<4>, grid, block, 0, s, a);
     return hipGetLastError();
 }
 

@@ -31,6 +31,10 @@ CFG_C5 = dict(H=256, W=256, width=32, modes=16, layers=4, hidden=128)
 # general-GEMM network (3 x 64 x 64 pixels), 16 for the fused one (4 x 64 x 64)
 CFG_SK = dict(H=64, W=64, width=8, modes=4, layers=2, hidden=16)
 CFG32_SK = dict(H=64, W=64, width=32, modes=16, layers=2, hidden=64)
+# fused row kernels with the hidden widths of the fused projection backward (32, 128)
+# and one it does not take (96: the projection runs as separate products)
+CFG32_P128 = dict(H=32, W=64, width=32, modes=16, layers=2, hidden=128)
+CFG32_P96 = dict(H=32, W=32, width=32, modes=16, layers=2, hidden=96)
 
 
 def _setup(FNO, B=3, seed=0, cfg=CFG):
@@ -100,8 +104,10 @@ def test_ensemble_arguments(FNO):
         f.infer(xd, out=xd)
 
 
-@pytest.mark.parametrize("cfg,B", [(CFG, 3), (CFG32, 3), (CFG_SK, 3), (CFG32_SK, 4)],
-                         ids=["gemm", "fused", "gemm-splitk", "fused-splitk"])
+@pytest.mark.parametrize("cfg,B", [(CFG, 3), (CFG32, 3), (CFG_SK, 3), (CFG32_SK, 4), (CFG32R, 1), (CFG32_P128, 3),
+                                   (CFG32_P96, 2)],
+                         ids=["gemm", "fused", "gemm-splitk", "fused-splitk", "fused-hidden32-ragged", "fused-hidden128",
+                              "fused-hidden96"])
 def test_gradients_match_oracle(FNO, cfg, B):
     print(f"[case] fno gradients {cfg} B={B}", flush=True)
     f, p, x, t = _setup(FNO, B=B, seed=1, cfg=cfg)
