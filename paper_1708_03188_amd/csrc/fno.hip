@@ -350,6 +350,7 @@ struct sgm_fno_s {
     bf16* W2P = nullptr;  // W2 as MFMA A operands of the fused projection (P % 32 == 0)
     // DFT matrices (bf16)
     bf16 *Fx = nullptr, *Fy = nullptr, *Gy = nullptr, *Gx = nullptr;
+    bf16 *FxT = nullptr, *GxT = nullptr;  // transposes of Fx and Gx (fused layer backward)
     // activations / scratch (sized for Bmax)
     bf16* acts = nullptr;   // (nl + 1) x [B H W C]
     bf16* zsv = nullptr;    // nl x [B H W C]
@@ -442,6 +443,7 @@ extern "C" sgm_status sgm_fno_create(const sgm_fno_desc* desc, uint64_t seed, sg
         {(void**)&f->W1T16, 2 * (size_t)C * P}, {(void**)&f->W2P, 2 * (size_t)(P / 16 + 1) * 512},
         {(void**)&f->Fx, 2 * (size_t)2 * f->K * d.W}, {(void**)&f->Fy, 2 * (size_t)4 * f->K * 2 * d.H},
         {(void**)&f->Gy, 2 * (size_t)2 * d.H * 4 * f->K}, {(void**)&f->Gx, 2 * (size_t)d.W * 2 * f->K},
+        {(void**)&f->FxT, 2 * (size_t)2 * f->K * d.W}, {(void**)&f->GxT, 2 * (size_t)d.W * 2 * f->K},
         {(void**)&f->acts, 2 * (size_t)(nl + 1) * act}, {(void**)&f->zsv, 2 * (size_t)nl * act},
         {(void**)&f->hbuf, 2 * (size_t)B * HW * P}, {(void**)&f->hpz, 2 * (size_t)B * HW * P},
         {(void**)&f->s32, 4 * (size_t)wide}, {(void**)&f->da32, 4 * (size_t)act}, {(void**)&f->d16, 2 * (size_t)wide},
@@ -497,6 +499,16 @@ extern "C" sgm_status sgm_fno_create(const sgm_fno_desc* desc, uint64_t seed, sg
     hipMemcpy(f->Fy, Fy.data(), Fy.size() * 2, hipMemcpyHostToDevice);
     hipMemcpy(f->Gy, Gy.data(), Gy.size() * 2, hipMemcpyHostToDevice);
     hipMemcpy(f->Gx, Gx.data(), Gx.size() * 2, hipMemcpyHostToDevice);
+    {
+        std::vector<uint16_t> FxT(Fx.size()), GxT(Gx.size());
+        for (int k = 0; k < 2 * K; ++k)
+            for (int x = 0; x < W; ++x) {
+                FxT[(long)x * 2 * K + k] = Fx[(long)k * W + x];
+                GxT[(long)k * W + x] = Gx[(long)x * 2 * K + k];
+            }
+        hipMemcpy(f->FxT, FxT.data(), FxT.size() * 2, hipMemcpyHostToDevice);
+        hipMemcpy(f->GxT, GxT.data(), GxT.size() * 2, hipMemcpyHostToDevice);
+    }
     // seeded initial parameters (normal / uniform scales as in common FNO practice)
     std::vector<float> hp(f->npar, 0.f);
     std::mt19937_64 rng(seed);
@@ -716,6 +728,34 @@ static hipError_t colsum_f32(const float* g, float* db, long P, int C, hipStream
 // Backward pass; dpred (fp32 [B H W 2]) is in f->outb.  Gradients -> f->grad.
 static sgm_status fno_backward_layers(sgm_fno f, const float* x, int B, hipStream_t s);
 
+// Adjoint of the y-DFT, the per-mode mixing and the inverse y-DFT of layer l:
+// gU (T, fp32 rows) -> gT (T), with the mixing weights' gradient folded into
+// the grad buffer.
+static sgm_status spectral_adjoint(sgm_fno f, int l, int B, hipStream_t s) {
+    const int C = f->C, H = f->H, K = f->K, NM = f->NM;
+    // gYt[b] (4K x K C) = Gy_real^T (4K x 2H) gU[b] (2H x K C)
+    SGM_HIP_TRY(gemm(G(B, 4 * K, K * C, 2 * H, f->Gy, 0, 1, 4L * K, 0, f->T, 2L * H * K * C, (long)K * C, 1, 1, f->Yt,
+                       4L * K * K * C, (long)K * C, 1), s));
+    hipLaunchKernelGGL(k_perm_modes<float>, dim3(nblk(perm_threads<float>(B, K, C))), dim3(256), 0, s,
+                       (const float*)f->Yt, f->Ym, B, 2 * K, K, C, 0);
+    // dRreal[m] (2C x 2C) = Xm[m]^T (2C x B) gYm[m] (B x 2C)   (Xm saved in bf16 by the forward pass)
+    const bf16* Xm = reinterpret_cast<const bf16*>(f->Xm) + (long)l * NM * f->Bmax * 2 * C;
+    SGM_HIP_TRY(gemm(G(NM, 2 * C, 2 * C, B, Xm, (long)B * 2 * C, 1, 2 * C, 0, f->Ym, (long)B * 2 * C, 2 * C, 1, 1, f->Rg,
+                       4L * C * C, 2 * C, 1), s));
+    hipLaunchKernelGGL(k_fold_rgrad, dim3(nblk((long)NM * C * C)), dim3(256), 0, s, (const float*)f->Rg,
+                       f->grad + f->oRr[l], f->grad + f->oRi[l], NM, C);
+    // gXm[m] (B x 2C) = gYm[m] (B x 2C) Rreal[m]^T   (into the X buffer, mode-major)
+    SGM_HIP_TRY(gemm(G(NM, B, 2 * C, 2 * C, f->Ym, (long)B * 2 * C, 2 * C, 1, 1, f->Rreal + (long)l * NM * 4 * C * C,
+                       4L * C * C, 1, 2 * C, 0, f->X, (long)B * 2 * C, 2 * C, 1), s));
+    hipLaunchKernelGGL(k_perm_modes<float>, dim3(nblk(perm_threads<float>(B, K, C))), dim3(256), 0, s,
+                       (const float*)f->X, f->Yt, B, 2 * K, K, C, 1);
+    // gT[b] (2H x K C) = Fy_real^T (2H x 4K) gX[b] (4K x K C)
+    SGM_HIP_TRY(gemm(G(B, 2 * H, K * C, 4 * K, f->Fy, 0, 1, 2L * H, 0, f->Yt, 4L * K * K * C, (long)K * C, 1, 1, f->T,
+                       2L * H * K * C, (long)K * C, 1), s));
+    return SGM_OK;
+}
+
+
 static sgm_status fno_backward(sgm_fno f, const float* x, int B, hipStream_t s) {
     const int C = f->C, P = f->P, H = f->H, W = f->W, K = f->K, NM = f->NM;
     const long HW = (long)H * W, pix = (long)B * HW, act = (long)f->Bmax * HW * C;
@@ -759,8 +799,21 @@ static sgm_status fno_backward_layers(sgm_fno f, const float* x, int B, hipStrea
     const int C = f->C, H = f->H, W = f->W, K = f->K, NM = f->NM;
     const long HW = (long)H * W, pix = (long)B * HW, act = (long)f->Bmax * HW * C;
     const int sk = splits_for(pix);
+    const bool fused = fno_fused_ok(C, K, W, f->P);
     for (int l = f->nl - 1; l >= 0; --l) {
         const bf16* aprev = f->acts + l * act;
+        if (fused) {
+            // dz, gWp, gbp, da = dz Wp^T and gU = Gx^T dz in one pass over the rows; the
+            // layer above's Fx^T gT is added to da on the way in
+            FnoLayerBwdArgs lb{};
+            lb.da = f->da32; lb.T = f->T; lb.z = f->zsv + l * act; lb.aprev = aprev;
+            lb.Wp = f->Wp16 + (long)l * C * C; lb.FxT = f->FxT; lb.GxT = f->GxT;
+            lb.gWp = f->grad + f->oWp[l]; lb.gbp = f->grad + f->obp[l];
+            lb.rows = (long)B * H; lb.W = W; lb.act = l < f->nl - 1 ? 1 : 0; lb.addT = l < f->nl - 1 ? 1 : 0;
+            SGM_HIP_TRY(launch_fno_layer_bwd(lb, s));
+            if (const sgm_status st = spectral_adjoint(f, l, B, s)) return st;
+            continue;
+        }
         // dz = da gelu'(z)
         if ((pix * C) % 4 == 0 && act % 4 == 0)  // whole 4-element groups, 8-byte aligned z rows
             hipLaunchKernelGGL(k_act_bwd4, dim3(nblk(pix * C / 4)), dim3(256), 0, s, (const float*)f->da32,
@@ -776,29 +829,15 @@ static sgm_status fno_backward_layers(sgm_fno f, const float* x, int B, hipStrea
         SGM_HIP_TRY(gemm(G(1, (int)pix, C, C, dz, 0, C, 1, 0, f->Wp16 + (long)l * C * C, 0, 1, C, 0, f->da32, 0, C, 1), s));
         // spectral adjoint: gU[(b,y)] (2K x C) = Gx^T (2K x W) dz[(b,y)] (W x C)
         SGM_HIP_TRY(gemm(G(B * H, 2 * K, C, W, f->Gx, 0, 1, 2L * K, 0, dz, (long)W * C, C, 1, 0, f->T, 2L * K * C, C, 1), s));
-        // gYt[b] (4K x K C) = Gy_real^T (4K x 2H) gU[b] (2H x K C)
-        SGM_HIP_TRY(gemm(G(B, 4 * K, K * C, 2 * H, f->Gy, 0, 1, 4L * K, 0, f->T, 2L * H * K * C, (long)K * C, 1, 1, f->Yt,
-                           4L * K * K * C, (long)K * C, 1), s));
-        hipLaunchKernelGGL(k_perm_modes<float>, dim3(nblk(perm_threads<float>(B, K, C))), dim3(256), 0, s,
-                           (const float*)f->Yt, f->Ym, B, 2 * K, K, C, 0);
-        // dRreal[m] (2C x 2C) = Xm[m]^T (2C x B) gYm[m] (B x 2C)   (Xm saved in bf16 by the forward pass)
-        const bf16* Xm = reinterpret_cast<const bf16*>(f->Xm) + (long)l * NM * f->Bmax * 2 * C;
-        SGM_HIP_TRY(gemm(G(NM, 2 * C, 2 * C, B, Xm, (long)B * 2 * C, 1, 2 * C, 0, f->Ym, (long)B * 2 * C, 2 * C, 1, 1, f->Rg,
-                           4L * C * C, 2 * C, 1), s));
-        hipLaunchKernelGGL(k_fold_rgrad, dim3(nblk((long)NM * C * C)), dim3(256), 0, s, (const float*)f->Rg,
-                           f->grad + f->oRr[l], f->grad + f->oRi[l], NM, C);
-        // gXm[m] (B x 2C) = gYm[m] (B x 2C) Rreal[m]^T   (into the X buffer, mode-major)
-        SGM_HIP_TRY(gemm(G(NM, B, 2 * C, 2 * C, f->Ym, (long)B * 2 * C, 2 * C, 1, 1, f->Rreal + (long)l * NM * 4 * C * C,
-                           4L * C * C, 1, 2 * C, 0, f->X, (long)B * 2 * C, 2 * C, 1), s));
-        hipLaunchKernelGGL(k_perm_modes<float>, dim3(nblk(perm_threads<float>(B, K, C))), dim3(256), 0, s,
-                           (const float*)f->X, f->Yt, B, 2 * K, K, C, 1);
-        // gT[b] (2H x K C) = Fy_real^T (2H x 4K) gX[b] (4K x K C)
-        SGM_HIP_TRY(gemm(G(B, 2 * H, K * C, 4 * K, f->Fy, 0, 1, 2L * H, 0, f->Yt, 4L * K * K * C, (long)K * C, 1, 1, f->T,
-                           2L * H * K * C, (long)K * C, 1), s));
+        if (const sgm_status st = spectral_adjoint(f, l, B, s)) return st;
         // da += Fx^T (W x 2K) gT[(b,y)] (2K x C)
         SGM_HIP_TRY(gemm(G(B * H, W, C, 2 * K, f->Fx, 0, 1, W, 0, f->T, 2L * K * C, C, 1, 1, f->da32, (long)W * C, C, 1,
                            1.f), s));
     }
+    // the fused layer kernels leave layer 0's Fx^T gT to add
+    if (fused)
+        SGM_HIP_TRY(gemm(G(B * H, W, C, 2 * K, f->Fx, 0, 1, W, 0, f->T, 2L * K * C, C, 1, 1, f->da32, (long)W * C, C, 1,
+                           1.f), s));
     // lift: Wl = x^T da (2 x C), bl = sum da
     SGM_HIP_TRY(gemm(G(1, 2, C, (int)pix, x, 0, 1, 2, 1, f->da32, 0, C, 1, 1, f->grad + f->oWl, 0, C, 1, 0.f, sk), s));
     SGM_HIP_TRY(colsum_f32(f->da32, f->grad + f->obl, pix, C, s));

@@ -80,6 +80,30 @@ struct FnoProjBwdArgs {
     int P;                // 32, 64 or 128
 };
 
+// Backward of one spectral layer a' = act(Gx U + a Wp + bp), one wave per
+// activation row (b, y), for the fused shapes.  In: da = gradient of the layer
+// output (fp32), completed on the fly by Fx^T gT of the layer above when addT
+// (gT: T's rows, fp32).  Out: da = dz Wp^T (the pointwise part of the input
+// gradient, overwritten in place), T = Gx^T dz per row (the adjoint of the
+// inverse x-DFT, overwriting gT row by row), gWp += a^T dz, gbp += sum dz,
+// with dz = da gelu'(z) (or da when !act) rounded to bf16.
+struct FnoLayerBwdArgs {
+    float* da;            // [rows][W][32]
+    float* T;             // [rows][32][32]
+    const __bf16* z;      // [rows][W][32] pre-activation (read when act)
+    const __bf16* aprev;  // [rows][W][32] layer input
+    const __bf16* Wp;     // [32][32]
+    const __bf16* FxT;    // [W][32] forward x-DFT, transposed
+    const __bf16* GxT;    // [32][W] inverse x-DFT, transposed
+    float* gWp;           // [32][32]
+    float* gbp;           // [32]
+    long rows;
+    int W;
+    int act;
+    int addT;
+};
+hipError_t launch_fno_layer_bwd(const FnoLayerBwdArgs& a, hipStream_t s);
+
 bool fno_fused_ok(int C, int K, int W, int P);
 // The fused projection backward handles width 32 with P in {32, 64, 128}.
 bool fno_proj_bwd_ok(int C, int P);

@@ -421,6 +421,118 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_proj_bwd(FnoProjBwdArgs p) {
     }
 }
 
+// Layer backward, one wave per row.  Accumulator ("pixel") layout of a 32-pixel
+// tile: lane (channel c, group g) entry e holds pixel 8 (e / 4) + 4 g + e % 4.
+//   da  = da_in + Fx^T gT        A = FxT rows (pixels), B = gT (bf16)
+//   dz  = da gelu'(z)            per entry
+//   gWp += a^T dz                A = a in the accumulator pixel order (K = the
+//                                lane group's pixels), B = dz from the accumulators
+//   gU  += Gx^T dz               A = GxT in the same pixel order, B = dz
+//   da' = dz Wp^T                A = dz rows through LDS, B = Wp rows
+__global__ void __launch_bounds__(64 * WAVES) k_fno_layer_bwd(FnoLayerBwdArgs p) {
+    __shared__ bf16 sdz[WAVES][32][FC + 8];
+    __shared__ float red[WAVES * 64 * 16];
+    const long row = (long)blockIdx.x * WAVES + (threadIdx.x >> 6);
+    const bool live = row < p.rows;
+    const int wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, c = lane & 31, g = lane >> 5;
+    const long rr = live ? row : 0;
+    const int W = p.W;
+    bf16x8 tb[2], wb[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        wb[s] = ld8(p.Wp + c * FC + 16 * s + 8 * g);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) tb[s][v] = p.addT ? (bf16)p.T[rr * F2K * FC + (16 * s + 8 * g + v) * FC + c] : (bf16)0.f;
+    }
+    floatx16 gw = zero16(), uacc = zero16();
+    float gb = 0.f;
+    for (int t = 0; t < W / 32; ++t) {
+        const int x0 = 32 * t;
+        const long pb = rr * W + x0;
+        floatx16 acc;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[e] = p.da[(pb + 8 * (e >> 2) + 4 * g + (e & 3)) * FC + c];
+        if (p.addT) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) acc = mfma(ld8(p.FxT + (long)(x0 + c) * F2K + 16 * s + 8 * g), tb[s], acc);
+        }
+        bf16x8 dz[2];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const long pe = pb + 8 * (e >> 2) + 4 * g + (e & 3);
+            float v = acc[e];
+            if (p.act) v *= fno_gelu_d((float)p.z[pe * FC + c]);
+            const bf16 d = (bf16)v;
+            dz[e >> 3][e & 7] = d;
+            gb += (float)d;
+            sdz[wv][8 * (e >> 2) + 4 * g + (e & 3)][c] = d;
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            // K entry 8 g + v <-> pixel 16 q + 8 (v / 4) + 4 g + v % 4 (accumulator entries 8 q + v)
+            bf16x8 ap;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) ap[v] = p.aprev[(pb + 16 * q + 8 * (v >> 2) + 4 * g + (v & 3)) * FC + c];
+            gw = mfma(ap, dz[q], gw);
+            const bf16* gx = p.GxT + (long)c * W + x0 + 16 * q + 4 * g;
+            const bf16x4 lo = *reinterpret_cast<const bf16x4*>(gx);
+            const bf16x4 hi = *reinterpret_cast<const bf16x4*>(gx + 8);
+            bf16x8 gop;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) { gop[v] = lo[v]; gop[4 + v] = hi[v]; }
+            uacc = mfma(gop, dz[q], uacc);
+        }
+        __syncthreads();
+        floatx16 dout = zero16();
+#pragma unroll
+        for (int s = 0; s < 2; ++s) dout = mfma(*reinterpret_cast<const bf16x8*>(&sdz[wv][c][16 * s + 8 * g]), wb[s], dout);
+        if (live) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) p.da[(pb + 8 * (e >> 2) + 4 * g + (e & 3)) * FC + c] = dout[e];
+        }
+        __syncthreads();
+    }
+    if (live) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) p.T[rr * F2K * FC + (8 * r + 4 * g + v) * FC + c] = uacc[4 * r + v];
+    } else {
+        gw = zero16();
+        gb = 0.f;
+    }
+    // block reduction of gWp (entry e of lane (c, g): input channel 8 (e / 4) + 4 g + e % 4,
+    // output channel c) and gbp, then one atomic add per value
+#pragma unroll
+    for (int e = 0; e < 16; ++e) red[(wv * 64 + lane) * 16 + e] = gw[e];
+    __syncthreads();
+    for (int i = threadIdx.x; i < 64 * 16; i += 64 * WAVES) {
+        float sum = 0.f;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) sum += red[w * 64 * 16 + i];
+        const int ln = i >> 4, e = i & 15;
+        atomicAdd(&p.gWp[(8 * (e >> 2) + 4 * (ln >> 5) + (e & 3)) * FC + (ln & 31)], sum);
+    }
+    __syncthreads();
+    red[wv * 64 + lane] = gb;
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        float sum = 0.f;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) sum += red[w * 64 + threadIdx.x] + red[w * 64 + 32 + threadIdx.x];
+        atomicAdd(&p.gbp[threadIdx.x], sum);
+    }
+}
+
+hipError_t launch_fno_layer_bwd(const FnoLayerBwdArgs& a, hipStream_t s) {
+    if (a.W % 32 != 0 || a.rows <= 0 || (reinterpret_cast<uintptr_t>(a.Wp) & 15) ||
+        (reinterpret_cast<uintptr_t>(a.FxT) & 15) || (reinterpret_cast<uintptr_t>(a.GxT) & 7))
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fno_layer_bwd, dim3((unsigned)((a.rows + WAVES - 1) / WAVES)), dim3(64 * WAVES), 0, s, a);
+    return hipGetLastError();
+}
+
 bool fno_proj_bwd_ok(int C, int P) { return C == FC && (P == 32 || P == 64 || P == 128); }
 
 hipError_t launch_fno_proj_bwd(const FnoProjBwdArgs& a, hipStream_t s) {
