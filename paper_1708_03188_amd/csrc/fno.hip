@@ -351,6 +351,7 @@ struct sgm_fno_s {
     // DFT matrices (bf16)
     bf16 *Fx = nullptr, *Fy = nullptr, *Gy = nullptr, *Gx = nullptr;
     bf16 *FxT = nullptr, *GxT = nullptr;  // transposes of Fx and Gx (fused layer backward)
+    float* part = nullptr;  // per-work-group partial parameter gradients of the fused backward kernels
     // activations / scratch (sized for Bmax)
     bf16* acts = nullptr;   // (nl + 1) x [B H W C]
     bf16* zsv = nullptr;    // nl x [B H W C]
@@ -444,6 +445,7 @@ extern "C" sgm_status sgm_fno_create(const sgm_fno_desc* desc, uint64_t seed, sg
         {(void**)&f->Fx, 2 * (size_t)2 * f->K * d.W}, {(void**)&f->Fy, 2 * (size_t)4 * f->K * 2 * d.H},
         {(void**)&f->Gy, 2 * (size_t)2 * d.H * 4 * f->K}, {(void**)&f->Gx, 2 * (size_t)d.W * 2 * f->K},
         {(void**)&f->FxT, 2 * (size_t)2 * f->K * d.W}, {(void**)&f->GxT, 2 * (size_t)d.W * 2 * f->K},
+        {(void**)&f->part, 4 * (size_t)kFnoBwdMaxGroups * std::max((long)C * C + C, (long)(C + 3) * P)},
         {(void**)&f->acts, 2 * (size_t)(nl + 1) * act}, {(void**)&f->zsv, 2 * (size_t)nl * act},
         {(void**)&f->hbuf, 2 * (size_t)B * HW * P}, {(void**)&f->hpz, 2 * (size_t)B * HW * P},
         {(void**)&f->s32, 4 * (size_t)wide}, {(void**)&f->da32, 4 * (size_t)act}, {(void**)&f->d16, 2 * (size_t)wide},
@@ -766,9 +768,11 @@ static sgm_status fno_backward(sgm_fno f, const float* x, int B, hipStream_t s) 
         FnoProjBwdArgs pa{};
         pa.a = f->acts + f->nl * act; pa.dpred = dpred;
         pa.W1T = f->W1T16; pa.W1 = f->W1_16; pa.b1 = f->par + f->ob1; pa.W2 = f->W2_16;
-        pa.da = f->da32; pa.gW1 = f->grad + f->oW1; pa.gb1 = f->grad + f->ob1; pa.gW2 = f->grad + f->oW2;
+        pa.da = f->da32; pa.part = f->part;
         pa.pix = pix; pa.P = P;
         SGM_HIP_TRY(launch_fno_proj_bwd(pa, s));
+        // the partial rows are [gW1 | gb1 | gW2], the parameters' order in the gradient buffer
+        SGM_HIP_TRY(launch_fno_sum_partials(f->part, fno_proj_bwd_groups(pix), (C + 3) * P, f->grad + f->oW1, s));
         SGM_HIP_TRY(colsum_f32(dpred, f->grad + f->ob2, pix, 2, s));
         return fno_backward_layers(f, x, B, s);
     }
@@ -808,9 +812,11 @@ static sgm_status fno_backward_layers(sgm_fno f, const float* x, int B, hipStrea
             FnoLayerBwdArgs lb{};
             lb.da = f->da32; lb.T = f->T; lb.z = f->zsv + l * act; lb.aprev = aprev;
             lb.Wp = f->Wp16 + (long)l * C * C; lb.FxT = f->FxT; lb.GxT = f->GxT;
-            lb.gWp = f->grad + f->oWp[l]; lb.gbp = f->grad + f->obp[l];
+            lb.part = f->part;
             lb.rows = (long)B * H; lb.W = W; lb.act = l < f->nl - 1 ? 1 : 0; lb.addT = l < f->nl - 1 ? 1 : 0;
             SGM_HIP_TRY(launch_fno_layer_bwd(lb, s));
+            // partial rows [gWp | gbp], the parameters' order in the gradient buffer
+            SGM_HIP_TRY(launch_fno_sum_partials(f->part, fno_layer_bwd_groups(lb.rows), C * C + C, f->grad + f->oWp[l], s));
             if (const sgm_status st = spectral_adjoint(f, l, B, s)) return st;
             continue;
         }

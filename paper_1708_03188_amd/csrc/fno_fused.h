@@ -60,11 +60,18 @@ struct FnoLayerArgs {
     int P;
 };
 
+// Work-groups of the fused backward kernels (persistent grids): each writes one
+// row of partial parameter gradients, summed afterwards by launch_fno_sum_partials
+// (device-scope atomics from every work-group onto the same few cache lines are
+// serialised).
+constexpr int kFnoBwdMaxGroups = 512;
+
 // Backward of the projection pred = x + gelu(a W1 + b1) W2 + b2 over tiles of
 // 32 pixels, with the hidden pre-activation recomputed from a (it is not kept):
-// da = dz W1^T (overwritten) and the parameter gradients gW1 (+= a^T dz, [32][P]),
-// gb1 (+= sum dz), gW2 (+= h^T dpred, [P][2]), with dz = (dpred W2^T) gelu'(z)
-// rounded to bf16 and dpred rounded to bf16 as the products' operands.
+// da = dz W1^T (overwritten) and the parameter gradients gW1 = a^T dz ([32][P]),
+// gb1 = sum dz, gW2 = h^T dpred ([P][2]) as per-work-group partials, with
+// dz = (dpred W2^T) gelu'(z) rounded to bf16 and dpred rounded to bf16 as the
+// products' operands.
 struct FnoProjBwdArgs {
     const __bf16* a;      // last layer output [pix][32]
     const float* dpred;   // [pix][2]
@@ -73,9 +80,9 @@ struct FnoProjBwdArgs {
     const float* b1;      // [P]
     const __bf16* W2;     // [P][2]
     float* da;            // [pix][32]
-    float* gW1;           // [32][P]
-    float* gb1;           // [P]
-    float* gW2;           // [P][2]
+    // per-work-group partial sums, one row of 32 P + 3 P values per work-group:
+    // gW1 [32][P], gb1 [P], gW2 [P][2] (the grid is at most kFnoBwdMaxGroups)
+    float* part;
     long pix;             // multiple of 32
     int P;                // 32, 64 or 128
 };
@@ -85,8 +92,8 @@ struct FnoProjBwdArgs {
 // output (fp32), completed on the fly by Fx^T gT of the layer above when addT
 // (gT: T's rows, fp32).  Out: da = dz Wp^T (the pointwise part of the input
 // gradient, overwritten in place), T = Gx^T dz per row (the adjoint of the
-// inverse x-DFT, overwriting gT row by row), gWp += a^T dz, gbp += sum dz,
-// with dz = da gelu'(z) (or da when !act) rounded to bf16.
+// inverse x-DFT, overwriting gT row by row), gWp = a^T dz and gbp = sum dz as
+// per-work-group partials, with dz = da gelu'(z) (or da when !act) rounded to bf16.
 struct FnoLayerBwdArgs {
     float* da;            // [rows][W][32]
     float* T;             // [rows][32][32]
@@ -95,14 +102,18 @@ struct FnoLayerBwdArgs {
     const __bf16* Wp;     // [32][32]
     const __bf16* FxT;    // [W][32] forward x-DFT, transposed
     const __bf16* GxT;    // [32][W] inverse x-DFT, transposed
-    float* gWp;           // [32][32]
-    float* gbp;           // [32]
+    float* part;          // per-work-group rows of 32 x 32 + 32 values: gWp [32][32], gbp [32]
     long rows;
     int W;
     int act;
     int addT;
 };
 hipError_t launch_fno_layer_bwd(const FnoLayerBwdArgs& a, hipStream_t s);
+// Work-groups (= partial rows) a backward launch over `rows` rows / `pix` pixels uses.
+int fno_layer_bwd_groups(long rows);
+int fno_proj_bwd_groups(long pix);
+// out[v] += sum over r < nrows of part[r nvals + v]
+hipError_t launch_fno_sum_partials(const float* part, int nrows, int nvals, float* out, hipStream_t s);
 
 bool fno_fused_ok(int C, int K, int W, int P);
 // The fused projection backward handles width 32 with P in {32, 64, 128}.

@@ -382,8 +382,9 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_proj_bwd(FnoProjBwdArgs p) {
             for (int e = 0; e < 16; ++e) p.da[(p0 + 8 * (e >> 2) + 4 * g + (e & 3)) * FC + c] = da[e];
         }
     }
-    // block reduction of the parameter gradients through LDS, then one atomic add per value
+    // block reduction of the parameter gradients through LDS into this work-group's partial row
     __syncthreads();
+    float* prow = p.part + (long)blockIdx.x * 35 * P;
     float* red = reinterpret_cast<float*>(&sm[0][0][0][0]);  // >= WAVES * 64 * 16 floats
     static_assert(sizeof(sm) >= sizeof(float) * WAVES * 64 * 16, "reduction buffer");
 #pragma unroll
@@ -398,7 +399,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_proj_bwd(FnoProjBwdArgs p) {
             const int ln = i >> 4, e = i & 15;
             // entry e of lane (channel ln % 32, group ln / 32): unit 32 T + 8 (e / 4) + 4 g + e % 4
             const int unit = 32 * T + 8 * (e >> 2) + 4 * (ln >> 5) + (e & 3);
-            atomicAdd(&p.gW1[(long)(ln & 31) * P + unit], sum);
+            prow[(long)(ln & 31) * P + unit] = sum;
         }
         __syncthreads();
     }
@@ -416,8 +417,8 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_proj_bwd(FnoProjBwdArgs p) {
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) sum += red[(w * 64 + cc) * 3 * NT + k] + red[(w * 64 + cc + 32) * 3 * NT + k];
         const int unit = 32 * T + cc;
-        if (which == 2) atomicAdd(&p.gb1[unit], sum);
-        else atomicAdd(&p.gW2[2 * unit + which], sum);
+        if (which == 2) prow[32 * P + unit] = sum;
+        else prow[33 * P + 2 * unit + which] = sum;
     }
 }
 
@@ -432,78 +433,87 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_proj_bwd(FnoProjBwdArgs p) {
 __global__ void __launch_bounds__(64 * WAVES) k_fno_layer_bwd(FnoLayerBwdArgs p) {
     __shared__ bf16 sdz[WAVES][32][FC + 8];
     __shared__ float red[WAVES * 64 * 16];
-    const long row = (long)blockIdx.x * WAVES + (threadIdx.x >> 6);
-    const bool live = row < p.rows;
     const int wv = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63, c = lane & 31, g = lane >> 5;
-    const long rr = live ? row : 0;
     const int W = p.W;
-    bf16x8 tb[2], wb[2];
+    bf16x8 wb[2];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        wb[s] = ld8(p.Wp + c * FC + 16 * s + 8 * g);
-#pragma unroll
-        for (int v = 0; v < 8; ++v) tb[s][v] = p.addT ? (bf16)p.T[rr * F2K * FC + (16 * s + 8 * g + v) * FC + c] : (bf16)0.f;
-    }
-    floatx16 gw = zero16(), uacc = zero16();
+    for (int s = 0; s < 2; ++s) wb[s] = ld8(p.Wp + c * FC + 16 * s + 8 * g);
+    floatx16 gw = zero16();
     float gb = 0.f;
-    for (int t = 0; t < W / 32; ++t) {
-        const int x0 = 32 * t;
-        const long pb = rr * W + x0;
-        floatx16 acc;
+    // rows in groups of WAVES, the same number of groups for every wave of the block
+    const long ngr = (p.rows + WAVES - 1) / WAVES;
+    for (long gr = blockIdx.x; gr < ngr; gr += gridDim.x) {
+        const long row = gr * WAVES + wv;
+        const bool live = row < p.rows;
+        const long rr = live ? row : 0;
+        bf16x8 tb[2];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) acc[e] = p.da[(pb + 8 * (e >> 2) + 4 * g + (e & 3)) * FC + c];
-        if (p.addT) {
+        for (int s = 0; s < 2; ++s)
 #pragma unroll
-            for (int s = 0; s < 2; ++s) acc = mfma(ld8(p.FxT + (long)(x0 + c) * F2K + 16 * s + 8 * g), tb[s], acc);
+            for (int v = 0; v < 8; ++v) tb[s][v] = p.addT ? (bf16)p.T[rr * F2K * FC + (16 * s + 8 * g + v) * FC + c] : (bf16)0.f;
+        floatx16 uacc = zero16(), gwr = zero16();
+        float gbr = 0.f;
+        for (int t = 0; t < W / 32; ++t) {
+            const int x0 = 32 * t;
+            const long pb = rr * W + x0;
+            floatx16 acc;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[e] = p.da[(pb + 8 * (e >> 2) + 4 * g + (e & 3)) * FC + c];
+            if (p.addT) {
+#pragma unroll
+                for (int s = 0; s < 2; ++s) acc = mfma(ld8(p.FxT + (long)(x0 + c) * F2K + 16 * s + 8 * g), tb[s], acc);
+            }
+            bf16x8 dz[2];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const long pe = pb + 8 * (e >> 2) + 4 * g + (e & 3);
+                float v = acc[e];
+                if (p.act) v *= fno_gelu_d((float)p.z[pe * FC + c]);
+                const bf16 d = (bf16)v;
+                dz[e >> 3][e & 7] = d;
+                gbr += (float)d;
+                sdz[wv][8 * (e >> 2) + 4 * g + (e & 3)][c] = d;
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                // K entry 8 g + v <-> pixel 16 q + 8 (v / 4) + 4 g + v % 4 (accumulator entries 8 q + v)
+                bf16x8 ap;
+#pragma unroll
+                for (int v = 0; v < 8; ++v) ap[v] = p.aprev[(pb + 16 * q + 8 * (v >> 2) + 4 * g + (v & 3)) * FC + c];
+                gwr = mfma(ap, dz[q], gwr);
+                const bf16* gx = p.GxT + (long)c * W + x0 + 16 * q + 4 * g;
+                const bf16x4 lo = *reinterpret_cast<const bf16x4*>(gx);
+                const bf16x4 hi = *reinterpret_cast<const bf16x4*>(gx + 8);
+                bf16x8 gop;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) { gop[v] = lo[v]; gop[4 + v] = hi[v]; }
+                uacc = mfma(gop, dz[q], uacc);
+            }
+            __syncthreads();
+            floatx16 dout = zero16();
+#pragma unroll
+            for (int s = 0; s < 2; ++s) dout = mfma(*reinterpret_cast<const bf16x8*>(&sdz[wv][c][16 * s + 8 * g]), wb[s], dout);
+            if (live) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) p.da[(pb + 8 * (e >> 2) + 4 * g + (e & 3)) * FC + c] = dout[e];
+            }
+            __syncthreads();
         }
-        bf16x8 dz[2];
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const long pe = pb + 8 * (e >> 2) + 4 * g + (e & 3);
-            float v = acc[e];
-            if (p.act) v *= fno_gelu_d((float)p.z[pe * FC + c]);
-            const bf16 d = (bf16)v;
-            dz[e >> 3][e & 7] = d;
-            gb += (float)d;
-            sdz[wv][8 * (e >> 2) + 4 * g + (e & 3)][c] = d;
-        }
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            // K entry 8 g + v <-> pixel 16 q + 8 (v / 4) + 4 g + v % 4 (accumulator entries 8 q + v)
-            bf16x8 ap;
-#pragma unroll
-            for (int v = 0; v < 8; ++v) ap[v] = p.aprev[(pb + 16 * q + 8 * (v >> 2) + 4 * g + (v & 3)) * FC + c];
-            gw = mfma(ap, dz[q], gw);
-            const bf16* gx = p.GxT + (long)c * W + x0 + 16 * q + 4 * g;
-            const bf16x4 lo = *reinterpret_cast<const bf16x4*>(gx);
-            const bf16x4 hi = *reinterpret_cast<const bf16x4*>(gx + 8);
-            bf16x8 gop;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) { gop[v] = lo[v]; gop[4 + v] = hi[v]; }
-            uacc = mfma(gop, dz[q], uacc);
-        }
-        __syncthreads();
-        floatx16 dout = zero16();
-#pragma unroll
-        for (int s = 0; s < 2; ++s) dout = mfma(*reinterpret_cast<const bf16x8*>(&sdz[wv][c][16 * s + 8 * g]), wb[s], dout);
         if (live) {
 #pragma unroll
-            for (int e = 0; e < 16; ++e) p.da[(pb + 8 * (e >> 2) + 4 * g + (e & 3)) * FC + c] = dout[e];
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) p.T[rr * F2K * FC + (8 * r + 4 * g + v) * FC + c] = uacc[4 * r + v];
+            // only live rows count towards the parameter gradients
+#pragma unroll
+            for (int e = 0; e < 16; ++e) gw[e] += gwr[e];
+            gb += gbr;
         }
-        __syncthreads();
-    }
-    if (live) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) p.T[rr * F2K * FC + (8 * r + 4 * g + v) * FC + c] = uacc[4 * r + v];
-    } else {
-        gw = zero16();
-        gb = 0.f;
     }
     // block reduction of gWp (entry e of lane (c, g): input channel 8 (e / 4) + 4 g + e % 4,
-    // output channel c) and gbp, then one atomic add per value
+    // output channel c) and gbp into this work-group's partial row
+    float* prow = p.part + (long)blockIdx.x * (FC * FC + FC);
 #pragma unroll
     for (int e = 0; e < 16; ++e) red[(wv * 64 + lane) * 16 + e] = gw[e];
     __syncthreads();
@@ -512,7 +522,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer_bwd(FnoLayerBwdArgs p)
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) sum += red[w * 64 * 16 + i];
         const int ln = i >> 4, e = i & 15;
-        atomicAdd(&p.gWp[(8 * (e >> 2) + 4 * (ln >> 5) + (e & 3)) * FC + (ln & 31)], sum);
+        prow[(8 * (e >> 2) + 4 * (ln >> 5) + (e & 3)) * FC + (ln & 31)] = sum;
     }
     __syncthreads();
     red[wv * 64 + lane] = gb;
@@ -521,15 +531,38 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer_bwd(FnoLayerBwdArgs p)
         float sum = 0.f;
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) sum += red[w * 64 + threadIdx.x] + red[w * 64 + 32 + threadIdx.x];
-        atomicAdd(&p.gbp[threadIdx.x], sum);
+        prow[FC * FC + threadIdx.x] = sum;
     }
+}
+
+// out[v] += sum_r part[r nvals + v]: blockIdx.y takes every gridDim.y-th row
+__global__ void k_sum_partials(const float* part, int nrows, int nvals, float* out) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvals) return;
+    float sum = 0.f;
+    for (int r = blockIdx.y; r < nrows; r += gridDim.y) sum += part[(long)r * nvals + v];
+    atomicAdd(&out[v], sum);
+}
+
+int fno_layer_bwd_groups(long rows) {
+    return (int)std::max(1L, std::min((rows + WAVES - 1) / WAVES, (long)kFnoBwdMaxGroups));
+}
+int fno_proj_bwd_groups(long pix) {
+    return (int)std::max(1L, std::min((pix / 32 + WAVES - 1) / WAVES, (long)kFnoBwdMaxGroups));
+}
+
+hipError_t launch_fno_sum_partials(const float* part, int nrows, int nvals, float* out, hipStream_t s) {
+    const int ys = std::min(nrows, 8);
+    hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)((nvals + 255) / 256), (unsigned)ys), dim3(256), 0, s, part, nrows,
+                       nvals, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_fno_layer_bwd(const FnoLayerBwdArgs& a, hipStream_t s) {
     if (a.W % 32 != 0 || a.rows <= 0 || (reinterpret_cast<uintptr_t>(a.Wp) & 15) ||
         (reinterpret_cast<uintptr_t>(a.FxT) & 15) || (reinterpret_cast<uintptr_t>(a.GxT) & 7))
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_fno_layer_bwd, dim3((unsigned)((a.rows + WAVES - 1) / WAVES)), dim3(64 * WAVES), 0, s, a);
+    hipLaunchKernelGGL(k_fno_layer_bwd, dim3((unsigned)fno_layer_bwd_groups(a.rows)), dim3(64 * WAVES), 0, s, a);
     return hipGetLastError();
 }
 
@@ -540,8 +573,7 @@ hipError_t launch_fno_proj_bwd(const FnoProjBwdArgs& a, hipStream_t s) {
     if ((reinterpret_cast<uintptr_t>(a.a) & 15) || (reinterpret_cast<uintptr_t>(a.W1T) & 15) ||
         (reinterpret_cast<uintptr_t>(a.W1) & 15) || (reinterpret_cast<uintptr_t>(a.dpred) & 7))
         return hipErrorInvalidValue;
-    const long nbt = (a.pix / 32 + WAVES - 1) / WAVES;
-    const dim3 grid((unsigned)std::min(nbt, 512L)), block(64 * WAVES);
+    const dim3 grid((unsigned)fno_proj_bwd_groups(a.pix)), block(64 * WAVES);
     if (a.P == 32) hipLaunchKernelGGL(k_fno_proj_bwd<1>, grid, block, 0, s, a);
     else if (a.P == 64) hipLaunchKernelGGL(k_fno_proj_bwd<2>, grid, block, 0, s, a);
     else hipLaunchKernelGGL(k_fno_proj_bwd<4>, grid, block, 0, s, a);
