@@ -4,20 +4,10 @@
 
 namespace sgm {
 
-// erf by Abramowitz & Stegun 7.1.26 (absolute error <= 1.5e-7, far below the
-// bf16 rounding every activation goes through) and the exact-form GELU on it.
-__device__ __forceinline__ float fno_erf(float x) {
-    const float ax = fabsf(x);
-    const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.3275911f, ax, 1.f));
-    float q = __builtin_fmaf(1.061405429f, t, -1.453152027f);
-    q = __builtin_fmaf(q, t, 1.421413741f);
-    q = __builtin_fmaf(q, t, -0.284496736f);
-    q = __builtin_fmaf(q, t, 0.254829592f);
-    const float r = 1.f - q * t * __expf(-ax * ax);
-    return copysignf(r, x);
-}
-// GELU on the same approximation, written through erfc: with x = z / sqrt 2,
-// 1 - erf|x| = q(t) t exp(-x^2) and, for either sign of z,
+// GELU on erf by Abramowitz & Stegun 7.1.26 (absolute error <= 1.5e-7, far
+// below the bf16 rounding every activation goes through), written through erfc:
+// with x = z / sqrt 2, 1 - erf|x| = q(t) t exp(-x^2), t = 1 / (1 + p |x|), and,
+// for either sign of z,
 // z (1 + erf x) / 2 = z / 2 + |z| (1/2 - (1 - erf|x|) / 2).
 // The 1/sqrt 2, the -1/2 and log2 e are folded into the constants (10 plain
 // operations and two transcendental ones).
@@ -32,8 +22,26 @@ __device__ __forceinline__ float fno_gelu(float z) {
     const float e = __builtin_amdgcn_exp2f(z * z * (-0.5f * 1.4426950408889634f));
     return __builtin_fmaf(az, __builtin_fmaf(q * t, e, 0.5f), 0.5f * z);
 }
+// GELU and its derivative from one evaluation of the same approximation: with
+// m = erf(|z| / sqrt 2) / 2 (the fma inside fno_gelu) and e = exp(-z^2 / 2),
+// gelu = z / 2 + |z| m (bit-identical to fno_gelu) and
+// gelu' = Phi(z) + z phi(z) = 1/2 + sign(z) m + z e / sqrt(2 pi).
+__device__ __forceinline__ void fno_gelu_fd(float z, float& f, float& d) {
+    const float az = fabsf(z);
+    const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.3275911f * 0.70710678118654752f, az, 1.f));
+    float q = __builtin_fmaf(-0.5f * 1.061405429f, t, -0.5f * -1.453152027f);
+    q = __builtin_fmaf(q, t, -0.5f * 1.421413741f);
+    q = __builtin_fmaf(q, t, -0.5f * -0.284496736f);
+    q = __builtin_fmaf(q, t, -0.5f * 0.254829592f);
+    const float e = __builtin_amdgcn_exp2f(z * z * (-0.5f * 1.4426950408889634f));
+    const float m = __builtin_fmaf(q * t, e, 0.5f);
+    f = __builtin_fmaf(az, m, 0.5f * z);
+    d = __builtin_fmaf(z * e, 0.39894228040143268f, 0.5f + copysignf(m, z));
+}
 __device__ __forceinline__ float fno_gelu_d(float z) {
-    return 0.5f * (1.f + fno_erf(z * 0.70710678118654752f)) + z * __expf(-0.5f * z * z) * 0.39894228040143268f;
+    float f, d;
+    fno_gelu_fd(z, f, d);
+    return d;
 }
 
 struct FnoLayerArgs {

@@ -357,9 +357,10 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_proj_bwd(FnoProjBwdArgs p) {
             bf16x8 dz[2];
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
-                const float z = h[e];
-                const float hv = (float)(bf16)gelu(z);
-                const bf16 dzv = (bf16)((d0[e] * w2a[T] + d1[e] * w2b[T]) * fno_gelu_d(z));
+                float gf, gd;
+                fno_gelu_fd(h[e], gf, gd);
+                const float hv = (float)(bf16)gf;
+                const bf16 dzv = (bf16)((d0[e] * w2a[T] + d1[e] * w2b[T]) * gd);
                 dz[e >> 3][e & 7] = dzv;
                 gw2a[T] += hv * d0[e];
                 gw2b[T] += hv * d1[e];
@@ -431,76 +432,121 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_proj_bwd(FnoProjBwdArgs p) {
 //   gU  += Gx^T dz               A = GxT in the same pixel order, B = dz
 //   da' = dz Wp^T                A = dz rows through LDS, B = Wp rows
 __global__ void __launch_bounds__(64 * WAVES) k_fno_layer_bwd(FnoLayerBwdArgs p) {
-    __shared__ bf16 sdz[WAVES][32][FC + 8];
-    __shared__ float red[WAVES * 64 * 16];
+    // per-wave tiles: da [pixel][channel] fp32, z, a and dz [pixel][channel] bf16
+    __shared__ float sda[WAVES][32][FC + 4];
+    __shared__ bf16 sz[WAVES][32][FC + 8], sap[WAVES][32][FC + 8], sdz[WAVES][32][FC + 8];
     const int wv = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63, c = lane & 31, g = lane >> 5;
-    const int W = p.W;
+    const int W = p.W, nt = W / 32;
     bf16x8 wb[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) wb[s] = ld8(p.Wp + c * FC + 16 * s + 8 * g);
-    floatx16 gw = zero16();
-    float gb = 0.f;
-    // rows in groups of WAVES, the same number of groups for every wave of the block
+    floatx16 gw = zero16(), gwr = zero16(), uacc = zero16();
+    float gb = 0.f, gbr = 0.f;
+    bf16x8 tb[2];
+    // a tile is 32 consecutive pixels of one row: contiguous 4 KB of da, 2 KB of z and of a.
+    // Lane loads: da float4 j * 64 + lane (pixel / 8, channels 4 (i % 8)..), z and a 16-byte
+    // chunk j * 64 + lane (pixel i / 4, channels 8 (i % 4)..).
+    float4 nda[4];
+    uint4 nz[2], nap[2];
+    auto fetch = [&](long pb) {
+        const float4* d4 = reinterpret_cast<const float4*>(p.da + pb * FC);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) nda[j] = d4[j * 64 + lane];
+        const uint4* z4 = reinterpret_cast<const uint4*>(p.z + pb * FC);
+        const uint4* a4 = reinterpret_cast<const uint4*>(p.aprev + pb * FC);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            nz[j] = p.act ? z4[j * 64 + lane] : make_uint4(0, 0, 0, 0);
+            nap[j] = a4[j * 64 + lane];
+        }
+    };
+    // (row group, tile) steps, the same sequence for every wave of the block; rows past
+    // the end compute on row 0 and discard
     const long ngr = (p.rows + WAVES - 1) / WAVES;
-    for (long gr = blockIdx.x; gr < ngr; gr += gridDim.x) {
+    long gr = blockIdx.x;
+    int t = 0;
+    auto row_of = [&](long grp) {
+        const long r = grp * WAVES + wv;
+        return r < p.rows ? r : 0L;
+    };
+    if (gr < ngr) fetch(row_of(gr) * W);
+    while (gr < ngr) {
         const long row = gr * WAVES + wv;
         const bool live = row < p.rows;
         const long rr = live ? row : 0;
-        bf16x8 tb[2];
+        const int x0 = 32 * t;
+        const long pb = rr * W + x0;
+        if (t == 0) {
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
+            for (int s = 0; s < 2; ++s)
 #pragma unroll
-            for (int v = 0; v < 8; ++v) tb[s][v] = p.addT ? (bf16)p.T[rr * F2K * FC + (16 * s + 8 * g + v) * FC + c] : (bf16)0.f;
-        floatx16 uacc = zero16(), gwr = zero16();
-        float gbr = 0.f;
-        for (int t = 0; t < W / 32; ++t) {
-            const int x0 = 32 * t;
-            const long pb = rr * W + x0;
-            floatx16 acc;
-#pragma unroll
-            for (int e = 0; e < 16; ++e) acc[e] = p.da[(pb + 8 * (e >> 2) + 4 * g + (e & 3)) * FC + c];
-            if (p.addT) {
-#pragma unroll
-                for (int s = 0; s < 2; ++s) acc = mfma(ld8(p.FxT + (long)(x0 + c) * F2K + 16 * s + 8 * g), tb[s], acc);
-            }
-            bf16x8 dz[2];
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const long pe = pb + 8 * (e >> 2) + 4 * g + (e & 3);
-                float v = acc[e];
-                if (p.act) v *= fno_gelu_d((float)p.z[pe * FC + c]);
-                const bf16 d = (bf16)v;
-                dz[e >> 3][e & 7] = d;
-                gbr += (float)d;
-                sdz[wv][8 * (e >> 2) + 4 * g + (e & 3)][c] = d;
-            }
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                // K entry 8 g + v <-> pixel 16 q + 8 (v / 4) + 4 g + v % 4 (accumulator entries 8 q + v)
-                bf16x8 ap;
-#pragma unroll
-                for (int v = 0; v < 8; ++v) ap[v] = p.aprev[(pb + 16 * q + 8 * (v >> 2) + 4 * g + (v & 3)) * FC + c];
-                gwr = mfma(ap, dz[q], gwr);
-                const bf16* gx = p.GxT + (long)c * W + x0 + 16 * q + 4 * g;
-                const bf16x4 lo = *reinterpret_cast<const bf16x4*>(gx);
-                const bf16x4 hi = *reinterpret_cast<const bf16x4*>(gx + 8);
-                bf16x8 gop;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) { gop[v] = lo[v]; gop[4 + v] = hi[v]; }
-                uacc = mfma(gop, dz[q], uacc);
-            }
-            __syncthreads();
-            floatx16 dout = zero16();
-#pragma unroll
-            for (int s = 0; s < 2; ++s) dout = mfma(*reinterpret_cast<const bf16x8*>(&sdz[wv][c][16 * s + 8 * g]), wb[s], dout);
-            if (live) {
-#pragma unroll
-                for (int e = 0; e < 16; ++e) p.da[(pb + 8 * (e >> 2) + 4 * g + (e & 3)) * FC + c] = dout[e];
-            }
-            __syncthreads();
+                for (int v = 0; v < 8; ++v)
+                    tb[s][v] = p.addT ? (bf16)p.T[rr * F2K * FC + (16 * s + 8 * g + v) * FC + c] : (bf16)0.f;
+            uacc = zero16();
+            gwr = zero16();
+            gbr = 0.f;
         }
+        __syncthreads();  // the previous step's LDS reads are done
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int i = j * 64 + lane;
+            *reinterpret_cast<float4*>(&sda[wv][i >> 3][4 * (i & 7)]) = nda[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int i = j * 64 + lane;
+            *reinterpret_cast<uint4*>(&sz[wv][i >> 2][8 * (i & 3)]) = nz[j];
+            *reinterpret_cast<uint4*>(&sap[wv][i >> 2][8 * (i & 3)]) = nap[j];
+        }
+        // next step's tile, in flight during this step
+        int tn = t + 1;
+        long grn = gr;
+        if (tn == nt) { tn = 0; grn += gridDim.x; }
+        if (grn < ngr) fetch(row_of(grn) * W + 32 * tn);
+        __syncthreads();
+        floatx16 acc;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[e] = sda[wv][8 * (e >> 2) + 4 * g + (e & 3)][c];
+        if (p.addT) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) acc = mfma(ld8(p.FxT + (long)(x0 + c) * F2K + 16 * s + 8 * g), tb[s], acc);
+        }
+        bf16x8 dz[2];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int pe = 8 * (e >> 2) + 4 * g + (e & 3);
+            float v = acc[e];
+            if (p.act) v *= fno_gelu_d((float)sz[wv][pe][c]);
+            const bf16 d = (bf16)v;
+            dz[e >> 3][e & 7] = d;
+            gbr += (float)d;
+            sdz[wv][pe][c] = d;
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            // K entry 8 g + v <-> pixel 16 q + 8 (v / 4) + 4 g + v % 4 (accumulator entries 8 q + v)
+            bf16x8 ap;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) ap[v] = sap[wv][16 * q + 8 * (v >> 2) + 4 * g + (v & 3)][c];
+            gwr = mfma(ap, dz[q], gwr);
+            const bf16* gx = p.GxT + (long)c * W + x0 + 16 * q + 4 * g;
+            const bf16x4 lo = *reinterpret_cast<const bf16x4*>(gx);
+            const bf16x4 hi = *reinterpret_cast<const bf16x4*>(gx + 8);
+            bf16x8 gop;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) { gop[v] = lo[v]; gop[4 + v] = hi[v]; }
+            uacc = mfma(gop, dz[q], uacc);
+        }
+        __syncthreads();
+        floatx16 dout = zero16();
+#pragma unroll
+        for (int s = 0; s < 2; ++s) dout = mfma(*reinterpret_cast<const bf16x8*>(&sdz[wv][c][16 * s + 8 * g]), wb[s], dout);
         if (live) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) p.da[(pb + 8 * (e >> 2) + 4 * g + (e & 3)) * FC + c] = dout[e];
+        }
+        if (t == nt - 1 && live) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -510,9 +556,14 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer_bwd(FnoLayerBwdArgs p)
             for (int e = 0; e < 16; ++e) gw[e] += gwr[e];
             gb += gbr;
         }
+        t = tn;
+        gr = grn;
     }
     // block reduction of gWp (entry e of lane (c, g): input channel 8 (e / 4) + 4 g + e % 4,
-    // output channel c) and gbp into this work-group's partial row
+    // output channel c) and gbp into this work-group's partial row, through the da tiles' LDS
+    __syncthreads();
+    float* red = &sda[0][0][0];
+    static_assert(sizeof(sda) >= sizeof(float) * WAVES * 64 * 16, "reduction buffer");
     float* prow = p.part + (long)blockIdx.x * (FC * FC + FC);
 #pragma unroll
     for (int e = 0; e < 16; ++e) red[(wv * 64 + lane) * 16 + e] = gw[e];
@@ -552,7 +603,7 @@ int fno_proj_bwd_groups(long pix) {
 }
 
 hipError_t launch_fno_sum_partials(const float* part, int nrows, int nvals, float* out, hipStream_t s) {
-    const int ys = std::min(nrows, 8);
+    const int ys = std::min(nrows, 64);
     hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)((nvals + 255) / 256), (unsigned)ys), dim3(256), 0, s, part, nrows,
                        nvals, out);
     return hipGetLastError();
@@ -560,6 +611,8 @@ hipError_t launch_fno_sum_partials(const float* part, int nrows, int nvals, floa
 
 hipError_t launch_fno_layer_bwd(const FnoLayerBwdArgs& a, hipStream_t s) {
     if (a.W % 32 != 0 || a.rows <= 0 || (reinterpret_cast<uintptr_t>(a.Wp) & 15) ||
+        (reinterpret_cast<uintptr_t>(a.da) & 15) || (reinterpret_cast<uintptr_t>(a.z) & 15) ||
+        (reinterpret_cast<uintptr_t>(a.aprev) & 15) ||
         (reinterpret_cast<uintptr_t>(a.FxT) & 15) || (reinterpret_cast<uintptr_t>(a.GxT) & 7))
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_fno_layer_bwd, dim3((unsigned)fno_layer_bwd_groups(a.rows)), dim3(64 * WAVES), 0, s, a);
