@@ -840,10 +840,12 @@ static sgm_status fno_backward_layers(sgm_fno f, const float* x, int B, hipStrea
         SGM_HIP_TRY(gemm(G(B * H, W, C, 2 * K, f->Fx, 0, 1, W, 0, f->T, 2L * K * C, C, 1, 1, f->da32, (long)W * C, C, 1,
                            1.f), s));
     }
-    // the fused layer kernels leave layer 0's Fx^T gT to add
-    if (fused)
-        SGM_HIP_TRY(gemm(G(B * H, W, C, 2 * K, f->Fx, 0, 1, W, 0, f->T, 2L * K * C, C, 1, 1, f->da32, (long)W * C, C, 1,
-                           1.f), s));
+    if (fused) {
+        // layer 0's Fx^T gT is added on the fly; partial rows [gWl | gbl] in the parameters' order
+        SGM_HIP_TRY(launch_fno_lift_bwd(f->da32, f->T, x, f->FxT, (long)B * H, W, f->part, s));
+        SGM_HIP_TRY(launch_fno_sum_partials(f->part, fno_layer_bwd_groups((long)B * H), 3 * C, f->grad + f->oWl, s));
+        return SGM_OK;
+    }
     // lift: Wl = x^T da (2 x C), bl = sum da
     SGM_HIP_TRY(gemm(G(1, 2, C, (int)pix, x, 0, 1, 2, 1, f->da32, 0, C, 1, 1, f->grad + f->oWl, 0, C, 1, 0.f, sk), s));
     SGM_HIP_TRY(colsum_f32(f->da32, f->grad + f->obl, pix, C, s));

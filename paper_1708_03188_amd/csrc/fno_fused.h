@@ -117,6 +117,12 @@ struct FnoLayerBwdArgs {
     int addT;
 };
 hipError_t launch_fno_layer_bwd(const FnoLayerBwdArgs& a, hipStream_t s);
+// Backward of the lift a0 = x Wl + bl after the first layer's backward: with
+// da0 = da + Fx^T gT (da: the first layer's pointwise input gradient, gT: T's
+// rows, both fp32), per-work-group partial rows of gWl = x^T da0 ([2][32]) and
+// gbl = sum da0 ([32]); one wave per activation row, da0 is not stored.
+hipError_t launch_fno_lift_bwd(const float* da, const float* T, const float* x, const __bf16* FxT, long rows, int W,
+                               float* part, hipStream_t s);
 // Work-groups (= partial rows) a backward launch over `rows` rows / `pix` pixels uses.
 int fno_layer_bwd_groups(long rows);
 int fno_proj_bwd_groups(long pix);

@@ -586,6 +586,63 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer_bwd(FnoLayerBwdArgs p)
     }
 }
 
+// Lift backward, one wave per row: da0 = da + Fx^T gT in the accumulator pixel
+// layout (lane (channel c, group g), entry e: pixel 8 (e / 4) + 4 g + e % 4), then
+// per-lane sums x_0 da0, x_1 da0 and da0 over the lane's pixels.
+__global__ void __launch_bounds__(64 * WAVES) k_fno_lift_bwd(const float* __restrict__ da, const float* __restrict__ T,
+                                                         const float* __restrict__ x, const bf16* __restrict__ FxT,
+                                                         long rows, int W, float* __restrict__ part) {
+    __shared__ float red[WAVES * 64 * 3];
+    const int wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, c = lane & 31, g = lane >> 5;
+    float s0 = 0.f, s1 = 0.f, sb = 0.f;
+    const long ngr = (rows + WAVES - 1) / WAVES;
+    for (long gr = blockIdx.x; gr < ngr; gr += gridDim.x) {
+        const long row = gr * WAVES + wv;
+        if (row >= rows) continue;  // no barrier inside the loop
+        bf16x8 tb[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int v = 0; v < 8; ++v) tb[s][v] = (bf16)T[row * F2K * FC + (16 * s + 8 * g + v) * FC + c];
+        for (int x0 = 0; x0 < W; x0 += 32) {
+            const long pb = row * W + x0;
+            floatx16 acc;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[e] = da[(pb + 8 * (e >> 2) + 4 * g + (e & 3)) * FC + c];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) acc = mfma(ld8(FxT + (long)(x0 + c) * F2K + 16 * s + 8 * g), tb[s], acc);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const float2 xi = reinterpret_cast<const float2*>(x)[pb + 8 * (e >> 2) + 4 * g + (e & 3)];
+                s0 = __builtin_fmaf(xi.x, acc[e], s0);
+                s1 = __builtin_fmaf(xi.y, acc[e], s1);
+                sb += acc[e];
+            }
+        }
+    }
+    red[(wv * 64 + lane) * 3] = s0;
+    red[(wv * 64 + lane) * 3 + 1] = s1;
+    red[(wv * 64 + lane) * 3 + 2] = sb;
+    __syncthreads();
+    if (threadIdx.x < 3 * FC) {
+        const int k = threadIdx.x / FC, ch = threadIdx.x % FC;  // k: 0, 1 -> gWl row k; 2 -> gbl
+        float sum = 0.f;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) sum += red[(w * 64 + ch) * 3 + k] + red[(w * 64 + 32 + ch) * 3 + k];
+        part[(long)blockIdx.x * 3 * FC + k * FC + ch] = sum;
+    }
+}
+
+hipError_t launch_fno_lift_bwd(const float* da, const float* T, const float* x, const bf16* FxT, long rows, int W,
+                               float* part, hipStream_t s) {
+    if (W % 32 != 0 || rows <= 0 || (reinterpret_cast<uintptr_t>(FxT) & 15) || (reinterpret_cast<uintptr_t>(x) & 7))
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fno_lift_bwd, dim3((unsigned)fno_layer_bwd_groups(rows)), dim3(64 * WAVES), 0, s, da, T, x, FxT,
+                       rows, W, part);
+    return hipGetLastError();
+}
+
 // out[v] += sum_r part[r nvals + v]: blockIdx.y takes every gridDim.y-th row
 __global__ void k_sum_partials(const float* part, int nrows, int nvals, float* out) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
