@@ -434,7 +434,11 @@ extern "C" sgm_status sgm_fno_create(const sgm_fno_desc* desc, uint64_t seed, sg
     f->npar = o;
     // device allocation plan
     const long HW = (long)d.H * d.W, B = d.max_batch;
-    const long act = B * HW * C, wide = B * HW * std::max(C, P);
+    const long act = B * HW * C;
+    // the hidden projection layer and the wide GEMM scratch are only used outside the
+    // fused row kernels (other widths, mode counts or hidden sizes)
+    const bool all_fused = fno_fused_ok(C, f->K, d.W, P) && fno_proj_bwd_ok(C, P);
+    const long wide = all_fused ? 0 : B * HW * std::max(C, P), hid = all_fused ? 0 : B * HW * P;
     struct Slot { void** p; size_t bytes; };
     std::vector<Slot> slots = {
         {(void**)&f->par, 4 * (size_t)f->npar}, {(void**)&f->grad, 4 * (size_t)f->npar},
@@ -447,7 +451,7 @@ extern "C" sgm_status sgm_fno_create(const sgm_fno_desc* desc, uint64_t seed, sg
         {(void**)&f->FxT, 2 * (size_t)2 * f->K * d.W}, {(void**)&f->GxT, 2 * (size_t)d.W * 2 * f->K},
         {(void**)&f->part, 4 * (size_t)kFnoBwdMaxGroups * std::max((long)C * C + C, (long)(C + 3) * P)},
         {(void**)&f->acts, 2 * (size_t)(nl + 1) * act}, {(void**)&f->zsv, 2 * (size_t)nl * act},
-        {(void**)&f->hbuf, 2 * (size_t)B * HW * P}, {(void**)&f->hpz, 2 * (size_t)B * HW * P},
+        {(void**)&f->hbuf, 2 * (size_t)hid}, {(void**)&f->hpz, 2 * (size_t)hid},
         {(void**)&f->s32, 4 * (size_t)wide}, {(void**)&f->da32, 4 * (size_t)act}, {(void**)&f->d16, 2 * (size_t)wide},
         {(void**)&f->T, 4 * (size_t)B * d.H * 2 * f->K * C}, {(void**)&f->X, 4 * (size_t)B * 4 * f->K * f->K * C},
         {(void**)&f->Xm, 4 * (size_t)nl * NM * B * 2 * C}, {(void**)&f->Ym, 4 * (size_t)NM * B * 2 * C},
