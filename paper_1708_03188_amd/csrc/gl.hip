@@ -50,6 +50,9 @@ using GLCfgB = GLCfg<32, 8, 1, 98304>;   // 24 points per thread, wider column t
 using GLCfgC = GLCfg<64, 4, 2, 131072>;  // two exchange buffers
 constexpr int kGlCfgs = 3;
 
+// Padded lengths with register-FFT specialisations (kind k <-> kGlRegLen[k]).
+constexpr int kGlRegLen[7] = {48, 96, 192, 288, 384, 576, 768};
+
 template <int M, class CF>
 struct GGeo {
     static constexpr Sched sd = make_sched(M, CF::NTMAX, CF::MAXR);
@@ -176,8 +179,93 @@ __device__ __forceinline__ double2 stage_update(const GLStage& s, const GLProb& 
 }
 
 // ---------------- register-FFT specialisations -----------------------------
+// Twiddles of a work item's length M from a two-level table in LDS: w^i =
+// A[i / 16] B[i % 16] with A[h] = w^(16 h), B[l] = w^l (M / 16 + 16 entries per
+// compiled length, 259 for all seven, built on the host in extended precision;
+// the product is within a few ulp of w^i).  The register FFT of the transforms
+// reads each stage's twiddles from global memory, a dependent load right after
+// every exchange barrier; the GL passes wait on it at three waves per SIMD, so
+// they run their own copy of the stage loop with this table, which each
+// work-group loads into LDS once per launch.
+constexpr int kGlTwSize[7] = {48 / 16 + 16, 96 / 16 + 16, 192 / 16 + 16, 288 / 16 + 16,
+                              384 / 16 + 16, 576 / 16 + 16, 768 / 16 + 16};
+constexpr int gl_tw_base(int M) {
+    int off = 0;
+    for (int k = 0; k < 7 && kGlRegLen[k] != M; ++k) off += kGlTwSize[k];
+    return off;
+}
+constexpr int kGlTwTotal = gl_tw_base(0);
+static_assert(kGlTwTotal == 259, "sum of M / 16 + 16 over the compiled lengths");
+
+__device__ __forceinline__ void gl_load_tw_all(const double2* twtab, double2* lds) {
+    for (int i = threadIdx.x; i < kGlTwTotal; i += blockDim.x) lds[i] = twtab[i];
+    __syncthreads();
+}
+
+template <int M, int SIGN>
+__device__ __forceinline__ double2 gl_twiddle(const double2* twl, int i) {
+    const double2 w = cmul(twl[i >> 4], twl[M / 16 + (i & 15)]);
+    return SIGN < 0 ? w : cconj(w);
+}
+
+// The stage loop of reg_fft (same schedule, exchanges and barriers) with the
+// twiddles from gl_twiddle.
+template <int L, int NTMAX, int SIGN, int S, int NBUF, int MAXR>
+__device__ __forceinline__ void gl_stages(double2* x, double2* b0, double2* b1, int ps, int t, const double2* twl,
+                                          bool act) {
+    constexpr Sched sd = make_sched(L, NTMAX, MAXR);
+    if constexpr (S < sd.nst) {
+        constexpr int p = sd.rad[S];
+        constexpr int m = sched_m(sd, S);
+        constexpr int E = sd.E;
+        constexpr int NT = sd.NT;
+        constexpr int Q = E / p;
+        constexpr bool last = (S == sd.nst - 1);
+        double2* buf = (NBUF == 2 && (S & 1)) ? b1 : b0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = t + NT * q;
+            const int k = i % m;
+            double2 y[p];
+#pragma unroll
+            for (int r = 0; r < p; ++r) y[r] = x[q + r * Q];
+            if constexpr (m > 1) {
+                const int step = k * (L / (p * m));
+#pragma unroll
+                for (int r = 1; r < p; ++r) y[r] = cmul(y[r], gl_twiddle<L, SIGN>(twl, r * step));
+            }
+            Dft<p, SIGN>::run(y);
+            if constexpr (last) {
+#pragma unroll
+                for (int r = 0; r < p; ++r) x[q + r * Q] = y[r];
+            } else {
+                const int j = (i - k) * p + k;
+                if (act) {
+#pragma unroll
+                    for (int r = 0; r < p; ++r) buf[(j + r * m) * ps] = y[r];
+                }
+            }
+        }
+        if constexpr (!last) {
+            __syncthreads();
+            if (act) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) x[e] = buf[(t + NT * e) * ps];
+            }
+            if constexpr (NBUF == 1 && S + 1 < sd.nst - 1) __syncthreads();
+            gl_stages<L, NTMAX, SIGN, S + 1, NBUF, MAXR>(x, b0, b1, ps, t, twl, act);
+        }
+    }
+}
+
+template <int M, class CF, int SIGN>
+__device__ __forceinline__ void gl_fft(double2* x, double2* b0, double2* b1, int ps, int t, const double2* twl, bool act) {
+    gl_stages<M, CF::NTMAX, SIGN, 0, CF::NB, CF::MAXR>(x, b0, b1, ps, t, twl, act);
+}
+
 template <int M, class CF>
-__device__ __attribute__((noinline)) void rows_inv_reg(const GLProb& pr, int line0, const double2* src, double2* work, double2* lds) {
+__device__ __attribute__((noinline)) void rows_inv_reg(const GLProb& pr, int line0, const double2* src, double2* work, double2* lds,
+                                                       const double2* twall) {
     using G = GGeo<M, CF>;
     const int t = threadIdx.x % G::NT, g = threadIdx.x / G::NT;
     const int row = line0 + g;
@@ -190,7 +278,8 @@ __device__ __attribute__((noinline)) void rows_inv_reg(const GLProb& pr, int lin
         const int l = gwn(q, M);
         x[e] = (act && kept(l, N)) ? src[pr.off_s + (long)row * N + nidx(l, N)] : make_double2(0.0, 0.0);
     }
-    reg_fft<M, CF::NTMAX, 1, CF::NB, CF::MAXR>(x, lds + g * M, lds + G::B1OFF + g * M, 1, t, pr.rp.tw, act);
+    const double2* twl = twall + gl_tw_base(M);
+    gl_fft<M, CF, 1>(x, lds + g * M, lds + G::B1OFF + g * M, 1, t, twl, act);
     if (act) {
 #pragma unroll
         for (int e = 0; e < G::E; ++e) work[pr.off_w + (long)row * M + t + G::NT * e] = x[e];
@@ -198,7 +287,8 @@ __device__ __attribute__((noinline)) void rows_inv_reg(const GLProb& pr, int lin
 }
 
 template <int M, class CF>
-__device__ __attribute__((noinline)) void cols_reg(const GLProb& pr, int line0, double2* work, double2* lds, double cnl) {
+__device__ __attribute__((noinline)) void cols_reg(const GLProb& pr, int line0, double2* work, double2* lds, double cnl,
+                                                   const double2* twall) {
     using G = GGeo<M, CF>;
     const int c = threadIdx.x % G::W, t = threadIdx.x / G::W;
     const int y = line0 + c;
@@ -211,7 +301,8 @@ __device__ __attribute__((noinline)) void cols_reg(const GLProb& pr, int line0, 
         const int l = gwn(q, M);
         x[e] = (act && kept(l, N)) ? work[pr.off_w + (long)nidx(l, N) * M + y] : make_double2(0.0, 0.0);
     }
-    reg_fft<M, CF::NTMAX, 1, CF::NB, CF::MAXR>(x, lds + c, lds + G::B1OFF + c, G::W, t, pr.rp.tw, act);
+    const double2* twl = twall + gl_tw_base(M);
+    gl_fft<M, CF, 1>(x, lds + c, lds + G::B1OFF + c, G::W, t, twl, act);
 #pragma unroll
     for (int e = 0; e < G::E; ++e) {
         const double2 u = x[e];
@@ -220,7 +311,7 @@ __device__ __attribute__((noinline)) void cols_reg(const GLProb& pr, int line0, 
         x[e] = make_double2(r2 * (u.x - cnl * u.y), r2 * (u.y + cnl * u.x));
     }
     __syncthreads();
-    reg_fft<M, CF::NTMAX, -1, CF::NB, CF::MAXR>(x, lds + c, lds + G::B1OFF + c, G::W, t, pr.rp.tw, act);
+    gl_fft<M, CF, -1>(x, lds + c, lds + G::B1OFF + c, G::W, t, twl, act);
     if (act) {
         const double s = 1.0 / M;
 #pragma unroll
@@ -236,7 +327,7 @@ __device__ __attribute__((noinline)) void cols_reg(const GLProb& pr, int line0, 
 // inverse-transform it along y (pass A of the next stage) into the workspace.
 template <int M, class CF, bool FUSE>
 __device__ __attribute__((noinline)) void rows_fwd_reg(const GLProb& pr, int line0, double2* work, double2* lds,
-                                                       const GLStage& st) {
+                                                       const GLStage& st, const double2* twall) {
     using G = GGeo<M, CF>;
     const int t = threadIdx.x % G::NT, g = threadIdx.x / G::NT;
     const int row = line0 + g;
@@ -246,7 +337,8 @@ __device__ __attribute__((noinline)) void rows_fwd_reg(const GLProb& pr, int lin
 #pragma unroll
     for (int e = 0; e < G::E; ++e)
         x[e] = act ? work[pr.off_w + (long)row * M + t + G::NT * e] : make_double2(0.0, 0.0);
-    reg_fft<M, CF::NTMAX, -1, CF::NB, CF::MAXR>(x, lds + g * M, lds + G::B1OFF + g * M, 1, t, pr.rp.tw, act);
+    const double2* twl = twall + gl_tw_base(M);
+    gl_fft<M, CF, -1>(x, lds + g * M, lds + G::B1OFF + g * M, 1, t, twl, act);
     const double s = -1.0 / M;
     const bool store_v = !FUSE || st.mode == kGlRk4;
 #pragma unroll
@@ -262,7 +354,7 @@ __device__ __attribute__((noinline)) void rows_fwd_reg(const GLProb& pr, int lin
     }
     if constexpr (FUSE) {
         __syncthreads();
-        reg_fft<M, CF::NTMAX, 1, CF::NB, CF::MAXR>(x, lds + g * M, lds + G::B1OFF + g * M, 1, t, pr.rp.tw, act);
+        gl_fft<M, CF, 1>(x, lds + g * M, lds + G::B1OFF + g * M, 1, t, twl, act);
         if (act) {
 #pragma unroll
             for (int e = 0; e < G::E; ++e) work[pr.off_w + (long)row * M + t + G::NT * e] = x[e];
@@ -363,7 +455,6 @@ __device__ void rows_fwd_gen(const GLProb& pr, int line0, double2* work, double2
         case 6: CALL_REG(768); break;   \
         default: break;                 \
     }
-static const int kGlRegM[7] = {48, 96, 192, 288, 384, 576, 768};
 
 template <class CF>
 static int reg_w(int kind) {
@@ -397,15 +488,16 @@ __device__ __forceinline__ ItemRange item_range(int n) {
 }
 template <class CF, bool GEN>
 __global__ void __launch_bounds__(kGlThreads, kGlWavesPerSimd) k_gl_rows_inv(const GLProb* probs, const GLItem* items, int nitems,
-                                                            const double2* src, double2* work) {
+                                                            const double2* src, double2* work, const double2* twtab) {
     extern __shared__ double2 lds[];
+    if constexpr (!GEN) gl_load_tw_all(twtab, lds);
     for (ItemRange r = item_range(nitems); r.it < r.hi; r.it += r.step) {
         const GLItem item = items[r.it];
         const GLProb pr = probs[item.prob];
         if constexpr (GEN) {
             rows_inv_gen(pr, item.line0, src, work, lds);
         } else {
-#define R_(MM) rows_inv_reg<MM, CF>(pr, item.line0, src, work, lds)
+#define R_(MM) rows_inv_reg<MM, CF>(pr, item.line0, src, work, lds + kGlTwTotal, lds)
             SGM_GL_SWITCH(pr.kind, R_)
 #undef R_
         }
@@ -415,15 +507,16 @@ __global__ void __launch_bounds__(kGlThreads, kGlWavesPerSimd) k_gl_rows_inv(con
 
 template <class CF, bool GEN>
 __global__ void __launch_bounds__(kGlThreads, kGlWavesPerSimd) k_gl_cols(const GLProb* probs, const GLItem* items, int nitems,
-                                                        double2* work, double cnl) {
+                                                        double2* work, double cnl, const double2* twtab) {
     extern __shared__ double2 lds[];
+    if constexpr (!GEN) gl_load_tw_all(twtab, lds);
     for (ItemRange r = item_range(nitems); r.it < r.hi; r.it += r.step) {
         const GLItem item = items[r.it];
         const GLProb pr = probs[item.prob];
         if constexpr (GEN) {
             cols_gen(pr, item.line0, work, lds, cnl);
         } else {
-#define C_(MM) cols_reg<MM, CF>(pr, item.line0, work, lds, cnl)
+#define C_(MM) cols_reg<MM, CF>(pr, item.line0, work, lds + kGlTwTotal, cnl, lds)
             SGM_GL_SWITCH(pr.kind, C_)
 #undef C_
         }
@@ -433,15 +526,16 @@ __global__ void __launch_bounds__(kGlThreads, kGlWavesPerSimd) k_gl_cols(const G
 
 template <class CF, bool GEN, bool FUSE>
 __global__ void __launch_bounds__(kGlThreads, kGlWavesPerSimd) k_gl_rows_fwd(const GLProb* probs, const GLItem* items, int nitems,
-                                                            double2* work, GLStage st) {
+                                                            double2* work, GLStage st, const double2* twtab) {
     extern __shared__ double2 lds[];
+    if constexpr (!GEN) gl_load_tw_all(twtab, lds);
     for (ItemRange r = item_range(nitems); r.it < r.hi; r.it += r.step) {
         const GLItem item = items[r.it];
         const GLProb pr = probs[item.prob];
         if constexpr (GEN) {
             rows_fwd_gen(pr, item.line0, work, lds, st, FUSE);
         } else {
-#define F_(MM) rows_fwd_reg<MM, CF, FUSE>(pr, item.line0, work, lds, st)
+#define F_(MM) rows_fwd_reg<MM, CF, FUSE>(pr, item.line0, work, lds + kGlTwTotal, st, lds)
             SGM_GL_SWITCH(pr.kind, F_)
 #undef F_
         }
@@ -451,10 +545,10 @@ __global__ void __launch_bounds__(kGlThreads, kGlWavesPerSimd) k_gl_rows_fwd(con
 
 // Launch table of one configuration.
 struct GLKern {
-    void (*rows_inv)(const GLProb*, const GLItem*, int, const double2*, double2*);
-    void (*cols)(const GLProb*, const GLItem*, int, double2*, double);
-    void (*rows_fwd)(const GLProb*, const GLItem*, int, double2*, GLStage);
-    void (*rows_fwd_fused)(const GLProb*, const GLItem*, int, double2*, GLStage);
+    void (*rows_inv)(const GLProb*, const GLItem*, int, const double2*, double2*, const double2*);
+    void (*cols)(const GLProb*, const GLItem*, int, double2*, double, const double2*);
+    void (*rows_fwd)(const GLProb*, const GLItem*, int, double2*, GLStage, const double2*);
+    void (*rows_fwd_fused)(const GLProb*, const GLItem*, int, double2*, GLStage, const double2*);
     int (*w)(int);
     int nb, ldsb;
 };
@@ -498,6 +592,7 @@ struct sgm_gl_s {
     GLItem* ditemsA[kGlLists] = {};
     GLItem* ditemsB[kGlLists] = {};
     double2* etab = nullptr;
+    double2* twtab = nullptr;    // two-level twiddle tables of the compiled padded lengths
     double2* v = nullptr;
     double2* acc = nullptr;
     double2* work = nullptr;
@@ -509,7 +604,7 @@ struct sgm_gl_s {
 
 static int glkind(int M) {
     for (int i = 0; i < 7; ++i)
-        if (kGlRegM[i] == M) return i;
+        if (kGlRegLen[i] == M) return i;
     return -1;
 }
 
@@ -545,12 +640,12 @@ static sgm_status gl_pass(sgm_gl g, int pass, const double2* src, const GLStage&
         const dim3 grid(gl_grid(g, k, n)), block(kGlThreads);
         const GLProb* probs = g->dprobs[k];
         if (pass == 0)
-            hipLaunchKernelGGL(kn.rows_inv, grid, block, g->lds[k], s, probs, items, n, src, g->work);
+            hipLaunchKernelGGL(kn.rows_inv, grid, block, g->lds[k], s, probs, items, n, src, g->work, g->twtab);
         else if (pass == 1)
-            hipLaunchKernelGGL(kn.cols, grid, block, g->lds[k], s, probs, items, n, g->work, g->d.c);
+            hipLaunchKernelGGL(kn.cols, grid, block, g->lds[k], s, probs, items, n, g->work, g->d.c, g->twtab);
         else
             hipLaunchKernelGGL(pass == 3 ? kn.rows_fwd_fused : kn.rows_fwd, grid, block, g->lds[k], s, probs, items, n,
-                               g->work, st);
+                               g->work, st, g->twtab);
         SGM_HIP_TRY(hipGetLastError());
     }
     return SGM_OK;
@@ -727,7 +822,8 @@ extern "C" sgm_status sgm_gl_create(const sgm_gl_desc* desc, void* stream, sgm_g
             } else {
                 const GLKern kn = glkern_cfg(k, false);
                 pr.wrows = pr.wcols = pr.kind >= 0 ? kn.w(pr.kind) : 1;
-                lds = sizeof(double2) * (size_t)kn.nb * pr.wrows * pr.M;
+                // the two-level twiddle tables of every compiled length, then the exchange buffers
+                lds = sizeof(double2) * ((size_t)kGlTwTotal + (size_t)kn.nb * pr.wrows * pr.M);
             }
             const bool mine = (k == kGlCfgs) == (pr.kind < 0);
             if (mine) g->lds[k] = std::max(g->lds[k], lds);
@@ -759,7 +855,7 @@ extern "C" sgm_status sgm_gl_create(const sgm_gl_desc* desc, void* stream, sgm_g
             etab[2 * (g->off_e[i] + q)] = (double)(mag * cosl(d.b * a));
             etab[2 * (g->off_e[i] + q) + 1] = (double)(mag * sinl(d.b * a));
         }
-    // device blob: probs[k] | itemsA[k] | itemsB[k] | etab | twiddles
+    // device blob: probs[k] | itemsA[k] | itemsB[k] | etab | GL twiddle tables | twiddles
     std::vector<char> blob;
     auto add = [&](const void* p, size_t bytes) {
         size_t off = (blob.size() + 255) & ~size_t(255);
@@ -774,6 +870,18 @@ extern "C" sgm_status sgm_gl_create(const sgm_gl_desc* desc, void* stream, sgm_g
         o_B[k] = add(itB[k].data(), itB[k].size() * sizeof(GLItem));
     }
     size_t o_e = add(etab.data(), etab.size() * sizeof(double));
+    // per compiled length M: A[h] = exp(-2 pi i 16 h / M), h < M / 16, then B[l] = exp(-2 pi i l / M), l < 16
+    std::vector<double> gtab;
+    for (int k = 0; k < 7; ++k) {
+        const int M = kGlRegLen[k];
+        for (int j = 0; j < M / 16 + 16; ++j) {
+            const int r = j < M / 16 ? 16 * j : j - M / 16;
+            const long double a = -twopi * (long double)r / (long double)M;
+            gtab.push_back((double)cosl(a));
+            gtab.push_back((double)sinl(a));
+        }
+    }
+    size_t o_gt = add(gtab.data(), gtab.size() * sizeof(double));
     std::vector<size_t> o_tw(lens.size());
     for (size_t j = 0; j < lens.size(); ++j) {
         std::vector<double> tw = twiddles(lens[j]);
@@ -801,6 +909,7 @@ extern "C" sgm_status sgm_gl_create(const sgm_gl_desc* desc, void* stream, sgm_g
         g->ditemsB[k] = reinterpret_cast<GLItem*>(base + o_B[k]);
     }
     g->etab = reinterpret_cast<double2*>(base + o_e);
+    g->twtab = reinterpret_cast<double2*>(base + o_gt);
     g->rpN.resize(n);
     g->hasN.resize(n);
     g->rkN.resize(n);
