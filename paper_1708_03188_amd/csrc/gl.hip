@@ -115,32 +115,61 @@ __device__ __forceinline__ void ntst(double2* p, double2 v) {
     __builtin_nontemporal_store(w, reinterpret_cast<nt_d2*>(p));
 }
 
-// Stage update of one retained mode.  k = N(v) = -F_trunc[(1 + i c)|u_p|^2 u_p].
+// Operands of one retained mode's stage update (loaded together for several modes
+// before any of their updates is applied, so the loads are in flight at once).
+struct StageIn {
+    double2 vv, u0, a, ey;
+};
+
+typedef __attribute__((address_space(1))) const nt_d2 g_nt_d2;
+__device__ __forceinline__ double2 ntld_g(const double2* p) {
+    const nt_d2 v = __builtin_nontemporal_load((g_nt_d2*)(const void*)p);
+    return make_double2(v.x, v.y);
+}
+
+__device__ __forceinline__ StageIn stage_load(const GLStage& s, const GLProb& pr, long idx, int kyi) {
+    StageIn in;
+    in.vv = in.u0 = in.a = in.ey = make_double2(0.0, 0.0);
+    if (s.mode == kGlRhs || s.mode == kGlRk4) {
+        in.vv = ntld_g(s.vin + idx);
+        if (s.mode == kGlRhs) return in;
+    } else {
+        const __attribute__((address_space(1))) double* pe =
+            (const __attribute__((address_space(1))) double*)(const void*)(s.etab + pr.off_e + kyi);
+        in.ey = make_double2(pe[0], pe[1]);
+    }
+    in.u0 = ntld_g(s.state + idx);
+    if (s.stage > 0) in.a = ntld_g(s.acc + idx);
+    return in;
+}
+
+// Stage update of one retained mode from its loaded operands, ex = the
+// integrating factor's x part (IF-RK4).  k = N(v) = -F_trunc[(1 + i c)|u_p|^2 u_p].
 // Returns the input of the next stage (stages 0..2); stores it in s.v when
 // store_v (the explicit scheme needs it again for L v).
-__device__ __forceinline__ double2 stage_update(const GLStage& s, const GLProb& pr, long idx, int kxi, int kyi,
-                                                double2 k, bool store_v) {
+__device__ __forceinline__ double2 stage_apply(const GLStage& s, const GLProb& pr, long idx, int kxi, int kyi,
+                                               double2 k, const StageIn& in, double2 ex, bool store_v) {
     double2 vn = make_double2(0.0, 0.0);
     if (s.mode == kGlRhs || s.mode == kGlRk4) {
         const double kx = gwn(kxi, pr.N) * s.ks, ky = gwn(kyi, pr.N) * s.ks;
         const double k2 = kx * kx + ky * ky;
-        const double2 vv = ntld(s.vin + idx);
+        const double2 vv = in.vv;
         // dU = (1 - (1 + i b) k^2) v + k
         const double2 du = make_double2((1.0 - k2) * vv.x + s.b * k2 * vv.y + k.x,
                                         (1.0 - k2) * vv.y - s.b * k2 * vv.x + k.y);
         if (s.mode == kGlRhs) { s.rhs[idx] = du; return vn; }
-        const double2 u0 = ntld(s.state + idx);
+        const double2 u0 = in.u0;
         const double dt = s.dt;
         if (s.stage == 0) {
             ntst(s.acc + idx, make_double2(u0.x + dt / 6 * du.x, u0.y + dt / 6 * du.y));
             vn = make_double2(u0.x + dt / 2 * du.x, u0.y + dt / 2 * du.y);
         } else if (s.stage < 3) {
-            double2 a = ntld(s.acc + idx);
+            const double2 a = in.a;
             ntst(s.acc + idx, make_double2(a.x + dt / 3 * du.x, a.y + dt / 3 * du.y));
             const double bb = s.stage == 1 ? dt / 2 : dt;
             vn = make_double2(u0.x + bb * du.x, u0.y + bb * du.y);
         } else {
-            double2 a = ntld(s.acc + idx);
+            const double2 a = in.a;
             ntst(s.state + idx, make_double2(a.x + dt / 6 * du.x, a.y + dt / 6 * du.y));
             return vn;
         }
@@ -148,9 +177,8 @@ __device__ __forceinline__ double2 stage_update(const GLStage& s, const GLProb& 
         return vn;
     }
     // integrating-factor RK4; E = exp(Lhat dt/2) = e^{dt/2} ex(kx) ex(ky)
-    const double2 ex = s.etab[pr.off_e + kxi], ey = s.etab[pr.off_e + kyi];
-    const double2 E = cscale(cmul(ex, ey), s.edt);
-    const double2 u0 = ntld(s.state + idx);
+    const double2 E = cscale(cmul(ex, in.ey), s.edt);
+    const double2 u0 = in.u0;
     const double dt = s.dt;
     if (s.stage == 0) {
         const double2 E2 = cmul(E, E);
@@ -159,23 +187,42 @@ __device__ __forceinline__ double2 stage_update(const GLStage& s, const GLProb& 
         vn = cmul(E, make_double2(u0.x + dt / 2 * k.x, u0.y + dt / 2 * k.y));
     } else if (s.stage == 1) {
         const double2 Ek = cmul(E, k);
-        double2 a = ntld(s.acc + idx);
+        const double2 a = in.a;
         ntst(s.acc + idx, make_double2(a.x + dt / 3 * Ek.x, a.y + dt / 3 * Ek.y));
         const double2 Eu = cmul(E, u0);
         vn = make_double2(Eu.x + dt / 2 * k.x, Eu.y + dt / 2 * k.y);
     } else if (s.stage == 2) {
         const double2 Ek = cmul(E, k);
-        double2 a = ntld(s.acc + idx);
+        const double2 a = in.a;
         ntst(s.acc + idx, make_double2(a.x + dt / 3 * Ek.x, a.y + dt / 3 * Ek.y));
         const double2 E2u = cmul(E, cmul(E, u0));
         vn = make_double2(E2u.x + dt * Ek.x, E2u.y + dt * Ek.y);
     } else {
-        double2 a = ntld(s.acc + idx);
+        const double2 a = in.a;
         ntst(s.state + idx, make_double2(a.x + dt / 6 * k.x, a.y + dt / 6 * k.y));
         return vn;
     }
     if (store_v) s.v[idx] = vn;
     return vn;
+}
+
+__device__ __forceinline__ double2 stage_update(const GLStage& s, const GLProb& pr, long idx, int kxi, int kyi,
+                                                double2 k, bool store_v) {
+    const double2 ex = s.mode == kGlIfRk4 ? s.etab[pr.off_e + kxi] : make_double2(0.0, 0.0);
+    return stage_apply(s, pr, idx, kxi, kyi, k, stage_load(s, pr, idx, kyi), ex, store_v);
+}
+
+// A value every lane of the wave holds, moved to scalar registers.
+template <class T>
+__device__ __forceinline__ T wave_uniform(const T& v) {
+    static_assert(sizeof(T) % 4 == 0, "32-bit words");
+    int w[sizeof(T) / 4];
+    __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    T r;
+    __builtin_memcpy(&r, w, sizeof(T));
+    return r;
 }
 
 // ---------------- register-FFT specialisations -----------------------------
@@ -326,9 +373,18 @@ __device__ __attribute__((noinline)) void cols_reg(const GLProb& pr, int line0, 
 // FUSE: after the stage update, zero-pad the new stage input of the row and
 // inverse-transform it along y (pass A of the next stage) into the workspace.
 template <int M, class CF, bool FUSE>
-__device__ __attribute__((noinline)) void rows_fwd_reg(const GLProb& pr, int line0, double2* work, double2* lds,
-                                                       const GLStage& st, const double2* twall) {
+__device__ __attribute__((noinline)) void rows_fwd_reg(const GLProb& prr, int line0, double2* work, double2* lds,
+                                                       const GLStage& str, const double2* twall) {
     using G = GGeo<M, CF>;
+    // Descriptors by value in scalar registers (every lane holds the same ones):
+    // read through the references, every store of the stage update could (for the
+    // compiler) change them, so each retained mode would reload them.
+    GLProb pr;
+    pr.N = __builtin_amdgcn_readfirstlane(prr.N);
+    pr.off_s = wave_uniform(prr.off_s);
+    pr.off_w = wave_uniform(prr.off_w);
+    pr.off_e = wave_uniform(prr.off_e);
+    const GLStage st = wave_uniform(str);
     const int t = threadIdx.x % G::NT, g = threadIdx.x / G::NT;
     const int row = line0 + g;
     const bool act = threadIdx.x < G::THREADS && row < pr.N;
