@@ -115,8 +115,8 @@ __device__ __forceinline__ void ntst(double2* p, double2 v) {
     __builtin_nontemporal_store(w, reinterpret_cast<nt_d2*>(p));
 }
 
-// Operands of one retained mode's stage update (loaded together for several modes
-// before any of their updates is applied, so the loads are in flight at once).
+// Operands of one retained mode's stage update (the stage input for the explicit
+// schemes, state, accumulator, the integrating factor's y part).
 struct StageIn {
     double2 vv, u0, a, ey;
 };
