@@ -311,9 +311,14 @@ __device__ __forceinline__ void gl_fft(double2* x, double2* b0, double2* b1, int
 }
 
 template <int M, class CF>
-__device__ __attribute__((noinline)) void rows_inv_reg(const GLProb& pr, int line0, const double2* src, double2* work, double2* lds,
+__device__ __attribute__((noinline)) void rows_inv_reg(const GLProb& prr, int line0, const double2* src, double2* work, double2* lds,
                                                        const double2* twall) {
     using G = GGeo<M, CF>;
+    // the descriptor's fields in scalar registers (see rows_fwd_reg)
+    GLProb pr;
+    pr.N = __builtin_amdgcn_readfirstlane(prr.N);
+    pr.off_s = wave_uniform(prr.off_s);
+    pr.off_w = wave_uniform(prr.off_w);
     const int t = threadIdx.x % G::NT, g = threadIdx.x / G::NT;
     const int row = line0 + g;
     const bool act = threadIdx.x < G::THREADS && row < pr.N;
@@ -334,9 +339,13 @@ __device__ __attribute__((noinline)) void rows_inv_reg(const GLProb& pr, int lin
 }
 
 template <int M, class CF>
-__device__ __attribute__((noinline)) void cols_reg(const GLProb& pr, int line0, double2* work, double2* lds, double cnl,
+__device__ __attribute__((noinline)) void cols_reg(const GLProb& prr, int line0, double2* work, double2* lds, double cnl,
                                                    const double2* twall) {
     using G = GGeo<M, CF>;
+    // the descriptor's fields in scalar registers (see rows_fwd_reg)
+    GLProb pr;
+    pr.N = __builtin_amdgcn_readfirstlane(prr.N);
+    pr.off_w = wave_uniform(prr.off_w);
     const int c = threadIdx.x % G::W, t = threadIdx.x / G::W;
     const int y = line0 + c;
     const bool act = threadIdx.x < G::THREADS && y < M;
