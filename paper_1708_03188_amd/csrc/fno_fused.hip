@@ -128,11 +128,12 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer(FnoLayerArgs p) {
     // B operand over the concatenated K: U rows (x-spectral input) then Wp
     bf16x8 bop[4];
     {
+        // U may alias Tn, which row 0's wave rewrites: a wave past the end reads no U
         const bf16* u = p.U + rr * F2K * FC;
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
-            for (int v = 0; v < 8; ++v) bop[s][v] = u[(16 * s + 8 * g + v) * FC + c];
+            for (int v = 0; v < 8; ++v) bop[s][v] = live ? u[(16 * s + 8 * g + v) * FC + c] : (bf16)0.f;
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -449,6 +450,13 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer_bwd(FnoLayerBwdArgs p)
     // chunk j * 64 + lane (pixel i / 4, channels 8 (i % 4)..).
     float4 nda[4];
     uint4 nz[2], nap[2];
+    // rows past the end read nothing (zeros): da and T of a live row are updated in place
+    auto fetch_none = [&]() {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) nda[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) nz[j] = nap[j] = make_uint4(0, 0, 0, 0);
+    };
     auto fetch = [&](long pb) {
         const float4* d4 = reinterpret_cast<const float4*>(p.da + pb * FC);
 #pragma unroll
@@ -462,15 +470,16 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer_bwd(FnoLayerBwdArgs p)
         }
     };
     // (row group, tile) steps, the same sequence for every wave of the block; rows past
-    // the end compute on row 0 and discard
+    // the end compute on zeros and discard
     const long ngr = (p.rows + WAVES - 1) / WAVES;
     long gr = blockIdx.x;
     int t = 0;
-    auto row_of = [&](long grp) {
+    auto fetch_step = [&](long grp, int tile) {
         const long r = grp * WAVES + wv;
-        return r < p.rows ? r : 0L;
+        if (r < p.rows) fetch(r * W + 32 * tile);
+        else fetch_none();
     };
-    if (gr < ngr) fetch(row_of(gr) * W);
+    if (gr < ngr) fetch_step(gr, 0);
     while (gr < ngr) {
         const long row = gr * WAVES + wv;
         const bool live = row < p.rows;
@@ -482,7 +491,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer_bwd(FnoLayerBwdArgs p)
             for (int s = 0; s < 2; ++s)
 #pragma unroll
                 for (int v = 0; v < 8; ++v)
-                    tb[s][v] = p.addT ? (bf16)p.T[rr * F2K * FC + (16 * s + 8 * g + v) * FC + c] : (bf16)0.f;
+                    tb[s][v] = (p.addT && live) ? (bf16)p.T[rr * F2K * FC + (16 * s + 8 * g + v) * FC + c] : (bf16)0.f;
             uacc = zero16();
             gwr = zero16();
             gbr = 0.f;
@@ -503,7 +512,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer_bwd(FnoLayerBwdArgs p)
         int tn = t + 1;
         long grn = gr;
         if (tn == nt) { tn = 0; grn += gridDim.x; }
-        if (grn < ngr) fetch(row_of(grn) * W + 32 * tn);
+        if (grn < ngr) fetch_step(grn, tn);
         __syncthreads();
         floatx16 acc;
 #pragma unroll
