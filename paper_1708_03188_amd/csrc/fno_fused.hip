@@ -436,7 +436,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer_bwd(FnoLayerBwdArgs p)
     // per-wave tiles: da [pixel][channel] fp32, z, a and dz [pixel][channel] bf16
     __shared__ float sda[WAVES][32][FC + 4];
     __shared__ bf16 sz[WAVES][32][FC + 8], sap[WAVES][32][FC + 8], sdz[WAVES][32][FC + 8];
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: row tests branch per wave
     const int lane = threadIdx.x & 63, c = lane & 31, g = lane >> 5;
     const int W = p.W, nt = W / 32;
     bf16x8 wb[2];
@@ -446,40 +446,36 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer_bwd(FnoLayerBwdArgs p)
     float gb = 0.f, gbr = 0.f;
     bf16x8 tb[2];
     // a tile is 32 consecutive pixels of one row: contiguous 4 KB of da, 2 KB of z and of a.
-    // Lane loads: da float4 j * 64 + lane (pixel / 8, channels 4 (i % 8)..), z and a 16-byte
-    // chunk j * 64 + lane (pixel i / 4, channels 8 (i % 4)..).
-    float4 nda[4];
-    uint4 nz[2], nap[2];
-    // rows past the end read nothing (zeros): da and T of a live row are updated in place
-    auto fetch_none = [&]() {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) nda[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-        for (int j = 0; j < 2; ++j) nz[j] = nap[j] = make_uint4(0, 0, 0, 0);
-    };
-    auto fetch = [&](long pb) {
+    // Lane loads: da float4 i = j * 64 + lane (pixel i / 8, channels 4 (i % 8)..), z and a 16-byte
+    // chunk i = j * 64 + lane (pixel i / 4, channels 8 (i % 4)..), j = 0..3 and 0..1.
+    // the next step's tile, in flight during this step (named registers, not arrays)
+    float4 nd0, nd1, nd2, nd3;
+    uint4 nz0, nz1, na0, na1;
+    // rows past the end get zeros (their addresses are clamped to row 0, which another
+    // wave may be updating in place; whatever such a load returns is discarded)
+    auto fetch = [&](long row, int tile) __attribute__((always_inline)) {
+        const bool ok = row < p.rows;
+        const long pb = (ok ? row : 0) * W + 32 * tile;
         const float4* d4 = reinterpret_cast<const float4*>(p.da + pb * FC);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) nda[j] = d4[j * 64 + lane];
         const uint4* z4 = reinterpret_cast<const uint4*>(p.z + pb * FC);
         const uint4* a4 = reinterpret_cast<const uint4*>(p.aprev + pb * FC);
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            nz[j] = p.act ? z4[j * 64 + lane] : make_uint4(0, 0, 0, 0);
-            nap[j] = a4[j * 64 + lane];
-        }
+        const float4 f0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        const uint4 u0 = make_uint4(0, 0, 0, 0);
+        nd0 = ok ? d4[lane] : f0;
+        nd1 = ok ? d4[64 + lane] : f0;
+        nd2 = ok ? d4[128 + lane] : f0;
+        nd3 = ok ? d4[192 + lane] : f0;
+        nz0 = ok ? z4[lane] : u0;
+        nz1 = ok ? z4[64 + lane] : u0;
+        na0 = ok ? a4[lane] : u0;
+        na1 = ok ? a4[64 + lane] : u0;
     };
     // (row group, tile) steps, the same sequence for every wave of the block; rows past
     // the end compute on zeros and discard
     const long ngr = (p.rows + WAVES - 1) / WAVES;
     long gr = blockIdx.x;
     int t = 0;
-    auto fetch_step = [&](long grp, int tile) {
-        const long r = grp * WAVES + wv;
-        if (r < p.rows) fetch(r * W + 32 * tile);
-        else fetch_none();
-    };
-    if (gr < ngr) fetch_step(gr, 0);
+    if (gr < ngr) fetch(gr * WAVES + wv, 0);
     while (gr < ngr) {
         const long row = gr * WAVES + wv;
         const bool live = row < p.rows;
@@ -497,22 +493,20 @@ __global__ void __launch_bounds__(64 * WAVES) k_fno_layer_bwd(FnoLayerBwdArgs p)
             gbr = 0.f;
         }
         __syncthreads();  // the previous step's LDS reads are done
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int i = j * 64 + lane;
-            *reinterpret_cast<float4*>(&sda[wv][i >> 3][4 * (i & 7)]) = nda[j];
-        }
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int i = j * 64 + lane;
-            *reinterpret_cast<uint4*>(&sz[wv][i >> 2][8 * (i & 3)]) = nz[j];
-            *reinterpret_cast<uint4*>(&sap[wv][i >> 2][8 * (i & 3)]) = nap[j];
-        }
+        // float4 i of the tile: pixel i / 8, channels 4 (i % 8)..; 16-byte chunk i: pixel i / 4, channels 8 (i % 4)..
+        *reinterpret_cast<float4*>(&sda[wv][lane >> 3][4 * (lane & 7)]) = nd0;
+        *reinterpret_cast<float4*>(&sda[wv][8 + (lane >> 3)][4 * (lane & 7)]) = nd1;
+        *reinterpret_cast<float4*>(&sda[wv][16 + (lane >> 3)][4 * (lane & 7)]) = nd2;
+        *reinterpret_cast<float4*>(&sda[wv][24 + (lane >> 3)][4 * (lane & 7)]) = nd3;
+        *reinterpret_cast<uint4*>(&sz[wv][lane >> 2][8 * (lane & 3)]) = nz0;
+        *reinterpret_cast<uint4*>(&sz[wv][16 + (lane >> 2)][8 * (lane & 3)]) = nz1;
+        *reinterpret_cast<uint4*>(&sap[wv][lane >> 2][8 * (lane & 3)]) = na0;
+        *reinterpret_cast<uint4*>(&sap[wv][16 + (lane >> 2)][8 * (lane & 3)]) = na1;
         // next step's tile, in flight during this step
         int tn = t + 1;
         long grn = gr;
         if (tn == nt) { tn = 0; grn += gridDim.x; }
-        if (grn < ngr) fetch_step(grn, tn);
+        if (grn < ngr) fetch(grn * WAVES + wv, tn);
         __syncthreads();
         floatx16 acc;
 #pragma unroll
