@@ -212,6 +212,36 @@ __device__ __forceinline__ double2 stage_update(const GLStage& s, const GLProb& 
     return stage_apply(s, pr, idx, kxi, kyi, k, stage_load(s, pr, idx, kyi), ex, store_v);
 }
 
+// The stage updates of a thread's retained modes in one scope whose operand
+// arrays are restrict parameters: the state, accumulator, stage output, stage
+// input, right-hand side and integrating-factor table never overlap, so a mode's
+// loads may be issued before the previous mode's stores.
+template <int M, int NT, int E>
+__device__ __forceinline__ void stage_row(double2 (&x)[E], double2* __restrict__ state, double2* __restrict__ acc,
+                                          double2* __restrict__ v, const double2* __restrict__ etab,
+                                          const double2* __restrict__ vin, double2* __restrict__ rhs,
+                                          const GLStage& st0, const GLProb& pr, int row, int t, bool act, bool store_v) {
+    GLStage st = st0;
+    st.state = state;
+    st.acc = acc;
+    st.v = v;
+    st.etab = etab;
+    st.vin = vin;
+    st.rhs = rhs;
+    const int N = pr.N;
+    const double s = -1.0 / M;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int l = gwn(t + NT * e, M);
+        double2 vn = make_double2(0.0, 0.0);
+        if (act && kept(l, N)) {
+            const int ky = nidx(l, N);
+            vn = stage_update(st, pr, pr.off_s + (long)row * N + ky, row, ky, cscale(x[e], s), store_v);
+        }
+        x[e] = vn;
+    }
+}
+
 // A value every lane of the wave holds, moved to scalar registers.
 template <class T>
 __device__ __forceinline__ T wave_uniform(const T& v) {
@@ -397,26 +427,14 @@ __device__ __attribute__((noinline)) void rows_fwd_reg(const GLProb& prr, int li
     const int t = threadIdx.x % G::NT, g = threadIdx.x / G::NT;
     const int row = line0 + g;
     const bool act = threadIdx.x < G::THREADS && row < pr.N;
-    const int N = pr.N;
     double2 x[G::E];
 #pragma unroll
     for (int e = 0; e < G::E; ++e)
         x[e] = act ? work[pr.off_w + (long)row * M + t + G::NT * e] : make_double2(0.0, 0.0);
     const double2* twl = twall + gl_tw_base(M);
     gl_fft<M, CF, -1>(x, lds + g * M, lds + G::B1OFF + g * M, 1, t, twl, act);
-    const double s = -1.0 / M;
     const bool store_v = !FUSE || st.mode == kGlRk4;
-#pragma unroll
-    for (int e = 0; e < G::E; ++e) {
-        const int q = t + G::NT * e;
-        const int l = gwn(q, M);
-        double2 vn = make_double2(0.0, 0.0);
-        if (act && kept(l, N)) {
-            const int ky = nidx(l, N);
-            vn = stage_update(st, pr, pr.off_s + (long)row * N + ky, row, ky, cscale(x[e], s), store_v);
-        }
-        x[e] = vn;
-    }
+    stage_row<M, G::NT, G::E>(x, st.state, st.acc, st.v, st.etab, st.vin, st.rhs, st, pr, row, t, act, store_v);
     if constexpr (FUSE) {
         __syncthreads();
         gl_fft<M, CF, 1>(x, lds + g * M, lds + G::B1OFF + g * M, 1, t, twl, act);
