@@ -776,7 +776,7 @@ static sgm_status fno_backward(sgm_fno f, const float* x, int B, hipStream_t s) 
         pa.pix = pix; pa.P = P;
         SGM_HIP_TRY(launch_fno_proj_bwd(pa, s));
         // the partial rows are [gW1 | gb1 | gW2], the parameters' order in the gradient buffer
-        SGM_HIP_TRY(launch_fno_sum_partials(f->part, fno_proj_bwd_groups(pix), (C + 3) * P, f->grad + f->oW1, s));
+        SGM_HIP_TRY(launch_fno_sum_partials(f->part, fno_proj_bwd_groups(pix, P), (C + 3) * P, f->grad + f->oW1, s));
         SGM_HIP_TRY(colsum_f32(dpred, f->grad + f->ob2, pix, 2, s));
         return fno_backward_layers(f, x, B, s);
     }

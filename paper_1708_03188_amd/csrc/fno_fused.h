@@ -125,7 +125,7 @@ hipError_t launch_fno_lift_bwd(const float* da, const float* T, const float* x, 
                                float* part, hipStream_t s);
 // Work-groups (= partial rows) a backward launch over `rows` rows / `pix` pixels uses.
 int fno_layer_bwd_groups(long rows);
-int fno_proj_bwd_groups(long pix);
+int fno_proj_bwd_groups(long pix, int P);
 // out[v] += sum over r < nrows of part[r nvals + v]
 hipError_t launch_fno_sum_partials(const float* part, int nrows, int nvals, float* out, hipStream_t s);
 

@@ -658,8 +658,10 @@ __global__ void k_sum_partials(const float* part, int nrows, int nvals, float* o
 int fno_layer_bwd_groups(long rows) {
     return (int)std::max(1L, std::min((rows + WAVES - 1) / WAVES, (long)kFnoBwdMaxGroups));
 }
-int fno_proj_bwd_groups(long pix) {
-    return (int)std::max(1L, std::min((pix / 32 + WAVES - 1) / WAVES, (long)kFnoBwdMaxGroups));
+int fno_proj_bwd_groups(long pix, int P) {
+    // P = 128: a tile per work-group (four waves on one tile); else a tile per wave
+    const long per = P == 128 ? 1 : WAVES;
+    return (int)std::max(1L, std::min((pix / 32 + per - 1) / per, (long)kFnoBwdMaxGroups));
 }
 
 hipError_t launch_fno_sum_partials(const float* part, int nrows, int nvals, float* out, hipStream_t s) {
@@ -679,6 +681,114 @@ hipError_t launch_fno_layer_bwd(const FnoLayerBwdArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Projection backward for P = 128 = 4 x 32 hidden units: the four waves of a
+// work-group share each 32-pixel tile (a and dpred staged once in LDS) and wave w
+// takes hidden block w, so a wave holds one block's accumulators (against four in
+// k_fno_proj_bwd<4>, which runs at one wave per SIMD).  Per tile:
+//   z  = a W1 + b1 (block w)          A = a rows from LDS, B = W1T rows (fixed per wave)
+//   dz = (dpred W2^T) gelu'(z)        per accumulator entry; h = gelu(z)
+//   gW1^T(block w) += dz^T a          A = dz from the accumulators, B = a^T from LDS
+//   da_w = dz W1(block w)^T           A = dz rows through LDS, B = W1 rows (fixed)
+//   da = sum over the four waves      through LDS, stored by the whole work-group
+// gW1's block w, gb1 and gW2 of units 32 w + c are this wave's alone, so the
+// partial row needs no reduction across waves.
+__global__ void __launch_bounds__(64 * WAVES) k_fno_proj_bwd_split(FnoProjBwdArgs p) {
+    static_assert(WAVES == 4, "one hidden block of 32 units per wave");
+    constexpr int LD = FC + 8;
+    __shared__ bf16 sa[32][LD];            // a tile [pixel][channel]
+    __shared__ float sd[32][2];            // dpred tile, rounded to bf16
+    __shared__ bf16 sdz[WAVES][32][LD];    // dz [pixel][unit] per wave
+    __shared__ float sdp[WAVES][32][FC + 1];  // per-wave da partials [pixel][channel]
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, c = lane & 31, g = lane >> 5;
+    const int P = p.P;  // 128
+    const int T = wv;
+    // per-wave constants: W1T rows of the block (B of z), W1 rows (B of da), b1, W2
+    bf16x8 w1b[2], wb[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        w1b[s] = ld8(p.W1T + (long)(32 * T + c) * FC + 16 * s + 8 * g);
+        wb[s] = ld8(p.W1 + (long)c * P + 32 * T + 16 * s + 8 * g);
+    }
+    const float bb = p.b1[32 * T + c];
+    const float w2a = (float)p.W2[2 * (32 * T + c)], w2b = (float)p.W2[2 * (32 * T + c) + 1];
+    floatx16 gw1 = zero16();
+    float gw2a = 0.f, gw2b = 0.f, gb = 0.f;
+    const long ntiles = p.pix / 32;
+    for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const long p0 = tile * 32;
+        // stage a (2 KB: 128 threads x 16 B) and dpred (64 floats)
+        if (threadIdx.x < 128) {
+            const int px = threadIdx.x >> 2, ch = 8 * (threadIdx.x & 3);
+            *reinterpret_cast<bf16x8*>(&sa[px][ch]) = ld8(p.a + (p0 + px) * FC + ch);
+        } else if (threadIdx.x < 192) {
+            const int i = threadIdx.x - 128;
+            sd[i >> 1][i & 1] = (float)(bf16)p.dpred[2 * p0 + i];
+        }
+        __syncthreads();
+        bf16x8 aop[2], at[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) aop[s] = *reinterpret_cast<const bf16x8*>(&sa[c][16 * s + 8 * g]);
+        // a^T in accumulator pixel order: K entry 8 g + v of step q <-> pixel 16 q + 8 (v / 4) + 4 g + v % 4
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int v = 0; v < 8; ++v) at[q][v] = sa[16 * q + 8 * (v >> 2) + 4 * g + (v & 3)][c];
+        floatx16 h;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) h[e] = bb;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) h = mfma(aop[s], w1b[s], h);
+        bf16x8 dz[2];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int pe = 8 * (e >> 2) + 4 * g + (e & 3);
+            const float d0 = sd[pe][0], d1 = sd[pe][1];
+            float gf, gd;
+            fno_gelu_fd(h[e], gf, gd);
+            const float hv = (float)(bf16)gf;
+            const bf16 dzv = (bf16)((d0 * w2a + d1 * w2b) * gd);
+            dz[e >> 3][e & 7] = dzv;
+            gw2a += hv * d0;
+            gw2b += hv * d1;
+            gb += (float)dzv;
+            sdz[wv][pe][c] = dzv;
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) gw1 = mfma(dz[q], at[q], gw1);
+        __syncthreads();
+        floatx16 dp = zero16();
+#pragma unroll
+        for (int s = 0; s < 2; ++s) dp = mfma(*reinterpret_cast<const bf16x8*>(&sdz[wv][c][16 * s + 8 * g]), wb[s], dp);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) sdp[wv][8 * (e >> 2) + 4 * g + (e & 3)][c] = dp[e];
+        __syncthreads();
+        // da = sum of the four partials: 1024 values, four per thread, stored as float4 runs
+        {
+            const int px = threadIdx.x >> 3, ch = 4 * (threadIdx.x & 7);
+            float4 o;
+            o.x = sdp[0][px][ch] + sdp[1][px][ch] + sdp[2][px][ch] + sdp[3][px][ch];
+            o.y = sdp[0][px][ch + 1] + sdp[1][px][ch + 1] + sdp[2][px][ch + 1] + sdp[3][px][ch + 1];
+            o.z = sdp[0][px][ch + 2] + sdp[1][px][ch + 2] + sdp[2][px][ch + 2] + sdp[3][px][ch + 2];
+            o.w = sdp[0][px][ch + 3] + sdp[1][px][ch + 3] + sdp[2][px][ch + 3] + sdp[3][px][ch + 3];
+            *reinterpret_cast<float4*>(p.da + (p0 + px) * FC + ch) = o;
+        }
+        __syncthreads();  // LDS reused by the next tile
+    }
+    // partial row [gW1 (32 x P) | gb1 (P) | gW2 (P x 2)]: block T of gW1 and units 32 T + c are this wave's
+    float* prow = p.part + (long)blockIdx.x * (FC + 3) * P;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) prow[(long)c * P + 32 * T + 8 * (e >> 2) + 4 * g + (e & 3)] = gw1[e];
+    gw2a += __shfl_xor(gw2a, 32);
+    gw2b += __shfl_xor(gw2b, 32);
+    gb += __shfl_xor(gb, 32);
+    if (g == 0) {
+        prow[32 * P + 32 * T + c] = gb;
+        prow[33 * P + 2 * (32 * T + c)] = gw2a;
+        prow[33 * P + 2 * (32 * T + c) + 1] = gw2b;
+    }
+}
+
 bool fno_proj_bwd_ok(int C, int P) { return C == FC && (P == 32 || P == 64 || P == 128); }
 
 hipError_t launch_fno_proj_bwd(const FnoProjBwdArgs& a, hipStream_t s) {
@@ -686,10 +796,10 @@ hipError_t launch_fno_proj_bwd(const FnoProjBwdArgs& a, hipStream_t s) {
     if ((reinterpret_cast<uintptr_t>(a.a) & 15) || (reinterpret_cast<uintptr_t>(a.W1T) & 15) ||
         (reinterpret_cast<uintptr_t>(a.W1) & 15) || (reinterpret_cast<uintptr_t>(a.dpred) & 7))
         return hipErrorInvalidValue;
-    const dim3 grid((unsigned)fno_proj_bwd_groups(a.pix)), block(64 * WAVES);
+    const dim3 grid((unsigned)fno_proj_bwd_groups(a.pix, a.P)), block(64 * WAVES);
     if (a.P == 32) hipLaunchKernelGGL(k_fno_proj_bwd<1>, grid, block, 0, s, a);
     else if (a.P == 64) hipLaunchKernelGGL(k_fno_proj_bwd<2>, grid, block, 0, s, a);
-    else hipLaunchKernelGGL(k_fno_proj_bwd<4>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(k_fno_proj_bwd_split, grid, block, 0, s, a);
     return hipGetLastError();
 }
 
