@@ -739,9 +739,16 @@ static sgm_status fno_backward_layers(sgm_fno f, const float* x, int B, hipStrea
 // the grad buffer.
 static sgm_status spectral_adjoint(sgm_fno f, int l, int B, hipStream_t s) {
     const int C = f->C, H = f->H, K = f->K, NM = f->NM;
-    // gYt[b] (4K x K C) = Gy_real^T (4K x 2H) gU[b] (2H x K C)
+    // gYt[b] (4K x K C) = Gy_real^T (4K x 2H) gU[b] (2H x K C); the reduction (2H) split four
+    // ways into the zeroed output: at small batches the product alone is too few work-groups
+    const int skY = (B * ((4 * K + 63) / 64) * ((K * C + 63) / 64) < 512 && 2 * H >= 128) ? 4 : 1;
+    if (skY > 1) {
+        hipLaunchKernelGGL(k_fill, dim3(nblk((long)B * 4 * K * K * C)), dim3(256), 0, s, f->Yt, 0.f,
+                           (long)B * 4 * K * K * C);
+        SGM_HIP_TRY(hipGetLastError());
+    }
     SGM_HIP_TRY(gemm(G(B, 4 * K, K * C, 2 * H, f->Gy, 0, 1, 4L * K, 0, f->T, 2L * H * K * C, (long)K * C, 1, 1, f->Yt,
-                       4L * K * K * C, (long)K * C, 1), s));
+                       4L * K * K * C, (long)K * C, 1, 0.f, skY), s));
     hipLaunchKernelGGL(k_perm_modes<float>, dim3(nblk(perm_threads<float>(B, K, C))), dim3(256), 0, s,
                        (const float*)f->Yt, f->Ym, B, 2 * K, K, C, 0);
     // dRreal[m] (2C x 2C) = Xm[m]^T (2C x B) gYm[m] (B x 2C)   (Xm saved in bf16 by the forward pass)
