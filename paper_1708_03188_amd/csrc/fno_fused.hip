@@ -794,7 +794,8 @@ bool fno_proj_bwd_ok(int C, int P) { return C == FC && (P == 32 || P == 64 || P 
 hipError_t launch_fno_proj_bwd(const FnoProjBwdArgs& a, hipStream_t s) {
     if (!fno_proj_bwd_ok(FC, a.P) || a.pix % 32 != 0 || a.pix <= 0) return hipErrorInvalidValue;
     if ((reinterpret_cast<uintptr_t>(a.a) & 15) || (reinterpret_cast<uintptr_t>(a.W1T) & 15) ||
-        (reinterpret_cast<uintptr_t>(a.W1) & 15) || (reinterpret_cast<uintptr_t>(a.dpred) & 7))
+        (reinterpret_cast<uintptr_t>(a.W1) & 15) || (reinterpret_cast<uintptr_t>(a.dpred) & 7) ||
+        (reinterpret_cast<uintptr_t>(a.da) & 15))
         return hipErrorInvalidValue;
     const dim3 grid((unsigned)fno_proj_bwd_groups(a.pix, a.P)), block(64 * WAVES);
     if (a.P == 32) hipLaunchKernelGGL(k_fno_proj_bwd<1>, grid, block, 0, s, a);
