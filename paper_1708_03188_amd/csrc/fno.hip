@@ -226,6 +226,31 @@ __global__ void k_build_rreal(const float* Rr, const float* Ri, bf16* Rreal, int
     Rreal[i] = (bf16)v;
 }
 
+// The same for every layer in one launch (blockIdx.y = layer; layer l's Rr at
+// Rr0 + l lstride, its Ri right after it), eight consecutive outputs of one row per
+// thread: two 16-byte loads and one 16-byte store (C a multiple of 8).
+__global__ void k_build_rreal8(const float* Rr0, long lstride, bf16* Rreal0, int nm, int C) {
+    const int C2 = 2 * C;
+    const long n8 = (long)nm * C2 * C2 / 8;
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= n8) return;
+    const float* Rr = Rr0 + blockIdx.y * lstride;
+    const float* Ri = Rr + (long)nm * C * C;
+    const long e0 = 8 * i;
+    const int col0 = (int)(e0 % C2);
+    const int row = (int)((e0 / C2) % C2);
+    const long m = e0 / ((long)C2 * C2);
+    const int pi = row / C, c = row % C, po = col0 / C, o0 = col0 % C;
+    const float* srcp = (pi == po ? Rr : Ri) + (m * C + c) * C + o0;
+    const float sg = (pi == po || pi == 0) ? 1.f : -1.f;
+    const float4 u = reinterpret_cast<const float4*>(srcp)[0], w = reinterpret_cast<const float4*>(srcp)[1];
+    typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+    bf16x8v o;
+    o[0] = (bf16)(sg * u.x); o[1] = (bf16)(sg * u.y); o[2] = (bf16)(sg * u.z); o[3] = (bf16)(sg * u.w);
+    o[4] = (bf16)(sg * w.x); o[5] = (bf16)(sg * w.y); o[6] = (bf16)(sg * w.z); o[7] = (bf16)(sg * w.w);
+    reinterpret_cast<bf16x8v*>(Rreal0 + (long)blockIdx.y * nm * C2 * C2)[i] = o;
+}
+
 // dRr = G[(re,c),(re,o)] + G[(im,c),(im,o)], dRi = G[(re,c),(im,o)] - G[(im,c),(re,o)]
 __global__ void k_fold_rgrad(const float* G, float* dRr, float* dRi, int nm, int C) {
     long n = (long)nm * C * C;
@@ -538,12 +563,21 @@ extern "C" sgm_status sgm_fno_create(const sgm_fno_desc* desc, uint64_t seed, sg
 static sgm_status refresh_mirrors(sgm_fno f, hipStream_t s) {
     if (f->mirrors_ok) return SGM_OK;
     const int C = f->C, P = f->P;
+    // every layer's parameters sit at a fixed stride: Rr, Ri, Wp, bp
+    const long lstride = f->nl > 1 ? f->oRr[1] - f->oRr[0] : 0;
+    const bool vec = C % 8 == 0 && f->oRi[0] == f->oRr[0] + (long)f->NM * C * C && (f->oRr[0] & 3) == 0 &&
+                     (lstride & 3) == 0;
+    if (vec) {
+        hipLaunchKernelGGL(k_build_rreal8, dim3(nblk((long)f->NM * 4 * C * C / 8), f->nl), dim3(256), 0, s,
+                           (const float*)(f->par + f->oRr[0]), lstride, f->Rreal, f->NM, C);
+    }
     for (int l = 0; l < f->nl; ++l) {
         hipLaunchKernelGGL(k_f32_to_bf16, dim3(nblk((long)C * C)), dim3(256), 0, s, f->par + f->oWp[l],
                            f->Wp16 + (long)l * C * C, (long)C * C);
-        hipLaunchKernelGGL(k_build_rreal, dim3(nblk((long)f->NM * 4 * C * C)), dim3(256), 0, s,
-                           (const float*)(f->par + f->oRr[l]), (const float*)(f->par + f->oRi[l]),
-                           f->Rreal + (long)l * f->NM * 4 * C * C, f->NM, C);
+        if (!vec)
+            hipLaunchKernelGGL(k_build_rreal, dim3(nblk((long)f->NM * 4 * C * C)), dim3(256), 0, s,
+                               (const float*)(f->par + f->oRr[l]), (const float*)(f->par + f->oRi[l]),
+                               f->Rreal + (long)l * f->NM * 4 * C * C, f->NM, C);
     }
     hipLaunchKernelGGL(k_f32_to_bf16, dim3(nblk((long)C * P)), dim3(256), 0, s, f->par + f->oW1, f->W1_16, (long)C * P);
     hipLaunchKernelGGL(k_f32_to_bf16, dim3(nblk(2L * P)), dim3(256), 0, s, f->par + f->oW2, f->W2_16, 2L * P);
